@@ -1,0 +1,150 @@
+"""FP64 projection and front-to-back alpha blending, differentiable by autograd.
+
+Paper: Background, "Review of Gaussian Splatting": pixel colour
+C = sum_i c_i abar_i T_i with T_i = prod_{j<i} (1 - abar_j), over the
+depth-sorted splats of the pixel's tile.  Readings (the paper is silent on the
+rasteriser constants; these follow the original 3DGS design):
+
+* abar = min(0.99, alpha exp(power)), power = -1/2 d^T conic d with d the
+  offset from the splat centre to the pixel centre; power > 0 is skipped;
+* abar < 1/255 is skipped;
+* if T (1 - abar) < 1e-4 the pixel stops before adding that splat;
+* output C + T_final * background.
+
+The per-tile lists come from ``binning.bin_view`` (float32 keys).  Skip and
+stop decisions are taken here in float64 and returned so tests can detect a
+decision that flips between two nearby parameter vectors.  Pinned in
+tests/test_oracle_render.py (one- and two-splat closed forms, T_final as a
+product, the isotropic EWA closed form, central finite differences).
+"""
+from __future__ import annotations
+
+import torch
+
+from .gaussians import DT, covariance, colour, split
+from .binning import TILE, Bins, bin_view
+
+ALPHA_MAX = 0.99
+ALPHA_MIN = 1.0 / 255.0
+T_STOP = 1e-4
+NEAR = 0.2
+DILATION = 0.3
+FOV_CLAMP = 1.3
+
+
+def cam_tensors(cam):
+    W = torch.as_tensor(cam.R, dtype=DT)
+    t = torch.as_tensor(cam.t, dtype=DT)
+    centre = -(W.T @ t)
+    return W, t, centre
+
+
+def project(x: torch.Tensor, cam, sh_degree: int) -> dict:
+    """Screen-space splat of every Gaussian: centre (u, v), conic, opacity, RGB."""
+    p = split(x, sh_degree)
+    W, t, centre = cam_tensors(cam)
+    fx, fy, cx, cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    Sigma = covariance(p["log_s"], p["quat"])
+    pc = p["mu"] @ W.T + t[None, :]
+    z = pc[:, 2]
+    limx = FOV_CLAMP * (0.5 * cam.width / fx)
+    limy = FOV_CLAMP * (0.5 * cam.height / fy)
+    txtz = torch.clamp(pc[:, 0] / z, -limx, limx)
+    tytz = torch.clamp(pc[:, 1] / z, -limy, limy)
+    zero = torch.zeros_like(z)
+    J = torch.stack([
+        torch.stack([fx / z, zero, -fx * txtz / z], -1),
+        torch.stack([zero, fy / z, -fy * tytz / z], -1),
+    ], -2)
+    T = J @ W[None]
+    cov2 = T @ Sigma @ T.transpose(-1, -2)
+    a = cov2[:, 0, 0] + DILATION
+    b = cov2[:, 0, 1]
+    c = cov2[:, 1, 1] + DILATION
+    det = a * c - b * b
+    conic = torch.stack([c / det, -b / det, a / det], -1)
+    u = fx * pc[:, 0] / z + cx
+    v = fy * pc[:, 1] / z + cy
+    alpha = torch.sigmoid(p["logit"])
+    rgb = colour(p["sh"], p["mu"], centre, sh_degree)
+    return dict(u=u, v=v, conic=conic, alpha=alpha, rgb=rgb, depth=z)
+
+
+def render(x: torch.Tensor, cam, sh_degree: int, bins: Bins | None = None, background=(0.0, 0.0, 0.0),
+           return_aux: bool = False):
+    """Render one view: image [H, W, 3] (and T_final, n_contrib, decisions)."""
+    if bins is None:
+        bins = bin_view(x.detach().to(torch.float32).numpy(), cam)
+    pr = project(x, cam, sh_degree)
+    H, Wd = cam.height, cam.width
+    bg = torch.as_tensor(background, dtype=DT)
+    rows = []
+    T_rows = []
+    n_rows = []
+    decisions = {}
+    for ty in range(bins.tiles_y):
+        row_tiles = []
+        row_T = []
+        row_n = []
+        for tx in range(bins.tiles_x):
+            y_lo, y_hi = ty * TILE, min((ty + 1) * TILE, H)
+            x_lo, x_hi = tx * TILE, min((tx + 1) * TILE, Wd)
+            hh, ww = y_hi - y_lo, x_hi - x_lo
+            gids = torch.as_tensor(bins.tile_list(ty * bins.tiles_x + tx), dtype=torch.long)
+            if gids.numel() == 0:
+                row_tiles.append(bg.expand(hh, ww, 3).clone())
+                row_T.append(torch.ones(hh, ww, dtype=DT))
+                row_n.append(torch.zeros(hh, ww, dtype=torch.long))
+                continue
+            py, px = torch.meshgrid(torch.arange(y_lo, y_hi, dtype=DT) + 0.5,
+                                    torch.arange(x_lo, x_hi, dtype=DT) + 0.5, indexing="ij")
+            px = px.reshape(-1, 1)
+            py = py.reshape(-1, 1)
+            dx = pr["u"][gids][None, :] - px
+            dy = pr["v"][gids][None, :] - py
+            cn = pr["conic"][gids]
+            power = -0.5 * (cn[None, :, 0] * dx * dx + cn[None, :, 2] * dy * dy) - cn[None, :, 1] * dx * dy
+            abar = torch.clamp(pr["alpha"][gids][None, :] * torch.exp(power), max=ALPHA_MAX)
+            with torch.no_grad():
+                valid = (power <= 0) & (abar >= ALPHA_MIN)
+            a_eff = torch.where(valid, abar, torch.zeros_like(abar))
+            one_minus = 1.0 - a_eff
+            T_incl = torch.cumprod(one_minus, dim=1)
+            with torch.no_grad():
+                below = T_incl < T_STOP
+                L = below.shape[1]
+                idx = torch.arange(L)
+                first = torch.where(below, idx[None, :], torch.full_like(below, L, dtype=torch.long)).min(1).values
+                keep = idx[None, :] < first[:, None]
+            T_excl = torch.cat([torch.ones_like(T_incl[:, :1]), T_incl[:, :-1]], 1)
+            wgt = torch.where(keep, a_eff * T_excl, torch.zeros_like(a_eff))
+            col = wgt @ pr["rgb"][gids]
+            T_fin = torch.prod(torch.where(keep, one_minus, torch.ones_like(one_minus)), 1)
+            out = col + T_fin[:, None] * bg[None, :]
+            with torch.no_grad():
+                used = keep & valid
+                last = torch.where(used, idx[None, :] + 1, torch.zeros_like(idx)[None, :]).max(1).values
+            row_tiles.append(out.reshape(hh, ww, 3))
+            row_T.append(T_fin.reshape(hh, ww))
+            row_n.append(last.reshape(hh, ww))
+            if return_aux:
+                decisions[ty * bins.tiles_x + tx] = (valid.clone(), keep.clone(), (abar >= ALPHA_MAX).detach())
+        rows.append(torch.cat(row_tiles, 1))
+        T_rows.append(torch.cat(row_T, 1))
+        n_rows.append(torch.cat(row_n, 1))
+    img = torch.cat(rows, 0)
+    if not return_aux:
+        return img
+    return img, dict(T_final=torch.cat(T_rows, 0), n_contrib=torch.cat(n_rows, 0), decisions=decisions,
+                     bins=bins, proj=pr)
+
+
+def decisions_equal(d1: dict, d2: dict) -> bool:
+    """True when every skip / stop / clamp decision agrees between two renders."""
+    if d1.keys() != d2.keys():
+        return False
+    for k in d1:
+        for a, b in zip(d1[k], d2[k]):
+            if not torch.equal(a, b):
+                return False
+    return True
