@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Throughput of the 3DGS^2-TR optimizer iteration on one MI355X (gfx950).
+
+A step is one iteration of Algorithm 1 on the object-scale workload
+(100k Gaussians, SH degree 3, 48 cameras at 800x800, every 8th held out):
+the stochastic gradient on one training view, every l = 10 iterations the
+Hutchinson diagonal (one probe, one view), and the trust-region update of all
+5.9M parameters.  Inputs are seeded synthetic data resident in HBM before the
+timed region; targets are renders of a seeded ground-truth scene.
+
+Prints one JSON line: iterations/s, the roofline of the kernel that takes
+the most time (measured with HIP events around its launches during the timed
+region), the Adam baseline's iterations/s on the same views, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--fit TR_ITERS]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# fp32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock)
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Algorithmic arithmetic per (pixel, splat) evaluation of the blend kernels,
+# counted from the operations the method requires (add, mul, compare, exp and
+# divide each count 1): every evaluation forms the offset, the quadratic form
+# and the skip test; a contributing one also does the blend (and the JVP /
+# VJP arithmetic).
+OPS_EVAL = 14
+OPS_CONTRIB = {"blend_fwd": 12, "blend_jvp": 31, "blend_bwd": 47}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=32, help="tiles in the oracle's timed sample")
+    ap.add_argument("--fit", type=int, default=0,
+                    help="also run Adam for 2x this many iterations and TR until Adam's PSNR (seconds to PSNR)")
+    return ap.parse_args()
+
+
+def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int) -> dict | None:
+    """Algorithmic work of one stage over the timed launches -> roofline entry."""
+    if st["launches"] == 0 or st["total_ms"] <= 0:
+        return None
+    sec = st["total_ms"] / 1e3
+    if stage in OPS_CONTRIB:
+        ops = OPS_EVAL * st["work0"] + OPS_CONTRIB[stage] * st["work1"]
+        ach = ops / sec / 1e12
+        return dict(bound="alu", achieved=round(ach, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
+                    frac=round(ach / ALU_PEAK_TOPS, 4), traffic=None, kernel=stage,
+                    avg_launch_ms=round(st["total_ms"] / st["launches"], 4),
+                    evaluations_per_launch=st["work0"] // st["launches"],
+                    contributing_per_launch=st["work1"] // st["launches"])
+    if stage in ("tr_step", "adam_step"):
+        # tr_step reads x, g, ghat, Dhat and writes x, ghat (+ D read, Dhat write on Hutchinson steps);
+        # Adam reads x, g, m, v and writes x, m, v
+        per = 24 if stage == "tr_step" else 28
+        bytes_ = per * p * n * st["launches"] + (8 * p * n * hutch_launches if stage == "tr_step" else 0)
+        ach = bytes_ / sec / 1e9
+        return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=stage,
+                    avg_launch_ms=round(st["total_ms"] / st["launches"], 4),
+                    bytes_per_launch=bytes_ // st["launches"])
+    return dict(bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None, kernel=stage,
+                avg_launch_ms=round(st["total_ms"] / st["launches"], 4))
+
+
+def cpu_baseline(sc, n_tiles_sample: int, l: int) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload.
+
+    Sample: one training view of the object-scale scene; the oracle's float32
+    binning of all Gaussians, its render + autograd gradient (L1 loss) and its
+    Gauss-Newton product (JVP, GN weights, VJP) on `n_tiles_sample` random
+    non-empty tiles, scaled to the whole view by (pairs in view) / (pairs in
+    sample); its trust-region radius and step at full size.  One iteration =
+    binning + gradient + step + (binning + GN product) / l.
+    """
+    import numpy as np
+    import torch
+
+    from oracle import binning as OB
+    from oracle import method as OM
+    from oracle import render as OR
+
+    torch.set_num_threads(max(1, len(os.sched_getaffinity(0))))
+    threads = torch.get_num_threads()
+    x = sc.init.astype(np.float32)
+    cam = sc.cameras[1]
+    rng = np.random.default_rng(7)
+    tgt = torch.tensor(rng.uniform(0, 1, size=(cam.height, cam.width, 3)))
+    t0 = time.perf_counter()
+    bins = OB.bin_view(x, cam)
+    t_bin = time.perf_counter() - t0
+    counts = bins.ranges[:, 1] - bins.ranges[:, 0]
+    nonempty = np.flatnonzero(counts > 0)
+    pick = set(int(t) for t in rng.choice(nonempty, size=min(n_tiles_sample, len(nonempty)), replace=False))
+    scale = float(counts.sum()) / float(counts[list(pick)].sum())
+    xt = torch.tensor(x.astype(np.float64))
+    f = lambda xx: OR.render(xx, cam, sc.sh_degree, bins, tiles=pick)  # noqa: E731
+    t0 = time.perf_counter()
+    xg = xt.clone().requires_grad_(True)
+    img = f(xg)
+    m = ~torch.isnan(img)
+    torch.abs(img[m] - tgt[m]).sum().backward()
+    t_grad = (time.perf_counter() - t0) * scale
+    z = torch.tensor(OM.probe(5002, 0, *x.shape))
+    t0 = time.perf_counter()
+    img, u = torch.func.jvp(f, (xt,), (z,))
+    mm = ~torch.isnan(img)
+    y = torch.zeros_like(img)
+    y[mm] = OM.gn_cotangent(img[mm], tgt[mm], u[mm], 0.0)
+    _, vjp = torch.func.vjp(f, xt)
+    vjp(y)
+    t_hvp = (time.perf_counter() - t0) * scale
+    t0 = time.perf_counter()
+    g = np.zeros(x.shape)
+    OM.tr_step(x, g, g, g, None, 0.9, 0.999, 1e-6, sc.sh_degree)
+    t_step = time.perf_counter() - t0
+    t_iter = t_bin + t_grad + t_step + (t_bin + t_hvp) / l
+    return dict(value=round(1.0 / t_iter, 6), unit="iter/s", cores=threads, kind="oracle",
+                sample=(f"object-scale view, {len(pick)} of {len(nonempty)} non-empty tiles "
+                        f"(x{scale:.1f} by pair count) for render+grad and the GN product; "
+                        f"binning and trust-region step at full size; est. {t_iter:.1f} s/iter"))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the image-parallel sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthetic as syn
+    from paper_2602_00395_amd import Scene, profile_enable, profile_read, profile_reset
+    from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer, fit, mean_psnr
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    sc = syn.config2_scene()
+    cams = sc.cameras
+    train_ids, test_ids = sc.train_ids(), sc.test_ids()
+    mask = [i % sc.test_every != 0 for i in range(len(cams))]
+    blank = [torch.zeros((c.height, c.width, 3), device=dev) for c in cams]
+    gt_scene = Scene(torch.tensor(sc.gt, device=dev), blank, cams, sc.sh_degree, lam=0.2)
+    targets = [gt_scene.render(j).clone() for j in range(len(cams))]
+    gt_scene.close()
+    del blank
+    x0 = torch.tensor(sc.init, device=dev)
+    N, P = sc.n, sc.p
+    cfg = TRConfig()
+
+    def make():
+        return Scene(x0, targets, cams, sc.sh_degree, lam=0.2, train_mask=mask)
+
+    # ---- stage breakdown (untimed) to find the dominant kernel
+    s = make()
+    tr = TRTrainer(s, train_ids, cfg)
+    for _ in range(args.warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    profile_reset()
+    profile_enable("all")
+    for _ in range(2 * cfg.l):
+        tr.step()
+    torch.cuda.synchronize()
+    profile_enable("")
+    stages = ["project_fwd", "depth_sort", "scan", "emit_pairs", "pair_sort", "blend_fwd", "loss", "blend_bwd",
+              "project_bwd", "project_jvp", "blend_jvp", "tr_step"]
+    stage_ms = {k: profile_read(k)["total_ms"] / (2 * cfg.l) for k in stages}
+    dominant = max(stage_ms, key=stage_ms.get)
+    s.close()
+
+    # ---- timed TR iterations
+    s = make()
+    tr = TRTrainer(s, train_ids, cfg)
+    for _ in range(args.warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    profile_reset()
+    profile_enable(dominant)
+    first = tr.t + 1
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tr.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    profile_enable("")
+    hutch = sum(1 for t in range(first, first + args.steps) if (t - 1) % cfg.l == 0)
+    roof = roofline(dominant, profile_read(dominant), N, P, hutch)
+    psnr_tr = mean_psnr(s, test_ids)
+    s.close()
+
+    # ---- Adam on the same views, same clock
+    s = make()
+    extent = 1.1 * 4.0
+    ad = AdamTrainer(s, train_ids, extent)
+    for _ in range(args.warmup):
+        ad.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ad.step()
+    torch.cuda.synchronize()
+    dt_adam = time.perf_counter() - t0
+    s.close()
+
+    out = dict(
+        metric="iters/s", value=round(args.steps / dt, 3), unit="iter/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(1e3 * dt / args.steps, 3), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="object-scale TR iteration: 100k Gaussians, SH degree 3, 48 cameras 800x800 "
+                             "(42 train, 6 held out), L1+0.2 D-SSIM, |S1|=|S2|=nu=1, l=10",
+                    gaussians=N, params_per_gaussian=P, cameras=len(cams), resolution="800x800"),
+        roofline=roof,
+        adam_iters_per_s=round(args.steps / dt_adam, 3),
+        stage_ms_per_iter={k: round(v, 4) for k, v in stage_ms.items()},
+        psnr_after=round(psnr_tr, 3),
+    )
+
+    if args.fit > 0:
+        # seconds to the Adam baseline's PSNR: Adam runs 2x the TR budget
+        s = make()
+        ad = AdamTrainer(s, train_ids, extent, budget=2 * args.fit)
+        hist_a, _ = fit(ad, s, test_ids, 2 * args.fit, eval_every=500,
+                        log=lambda m: print("adam", m, file=sys.stderr, flush=True))
+        s.close()
+        target = hist_a[-1][2]
+        s = make()
+        tr = TRTrainer(s, train_ids, TRConfig(budget=args.fit))
+        hist_t, reached = fit(tr, s, test_ids, args.fit, eval_every=500, target_psnr=target,
+                              log=lambda m: print("tr", m, file=sys.stderr, flush=True))
+        s.close()
+        out["fit"] = dict(adam_iters=2 * args.fit, adam_psnr=round(target, 3), adam_train_s=round(hist_a[-1][1], 2),
+                          tr_iters=args.fit, tr_psnr=round(hist_t[-1][2], 3),
+                          tr_s_to_adam_psnr=None if reached is None else round(reached, 2),
+                          adam_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_a],
+                          tr_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_t])
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_tiles, cfg.l)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

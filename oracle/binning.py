@@ -21,6 +21,15 @@ original 3DGS design:
 Because a float64 key could never equal a float32 GPU key, this stage alone is
 written op for op in float32 (numpy float32 is IEEE round-to-nearest with no
 fused multiply-add; exp of the log-scale is taken in float64 and rounded).
+
+The same holds for the blend's skip decision, which decides an integer (which
+splats contribute to a pixel) from floating point: it is taken in float32 on
+both sides.  A splat is skipped at a pixel when its float32 power
+-1/2 (a dx^2 + c dy^2) - b dx dy (evaluated left to right) is positive or
+below tau = float32(-ln(255 alpha)); that is the 1/255 opacity threshold
+alpha exp(power) < 1/255 moved to the log domain, where it needs no exp.
+alpha = float32(sigmoid(logit)) is evaluated in float64 and rounded; the
+conic is (c, -b, a) / det of the float32 screen covariance.
 Pinned in tests/test_oracle_binning.py by brute-force rectangle checks, a
 principal-ray projection and sort invariants.
 """
@@ -45,6 +54,7 @@ class Bins:
     keys: np.ndarray  # uint64[Pi], sorted
     gids: np.ndarray  # int64[Pi], Gaussian index of each sorted pair
     ranges: np.ndarray  # int64[tiles, 2], [start, end) into the sorted pairs
+    dec: dict = None  # float32 decision inputs per Gaussian: u, v, conic_a, conic_b, conic_c, tau
 
     def tile_list(self, tile_id: int) -> np.ndarray:
         s, e = self.ranges[tile_id]
@@ -93,6 +103,9 @@ def project_f32(x32: np.ndarray, cam) -> dict:
         radius = np.ceil(F(3.0) * np.sqrt(lam))
         u = (fx * p[0]) / p[2] + cx
         v = (fy * p[1]) / p[2] + cy
+        conic = (c / det, -b / det, a / det)
+        alpha = (1.0 / (1.0 + np.exp(-x32[10].astype(np.float64)))).astype(F)
+        tau = (-np.log(255.0 * alpha.astype(np.float64))).astype(F)
     tx = (cam.width + TILE - 1) // TILE
     ty = (cam.height + TILE - 1) // TILE
     inv = F(1.0 / TILE)
@@ -110,6 +123,7 @@ def project_f32(x32: np.ndarray, cam) -> dict:
     visible &= touched > 0
     touched = np.where(visible, touched, 0)
     return dict(visible=visible, depth=p[2].astype(F), u=u, v=v, radius=radius, det=det, cov2=(a, b, c),
+                conic=conic, alpha=alpha, tau=tau,
                 rect=np.stack([x0, y0, x1, y1], 1).astype(np.int32), tiles_touched=touched,
                 tiles_x=tx, tiles_y=ty)
 
@@ -138,5 +152,21 @@ def bin_view(x32: np.ndarray, cam) -> Bins:
     n_tiles = tx * ty
     starts = np.searchsorted(tile_sorted, np.arange(n_tiles), side="left")
     ends = np.searchsorted(tile_sorted, np.arange(n_tiles), side="right")
+    dec = dict(u=pr["u"], v=pr["v"], ca=pr["conic"][0], cb=pr["conic"][1], cc=pr["conic"][2], tau=pr["tau"])
     return Bins(tx, ty, vis, depth_bits, pr["rect"], touched, keys_sorted, gids_sorted,
-                np.stack([starts, ends], 1))
+                np.stack([starts, ends], 1), dec)
+
+
+def power_f32(dec: dict, gids: np.ndarray, px: np.ndarray, py: np.ndarray) -> np.ndarray:
+    """float32 power of splats `gids` at pixel centres (px, py): [pixels, len(gids)]."""
+    with np.errstate(all="ignore"):
+        dx = dec["u"][gids][None, :] - px.astype(F)[:, None]
+        dy = dec["v"][gids][None, :] - py.astype(F)[:, None]
+        ca, cb, cc = dec["ca"][gids][None, :], dec["cb"][gids][None, :], dec["cc"][gids][None, :]
+        return F(-0.5) * ((ca * dx) * dx + (cc * dy) * dy) - (cb * dx) * dy
+
+
+def contributes_f32(dec: dict, gids: np.ndarray, px: np.ndarray, py: np.ndarray) -> np.ndarray:
+    """The skip decision: True where the splat is not skipped (power <= 0 and power >= tau)."""
+    pw = power_f32(dec, gids, px, py)
+    return (pw <= F(0.0)) & (pw >= dec["tau"][gids][None, :])

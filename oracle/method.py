@@ -231,7 +231,13 @@ def quaternion_beta(log_s, q) -> np.ndarray:
         dE = Rt @ dR[..., c]
         d2E = Rt @ d2R[..., c, c]
         SdES = s[:, :, None] * dE / s[:, None, :]
-        out[:, c] = (2.0 * (SdES ** 2).sum((-1, -2)) + 2.0 * d2E.diagonal(dim1=-2, dim2=-1).sum(-1)).numpy()
+        t1 = 2.0 * (SdES ** 2).sum((-1, -2))
+        t2 = 2.0 * d2E.diagonal(dim1=-2, dim2=-1).sum(-1)
+        b = (t1 + t2).numpy()
+        # The two terms cancel exactly when S is isotropic in the rotated
+        # plane (T is then constant); a sum below their rounding error is 0.
+        noise = 64.0 * np.finfo(np.float64).eps * (np.abs(t1.numpy()) + np.abs(t2.numpy()))
+        out[:, c] = np.where(np.abs(b) <= noise, 0.0, b)
     return out
 
 

@@ -7,22 +7,25 @@ rasteriser constants; these follow the original 3DGS design):
 
 * abar = min(0.99, alpha exp(power)), power = -1/2 d^T conic d with d the
   offset from the splat centre to the pixel centre; power > 0 is skipped;
-* abar < 1/255 is skipped;
+* alpha exp(power) < 1/255 is skipped -- a decision that picks which splats
+  count, so it is taken in float32 exactly as the kernel takes it
+  (``binning.contributes_f32``), while every value is computed in float64;
 * if T (1 - abar) < 1e-4 the pixel stops before adding that splat;
 * output C + T_final * background.
 
-The per-tile lists come from ``binning.bin_view`` (float32 keys).  Skip and
-stop decisions are taken here in float64 and returned so tests can detect a
-decision that flips between two nearby parameter vectors.  Pinned in
+The per-tile lists come from ``binning.bin_view`` (float32 keys).  The stop
+and clamp decisions are taken here in float64; all decisions are returned so
+tests can detect one that flips between two nearby parameter vectors.  Pinned in
 tests/test_oracle_render.py (one- and two-splat closed forms, T_final as a
 product, the isotropic EWA closed form, central finite differences).
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from .gaussians import DT, covariance, colour, split
-from .binning import TILE, Bins, bin_view
+from .binning import TILE, Bins, bin_view, contributes_f32
 
 ALPHA_MAX = 0.99
 ALPHA_MIN = 1.0 / 255.0
@@ -71,8 +74,11 @@ def project(x: torch.Tensor, cam, sh_degree: int) -> dict:
 
 
 def render(x: torch.Tensor, cam, sh_degree: int, bins: Bins | None = None, background=(0.0, 0.0, 0.0),
-           return_aux: bool = False):
-    """Render one view: image [H, W, 3] (and T_final, n_contrib, decisions)."""
+           return_aux: bool = False, tiles=None):
+    """Render one view: image [H, W, 3] (and T_final, n_contrib, decisions).
+
+    ``tiles`` (optional set of tile ids) restricts the work to those tiles;
+    pixels of the other tiles are NaN.  Used to sample full-size views."""
     if bins is None:
         bins = bin_view(x.detach().to(torch.float32).numpy(), cam)
     pr = project(x, cam, sh_degree)
@@ -91,6 +97,11 @@ def render(x: torch.Tensor, cam, sh_degree: int, bins: Bins | None = None, backg
             x_lo, x_hi = tx * TILE, min((tx + 1) * TILE, Wd)
             hh, ww = y_hi - y_lo, x_hi - x_lo
             gids = torch.as_tensor(bins.tile_list(ty * bins.tiles_x + tx), dtype=torch.long)
+            if tiles is not None and (ty * bins.tiles_x + tx) not in tiles:
+                row_tiles.append(torch.full((hh, ww, 3), float("nan"), dtype=DT))
+                row_T.append(torch.full((hh, ww), float("nan"), dtype=DT))
+                row_n.append(torch.zeros(hh, ww, dtype=torch.long))
+                continue
             if gids.numel() == 0:
                 row_tiles.append(bg.expand(hh, ww, 3).clone())
                 row_T.append(torch.ones(hh, ww, dtype=DT))
@@ -105,8 +116,9 @@ def render(x: torch.Tensor, cam, sh_degree: int, bins: Bins | None = None, backg
             cn = pr["conic"][gids]
             power = -0.5 * (cn[None, :, 0] * dx * dx + cn[None, :, 2] * dy * dy) - cn[None, :, 1] * dx * dy
             abar = torch.clamp(pr["alpha"][gids][None, :] * torch.exp(power), max=ALPHA_MAX)
-            with torch.no_grad():
-                valid = (power <= 0) & (abar >= ALPHA_MIN)
+            gy, gx = np.meshgrid(np.arange(y_lo, y_hi) + 0.5, np.arange(x_lo, x_hi) + 0.5, indexing="ij")
+            tile_ids = bins.tile_list(ty * bins.tiles_x + tx)
+            valid = torch.as_tensor(contributes_f32(bins.dec, tile_ids, gx.reshape(-1), gy.reshape(-1)))
             a_eff = torch.where(valid, abar, torch.zeros_like(abar))
             one_minus = 1.0 - a_eff
             T_incl = torch.cumprod(one_minus, dim=1)

@@ -1,0 +1,788 @@
+// Host side of the C ABI declared in include/gs3tr.h: scene ownership,
+// argument validation, per-view binning and the orchestration of one
+// optimizer iteration of 3DGS^2-TR (Algorithm 1) on a caller stream.
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gs3_internal.h"
+#include "gs3tr.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+gs3_status fail(gs3_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define GS3_HIP(call)                                                                                 \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess) return fail(GS3_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define GS3_LAUNCHED() GS3_HIP(hipGetLastError())
+#define GS3_TRY(expr)              \
+  do {                             \
+    gs3_status s_ = (expr);        \
+    if (s_ != GS3_OK) return s_;   \
+  } while (0)
+
+constexpr int kMaxLossViews = 4096;
+
+// ---------------------------------------------------------------- profiler
+// HIP events around named stages, plus device work counters for the blends.
+namespace prof {
+std::mutex mu;
+std::atomic<bool> active{false};
+std::string names;  // ",name,name," or ",all,"
+struct Entry {
+  std::string name;
+  hipEvent_t a = nullptr, b = nullptr;
+  int slot = -1;
+  int64_t w0 = 0, w1 = 0;
+};
+std::vector<Entry> entries;
+constexpr int kSlots = 1 << 15;
+unsigned long long* ctr = nullptr;
+int slots_used = 0;
+
+struct Scope {
+  int idx = -1;
+  unsigned long long* c = nullptr;
+};
+
+Scope begin(const char* name, hipStream_t st, bool counted = false) {
+  Scope sc;
+  if (!active.load(std::memory_order_relaxed)) return sc;
+  std::lock_guard<std::mutex> lk(mu);
+  if (names.find(",all,") == std::string::npos && names.find("," + std::string(name) + ",") == std::string::npos)
+    return sc;
+  Entry e;
+  e.name = name;
+  if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return sc;
+  (void)hipEventRecord(e.a, st);
+  if (counted && ctr && slots_used < kSlots) {
+    e.slot = slots_used++;
+    sc.c = ctr + 2 * e.slot;
+  }
+  entries.push_back(e);
+  sc.idx = (int)entries.size() - 1;
+  return sc;
+}
+
+void end(const Scope& sc, hipStream_t st, int64_t w0 = 0, int64_t w1 = 0) {
+  if (sc.idx < 0) return;
+  std::lock_guard<std::mutex> lk(mu);
+  Entry& e = entries[sc.idx];
+  (void)hipEventRecord(e.b, st);
+  e.w0 += w0;
+  e.w1 += w1;
+}
+
+void clear_locked() {
+  for (auto& e : entries) {
+    if (e.a) (void)hipEventDestroy(e.a);
+    if (e.b) (void)hipEventDestroy(e.b);
+  }
+  entries.clear();
+  slots_used = 0;
+}
+}  // namespace prof
+
+}  // namespace
+
+struct gs3_scene {
+  int64_t N = 0;
+  int deg = 0, K = 1, P = 14, n_cams = 0, n_train = 0;
+  std::vector<gs3_camera> cams;
+  std::vector<uint8_t> train;
+  std::vector<int64_t> tgt_off;
+  float bg[3] = {0, 0, 0};
+  float lam = 0.f;
+  uint32_t flags = 0;
+  int64_t m_comp = 0;  // m = 6 * sum over training views of H W
+  int64_t max_px = 0;
+  int max_tiles = 0;
+  // resident state
+  float *x = nullptr, *targets = nullptr, *ghat = nullptr, *dhat = nullptr, *am = nullptr, *av = nullptr;
+  // per-Gaussian scratch
+  Rec* rec = nullptr;
+  uint2* rect = nullptr;
+  TRec* trec = nullptr;
+  uint32_t *depth_key = nullptr, *tiles = nullptr, *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
+  uint32_t *counts = nullptr, *offsets = nullptr, *total_dev = nullptr;
+  void* stmp = nullptr;
+  void* rtmp = nullptr;
+  size_t rtmp_bytes = 0;
+  // per-pair scratch
+  int64_t pair_cap = 0;
+  uint32_t *pt = nullptr, *pg = nullptr, *pt2 = nullptr, *pg2 = nullptr;
+  float* partials = nullptr;
+  // per-view image scratch
+  uint2* ranges = nullptr;
+  float *img = nullptr, *cot = nullptr, *tan_img = nullptr, *ssim_tmp = nullptr;
+  double *dpart = nullptr, *dsum = nullptr;
+  uint32_t* host_u32 = nullptr;
+  double* host_f64 = nullptr;
+  hipEvent_t done_ev = nullptr;
+  // state of the last binned view
+  const uint32_t* sorted_gid = nullptr;
+  const uint32_t* sorted_tile = nullptr;
+  int64_t n_pairs = 0;
+};
+
+namespace {
+
+int params_for(int deg) { return (deg < 0 || deg > 3) ? -1 : 11 + 3 * (deg + 1) * (deg + 1); }
+
+CamDev make_cam(const gs3_camera& c) {
+  CamDev d;
+  for (int i = 0; i < 9; ++i) d.W[i] = c.R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = c.t[i];
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  const float hw = (float)c.width * 0.5f, hh = (float)c.height * 0.5f;
+  const float tx = hw / c.fx, ty = hh / c.fy;
+  d.limx = GS3_FOV_CLAMP * tx;
+  d.limy = GS3_FOV_CLAMP * ty;
+  for (int i = 0; i < 3; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < 3; ++k) acc -= (double)c.R[k * 3 + i] * (double)c.t[k];
+    d.campos[i] = (float)acc;
+  }
+  d.width = c.width;
+  d.height = c.height;
+  d.tiles_x = (c.width + GS3_TILE - 1) / GS3_TILE;
+  d.tiles_y = (c.height + GS3_TILE - 1) / GS3_TILE;
+  return d;
+}
+
+template <class T>
+gs3_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(GS3_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  return GS3_OK;
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+void free_all(gs3_scene* s) {
+  dfree(s->x);
+  dfree(s->targets);
+  dfree(s->ghat);
+  dfree(s->dhat);
+  dfree(s->am);
+  dfree(s->av);
+  dfree(s->rec);
+  dfree(s->rect);
+  dfree(s->trec);
+  dfree(s->depth_key);
+  dfree(s->tiles);
+  dfree(s->ka);
+  dfree(s->va);
+  dfree(s->kb);
+  dfree(s->vb);
+  dfree(s->counts);
+  dfree(s->offsets);
+  dfree(s->total_dev);
+  dfree(s->stmp);
+  dfree(s->rtmp);
+  dfree(s->pt);
+  dfree(s->pg);
+  dfree(s->pt2);
+  dfree(s->pg2);
+  dfree(s->partials);
+  dfree(s->ranges);
+  dfree(s->img);
+  dfree(s->cot);
+  dfree(s->tan_img);
+  dfree(s->ssim_tmp);
+  dfree(s->dpart);
+  dfree(s->dsum);
+  if (s->host_u32) (void)hipHostFree(s->host_u32);
+  if (s->host_f64) (void)hipHostFree(s->host_f64);
+  s->host_u32 = nullptr;
+  s->host_f64 = nullptr;
+  if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+  s->done_ev = nullptr;
+}
+
+gs3_status ensure_pairs(gs3_scene* s, int64_t n_pairs) {
+  if (n_pairs <= s->pair_cap && s->rtmp) return GS3_OK;
+  const int64_t cap = std::max<int64_t>(n_pairs + n_pairs / 4 + 4096, s->pair_cap);
+  dfree(s->pt);
+  dfree(s->pg);
+  dfree(s->pt2);
+  dfree(s->pg2);
+  dfree(s->partials);
+  dfree(s->rtmp);
+  s->pair_cap = 0;
+  GS3_TRY(dalloc(&s->pt, cap));
+  GS3_TRY(dalloc(&s->pg, cap));
+  GS3_TRY(dalloc(&s->pt2, cap));
+  GS3_TRY(dalloc(&s->pg2, cap));
+  GS3_TRY(dalloc(&s->partials, (size_t)cap * 9));
+  s->rtmp_bytes = radix_temp_bytes(std::max<int64_t>(cap, s->N));
+  GS3_TRY(dalloc((char**)&s->rtmp, s->rtmp_bytes));
+  s->pair_cap = cap;
+  return GS3_OK;
+}
+
+gs3_status check_scene(gs3_scene* s) {
+  if (!s) return fail(GS3_EINVAL, "scene is NULL");
+  if (!s->x) return fail(GS3_ESTATE, "scene has been destroyed");
+  return GS3_OK;
+}
+
+gs3_status check_cam(gs3_scene* s, int32_t cam) {
+  if (cam < 0 || cam >= s->n_cams)
+    return fail(GS3_EINVAL, "camera index " + std::to_string(cam) + " out of range [0, " + std::to_string(s->n_cams) + ")");
+  return GS3_OK;
+}
+
+int bits_for(int n_tiles) {
+  int b = 1;
+  while ((1 << b) < n_tiles) ++b;
+  return b;
+}
+
+// Project, sort by depth, emit pairs, sort pairs by tile, per-tile ranges.
+// Synchronises `st` once to learn the pair count.
+gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
+  const CamDev cd = make_cam(s->cams[cam]);
+  const int64_t N = s->N;
+  auto p0 = prof::begin("project_fwd", st);
+  launch_project_fwd(s->x, N, s->deg, cd, s->rec, s->rect, s->depth_key, s->tiles, st);
+  prof::end(p0, st);
+  GS3_LAUNCHED();
+  auto p1 = prof::begin("depth_sort", st);
+  GS3_HIP(hipMemcpyAsync(s->ka, s->depth_key, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  launch_iota(s->va, N, st);
+  uint32_t *k_sorted, *order;
+  radix_sort_u32(s->ka, s->va, s->kb, s->vb, N, 32, s->rtmp, st, &k_sorted, &order);
+  prof::end(p1, st);
+  auto p2 = prof::begin("scan", st);
+  launch_gather_counts(order, s->tiles, N, s->counts, st);
+  scan_exclusive_u32(s->counts, s->offsets, N, s->total_dev, s->stmp, st);
+  prof::end(p2, st);
+  GS3_LAUNCHED();
+  GS3_HIP(hipMemcpyAsync(s->host_u32, s->total_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  GS3_HIP(hipStreamSynchronize(st));
+  const int64_t n_pairs = s->host_u32[0];
+  GS3_TRY(ensure_pairs(s, n_pairs));
+  auto p3 = prof::begin("emit_pairs", st);
+  launch_emit_pairs(order, s->offsets, s->rec, s->rect, s->tiles, N, cd.tiles_x, s->pt, s->pg, st);
+  prof::end(p3, st, N, n_pairs);
+  const int n_tiles = cd.tiles_x * cd.tiles_y;
+  uint32_t *tk, *tv;
+  auto p4 = prof::begin("pair_sort", st);
+  radix_sort_u32(s->pt, s->pg, s->pt2, s->pg2, n_pairs, bits_for(n_tiles), s->rtmp, st, &tk, &tv);
+  launch_tile_ranges(tk, n_pairs, s->ranges, n_tiles, st);
+  prof::end(p4, st, n_pairs, bits_for(n_tiles));
+  GS3_LAUNCHED();
+  s->sorted_gid = tv;
+  s->sorted_tile = tk;
+  s->n_pairs = n_pairs;
+  return GS3_OK;
+}
+
+gs3_status finish(gs3_scene* s, hipStream_t st) {
+  GS3_LAUNCHED();
+  GS3_HIP(hipEventRecord(s->done_ev, st));
+  return GS3_OK;
+}
+
+const float* target_of(gs3_scene* s, int cam) { return s->targets + s->tgt_off[cam]; }
+
+void blend_fwd(gs3_scene* s, const CamDev& cd, float* out, hipStream_t st) {
+  auto p = prof::begin("blend_fwd", st, true);
+  launch_blend_fwd(s->rec, s->sorted_gid, s->ranges, cd, s->bg, out, st, p.c);
+  prof::end(p, st);
+}
+
+void blend_jvp(gs3_scene* s, const CamDev& cd, float* out, float* tan, hipStream_t st) {
+  auto p = prof::begin("blend_jvp", st, true);
+  launch_blend_jvp(s->rec, s->trec, s->sorted_gid, s->ranges, cd, s->bg, out, tan, st, p.c);
+  prof::end(p, st);
+}
+
+void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st) {
+  auto p = prof::begin("blend_bwd", st, true);
+  launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, cd, s->img, cot, s->partials, st, p.c);
+  prof::end(p, st);
+}
+
+void project_bwd(gs3_scene* s, const CamDev& cd, int mode, int acc, uint64_t seed, uint32_t i, float scale,
+                 float* out, hipStream_t st) {
+  auto p = prof::begin("project_bwd", st);
+  launch_project_bwd(s->x, s->N, s->deg, cd, s->rec, s->tiles, s->partials, mode, acc, seed, i, scale, out, st);
+  prof::end(p, st, s->N, 0);
+}
+
+void project_jvp(gs3_scene* s, const CamDev& cd, int kind, uint64_t seed, uint32_t i, const float* tangent,
+                 hipStream_t st) {
+  auto p = prof::begin("project_jvp", st);
+  launch_project_jvp(s->x, s->N, s->deg, cd, s->rec, s->tiles, kind, seed, i, tangent, s->trec, st);
+  prof::end(p, st, s->N, 0);
+}
+
+gs3_status validate_desc(const gs3_scene_desc* d) {
+  if (!d) return fail(GS3_EINVAL, "desc is NULL");
+  if (d->n_gaussians < 1 || d->n_gaussians > 0x7fffffffLL) return fail(GS3_EINVAL, "n_gaussians must be in [1, 2^31)");
+  if (params_for(d->sh_degree) < 0) return fail(GS3_EINVAL, "sh_degree must be 0..3");
+  if (d->n_cameras < 1 || !d->cameras) return fail(GS3_EINVAL, "need at least one camera");
+  if (!(d->lambda_dssim >= 0.f && d->lambda_dssim <= 1.f)) return fail(GS3_EINVAL, "lambda_dssim must be in [0, 1]");
+  int n_train = 0;
+  for (int j = 0; j < d->n_cameras; ++j) {
+    const gs3_camera& c = d->cameras[j];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+      return fail(GS3_EINVAL, "camera " + std::to_string(j) + " has an invalid size");
+    if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(GS3_EINVAL, "camera " + std::to_string(j) + " has fx/fy <= 0");
+    n_train += (!d->train_mask || d->train_mask[j]) ? 1 : 0;
+  }
+  if (n_train < 1) return fail(GS3_EINVAL, "no training camera");
+  return GS3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gs3_n_params(int32_t sh_degree) { return params_for(sh_degree); }
+
+const char* gs3_version(void) { return "gs3tr 0.1 gfx950"; }
+
+const char* gs3_last_error(void) { return g_err.c_str(); }
+
+gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* peak_scratch) {
+  GS3_TRY(validate_desc(d));
+  if (!resident || !peak_scratch) return fail(GS3_EINVAL, "output pointers must not be NULL");
+  const int64_t N = d->n_gaussians, P = params_for(d->sh_degree);
+  int64_t px_total = 0, max_px = 0;
+  for (int j = 0; j < d->n_cameras; ++j) {
+    const int64_t px = (int64_t)d->cameras[j].width * d->cameras[j].height;
+    px_total += px;
+    max_px = std::max(max_px, px);
+  }
+  *resident = 4 * P * N * 5 + 12 * px_total;
+  // records, tangent records, eight u32 arrays, and pair buffers for about
+  // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair, +25% slack)
+  const int64_t pairs = 20 * N;
+  *peak_scratch = 96 * N + 32 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px;
+  return GS3_OK;
+}
+
+gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, const float* targets_dev,
+                            hipStream_t st, gs3_scene** out) {
+  if (!out) return fail(GS3_EINVAL, "out is NULL");
+  *out = nullptr;
+  GS3_TRY(validate_desc(d));
+  if (!params_dev || !targets_dev) return fail(GS3_EINVAL, "params_dev and targets_dev must not be NULL");
+  gs3_scene* s = new gs3_scene();
+  s->N = d->n_gaussians;
+  s->deg = d->sh_degree;
+  s->K = (d->sh_degree + 1) * (d->sh_degree + 1);
+  s->P = params_for(d->sh_degree);
+  s->n_cams = d->n_cameras;
+  s->cams.assign(d->cameras, d->cameras + d->n_cameras);
+  s->train.resize(d->n_cameras);
+  s->tgt_off.resize(d->n_cameras);
+  int64_t off = 0;
+  for (int j = 0; j < d->n_cameras; ++j) {
+    s->train[j] = (!d->train_mask || d->train_mask[j]) ? 1 : 0;
+    const int64_t px = (int64_t)s->cams[j].width * s->cams[j].height;
+    s->tgt_off[j] = off;
+    off += px * 3;
+    s->max_px = std::max(s->max_px, px);
+    const CamDev cd = make_cam(s->cams[j]);
+    s->max_tiles = std::max(s->max_tiles, cd.tiles_x * cd.tiles_y);
+    if (s->train[j]) {
+      s->n_train += 1;
+      s->m_comp += 6 * px;
+    }
+  }
+  for (int c = 0; c < 3; ++c) s->bg[c] = d->background[c];
+  s->lam = d->lambda_dssim;
+  s->flags = d->flags;
+  const int64_t PN = (int64_t)s->P * s->N;
+  gs3_status rc = GS3_OK;
+  auto step = [&](gs3_status r) {
+    if (rc == GS3_OK) rc = r;
+  };
+  step(dalloc(&s->x, PN));
+  step(dalloc(&s->targets, off));
+  step(dalloc(&s->ghat, PN));
+  step(dalloc(&s->dhat, PN));
+  step(dalloc(&s->am, PN));
+  step(dalloc(&s->av, PN));
+  step(dalloc(&s->rec, s->N));
+  step(dalloc(&s->rect, s->N));
+  step(dalloc(&s->trec, s->N));
+  step(dalloc(&s->depth_key, s->N));
+  step(dalloc(&s->tiles, s->N));
+  step(dalloc(&s->ka, s->N));
+  step(dalloc(&s->va, s->N));
+  step(dalloc(&s->kb, s->N));
+  step(dalloc(&s->vb, s->N));
+  step(dalloc(&s->counts, s->N));
+  step(dalloc(&s->offsets, s->N));
+  step(dalloc(&s->total_dev, 4));
+  step(dalloc((char**)&s->stmp, scan_temp_bytes(s->N)));
+  step(dalloc(&s->ranges, s->max_tiles));
+  step(dalloc(&s->img, s->max_px * 3));
+  step(dalloc(&s->cot, s->max_px * 3));
+  step(dalloc(&s->tan_img, s->max_px * 3));
+  step(dalloc(&s->ssim_tmp, ssim_tmp_floats(1, (int)s->max_px)));
+  step(dalloc(&s->dpart, s->max_px * 3 / 256 + s->max_tiles + 1024));
+  step(dalloc(&s->dsum, kMaxLossViews));
+  if (rc == GS3_OK && hipHostMalloc((void**)&s->host_u32, 64, hipHostMallocDefault) != hipSuccess)
+    rc = fail(GS3_ENOMEM, "hipHostMalloc failed");
+  if (rc == GS3_OK && hipHostMalloc((void**)&s->host_f64, sizeof(double) * kMaxLossViews, hipHostMallocDefault) != hipSuccess)
+    rc = fail(GS3_ENOMEM, "hipHostMalloc failed");
+  if (rc == GS3_OK && hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming) != hipSuccess)
+    rc = fail(GS3_EDEVICE, "hipEventCreate failed");
+  if (rc == GS3_OK) rc = ensure_pairs(s, 16 * s->N);
+  if (rc != GS3_OK) {
+    free_all(s);
+    delete s;
+    return rc;
+  }
+  auto copy = [&](void* dst, const void* src, size_t bytes) -> gs3_status {
+    GS3_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+    return GS3_OK;
+  };
+  rc = copy(s->x, params_dev, PN * sizeof(float));
+  if (rc == GS3_OK) rc = copy(s->targets, targets_dev, off * sizeof(float));
+  if (rc == GS3_OK) {
+    launch_fill_f32(s->ghat, PN, 0.f, st);
+    launch_fill_f32(s->dhat, PN, 0.f, st);
+    launch_fill_f32(s->am, PN, 0.f, st);
+    launch_fill_f32(s->av, PN, 0.f, st);
+    rc = finish(s, st);
+  }
+  if (rc != GS3_OK) {
+    (void)hipStreamSynchronize(st);
+    free_all(s);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return GS3_OK;
+}
+
+gs3_status gs3_scene_destroy(gs3_scene* s) {
+  if (!s) return fail(GS3_EINVAL, "scene is NULL");
+  if (s->done_ev) (void)hipEventSynchronize(s->done_ev);
+  (void)hipDeviceSynchronize();
+  free_all(s);
+  delete s;
+  return GS3_OK;
+}
+
+gs3_status gs3_scene_params(gs3_scene* s, float** p) {
+  GS3_TRY(check_scene(s));
+  if (!p) return fail(GS3_EINVAL, "output pointer is NULL");
+  *p = s->x;
+  return GS3_OK;
+}
+
+gs3_status gs3_scene_set_params(gs3_scene* s, const float* params_dev, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  if (!params_dev) return fail(GS3_EINVAL, "params_dev is NULL");
+  GS3_HIP(hipMemcpyAsync(s->x, params_dev, (size_t)s->P * s->N * sizeof(float), hipMemcpyDeviceToDevice, st));
+  return finish(s, st);
+}
+
+gs3_status gs3_scene_sync(gs3_scene* s) {
+  GS3_TRY(check_scene(s));
+  GS3_HIP(hipEventSynchronize(s->done_ev));
+  GS3_HIP(hipGetLastError());
+  return GS3_OK;
+}
+
+gs3_status gs3_render(gs3_scene* s, int32_t cam, float* rgb, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_cam(s, cam));
+  if (!rgb) return fail(GS3_EINVAL, "rgb_dev is NULL");
+  GS3_TRY(bin_view(s, cam, st));
+  const CamDev cd = make_cam(s->cams[cam]);
+  blend_fwd(s, cd, rgb, st);
+  return finish(s, st);
+}
+
+gs3_status gs3_bin(gs3_scene* s, int32_t cam, uint64_t* keys, uint32_t* gids, uint32_t* ranges, int64_t capacity,
+                   int64_t* n_pairs, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_cam(s, cam));
+  if (!n_pairs) return fail(GS3_EINVAL, "n_pairs is NULL");
+  GS3_TRY(bin_view(s, cam, st));
+  *n_pairs = s->n_pairs;
+  if ((keys || gids) && s->n_pairs > capacity)
+    return fail(GS3_EINVAL, "pair count " + std::to_string(s->n_pairs) + " exceeds capacity");
+  if (keys) launch_make_keys(s->sorted_tile, s->sorted_gid, s->depth_key, s->n_pairs, keys, st);
+  if (gids && s->n_pairs > 0)
+    GS3_HIP(hipMemcpyAsync(gids, s->sorted_gid, s->n_pairs * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  if (ranges) {
+    const CamDev cd = make_cam(s->cams[cam]);
+    GS3_HIP(hipMemcpyAsync(ranges, s->ranges, (size_t)cd.tiles_x * cd.tiles_y * sizeof(uint2),
+                           hipMemcpyDeviceToDevice, st));
+  }
+  GS3_TRY(finish(s, st));
+  GS3_HIP(hipStreamSynchronize(st));
+  return GS3_OK;
+}
+
+gs3_status gs3_grad(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* grad, double* loss_out,
+                    hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  if (!cams || n_cams < 1 || n_cams > kMaxLossViews) return fail(GS3_EINVAL, "need 1..4096 camera indices");
+  if (!grad) return fail(GS3_EINVAL, "grad_dev is NULL");
+  for (int k = 0; k < n_cams; ++k) GS3_TRY(check_cam(s, cams[k]));
+  const float scale = (float)((double)s->n_train / (2.0 * (double)s->m_comp * n_cams));
+  for (int k = 0; k < n_cams; ++k) {
+    const int j = cams[k];
+    GS3_TRY(bin_view(s, j, st));
+    const CamDev cd = make_cam(s->cams[j]);
+    blend_fwd(s, cd, s->img, st);
+    int np = 0;
+    auto pl = prof::begin("loss", st);
+    launch_loss_grad(s->img, target_of(s, j), cd.width, cd.height, s->lam, scale, s->cot, s->ssim_tmp, s->dpart, &np,
+                     st);
+    prof::end(pl, st);
+    if (loss_out) launch_sum_partials(s->dpart, np, s->dsum + k, st);
+    blend_bwd(s, cd, s->cot, st);
+    project_bwd(s, cd, 0, k > 0, 0, 0, 0.f, grad, st);
+    GS3_LAUNCHED();
+  }
+  if (loss_out) {
+    GS3_HIP(hipMemcpyAsync(s->host_f64, s->dsum, sizeof(double) * n_cams, hipMemcpyDeviceToHost, st));
+    GS3_HIP(hipStreamSynchronize(st));
+    double tot = 0.0;
+    for (int k = 0; k < n_cams; ++k) tot += s->host_f64[k];
+    *loss_out = tot / (2.0 * (double)s->m_comp);
+  }
+  return finish(s, st);
+}
+
+gs3_status gs3_hvp_diag(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed, float* D,
+                        hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  if (!cams || n_cams < 1) return fail(GS3_EINVAL, "need at least one camera index");
+  if (nu < 1) return fail(GS3_EINVAL, "nu must be >= 1");
+  if (!D) return fail(GS3_EINVAL, "D_dev is NULL");
+  for (int k = 0; k < n_cams; ++k) GS3_TRY(check_cam(s, cams[k]));
+  launch_fill_f32(D, (int64_t)s->P * s->N, 0.f, st);
+  const float scale = (float)((double)s->n_train / ((double)s->m_comp * n_cams * nu));
+  for (int k = 0; k < n_cams; ++k) {
+    const int j = cams[k];
+    GS3_TRY(bin_view(s, j, st));
+    const CamDev cd = make_cam(s->cams[j]);
+    for (int i = 0; i < nu; ++i) {
+      project_jvp(s, cd, PROBE_HASH, seed, (uint32_t)i, nullptr, st);
+      blend_jvp(s, cd, s->img, s->tan_img, st);
+      auto pl = prof::begin("loss", st);
+      launch_loss_gn(s->img, target_of(s, j), s->tan_img, cd.width, cd.height, s->lam, 1.f, s->cot, s->ssim_tmp, st);
+      prof::end(pl, st);
+      blend_bwd(s, cd, s->cot, st);
+      project_bwd(s, cd, 1, 0, seed, (uint32_t)i, scale, D, st);
+      GS3_LAUNCHED();
+    }
+  }
+  return finish(s, st);
+}
+
+gs3_status gs3_tr_step(gs3_scene* s, const float* grad, const float* D, const gs3_tr_hparams* hp, float* eta_out,
+                       float* dx_out, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  if (!grad || !hp) return fail(GS3_EINVAL, "grad_dev and hp must not be NULL");
+  if (!(hp->theta1 >= 0.f && hp->theta1 < 1.f && hp->theta2 >= 0.f && hp->theta2 < 1.f))
+    return fail(GS3_EINVAL, "theta1 and theta2 must be in [0, 1)");
+  if (!(hp->epsilon > 0.f) || !std::isfinite(hp->epsilon)) return fail(GS3_EINVAL, "epsilon must be > 0 and finite");
+  TrArgs a{hp->theta1, hp->theta2, hp->epsilon, D != nullptr};
+  auto p = prof::begin("tr_step", st);
+  launch_tr_step(s->x, grad, s->ghat, s->dhat, D, s->N, s->deg, a, eta_out, dx_out, st);
+  prof::end(p, st, s->N, (int64_t)s->P * s->N);
+  return finish(s, st);
+}
+
+static gs3_status adam_common(gs3_scene* s, const float* grad, const float* lr, int32_t step, float epsilon,
+                              hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  if (!grad || !lr) return fail(GS3_EINVAL, "grad_dev and lr_per_group must not be NULL");
+  if (step < 1) return fail(GS3_EINVAL, "step is 1-based");
+  AdamArgs a;
+  for (int r = 0; r < 64; ++r) a.lr_row[r] = 0.f;
+  for (int r = 0; r < s->P; ++r) {
+    int grp;
+    if (r < 3) grp = 0;          // mean
+    else if (r < 6) grp = 4;     // scale
+    else if (r < 10) grp = 5;    // rotation
+    else if (r == 10) grp = 3;   // opacity
+    else if (r < 14) grp = 1;    // SH DC
+    else grp = 2;                // SH rest
+    a.lr_row[r] = lr[grp];
+  }
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-15f;
+  a.bc1 = (float)(1.0 - std::pow(0.9, step));
+  a.bc2 = (float)(1.0 - std::pow(0.999, step));
+  a.epsilon = epsilon;
+  auto p = prof::begin("adam_step", st);
+  launch_adam_step(s->x, grad, s->am, s->av, s->N, s->deg, a, st);
+  prof::end(p, st, s->N, (int64_t)s->P * s->N);
+  return finish(s, st);
+}
+
+gs3_status gs3_adam_step(gs3_scene* s, const float* grad, const float* lr, int32_t step, hipStream_t st) {
+  return adam_common(s, grad, lr, step, 0.f, st);
+}
+
+gs3_status gs3_adam_tr_step(gs3_scene* s, const float* grad, const float* lr, int32_t step, float epsilon,
+                            hipStream_t st) {
+  if (!(epsilon > 0.f)) return fail(GS3_EINVAL, "epsilon must be > 0");
+  return adam_common(s, grad, lr, step, epsilon, st);
+}
+
+gs3_status gs3_psnr(gs3_scene* s, int32_t cam, double* out, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_cam(s, cam));
+  if (!out) return fail(GS3_EINVAL, "psnr_out is NULL");
+  GS3_TRY(bin_view(s, cam, st));
+  const CamDev cd = make_cam(s->cams[cam]);
+  blend_fwd(s, cd, s->img, st);
+  int np = 0;
+  const int64_t n = (int64_t)cd.width * cd.height * 3;
+  launch_sq_err(s->img, target_of(s, cam), n, s->dpart, &np, st);
+  launch_sum_partials(s->dpart, np, s->dsum, st);
+  GS3_HIP(hipMemcpyAsync(s->host_f64, s->dsum, sizeof(double), hipMemcpyDeviceToHost, st));
+  GS3_HIP(hipStreamSynchronize(st));
+  const double mse = s->host_f64[0] / (double)n;
+  *out = mse > 0.0 ? 10.0 * std::log10(1.0 / mse) : INFINITY;
+  return finish(s, st);
+}
+
+gs3_status gs3_render_vjp(gs3_scene* s, int32_t cam, const float* cot, float* grad, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_cam(s, cam));
+  if (!cot || !grad) return fail(GS3_EINVAL, "cot_dev and grad_dev must not be NULL");
+  GS3_TRY(bin_view(s, cam, st));
+  const CamDev cd = make_cam(s->cams[cam]);
+  blend_fwd(s, cd, s->img, st);
+  blend_bwd(s, cd, cot, st);
+  project_bwd(s, cd, 0, 0, 0, 0, 0.f, grad, st);
+  return finish(s, st);
+}
+
+gs3_status gs3_render_jvp(gs3_scene* s, int32_t cam, const float* tangent, float* rgb, float* tan, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_cam(s, cam));
+  if (!tangent || !rgb || !tan) return fail(GS3_EINVAL, "tangent_dev, rgb_dev and tan_dev must not be NULL");
+  GS3_TRY(bin_view(s, cam, st));
+  const CamDev cd = make_cam(s->cams[cam]);
+  project_jvp(s, cd, PROBE_ARRAY, 0, 0, tangent, st);
+  blend_jvp(s, cd, rgb, tan, st);
+  return finish(s, st);
+}
+
+gs3_status gs3_scene_export(gs3_scene* s, float* x, float* ghat, float* dhat, float* m, float* v, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  const size_t bytes = (size_t)s->P * s->N * sizeof(float);
+  const float* src[5] = {s->x, s->ghat, s->dhat, s->am, s->av};
+  float* dst[5] = {x, ghat, dhat, m, v};
+  for (int i = 0; i < 5; ++i)
+    if (dst[i]) GS3_HIP(hipMemcpyAsync(dst[i], src[i], bytes, hipMemcpyDeviceToDevice, st));
+  return finish(s, st);
+}
+
+gs3_status gs3_scene_import(gs3_scene* s, const float* x, const float* ghat, const float* dhat, const float* m,
+                            const float* v, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  const size_t bytes = (size_t)s->P * s->N * sizeof(float);
+  float* dst[5] = {s->x, s->ghat, s->dhat, s->am, s->av};
+  const float* src[5] = {x, ghat, dhat, m, v};
+  for (int i = 0; i < 5; ++i)
+    if (src[i]) GS3_HIP(hipMemcpyAsync(dst[i], src[i], bytes, hipMemcpyDeviceToDevice, st));
+  return finish(s, st);
+}
+
+gs3_status gs3_profile_enable(const char* names) {
+  std::lock_guard<std::mutex> lk(prof::mu);
+  if (!names || !*names) {
+    prof::active.store(false);
+    prof::names.clear();
+    return GS3_OK;
+  }
+  if (!prof::ctr) {
+    if (hipMalloc((void**)&prof::ctr, sizeof(unsigned long long) * 2 * prof::kSlots) != hipSuccess) {
+      prof::ctr = nullptr;
+      return fail(GS3_ENOMEM, "profiler counter allocation failed");
+    }
+    GS3_HIP(hipMemset(prof::ctr, 0, sizeof(unsigned long long) * 2 * prof::kSlots));
+  }
+  prof::names = "," + std::string(names) + ",";
+  prof::active.store(true);
+  return GS3_OK;
+}
+
+gs3_status gs3_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(prof::mu);
+  for (auto& e : prof::entries)
+    if (e.b) (void)hipEventSynchronize(e.b);
+  prof::clear_locked();
+  if (prof::ctr) GS3_HIP(hipMemset(prof::ctr, 0, sizeof(unsigned long long) * 2 * prof::kSlots));
+  return GS3_OK;
+}
+
+gs3_status gs3_profile_read(const char* name, int64_t* launches, double* total_ms, int64_t* work0, int64_t* work1) {
+  if (!name) return fail(GS3_EINVAL, "name is NULL");
+  std::lock_guard<std::mutex> lk(prof::mu);
+  int64_t n = 0, w0 = 0, w1 = 0;
+  double ms = 0.0;
+  std::vector<unsigned long long> host;
+  bool need_ctr = false;
+  for (auto& e : prof::entries)
+    if (e.name == name) {
+      GS3_HIP(hipEventSynchronize(e.b));
+      float t = 0.f;
+      GS3_HIP(hipEventElapsedTime(&t, e.a, e.b));
+      ms += t;
+      ++n;
+      w0 += e.w0;
+      w1 += e.w1;
+      need_ctr |= e.slot >= 0;
+    }
+  if (need_ctr) {
+    host.resize(2 * (size_t)prof::slots_used);
+    if (!host.empty())
+      GS3_HIP(hipMemcpy(host.data(), prof::ctr, host.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (auto& e : prof::entries)
+      if (e.name == name && e.slot >= 0) {
+        w0 += (int64_t)host[2 * e.slot];
+        w1 += (int64_t)host[2 * e.slot + 1];
+      }
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  if (work0) *work0 = w0;
+  if (work1) *work1 = w1;
+  return GS3_OK;
+}
+
+}  // extern "C"

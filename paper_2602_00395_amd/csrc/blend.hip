@@ -1,0 +1,380 @@
+// Front-to-back alpha blending of depth-sorted splats, its JVP and its VJP,
+// for gfx950.
+//
+// Paper: Background, "Review of Gaussian Splatting": C = sum_i c_i abar_i T_i
+// with T_i = prod_{j<i} (1 - abar_j) over the splats of the pixel's tile in
+// depth order.  Rasteriser readings (the paper names none): abar =
+// min(0.99, alpha exp(power)), power = -1/2 d^T conic d; power > 0 or
+// abar < 1/255 is skipped; a pixel stops before the splat that would take T
+// below 1e-4; the output adds T_final times the background colour.
+// The skip test is taken as power < tau with tau = float32(-ln(255 alpha)),
+// power evaluated in float32 in a fixed order without contraction: the
+// decision which splats contribute is then a reproducible float32 function
+// of the splat record, not a side effect of exp's rounding.
+//
+// Layout: one 256-thread workgroup per 16x16 tile, one pixel per thread;
+// records of 256 splats are staged in LDS per batch and every pixel walks the
+// batch.  Workgroups are mapped so that each of the 8 XCDs receives a
+// contiguous band of tiles (neighbouring tiles share splats, and each XCD has
+// its own L2).
+//
+// The backward pass runs front to back as well, recomputing T exactly as the
+// forward did (so the stop decision repeats bit for bit without storing any
+// per-pixel state) and obtaining the weight of the splats behind splat i from
+// the stored output: sum_{j>i} c_j abar_j T_j + T_final bg = C_out - S_i,
+// S_i the running front-to-back sum.  Gradients of each (splat, tile) pair are
+// reduced over the workgroup (wave64 shuffles, then the four waves in LDS in
+// a fixed order) and written to the pair's own slot: no float atomics, so the
+// backward is deterministic.
+#include "gs3_internal.h"
+
+namespace {
+
+__device__ __forceinline__ int tile_of_block(int b, int n_tiles, int chunk) {
+  return (b & 7) * chunk + (b >> 3);
+}
+
+// Measurement hook: when `ctr` is not null, adds this workgroup's number of
+// (pixel, splat) evaluations and of contributing evaluations to ctr[0], ctr[1].
+__device__ __forceinline__ void count_evals(unsigned long long* ctr, uint32_t nev, uint32_t ncon) {
+  if (ctr == nullptr) return;
+  unsigned long long a = nev, b = ncon;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    a += __shfl_xor(a, m, 64);
+    b += __shfl_xor(b, m, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(ctr, a);
+    atomicAdd(ctr + 1, b);
+  }
+}
+
+// -1/2 d^T conic d in float32, rounded exactly as written.
+__device__ __forceinline__ float splat_power(float ca, float cb, float cc, float dx, float dy) {
+#pragma clang fp contract(off)
+  return -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy;
+}
+
+struct Stage {
+  float4 a[GS3_BLOCK];
+  float4 b[GS3_BLOCK];
+  float2 c[GS3_BLOCK];  // b, tau
+};
+
+__global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__ rec,
+                                                          const uint32_t* __restrict__ pair_gid,
+                                                          const uint2* __restrict__ ranges, CamDev cam, float bg0,
+                                                          float bg1, float bg2, float* __restrict__ img, int n_tiles,
+                                                          int chunk, unsigned long long* __restrict__ ctr) {
+  const int t = tile_of_block(blockIdx.x, n_tiles, chunk);
+  if (t >= n_tiles) return;
+  __shared__ Stage s;
+  uint32_t nev = 0, ncon = 0;
+  const int tid = threadIdx.x;
+  const int px = (t % cam.tiles_x) * GS3_TILE + (tid & 15);
+  const int py = (t / cam.tiles_x) * GS3_TILE + (tid >> 4);
+  const bool inside = px < cam.width && py < cam.height;
+  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
+  const uint2 range = ranges[t];
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !inside;
+  for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
+    if (__syncthreads_count(done) == GS3_BLOCK) break;
+    const uint32_t i = start + tid;
+    if (i < range.y) {
+      const Rec r = rec[pair_gid[i]];
+      s.a[tid] = r.a;
+      s.b[tid] = r.b;
+      s.c[tid] = make_float2(r.c.x, r.c.y);
+    }
+    __syncthreads();
+    const int cnt = min((int)(range.y - start), GS3_BLOCK);
+    if (!done) {
+      for (int j = 0; j < cnt; ++j) {
+        ++nev;
+        const float4 A = s.a[j], B = s.b[j];
+        const float2 Cc = s.c[j];
+        const float dx = A.x - pxf, dy = A.y - pyf;
+        const float power = splat_power(A.z, A.w, B.x, dx, dy);
+        if (power > 0.f || power < Cc.y) continue;
+        const float a = fminf(GS3_ALPHA_MAX, B.y * __expf(power));
+        const float Tn = T * (1.f - a);
+        if (Tn < GS3_T_STOP) {
+          done = true;
+          break;
+        }
+        ++ncon;
+        const float w = a * T;
+        C0 += B.z * w;
+        C1 += B.w * w;
+        C2 += Cc.x * w;
+        T = Tn;
+      }
+    }
+    __syncthreads();
+  }
+  if (inside) {
+    float* o = img + ((int64_t)py * cam.width + px) * 3;
+    o[0] = C0 + T * bg0;
+    o[1] = C1 + T * bg1;
+    o[2] = C2 + T * bg2;
+  }
+  count_evals(ctr, nev, ncon);
+}
+
+struct StageJ {
+  float4 a[GS3_BLOCK];
+  float4 b[GS3_BLOCK];
+  float4 ta[GS3_BLOCK];
+  float4 tb[GS3_BLOCK];
+  float2 c[GS3_BLOCK];  // b, tau
+  float tc[GS3_BLOCK];
+};
+
+__global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__ rec, const TRec* __restrict__ trec,
+                                                          const uint32_t* __restrict__ pair_gid,
+                                                          const uint2* __restrict__ ranges, CamDev cam, float bg0,
+                                                          float bg1, float bg2, float* __restrict__ img,
+                                                          float* __restrict__ tan_img, int n_tiles, int chunk,
+                                                          unsigned long long* __restrict__ ctr) {
+  const int t = tile_of_block(blockIdx.x, n_tiles, chunk);
+  if (t >= n_tiles) return;
+  __shared__ StageJ s;
+  uint32_t nev = 0, ncon = 0;
+  const int tid = threadIdx.x;
+  const int px = (t % cam.tiles_x) * GS3_TILE + (tid & 15);
+  const int py = (t / cam.tiles_x) * GS3_TILE + (tid >> 4);
+  const bool inside = px < cam.width && py < cam.height;
+  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
+  const uint2 range = ranges[t];
+  float T = 1.f, dT = 0.f;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
+  bool done = !inside;
+  for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
+    if (__syncthreads_count(done) == GS3_BLOCK) break;
+    const uint32_t i = start + tid;
+    if (i < range.y) {
+      const uint32_t g = pair_gid[i];
+      const Rec r = rec[g];
+      const TRec q = trec[g];
+      s.a[tid] = r.a;
+      s.b[tid] = r.b;
+      s.c[tid] = make_float2(r.c.x, r.c.y);
+      s.ta[tid] = q.a;
+      s.tb[tid] = q.b;
+      s.tc[tid] = q.c.x;
+    }
+    __syncthreads();
+    const int cnt = min((int)(range.y - start), GS3_BLOCK);
+    if (!done) {
+      for (int j = 0; j < cnt; ++j) {
+        ++nev;
+        const float4 A = s.a[j], B = s.b[j];
+        const float2 Cc = s.c[j];
+        const float dx = A.x - pxf, dy = A.y - pyf;
+        const float power = splat_power(A.z, A.w, B.x, dx, dy);
+        if (power > 0.f || power < Cc.y) continue;
+        const float G = __expf(power);
+        const float araw = B.y * G;
+        const float a = fminf(GS3_ALPHA_MAX, araw);
+        const float Tn = T * (1.f - a);
+        if (Tn < GS3_T_STOP) {
+          done = true;
+          break;
+        }
+        ++ncon;
+        const float4 TA = s.ta[j], TB = s.tb[j];
+        // d power along the tangent: d = (u - px, v - py), dd = (du, dv)
+        const float dpow = -(A.z * dx * TA.x + B.x * dy * TA.y) - 0.5f * (TA.z * dx * dx + TB.x * dy * dy) -
+                           A.w * (TA.x * dy + dx * TA.y) - TA.w * dx * dy;
+        const float da = araw > GS3_ALPHA_MAX ? 0.f : (TB.y * G + B.y * G * dpow);
+        const float w = a * T;
+        const float dw = da * T + a * dT;
+        C0 += B.z * w;
+        C1 += B.w * w;
+        C2 += Cc.x * w;
+        D0 += TB.z * w + B.z * dw;
+        D1 += TB.w * w + B.w * dw;
+        D2 += s.tc[j] * w + Cc.x * dw;
+        dT = dT * (1.f - a) - T * da;
+        T = Tn;
+      }
+    }
+    __syncthreads();
+  }
+  if (inside) {
+    const int64_t o = ((int64_t)py * cam.width + px) * 3;
+    img[o + 0] = C0 + T * bg0;
+    img[o + 1] = C1 + T * bg1;
+    img[o + 2] = C2 + T * bg2;
+    tan_img[o + 0] = D0 + dT * bg0;
+    tan_img[o + 1] = D1 + dT * bg1;
+    tan_img[o + 2] = D2 + dT * bg2;
+  }
+  count_evals(ctr, nev, ncon);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+struct StageB {
+  float4 a[GS3_BLOCK];
+  float4 b[GS3_BLOCK];
+  float2 c[GS3_BLOCK];  // b, tau
+  uint32_t slot[GS3_BLOCK];
+  float red[4][9][GS3_BLOCK];
+};
+
+// Slot of the (Gaussian, tile) pair in the Gaussian-contiguous partials
+// buffer: the Gaussian's first pair plus the tile's row-major index in its
+// rectangle.
+__device__ __forceinline__ uint32_t pair_slot(uint32_t pair_off, uint2 rc, int tx, int ty) {
+  const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
+  return pair_off + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
+}
+
+__global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__ rec,
+                                                          const uint2* __restrict__ rect,
+                                                          const uint32_t* __restrict__ pair_gid,
+                                                          const uint2* __restrict__ ranges, CamDev cam,
+                                                          const float* __restrict__ img, const float* __restrict__ cot,
+                                                          float* __restrict__ partials, int n_tiles, int chunk,
+                                                          unsigned long long* __restrict__ ctr) {
+  const int t = tile_of_block(blockIdx.x, n_tiles, chunk);
+  if (t >= n_tiles) return;
+  __shared__ StageB s;
+  uint32_t nev = 0, ncon = 0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tx = t % cam.tiles_x, ty = t / cam.tiles_x;
+  const int px = tx * GS3_TILE + (tid & 15);
+  const int py = ty * GS3_TILE + (tid >> 4);
+  const bool inside = px < cam.width && py < cam.height;
+  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
+  const uint2 range = ranges[t];
+  float out0 = 0.f, out1 = 0.f, out2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  if (inside) {
+    const int64_t o = ((int64_t)py * cam.width + px) * 3;
+    out0 = img[o + 0];
+    out1 = img[o + 1];
+    out2 = img[o + 2];
+    g0 = cot[o + 0];
+    g1 = cot[o + 1];
+    g2 = cot[o + 2];
+  }
+  float T = 1.f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
+  bool done = !inside;
+  uint32_t start = range.x;
+  for (; start < range.y; start += GS3_BLOCK) {
+    if (__syncthreads_count(done) == GS3_BLOCK) break;
+    const uint32_t i = start + tid;
+    if (i < range.y) {
+      const uint32_t g = pair_gid[i];
+      const Rec r = rec[g];
+      s.a[tid] = r.a;
+      s.b[tid] = r.b;
+      s.c[tid] = make_float2(r.c.x, r.c.y);
+      s.slot[tid] = pair_slot(__float_as_uint(r.c.z), rect[g], tx, ty);
+    }
+    __syncthreads();
+    const int cnt = min((int)(range.y - start), GS3_BLOCK);
+    for (int j = 0; j < cnt; ++j) {
+      float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      bool contrib = false;
+      if (!done) {
+        ++nev;
+        const float4 A = s.a[j], B = s.b[j];
+        const float2 Cc = s.c[j];
+        const float dx = A.x - pxf, dy = A.y - pyf;
+        const float power = splat_power(A.z, A.w, B.x, dx, dy);
+        if (power <= 0.f && power >= Cc.y) {
+          const float G = __expf(power);
+          const float araw = B.y * G;
+          const float a = fminf(GS3_ALPHA_MAX, araw);
+          {
+            const float Tn = T * (1.f - a);
+            if (Tn < GS3_T_STOP) {
+              done = true;
+            } else {
+              const float cr = B.z, cg = B.w, cb = Cc.x;
+              const float wgt = a * T;
+              S0 += cr * wgt;
+              S1 += cg * wgt;
+              S2 += cb * wgt;
+              const float behind = (out0 - S0) * g0 + (out1 - S1) * g1 + (out2 - S2) * g2;
+              const float dL_da = T * (cr * g0 + cg * g1 + cb * g2) - behind / (1.f - a);
+              const bool clamped = araw > GS3_ALPHA_MAX;
+              const float dL_dG = clamped ? 0.f : B.y * dL_da;
+              const float dL_dpow = dL_dG * G;
+              gr[0] = dL_dpow * (-(A.z * dx + A.w * dy));
+              gr[1] = dL_dpow * (-(B.x * dy + A.w * dx));
+              gr[2] = dL_dpow * (-0.5f * dx * dx);
+              gr[3] = dL_dpow * (-dx * dy);
+              gr[4] = dL_dpow * (-0.5f * dy * dy);
+              gr[5] = clamped ? 0.f : G * dL_da;
+              gr[6] = wgt * g0;
+              gr[7] = wgt * g1;
+              gr[8] = wgt * g2;
+              contrib = true;
+              ++ncon;
+              T = Tn;
+            }
+          }
+        }
+      }
+      if (__ballot(contrib) != 0ull) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gr[k] = wave_sum(gr[k]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s.red[w][k][j] = gr[k];
+      }
+    }
+    __syncthreads();
+    if (tid < cnt) {
+      float* dst = partials + (int64_t)s.slot[tid] * 9;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) dst[k] = ((s.red[0][k][tid] + s.red[1][k][tid]) + s.red[2][k][tid]) + s.red[3][k][tid];
+    }
+    __syncthreads();
+  }
+  // pairs after the point where every pixel of the tile stopped: zero slots
+  for (uint32_t i = start + tid; i < range.y; i += GS3_BLOCK) {
+    const uint32_t g = pair_gid[i];
+    float* dst = partials + (int64_t)pair_slot(__float_as_uint(rec[g].c.z), rect[g], tx, ty) * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dst[k] = 0.f;
+  }
+  count_evals(ctr, nev, ncon);
+}
+
+inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }
+
+}  // namespace
+
+void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const CamDev& cam,
+                      const float* bg, float* img, hipStream_t st, unsigned long long* ctr) {
+  const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
+  hipLaunchKernelGGL(k_blend_fwd, dim3(8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, cam, bg[0], bg[1],
+                     bg[2], img, nt, ch, ctr);
+}
+
+void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
+                      const CamDev& cam, const float* bg, float* img, float* tan_img, hipStream_t st,
+                      unsigned long long* ctr) {
+  const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
+  hipLaunchKernelGGL(k_blend_jvp, dim3(8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges, cam, bg[0],
+                     bg[1], bg[2], img, tan_img, nt, ch, ctr);
+}
+
+void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
+                      const CamDev& cam, const float* img, const float* cot, float* partials, hipStream_t st,
+                      unsigned long long* ctr) {
+  const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
+  hipLaunchKernelGGL(k_blend_bwd, dim3(8 * ch), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges, cam, img, cot,
+                     partials, nt, ch, ctr);
+}

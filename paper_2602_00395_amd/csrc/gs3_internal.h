@@ -1,0 +1,121 @@
+// Internal declarations shared by the gfx950 kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GS3_TILE 16
+#define GS3_BLOCK (GS3_TILE * GS3_TILE)
+
+// Rasteriser constants of the original 3DGS design (the paper states only the
+// blend equation): near plane, screen-space dilation, frustum clamp of the
+// EWA Jacobian, opacity clamp and skip threshold, transmittance stop.
+#define GS3_NEAR 0.2f
+#define GS3_DILATION 0.3f
+#define GS3_FOV_CLAMP 1.3f
+#define GS3_ALPHA_MAX 0.99f
+#define GS3_ALPHA_MIN (1.0f / 255.0f)
+#define GS3_T_STOP 1e-4f
+// Gauss-Newton weight floor and colour floor of the trust region.
+#define GS3_GN_FLOOR 1e-6f
+#define GS3_COLOUR_FLOOR (1.0f / 255.0f)
+
+struct CamDev {
+  float W[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float limx, limy;
+  float campos[3];
+  int width, height, tiles_x, tiles_y;
+};
+
+// Per-Gaussian screen-space record, 12 words (three float4):
+//   {u, v, conic_a, conic_b}, {conic_c, opacity, r, g}, {b, tau, pair_off, 0}
+// tau = float32(-ln(255 opacity)): a splat is skipped at a pixel where its
+// float32 power is below tau (equivalently opacity exp(power) < 1/255).
+// The tile rectangle lives in a separate uint2 array:
+//   x = x0 | y0 << 16, y = x1 | y1 << 16 (half-open).
+struct __align__(16) Rec {
+  float4 a, b, c;
+};
+
+// Tangent of the record under a parameter-space direction, 12 words:
+//   {du, dv, dconic_a, dconic_b}, {dconic_c, dopacity, dr, dg}, {db, 0, 0, 0}
+struct __align__(16) TRec {
+  float4 a, b, c;
+};
+
+enum ProbeKind { PROBE_NONE = 0, PROBE_HASH = 1, PROBE_ARRAY = 2 };
+
+// --------------------------------------------------------------------------
+// launchers (all asynchronous on `st`)
+
+// projection: records + depth keys + tiles touched; culled Gaussians get
+// key 0xffffffff and zero tiles.
+void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, Rec* rec, uint2* rect,
+                        uint32_t* depth_key, uint32_t* tiles, hipStream_t st);
+// tangent records for a probe (hash) or a caller tangent array.
+void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
+                        const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
+                        const float* tangent, TRec* trec, hipStream_t st);
+// mode 0: grad[r][g] = (accumulate ? grad : 0) + dL/dx; mode 1: out[r][g] += scale * z_r * dL/dx
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
+                        const uint32_t* tiles, const float* partials, int mode, int accumulate, uint64_t seed,
+                        uint32_t probe_index, float scale, float* out, hipStream_t st);
+
+// sorting and binning
+size_t radix_temp_bytes(int64_t n);
+void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n, int bits,
+                    void* temp, hipStream_t st, uint32_t** keys_out, uint32_t** vals_out);
+size_t scan_temp_bytes(int64_t n);
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st);
+void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
+                          hipStream_t st);
+void launch_iota(uint32_t* v, int64_t n, hipStream_t st);
+// writes each visible Gaussian's pair offset into its record (rec.c.w)
+void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Rec* rec, const uint2* rect,
+                       const uint32_t* tiles, int64_t n, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
+                       hipStream_t st);
+void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st);
+void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const uint32_t* depth_key,
+                      int64_t n_pairs, uint64_t* keys, hipStream_t st);
+
+// blending
+// ctr (nullable): two u64 counters receiving the number of (pixel, splat)
+// evaluations and of contributing evaluations (measurement only).
+void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const CamDev& cam,
+                      const float* bg, float* img, hipStream_t st, unsigned long long* ctr = nullptr);
+void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
+                      const CamDev& cam, const float* bg, float* img, float* tan_img, hipStream_t st,
+                      unsigned long long* ctr = nullptr);
+void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
+                      const CamDev& cam, const float* img, const float* cot, float* partials, hipStream_t st,
+                      unsigned long long* ctr = nullptr);
+
+// loss
+// cot = scale * d(sum_k l_k)/dC; optional per-block loss partial sums (double).
+void launch_loss_grad(const float* img, const float* tgt, int w, int h, float lam, float scale, float* cot,
+                      float* ssim_tmp, double* loss_partials, int* n_partials, hipStream_t st);
+// cot = scale * sum_k (dl_k/dC)^T w_k, w_k = (dl_k/dC . u) / (4 max(l_k, floor)).
+void launch_loss_gn(const float* img, const float* tgt, const float* u, int w, int h, float lam, float scale,
+                    float* cot, float* ssim_tmp, hipStream_t st);
+size_t ssim_tmp_floats(int w, int h);
+void launch_sq_err(const float* img, const float* tgt, int64_t n, double* partials, int* n_partials, hipStream_t st);
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
+
+// optimizer
+struct TrArgs {
+  float theta1, theta2, epsilon;
+  int hutch;
+};
+void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
+                    TrArgs a, float* eta_out, float* dx_out, hipStream_t st);
+struct AdamArgs {
+  float lr_row[64];
+  float b1, b2, eps, bc1, bc2;
+  float epsilon;  // > 0: clip by the trust-region radius (ADAM-TR)
+};
+void launch_adam_step(float* x, const float* grad, float* m, float* v, int64_t n, int deg, const AdamArgs& a,
+                      hipStream_t st);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);

@@ -1,0 +1,300 @@
+// Image-space loss kernels for gfx950: the L1 / D-SSIM components of
+// Eq. pixel_loss, their gradient cotangent and the Gauss-Newton cotangent.
+//
+// Paper: Background, Eq. pixel_loss (L = (1-lambda) L1 + lambda D-SSIM, one
+// component per RGB channel) and Eq. objective (F = square roots of the
+// components).  With l1 = (1-lambda)|r| and ls = lambda (1 - SSIM):
+//  * gradient mode writes  cot = scale * d(sum_k l_k)/dC;
+//  * Gauss-Newton mode, given the image tangent u = J_img z, writes
+//      cot = scale * sum_k (dl_k/dC)^T (dl_k/dC . u) / (4 max(l_k, 1e-6)),
+//    i.e. J_F^T J_F z pulled back to image space (J_F = dl/dC / (2 sqrt(l))).
+// SSIM (Wang et al.): 11x11 Gaussian window, sigma 1.5, zero-padded "same"
+// filtering, C1 = 0.01^2, C2 = 0.03^2.  SSIM is a function of five filtered
+// maps (x, y, x^2, y^2, xy); its VJP filters three coefficient maps with the
+// same symmetric window (the adjoint of zero-padded filtering).  Each
+// 256-thread workgroup owns a 16x16 output tile and stages a 26x26 halo
+// region per channel in LDS, filtering separably (rows, then columns).
+#include "gs3_internal.h"
+
+namespace {
+
+constexpr int R = 5;                 // window radius
+constexpr int HW = GS3_TILE + 2 * R; // halo width 26
+constexpr float kC1 = 0.01f * 0.01f;
+constexpr float kC2 = 0.03f * 0.03f;
+
+struct Win {
+  float w[11];
+};
+
+__device__ __forceinline__ float sgn(float r) { return r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f); }
+
+__device__ __forceinline__ double block_sum_d(double v) {
+  __shared__ double ws[4];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+  __syncthreads();
+  return r;
+}
+
+// Gradient (GN = false) or Gauss-Newton (GN = true) coefficient maps of the
+// SSIM term, and (gradient mode) per-block loss sums.
+template <bool GN>
+__global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                          const float* __restrict__ u, int W, int H, float lam,
+                                                          float scale, Win win, float* __restrict__ coef,
+                                                          double* __restrict__ loss_partials) {
+  __shared__ float sx[HW][HW + 1], sy[HW][HW + 1], su[GN ? HW : 1][HW + 1];
+  constexpr int NM = GN ? 8 : 5;
+  __shared__ float hb[NM][HW][GS3_TILE];
+  const int tid = threadIdx.x;
+  const int ox = blockIdx.x * GS3_TILE - R, oy = blockIdx.y * GS3_TILE - R;
+  const int i = tid >> 4, j = tid & 15;
+  const int px = blockIdx.x * GS3_TILE + j, py = blockIdx.y * GS3_TILE + i;
+  const bool inside = px < W && py < H;
+  const int64_t npix = (int64_t)W * H;
+  double lsum = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    for (int e = tid; e < HW * HW; e += GS3_BLOCK) {
+      const int r = e / HW, q = e % HW;
+      const int gx = ox + q, gy = oy + r;
+      const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
+      const int64_t o = ((int64_t)gy * W + gx) * 3 + c;
+      sx[r][q] = ok ? img[o] : 0.f;
+      sy[r][q] = ok ? tgt[o] : 0.f;
+      if (GN) su[r][q] = ok ? u[o] : 0.f;
+    }
+    __syncthreads();
+    for (int e = tid; e < HW * GS3_TILE; e += GS3_BLOCK) {
+      const int r = e / GS3_TILE, q = e % GS3_TILE;
+      float m[NM];
+#pragma unroll
+      for (int k = 0; k < NM; ++k) m[k] = 0.f;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) {
+        const float xv = sx[r][q + k], yv = sy[r][q + k], wk = win.w[k];
+        m[0] += wk * xv;
+        m[1] += wk * yv;
+        m[2] += wk * (xv * xv);
+        m[3] += wk * (yv * yv);
+        m[4] += wk * (xv * yv);
+        if (GN) {
+          const float uv = su[r][q + k];
+          m[5] += wk * uv;
+          m[6] += wk * (2.f * xv * uv);
+          m[7] += wk * (yv * uv);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NM; ++k) hb[k][r][q] = m[k];
+    }
+    __syncthreads();
+    float f[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) f[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) {
+      const float wk = win.w[k];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) f[m] += wk * hb[m][i + k][j];
+    }
+    const float A = f[0], B = f[1];
+    const float sxx = f[2] - A * A, syy = f[3] - B * B, sxy = f[4] - A * B;
+    const float n1 = 2.f * A * B + kC1, n2 = 2.f * sxy + kC2;
+    const float d1 = A * A + B * B + kC1, d2 = sxx + syy + kC2;
+    const float den = d1 * d2;
+    const float S = (n1 * n2) / den;
+    const float dS_dA = (2.f * B * (n2 - n1) - S * 2.f * A * (d2 - d1)) / den;
+    const float dS_dXX = -S / d2;
+    const float dS_dXY = 2.f * n1 / den;
+    float wgt;
+    if (GN) {
+      const float dS = dS_dA * f[5] + dS_dXX * f[6] + dS_dXY * f[7];
+      const float ls = lam * (1.f - S);
+      wgt = scale * (lam * lam * dS) / (4.f * fmaxf(ls, GS3_GN_FLOOR));
+    } else {
+      wgt = -lam * scale;
+      if (inside) {
+        const float xv = sx[i + R][j + R], yv = sy[i + R][j + R];
+        lsum += (double)((1.f - lam) * fabsf(xv - yv)) + (double)(lam * (1.f - S));
+      }
+    }
+    if (inside) {
+      const int64_t o = ((int64_t)py * W + px) * 3 + c;
+      coef[o] = wgt * dS_dA;
+      coef[npix * 3 + o] = wgt * dS_dXX;
+      coef[2 * npix * 3 + o] = wgt * dS_dXY;
+    }
+    __syncthreads();
+  }
+  if (!GN) {
+    const double tot = block_sum_d(lsum);
+    if (tid == 0) loss_partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+// Filter the three coefficient maps and add the L1 term: the final cotangent.
+template <bool GN>
+__global__ __launch_bounds__(GS3_BLOCK) void k_ssim_combine(const float* __restrict__ img,
+                                                             const float* __restrict__ tgt,
+                                                             const float* __restrict__ u,
+                                                             const float* __restrict__ coef, int W, int H, float lam,
+                                                             float scale, Win win, float* __restrict__ cot) {
+  __shared__ float sc[3][HW][HW + 1];
+  __shared__ float hb[3][HW][GS3_TILE];
+  const int tid = threadIdx.x;
+  const int ox = blockIdx.x * GS3_TILE - R, oy = blockIdx.y * GS3_TILE - R;
+  const int i = tid >> 4, j = tid & 15;
+  const int px = blockIdx.x * GS3_TILE + j, py = blockIdx.y * GS3_TILE + i;
+  const bool inside = px < W && py < H;
+  const int64_t npix = (int64_t)W * H;
+  for (int c = 0; c < 3; ++c) {
+    for (int e = tid; e < HW * HW; e += GS3_BLOCK) {
+      const int r = e / HW, q = e % HW;
+      const int gx = ox + q, gy = oy + r;
+      const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
+      const int64_t o = ((int64_t)gy * W + gx) * 3 + c;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) sc[m][r][q] = ok ? coef[m * npix * 3 + o] : 0.f;
+    }
+    __syncthreads();
+    for (int e = tid; e < HW * GS3_TILE; e += GS3_BLOCK) {
+      const int r = e / GS3_TILE, q = e % GS3_TILE;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) acc += win.w[k] * sc[m][r][q + k];
+        hb[m][r][q] = acc;
+      }
+    }
+    __syncthreads();
+    float bA = 0.f, bXX = 0.f, bXY = 0.f;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) {
+      bA += win.w[k] * hb[0][i + k][j];
+      bXX += win.w[k] * hb[1][i + k][j];
+      bXY += win.w[k] * hb[2][i + k][j];
+    }
+    if (inside) {
+      const int64_t o = ((int64_t)py * W + px) * 3 + c;
+      const float xv = img[o], yv = tgt[o];
+      const float r = xv - yv, s = sgn(r);
+      float l1term;
+      if (GN) {
+        const float l1 = (1.f - lam) * fabsf(r);
+        const float w1 = (1.f - lam) * s * u[o] / (4.f * fmaxf(l1, GS3_GN_FLOOR));
+        l1term = scale * (1.f - lam) * s * w1;
+      } else {
+        l1term = scale * (1.f - lam) * s;
+      }
+      cot[o] = l1term + (bA + 2.f * xv * bXX + yv * bXY);
+    }
+    __syncthreads();
+  }
+}
+
+// lambda = 0: the L1 term only.
+template <bool GN>
+__global__ __launch_bounds__(256) void k_l1_only(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                  const float* __restrict__ u, int64_t n, float scale,
+                                                  float* __restrict__ cot, double* __restrict__ loss_partials) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (o < n) {
+    const float r = img[o] - tgt[o], s = sgn(r);
+    if (GN) {
+      const float l1 = fabsf(r);
+      cot[o] = scale * s * (s * u[o] / (4.f * fmaxf(l1, GS3_GN_FLOOR)));
+    } else {
+      cot[o] = scale * s;
+      l = (double)fabsf(r);
+    }
+  }
+  if (!GN) {
+    const double tot = block_sum_d(l);
+    if (threadIdx.x == 0) loss_partials[blockIdx.x] = tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sq_err(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                 int64_t n, double* __restrict__ partials) {
+  double acc = 0.0;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)img[o] - (double)tgt[o];
+    acc += d * d;
+  }
+  const double tot = block_sum_d(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ p, int n, double* __restrict__ out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += p[i];
+  const double tot = block_sum_d(acc);
+  if (threadIdx.x == 0) *out = tot;
+}
+
+Win make_window() {
+  Win w;
+  double s = 0.0, v[11];
+  for (int k = 0; k < 11; ++k) {
+    const double d = k - 5;
+    v[k] = exp(-(d * d) / (2.0 * 1.5 * 1.5));
+    s += v[k];
+  }
+  for (int k = 0; k < 11; ++k) w.w[k] = (float)(v[k] / s);
+  return w;
+}
+
+}  // namespace
+
+size_t ssim_tmp_floats(int w, int h) { return (size_t)3 * 3 * w * h; }
+
+void launch_loss_grad(const float* img, const float* tgt, int w, int h, float lam, float scale, float* cot,
+                      float* ssim_tmp, double* loss_partials, int* n_partials, hipStream_t st) {
+  const int64_t n = (int64_t)w * h * 3;
+  if (lam == 0.f) {
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_l1_only<false>, dim3(nb), dim3(256), 0, st, img, tgt, nullptr, n, scale, cot,
+                       loss_partials);
+    *n_partials = (int)nb;
+    return;
+  }
+  const dim3 grid((w + GS3_TILE - 1) / GS3_TILE, (h + GS3_TILE - 1) / GS3_TILE);
+  const Win win = make_window();
+  hipLaunchKernelGGL(k_ssim_coef<false>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, nullptr, w, h, lam, scale, win,
+                     ssim_tmp, loss_partials);
+  hipLaunchKernelGGL(k_ssim_combine<false>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, nullptr, ssim_tmp, w, h, lam,
+                     scale, win, cot);
+  *n_partials = (int)(grid.x * grid.y);
+}
+
+void launch_loss_gn(const float* img, const float* tgt, const float* u, int w, int h, float lam, float scale,
+                    float* cot, float* ssim_tmp, hipStream_t st) {
+  const int64_t n = (int64_t)w * h * 3;
+  if (lam == 0.f) {
+    hipLaunchKernelGGL(k_l1_only<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, img, tgt, u, n, scale,
+                       cot, nullptr);
+    return;
+  }
+  const dim3 grid((w + GS3_TILE - 1) / GS3_TILE, (h + GS3_TILE - 1) / GS3_TILE);
+  const Win win = make_window();
+  hipLaunchKernelGGL(k_ssim_coef<true>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, u, w, h, lam, scale, win, ssim_tmp,
+                     nullptr);
+  hipLaunchKernelGGL(k_ssim_combine<true>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, u, ssim_tmp, w, h, lam, scale,
+                     win, cot);
+}
+
+void launch_sq_err(const float* img, const float* tgt, int64_t n, double* partials, int* n_partials, hipStream_t st) {
+  const unsigned nb = 256;
+  hipLaunchKernelGGL(k_sq_err, dim3(nb), dim3(256), 0, st, img, tgt, n, partials);
+  *n_partials = (int)nb;
+}
+
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, n, out);
+}

@@ -1,0 +1,149 @@
+// Parameter updates for gfx950: the trust-region step of Algorithm 1 and the
+// Adam baseline (optionally clipped by the same trust region, ADAM-TR).
+//
+// Paper: Algorithm 1 and Methodology ("Algorithm Design"; "Trust-Region
+// Based on Squared Hellinger Distance"; appendix derivations of the bounds).
+// Per Gaussian, with alpha = sigmoid(logit), s = exp(log-scale), R from the
+// quaternion and L = -ln(1 - eps/alpha) (infinite when eps >= alpha):
+//   mean_c      eta = sqrt(8 Sigma_cc L)                     (printed bound)
+//   log-scale   eta = sqrt(2 s_c^2 eps / alpha) / s_c = sqrt(2 eps / alpha)
+//   quaternion  eta = sqrt(8 L / beta_c),  beta_c = T''(0) of the appendix
+//   logit       eta = sqrt(4 alpha eps) / (alpha (1 - alpha))
+//   SH (k, c)   eta = sqrt(4 max(C_c, 1/255) eps / alpha) / C0, C_c the base colour
+// Readings: the clip acts on raw parameters through the first-order chain
+// rule; every SH coefficient of a channel shares the base colour's radius.
+// beta_c in closed form: R^T dR/dq_c is the skew matrix of the body-frame
+// angular velocity w_c = (2/|q|^2) vec(conj(q) e_c), and
+//   beta_c = 2 sum_{i<j} A_ij^2 (s_i/s_j - s_j/s_i)^2,
+// with A_01 = -w_2, A_02 = w_1, A_12 = -w_0; it vanishes for isotropic s.
+//
+// One thread per Gaussian: the radius needs the whole Gaussian, and rows are
+// read and written row-major across threads, so every access is a coalesced
+// 256-byte wave load/store (the kernel is HBM-bound).
+#include "gs3_internal.h"
+
+namespace {
+
+#define SH_C0 0.28209479177387814f
+
+struct Radius {
+  float mu[3], ls, q[4], logit, col[3];
+};
+
+__device__ __forceinline__ Radius trust_radius(const float* __restrict__ x, int64_t n, int64_t g, float eps) {
+  Radius o;
+  const float alpha = 1.f / (1.f + expf(-x[10 * n + g]));
+  const float s0 = expf(x[3 * n + g]), s1 = expf(x[4 * n + g]), s2 = expf(x[5 * n + g]);
+  const float qx = x[6 * n + g], qy = x[7 * n + g], qz = x[8 * n + g], qw = x[9 * n + g];
+  const float r2 = qx * qx + qy * qy + qz * qz + qw * qw;
+  const float ir2 = 1.f / r2;
+  // rows of R (normalised), Sigma_cc = sum_k R_ck^2 s_k^2
+  const float R00 = 1.f - 2.f * (qy * qy + qz * qz) * ir2, R01 = 2.f * (qx * qy - qw * qz) * ir2,
+              R02 = 2.f * (qx * qz + qw * qy) * ir2;
+  const float R10 = 2.f * (qx * qy + qw * qz) * ir2, R11 = 1.f - 2.f * (qz * qz + qx * qx) * ir2,
+              R12 = 2.f * (qy * qz - qw * qx) * ir2;
+  const float R20 = 2.f * (qx * qz - qw * qy) * ir2, R21 = 2.f * (qy * qz + qw * qx) * ir2,
+              R22 = 1.f - 2.f * (qx * qx + qy * qy) * ir2;
+  const float v0 = s0 * s0, v1 = s1 * s1, v2 = s2 * s2;
+  const float Sxx = R00 * R00 * v0 + R01 * R01 * v1 + R02 * R02 * v2;
+  const float Syy = R10 * R10 * v0 + R11 * R11 * v1 + R12 * R12 * v2;
+  const float Szz = R20 * R20 * v0 + R21 * R21 * v1 + R22 * R22 * v2;
+  const float L = eps < alpha ? -log1pf(-eps / alpha) : INFINITY;
+  o.mu[0] = sqrtf(8.f * Sxx * L);
+  o.mu[1] = sqrtf(8.f * Syy * L);
+  o.mu[2] = sqrtf(8.f * Szz * L);
+  o.ls = sqrtf(2.f * eps / alpha);
+  const float p01 = s0 / s1 - s1 / s0, p02 = s0 / s2 - s2 / s0, p12 = s1 / s2 - s2 / s1;
+  const float e01 = p01 * p01, e02 = p02 * p02, e12 = p12 * p12;
+  // vec(conj(q) e_c) for c = x, y, z, w
+  const float wv[4][3] = {{qw, -qz, qy}, {qz, qw, -qx}, {-qy, qx, qw}, {-qx, -qy, -qz}};
+  const float k2 = 4.f * ir2 * ir2;  // (2 / |q|^2)^2
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float beta = 2.f * k2 * (wv[c][2] * wv[c][2] * e01 + wv[c][1] * wv[c][1] * e02 + wv[c][0] * wv[c][0] * e12);
+    o.q[c] = beta > 0.f ? sqrtf(8.f * L / beta) : INFINITY;
+  }
+  o.logit = sqrtf(4.f * alpha * eps) / (alpha * (1.f - alpha));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float base = 0.5f + SH_C0 * x[(int64_t)(11 + c) * n + g];
+    o.col[c] = sqrtf(4.f * fmaxf(base, GS3_COLOUR_FLOOR) * eps / alpha) / SH_C0;
+  }
+  return o;
+}
+
+__device__ __forceinline__ float row_radius(const Radius& r, int row) {
+  if (row < 3) return r.mu[row];
+  if (row < 6) return r.ls;
+  if (row < 10) return r.q[row - 6];
+  if (row == 10) return r.logit;
+  return r.col[(row - 11) % 3];
+}
+
+__device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
+
+__global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const float* __restrict__ grad,
+                                                  float* __restrict__ ghat, float* __restrict__ dhat,
+                                                  const float* __restrict__ D, int64_t n, int P, TrArgs a,
+                                                  float* __restrict__ eta_out, float* __restrict__ dx_out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const Radius rad = trust_radius(x, n, g, a.epsilon);
+  for (int r = 0; r < P; ++r) {
+    const int64_t k = (int64_t)r * n + g;
+    const float eta = row_radius(rad, r);
+    const float gh = a.theta1 * ghat[k] + (1.f - a.theta1) * grad[k];
+    float dh = dhat[k];
+    if (a.hutch) {
+      dh = a.theta2 * dh + (1.f - a.theta2) * D[k];
+      dhat[k] = dh;
+    }
+    ghat[k] = gh;
+    const float newton = -gh / dh;
+    const float dx = (dh > 0.f && isfinite(dh) && isfinite(newton)) ? newton
+                                                                     : (isfinite(eta) ? -sgnf(gh) * eta : 0.f);
+    const float step = fminf(fmaxf(dx, -eta), eta);
+    x[k] += step;
+    if (eta_out) eta_out[k] = eta;
+    if (dx_out) dx_out[k] = step;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const float* __restrict__ grad,
+                                                    float* __restrict__ m, float* __restrict__ v, int64_t n, int P,
+                                                    AdamArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  Radius rad;
+  const bool clip = a.epsilon > 0.f;
+  if (clip) rad = trust_radius(x, n, g, a.epsilon);
+  for (int r = 0; r < P; ++r) {
+    const int64_t k = (int64_t)r * n + g;
+    const float gr = grad[k];
+    const float mm = a.b1 * m[k] + (1.f - a.b1) * gr;
+    const float vv = a.b2 * v[k] + (1.f - a.b2) * gr * gr;
+    m[k] = mm;
+    v[k] = vv;
+    float step = -a.lr_row[r] * (mm / a.bc1) / (sqrtf(vv / a.bc2) + a.eps);
+    if (clip) {
+      const float eta = row_radius(rad, r);
+      step = fminf(fmaxf(step, -eta), eta);
+    }
+    x[k] += step;
+  }
+}
+
+}  // namespace
+
+void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
+                    TrArgs a, float* eta_out, float* dx_out, hipStream_t st) {
+  const int P = 11 + 3 * (deg + 1) * (deg + 1);
+  hipLaunchKernelGGL(k_tr_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, ghat, dhat, D, n, P, a,
+                     eta_out, dx_out);
+}
+
+void launch_adam_step(float* x, const float* grad, float* m, float* v, int64_t n, int deg, const AdamArgs& a,
+                      hipStream_t st) {
+  const int P = 11 + 3 * (deg + 1) * (deg + 1);
+  hipLaunchKernelGGL(k_adam_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, m, v, n, P, a);
+}

@@ -1,0 +1,364 @@
+// Projection of 3D Gaussians to screen-space splats, its tangent (JVP) and
+// its gradient (VJP), for gfx950.
+//
+// Paper: Background, "Review of Gaussian Splatting" -- each Gaussian
+// G(z) = alpha C exp(-1/2 (z-mu)^T Sigma^-1 (z-mu)) is projected to a 2D splat
+// before alpha blending; Sigma is built from a scale and a rotation given by
+// an unnormalised quaternion (appendix, "Bound on the rotation R"), and the
+// colour is a view-dependent spherical-harmonic expansion of order 3.
+// Sigma = R diag(s)^2 R^T (the form the rotation derivation composes with).
+//
+// One generic routine, templated on the scalar, serves three purposes:
+//  * float: the forward pass.  This file is compiled with -ffp-contract=off
+//    and correctly rounded division and square root, and the
+//    key-determining expressions are written in a fixed evaluation order, so
+//    depths, radii and tile rectangles are reproducible bit for bit by any
+//    IEEE float32 evaluation of the same expressions;
+//  * Dual (value, tangent): the Jacobian-vector product along a Rademacher
+//    probe or a caller tangent;
+//  * Dual with one-hot tangents: the backward pass, one forward-mode sweep
+//    per geometric parameter (mean, log-scale, quaternion) -- exact and
+//    cheap next to the blend, and it keeps a single source for the
+//    projection's derivative.  Opacity and SH rows have closed forms.
+#include "gs3_internal.h"
+
+namespace {
+
+struct Dual {
+  float v, t;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.t + b.t}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.t - b.t}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.t}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.t * b.v + a.v * b.t}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  float q = a.v / b.v;
+  return {q, (a.t - q * b.t) / b.v};
+}
+__device__ __forceinline__ Dual operator*(float a, Dual b) { return {a * b.v, a * b.t}; }
+__device__ __forceinline__ Dual operator*(Dual a, float b) { return {a.v * b, a.t * b}; }
+__device__ __forceinline__ Dual operator+(Dual a, float b) { return {a.v + b, a.t}; }
+__device__ __forceinline__ Dual operator-(Dual a, float b) { return {a.v - b, a.t}; }
+__device__ __forceinline__ Dual operator-(float a, Dual b) { return {a - b.v, -b.t}; }
+__device__ __forceinline__ Dual operator/(float a, Dual b) {
+  float q = a / b.v;
+  return {q, -q * b.t / b.v};
+}
+
+__device__ __forceinline__ float val(float a) { return a; }
+__device__ __forceinline__ float val(Dual a) { return a.v; }
+__device__ __forceinline__ float sqrt_(float a) { return sqrtf(a); }
+__device__ __forceinline__ Dual sqrt_(Dual a) {
+  float s = sqrtf(a.v);
+  return {s, s > 0.f ? 0.5f * a.t / s : 0.f};
+}
+// exp of a log-scale, evaluated in double and rounded once: reproducible in
+// float32 by any correctly rounded double exp.
+__device__ __forceinline__ float exp_ls(float a) { return (float)exp((double)a); }
+__device__ __forceinline__ Dual exp_ls(Dual a) {
+  float e = exp_ls(a.v);
+  return {e, e * a.t};
+}
+__device__ __forceinline__ float sigmoid_(float a) { return 1.f / (1.f + expf(-a)); }
+__device__ __forceinline__ Dual sigmoid_(Dual a) {
+  float s = sigmoid_(a.v);
+  return {s, a.t * s * (1.f - s)};
+}
+__device__ __forceinline__ float min_(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ float max_(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ Dual min_(Dual a, float b) { return a.v <= b ? a : Dual{b, 0.f}; }
+__device__ __forceinline__ Dual max_(Dual a, float b) { return a.v >= b ? a : Dual{b, 0.f}; }
+
+template <class T>
+__device__ __forceinline__ T cst(float v);
+template <>
+__device__ __forceinline__ float cst<float>(float v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ Dual cst<Dual>(float v) {
+  return Dual{v, 0.f};
+}
+
+template <class T>
+struct Proj {
+  T u, v, ca, cb, cc;
+  float depth, radius;
+  bool ok;  // in front of the near plane and a positive-definite screen covariance
+};
+
+// Screen-space centre, conic, depth and radius of one Gaussian.  `src(r)`
+// returns row r of the raw parameters (as float or Dual).
+template <class T, class Src>
+__device__ __forceinline__ void project_geo(const Src& src, const CamDev& cam, Proj<T>& o) {
+  const T mu0 = src(0), mu1 = src(1), mu2 = src(2);
+  const T s0 = exp_ls(src(3)), s1 = exp_ls(src(4)), s2 = exp_ls(src(5));
+  const T qx = src(6), qy = src(7), qz = src(8), qw = src(9);
+  const float two = 2.f;
+  const T r2 = ((qx * qx + qy * qy) + qz * qz) + qw * qw;
+  const T R00 = (((qw * qw + qx * qx) - qy * qy) - qz * qz) / r2;
+  const T R01 = (two * (qx * qy - qw * qz)) / r2;
+  const T R02 = (two * (qx * qz + qw * qy)) / r2;
+  const T R10 = (two * (qx * qy + qw * qz)) / r2;
+  const T R11 = (((qw * qw - qx * qx) + qy * qy) - qz * qz) / r2;
+  const T R12 = (two * (qy * qz - qw * qx)) / r2;
+  const T R20 = (two * (qx * qz - qw * qy)) / r2;
+  const T R21 = (two * (qy * qz + qw * qx)) / r2;
+  const T R22 = (((qw * qw - qx * qx) - qy * qy) + qz * qz) / r2;
+  // M = R diag(s): Sigma = M M^T
+  const T M00 = R00 * s0, M01 = R01 * s1, M02 = R02 * s2;
+  const T M10 = R10 * s0, M11 = R11 * s1, M12 = R12 * s2;
+  const T M20 = R20 * s0, M21 = R21 * s1, M22 = R22 * s2;
+  const float* W = cam.W;
+  const T p0 = ((W[0] * mu0 + W[1] * mu1) + W[2] * mu2) + cam.t[0];
+  const T p1 = ((W[3] * mu0 + W[4] * mu1) + W[5] * mu2) + cam.t[1];
+  const T p2 = ((W[6] * mu0 + W[7] * mu1) + W[8] * mu2) + cam.t[2];
+  const T txtz = min_(max_(p0 / p2, -cam.limx), cam.limx);
+  const T tytz = min_(max_(p1 / p2, -cam.limy), cam.limy);
+  const T j00 = cam.fx / p2;
+  const T j02 = -(cam.fx * txtz) / p2;
+  const T j11 = cam.fy / p2;
+  const T j12 = -(cam.fy * tytz) / p2;
+  // T = J W (2x3), V = T M (2x3), screen covariance V V^T + dilation
+  const T T00 = j00 * W[0] + j02 * W[6], T01 = j00 * W[1] + j02 * W[7], T02 = j00 * W[2] + j02 * W[8];
+  const T T10 = j11 * W[3] + j12 * W[6], T11 = j11 * W[4] + j12 * W[7], T12 = j11 * W[5] + j12 * W[8];
+  const T V00 = (T00 * M00 + T01 * M10) + T02 * M20;
+  const T V01 = (T00 * M01 + T01 * M11) + T02 * M21;
+  const T V02 = (T00 * M02 + T01 * M12) + T02 * M22;
+  const T V10 = (T10 * M00 + T11 * M10) + T12 * M20;
+  const T V11 = (T10 * M01 + T11 * M11) + T12 * M21;
+  const T V12 = (T10 * M02 + T11 * M12) + T12 * M22;
+  const T a = ((V00 * V00 + V01 * V01) + V02 * V02) + GS3_DILATION;
+  const T b = (V00 * V10 + V01 * V11) + V02 * V12;
+  const T c = ((V10 * V10 + V11 * V11) + V12 * V12) + GS3_DILATION;
+  const T det = a * c - b * b;
+  const float mid = 0.5f * (val(a) + val(c));
+  const float lam = mid + sqrtf(fmaxf(mid * mid - val(det), 0.f));
+  o.radius = ceilf(3.f * sqrtf(lam));
+  o.u = (cam.fx * p0) / p2 + cam.cx;
+  o.v = (cam.fy * p1) / p2 + cam.cy;
+  o.ca = c / det;
+  o.cb = -b / det;
+  o.cc = a / det;
+  o.depth = val(p2);
+  o.ok = val(p2) > GS3_NEAR && val(det) > 0.f;
+}
+
+// Real spherical harmonics up to degree 3 (orthonormal on the sphere).
+#define SH_C0 0.28209479177387814f
+#define SH_C1 0.4886025119029199f
+__constant__ float kSH2[5] = {1.0925484305920792f, -1.0925484305920792f, 0.31539156525252005f,
+                              -1.0925484305920792f, 0.5462742152960396f};
+__constant__ float kSH3[7] = {-0.5900435899266435f, 2.890611442640554f, -0.4570457994644658f,
+                              0.3731763325901154f, -0.4570457994644658f, 1.445305721320277f,
+                              -0.5900435899266435f};
+
+template <class T>
+__device__ __forceinline__ void sh_basis(T x, T y, T z, int deg, T* Y) {
+  Y[0] = cst<T>(SH_C0);
+  if (deg < 1) return;
+  Y[1] = (-SH_C1) * y;
+  Y[2] = SH_C1 * z;
+  Y[3] = (-SH_C1) * x;
+  if (deg < 2) return;
+  const T xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
+  Y[4] = kSH2[0] * xy;
+  Y[5] = kSH2[1] * yz;
+  Y[6] = kSH2[2] * ((2.f * zz - xx) - yy);
+  Y[7] = kSH2[3] * xz;
+  Y[8] = kSH2[4] * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = kSH3[0] * y * (3.f * xx - yy);
+  Y[10] = kSH3[1] * xy * z;
+  Y[11] = kSH3[2] * y * ((4.f * zz - xx) - yy);
+  Y[12] = kSH3[3] * z * ((2.f * zz - 3.f * xx) - 3.f * yy);
+  Y[13] = kSH3[4] * x * ((4.f * zz - xx) - yy);
+  Y[14] = kSH3[5] * z * (xx - yy);
+  Y[15] = kSH3[6] * x * (xx - 3.f * yy);
+}
+
+// RGB = sum_k Y_k(dir) f_k + 0.5, clamped at 0; raw_pos[c] tells whether the
+// clamp is inactive (its derivative is then 1).
+template <class T, class Src>
+__device__ __forceinline__ void colour(const Src& src, const CamDev& cam, int deg, T rgb[3], bool raw_pos[3],
+                                       float* Yout = nullptr) {
+  const T dx = src(0) - cam.campos[0], dy = src(1) - cam.campos[1], dz = src(2) - cam.campos[2];
+  const T inv = cst<T>(1.f) / sqrt_((dx * dx + dy * dy) + dz * dz);
+  T Y[16];
+  sh_basis<T>(dx * inv, dy * inv, dz * inv, deg, Y);
+  const int K = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    T acc = cst<T>(0.5f);
+    for (int k = 0; k < K; ++k) acc = acc + Y[k] * src(11 + 3 * k + ch);
+    raw_pos[ch] = val(acc) >= 0.f;
+    rgb[ch] = max_(acc, 0.f);
+  }
+  if (Yout)
+    for (int k = 0; k < K; ++k) Yout[k] = val(Y[k]);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t v) {
+  uint64_t z = v + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Rademacher entry k of probe i: +1 when the top bit of the hash is clear.
+__device__ __forceinline__ float probe_sign(uint64_t inner, uint64_t k) {
+  return (splitmix64(inner ^ k) >> 63) ? -1.f : 1.f;
+}
+
+// Opacity and skip threshold, each evaluated in double and rounded once so
+// that any float32 reproduction of the skip decision agrees bit for bit.
+__device__ __forceinline__ float opacity_of(float logit) { return (float)(1.0 / (1.0 + exp(-(double)logit))); }
+__device__ __forceinline__ float skip_threshold(float op) { return (float)(-log(255.0 * (double)op)); }
+
+__global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x, int64_t n, int deg, CamDev cam,
+                                                      Rec* __restrict__ rec, uint2* __restrict__ rect,
+                                                      uint32_t* __restrict__ depth_key,
+                                                      uint32_t* __restrict__ tiles) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  auto src = [&](int r) { return x[(int64_t)r * n + g]; };
+  Proj<float> p;
+  project_geo<float>(src, cam, p);
+  const float inv = 0.0625f;
+  const float txf = (float)cam.tiles_x, tyf = (float)cam.tiles_y;
+  const float x0 = fminf(fmaxf(floorf((p.u - p.radius) * inv), 0.f), txf);
+  const float x1 = fminf(fmaxf(floorf((p.u + p.radius) * inv) + 1.f, 0.f), txf);
+  const float y0 = fminf(fmaxf(floorf((p.v - p.radius) * inv), 0.f), tyf);
+  const float y1 = fminf(fmaxf(floorf((p.v + p.radius) * inv) + 1.f, 0.f), tyf);
+  bool vis = p.ok && isfinite(p.u) && isfinite(p.v) && isfinite(p.radius);
+  const int ix0 = vis ? (int)x0 : 0, ix1 = vis ? (int)x1 : 0, iy0 = vis ? (int)y0 : 0, iy1 = vis ? (int)y1 : 0;
+  const int touched = max(ix1 - ix0, 0) * max(iy1 - iy0, 0);
+  vis = vis && touched > 0;
+  if (!vis) {
+    depth_key[g] = 0xffffffffu;
+    tiles[g] = 0u;
+    return;
+  }
+  float rgb[3];
+  bool pos[3];
+  colour<float>(src, cam, deg, rgb, pos);
+  const float op = opacity_of(src(10));
+  Rec r;
+  r.a = make_float4(p.u, p.v, p.ca, p.cb);
+  r.b = make_float4(p.cc, op, rgb[0], rgb[1]);
+  r.c = make_float4(rgb[2], skip_threshold(op), 0.f, 0.f);
+  rec[g] = r;
+  rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
+  depth_key[g] = __float_as_uint(p.depth);
+  tiles[g] = (uint32_t)touched;
+}
+
+__global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x, int64_t n, int deg, CamDev cam,
+                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
+                                                      int kind, uint64_t inner, const float* __restrict__ tangent,
+                                                      TRec* __restrict__ trec) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (tiles[g] == 0u) return;
+  auto src = [&](int r) {
+    const int64_t k = (int64_t)r * n + g;
+    float t = kind == PROBE_HASH ? probe_sign(inner, (uint64_t)k) : tangent[k];
+    return Dual{x[k], t};
+  };
+  Proj<Dual> p;
+  project_geo<Dual>(src, cam, p);
+  Dual rgb[3];
+  bool pos[3];
+  colour<Dual>(src, cam, deg, rgb, pos);
+  const Dual op = sigmoid_(src(10));
+  TRec t;
+  t.a = make_float4(p.u.t, p.v.t, p.ca.t, p.cb.t);
+  t.b = make_float4(p.cc.t, op.t, rgb[0].t, rgb[1].t);
+  t.c = make_float4(rgb[2].t, 0.f, 0.f, 0.f);
+  trec[g] = t;
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, int deg, CamDev cam,
+                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
+                                                      const float* __restrict__ partials, int mode, int accumulate,
+                                                      uint64_t inner, float scale, float* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int P = 11 + 3 * (deg + 1) * (deg + 1);
+  const uint32_t cnt = tiles[g];
+  auto emit = [&](int r, float v) {
+    const int64_t k = (int64_t)r * n + g;
+    if (mode == 0) {
+      out[k] = accumulate ? out[k] + v : v;
+    } else {
+      out[k] += scale * probe_sign(inner, (uint64_t)k) * v;
+    }
+  };
+  if (cnt == 0u) {
+    if (mode == 0 && !accumulate)
+      for (int r = 0; r < P; ++r) out[(int64_t)r * n + g] = 0.f;
+    return;
+  }
+  // sum the per-(Gaussian, tile) partials: contiguous slots [off, off + cnt)
+  const uint32_t off = __float_as_uint(rec[g].c.z);
+  float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (uint32_t s = 0; s < cnt; ++s) {
+    const float* pp = partials + (int64_t)(off + s) * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G[k] += pp[k];
+  }
+  // geometric rows: one forward-mode sweep each
+  for (int k = 0; k < 10; ++k) {
+    auto src = [&](int r) { return Dual{x[(int64_t)r * n + g], r == k ? 1.f : 0.f}; };
+    Proj<Dual> p;
+    project_geo<Dual>(src, cam, p);
+    float d = G[0] * p.u.t + G[1] * p.v.t + G[2] * p.ca.t + G[3] * p.cb.t + G[4] * p.cc.t;
+    if (k < 3) {
+      Dual rgb[3];
+      bool pos[3];
+      colour<Dual>(src, cam, deg, rgb, pos);
+      d += G[6] * rgb[0].t + G[7] * rgb[1].t + G[8] * rgb[2].t;
+    }
+    emit(k, d);
+  }
+  // opacity logit
+  const float s = sigmoid_(x[10 * n + g]);
+  emit(10, G[5] * s * (1.f - s));
+  // SH rows: d rgb_c / d f_kc = Y_k(dir) where the clamp is inactive
+  auto srcf = [&](int r) { return x[(int64_t)r * n + g]; };
+  float rgb[3], Y[16];
+  bool pos[3];
+  colour<float>(srcf, cam, deg, rgb, pos, Y);
+  const int K = (deg + 1) * (deg + 1);
+  for (int k = 0; k < K; ++k)
+    for (int ch = 0; ch < 3; ++ch) emit(11 + 3 * k + ch, pos[ch] ? Y[k] * G[6 + ch] : 0.f);
+}
+
+uint64_t probe_inner(uint64_t seed, uint32_t i) {
+  uint64_t z = (seed ^ (uint64_t)i) + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, Rec* rec, uint2* rect,
+                        uint32_t* depth_key, uint32_t* tiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_project_fwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, deg, cam, rec, rect, depth_key,
+                     tiles);
+}
+
+void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
+                        const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
+                        const float* tangent, TRec* trec, hipStream_t st) {
+  hipLaunchKernelGGL(k_project_jvp, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, deg, cam, rec, tiles,
+                     probe_kind, probe_inner(seed, probe_index), tangent, trec);
+}
+
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
+                        const uint32_t* tiles, const float* partials, int mode, int accumulate, uint64_t seed,
+                        uint32_t probe_index, float scale, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_project_bwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, deg, cam, rec, tiles,
+                     partials, mode, accumulate, probe_inner(seed, probe_index), scale, out);
+}

@@ -1,0 +1,335 @@
+// Tile binning for gfx950: exclusive scan, stable LSD radix sort of 32-bit
+// keys with 32-bit values, pair emission and per-tile ranges.
+//
+// Paper: Background ("Review of Gaussian Splatting") -- splats are bucketed
+// per screen tile and blended in depth order; the Introduction notes that this
+// order changes discontinuously with the positions.  The required order is
+// lexicographic in (tile, float bits of depth, Gaussian index).  Instead of
+// one radix sort over 64-bit (tile, depth) keys of every pair, the visible
+// Gaussians are sorted once by depth (N elements, 32 key bits), pairs are
+// emitted in that order, and the pairs are then stably sorted by tile id
+// (ceil(log2 tiles) key bits).  Stability makes the two orders identical and
+// moves far fewer bytes: the pair sort needs 2 passes instead of 6.
+//
+// Radix pass = upsweep (per-block digit histograms), per-digit scan across
+// blocks (one workgroup per digit), scatter (stable ranking with wave64
+// ballots: lanes holding the same digit are found with 8 ballots).  No
+// workgroup ever waits on another: every kernel is a plain data-parallel
+// launch.
+#include "gs3_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;  // items per thread per block
+constexpr int kTileItems = kThreads * kItems;
+constexpr int kRadix = 256;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(v, d, 64);
+    if (lane >= d) v += y;
+  }
+  return v;
+}
+
+// Exclusive scan across a 256-thread block; returns the block total in *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    off += (i < w) ? wsum[i] : 0u;
+    tot += wsum[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+// ---------------------------------------------------------------- scan
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                           uint32_t* __restrict__ block_sums) {
+  const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i)
+    if (base + i < n) s += in[base + i];
+  uint32_t tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ block_sums, int nb,
+                                                        uint32_t* __restrict__ total) {
+  uint32_t running = 0;
+  for (int base = 0; base < nb; base += kThreads) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < nb ? block_sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, &tot);
+    if (i < nb) block_sums[i] = running + ex;
+    running += tot;
+  }
+  if (threadIdx.x == 0) *total = running;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                         int64_t n, const uint32_t* __restrict__ block_sums) {
+  const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
+  uint32_t v[kItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, &tot) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+// ---------------------------------------------------------------- radix sort
+
+__global__ __launch_bounds__(kThreads) void k_rs_upsweep(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                          uint32_t* __restrict__ hist, int nb) {
+  __shared__ uint32_t h[kRadix];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kTileItems;
+#pragma unroll 4
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + r * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup per digit: exclusive scan of hist[d][0..nb) in place.
+__global__ __launch_bounds__(kThreads) void k_rs_scan(uint32_t* __restrict__ hist, int nb,
+                                                       uint32_t* __restrict__ digit_total) {
+  uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  uint32_t running = 0;
+  for (int base = 0; base < nb; base += kThreads) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < nb ? row[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, &tot);
+    if (i < nb) row[i] = running + ex;
+    running += tot;
+  }
+  if (threadIdx.x == 0) digit_total[blockIdx.x] = running;
+}
+
+__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ vals,
+                                                          uint32_t* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out, int64_t n, int shift,
+                                                          const uint32_t* __restrict__ hist, int nb,
+                                                          const uint32_t* __restrict__ digit_total) {
+  __shared__ uint32_t base[kRadix];
+  __shared__ uint32_t wcnt[4][kRadix];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  {
+    uint32_t tot;
+    const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
+    base[tid] = dbase + hist[(int64_t)tid * nb + blockIdx.x];
+  }
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t blk = (int64_t)blockIdx.x * kTileItems;
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = blk + r * kThreads + tid;
+    const bool valid = i < n;
+    const uint32_t k = valid ? keys[i] : 0u;
+    const uint32_t v = valid ? vals[i] : 0u;
+    const uint32_t d = (k >> shift) & 0xffu;
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      same &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(same & lt_mask);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wcnt[q][tid] = 0u;
+    __syncthreads();
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    // per-digit prefix over the four waves (wave order == item order)
+    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+    __syncthreads();
+    wcnt[0][tid] = 0u;
+    wcnt[1][tid] = c0;
+    wcnt[2][tid] = c0 + c1;
+    wcnt[3][tid] = c0 + c1 + c2;
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = base[d] + wcnt[w][d] + rank;
+      keys_out[pos] = k;
+      vals_out[pos] = v;
+    }
+    __syncthreads();
+    base[tid] += c0 + c1 + c2 + c3;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- binning
+
+__global__ __launch_bounds__(256) void k_iota(uint32_t* __restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* __restrict__ order,
+                                                        const uint32_t* __restrict__ tiles, int64_t n,
+                                                        uint32_t* __restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counts[i] = tiles[order[i]];
+}
+
+__global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ order,
+                                                     const uint32_t* __restrict__ offsets, Rec* __restrict__ rec,
+                                                     const uint2* __restrict__ rect,
+                                                     const uint32_t* __restrict__ tiles, int64_t n, int tiles_x,
+                                                     uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_gid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t g = order[i];
+  const uint32_t cnt = tiles[g];
+  if (cnt == 0u) return;
+  const uint32_t off = offsets[i];
+  const uint2 rc = rect[g];
+  const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
+  const int w = x1 - x0;
+  rec[g].c.z = __uint_as_float(off);
+  for (uint32_t k = 0; k < cnt; ++k) {
+    const int ty = y0 + (int)k / w, tx = x0 + (int)k % w;
+    pair_tile[off + k] = (uint32_t)(ty * tiles_x + tx);
+    pair_gid[off + k] = g;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ tile, int64_t n,
+                                                      uint2* __restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = tile[i];
+  if (i == 0 || tile[i - 1] != t) ranges[t].x = (uint32_t)i;
+  if (i == n - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+__global__ __launch_bounds__(256) void k_make_keys(const uint32_t* __restrict__ tile, const uint32_t* __restrict__ gid,
+                                                    const uint32_t* __restrict__ depth_key, int64_t n,
+                                                    uint64_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = ((uint64_t)tile[i] << 32) | (uint64_t)depth_key[gid[i]];
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+size_t scan_temp_bytes(int64_t n) { return (size_t)(nblk(n, kTileItems) + 1) * sizeof(uint32_t); }
+
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st) {
+  const int nb = (int)nblk(n, kTileItems);
+  uint32_t* sums = (uint32_t*)temp;
+  if (n <= 0) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, total, (int64_t)1, 0u);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, st, in, n, sums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, sums, nb, total);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, st, in, out, n, sums);
+}
+
+size_t radix_temp_bytes(int64_t n) {
+  const int64_t nb = nblk(n > 0 ? n : 1, kTileItems);
+  return (size_t)(kRadix * nb + kRadix) * sizeof(uint32_t);
+}
+
+void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n, int bits,
+                    void* temp, hipStream_t st, uint32_t** keys_out, uint32_t** vals_out) {
+  uint32_t *ka = keys, *va = vals, *kb = keys_alt, *vb = vals_alt;
+  if (n > 1) {
+    const int nb = (int)nblk(n, kTileItems);
+    uint32_t* hist = (uint32_t*)temp;
+    uint32_t* dtot = hist + (size_t)kRadix * nb;
+    for (int shift = 0; shift < bits; shift += 8) {
+      hipLaunchKernelGGL(k_rs_upsweep, dim3(nb), dim3(kThreads), 0, st, ka, n, shift, hist, nb);
+      hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb, dtot);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, st, ka, va, kb, vb, n, shift, hist, nb, dtot);
+      uint32_t* t = ka;
+      ka = kb;
+      kb = t;
+      t = va;
+      va = vb;
+      vb = t;
+    }
+  }
+  *keys_out = ka;
+  *vals_out = va;
+}
+
+void launch_iota(uint32_t* v, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_iota, dim3(nblk(n, 256)), dim3(256), 0, st, v, n);
+}
+
+void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
+                          hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_counts, dim3(nblk(n, 256)), dim3(256), 0, st, order, tiles, n, counts_sorted);
+}
+
+void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Rec* rec, const uint2* rect,
+                       const uint32_t* tiles, int64_t n, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
+                       hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_emit_pairs, dim3(nblk(n, 256)), dim3(256), 0, st, order, offsets_sorted, rec, rect, tiles, n,
+                       tiles_x, pair_tile, pair_gid);
+}
+
+void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(nblk(2 * (int64_t)n_tiles, 256)), dim3(256), 0, st, (uint32_t*)ranges,
+                     2 * (int64_t)n_tiles, 0u);
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_tile_ranges, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, pair_tile, n_pairs, ranges);
+}
+
+void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const uint32_t* depth_key,
+                      int64_t n_pairs, uint64_t* keys, hipStream_t st) {
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_make_keys, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, pair_tile, pair_gid, depth_key,
+                       n_pairs, keys);
+}
+
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+}

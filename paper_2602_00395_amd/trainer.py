@@ -1,0 +1,128 @@
+"""Host-side drivers of the optimizer loop (Algorithm 1) and the Adam baseline.
+
+Paper: Algorithm 1 (order of the steps), Methodology ("Algorithm Design":
+mini-batches S1, S2 and the Hutchinson interval l) and the evaluation
+settings: l = 10, theta1 = 0.9, theta2 = 0.999, |S1| = |S2| = nu = 1, epsilon
+decaying exponentially from 1e-6 to 1e-8 over the run.  Readings: iteration t
+is a Hutchinson step when (t - 1) mod l == 0; the decay is log-linear in t.
+Adam uses the 3DGS per-group learning rates, the mean's decaying
+log-linearly from 1.6e-4 to 1.6e-6 times the scene extent.
+
+Every iteration runs entirely in the HIP library; this module only picks
+cameras and schedules.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .api import Scene
+
+
+def eps_schedule(t: int, T: int, eps0: float = 1e-6, eps1: float = 1e-8) -> float:
+    if T <= 1:
+        return eps0
+    f = min(max((t - 1) / (T - 1), 0.0), 1.0)
+    return math.exp(math.log(eps0) + f * (math.log(eps1) - math.log(eps0)))
+
+
+def adam_lrs(t: int, T: int, extent: float) -> dict:
+    f = min(max(t / max(T, 1), 0.0), 1.0)
+    lr_mu = math.exp((1 - f) * math.log(1.6e-4 * extent) + f * math.log(1.6e-6 * extent))
+    return dict(mu=lr_mu, f_dc=2.5e-3, f_rest=2.5e-3 / 20.0, opacity=0.05, scale=5e-3, rot=1e-3)
+
+
+@dataclass
+class TRConfig:
+    l: int = 10
+    theta1: float = 0.9
+    theta2: float = 0.999
+    nu: int = 1
+    s1: int = 1
+    s2: int = 1
+    budget: int = 30000
+    seed: int = 4002
+    probe_seed: int = 5002
+
+
+class TRTrainer:
+    """Algorithm 1 on a resident Scene."""
+
+    def __init__(self, scene: Scene, train_ids, cfg: TRConfig | None = None):
+        self.scene = scene
+        self.train = list(train_ids)
+        self.cfg = cfg or TRConfig()
+        self.rng = np.random.default_rng(self.cfg.seed)
+        self.g = scene._empty_like_params()
+        self.D = scene._empty_like_params()
+        self.t = 0
+
+    def step(self):
+        c = self.cfg
+        self.t += 1
+        t = self.t
+        S1 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s1)]
+        self.scene.grad(S1, out=self.g)
+        eps = eps_schedule(t, c.budget)
+        if (t - 1) % c.l == 0:
+            S2 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s2)]
+            self.scene.hvp_diag(S2, c.nu, c.probe_seed + t, out=self.D)
+            self.scene.tr_step(self.g, self.D, c.theta1, c.theta2, eps)
+        else:
+            self.scene.tr_step(self.g, None, c.theta1, c.theta2, eps)
+
+
+class AdamTrainer:
+    """The Adam baseline (optionally ADAM-TR: clipped by the Hellinger radius)."""
+
+    def __init__(self, scene: Scene, train_ids, extent: float, budget: int = 30000, seed: int = 4002,
+                 trust_region: bool = False):
+        self.scene = scene
+        self.train = list(train_ids)
+        self.extent = extent
+        self.budget = budget
+        self.trust_region = trust_region
+        self.rng = np.random.default_rng(seed)
+        self.g = scene._empty_like_params()
+        self.t = 0
+
+    def step(self):
+        self.t += 1
+        j = self.train[int(self.rng.integers(len(self.train)))]
+        self.scene.grad([j], out=self.g)
+        eps = eps_schedule(self.t, self.budget) if self.trust_region else None
+        self.scene.adam_step(self.g, adam_lrs(self.t, self.budget, self.extent), self.t, epsilon=eps)
+
+
+def mean_psnr(scene: Scene, ids) -> float:
+    return float(np.mean([scene.psnr(j) for j in ids]))
+
+
+def fit(trainer, scene: Scene, test_ids, iters: int, eval_every: int = 500, target_psnr: float | None = None,
+        log=None):
+    """Run `iters` iterations; evaluate every `eval_every`.  The clock counts
+    training only (evaluation excluded).  Returns (history, seconds to target)."""
+    hist = []
+    train_s = 0.0
+    reached = None
+    done = 0
+    while done < iters:
+        n = min(eval_every, iters - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            trainer.step()
+        torch.cuda.synchronize()
+        train_s += time.perf_counter() - t0
+        done += n
+        p = mean_psnr(scene, test_ids)
+        hist.append((done, train_s, p))
+        if log:
+            log(f"iter {done} train_s {train_s:.2f} psnr {p:.3f}")
+        if target_psnr is not None and reached is None and p >= target_psnr:
+            reached = train_s
+    return hist, reached

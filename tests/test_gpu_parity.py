@@ -1,0 +1,304 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bit-exact: tile keys, sorted Gaussian order, per-tile ranges.  Floating
+point: relative L2 <= 1e-4 per parameter group (images, gradients, Hessian
+diagonals, trust-region steps).  Inputs are seeded; targets for the loss are
+the oracle's render plus +-U[0.05, 0.15] so every residual is far from the L1
+kink and the Gauss-Newton weights are well conditioned.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic as syn
+from oracle import binning as B
+from oracle import method as Mth
+from oracle import render as R
+from tests.helpers import group_errors, offset_targets, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_scene(x, targets, cams, deg, lam=0.2, bg=(0.0, 0.0, 0.0)):
+    from paper_2602_00395_amd import Scene
+
+    xt = torch.tensor(np.asarray(x, np.float32), device=DEV)
+    tg = [torch.tensor(np.asarray(t, np.float32), device=DEV) for t in targets]
+    return Scene(xt, tg, cams, deg, lam=lam, background=bg)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    sc = syn.config1_scene()
+    x = sc.init.astype(np.float32)
+    targets = offset_targets(x, sc.cameras, 0, seed=4001)
+    return sc, x, targets
+
+
+def _check_bins(gpu, ob, tag):
+    keys, gids, ranges = gpu
+    k = keys.cpu().numpy().view(np.uint64)
+    assert len(k) == len(ob.keys), (tag, len(k), len(ob.keys))
+    assert np.array_equal(k, ob.keys), tag
+    assert np.array_equal(gids.cpu().numpy().astype(np.int64), ob.gids), tag
+    # an empty tile's range is any [s, s); non-empty ranges are unique
+    r = ranges.cpu().numpy().astype(np.int64)
+    empty = ob.ranges[:, 0] == ob.ranges[:, 1]
+    assert np.array_equal(r[~empty], ob.ranges[~empty]), tag
+    assert np.all(r[empty, 0] == r[empty, 1]), tag
+
+
+def test_binning_bit_exact_config1(c1):
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0)
+    for j, cam in enumerate(sc.cameras):
+        say("bin c1 camera", j)
+        _check_bins(s.bin(j), B.bin_view(x, cam), f"cam{j}")
+    s.close()
+
+
+def test_binning_bit_exact_ragged_and_large_splats():
+    sc = syn.config1_scene()
+    x = sc.gt.copy()
+    x[3:6] += 1.5  # splats spanning many tiles
+    cams = [syn.make_camera((0.3, -3.0, 0.4), 80, 56), syn.make_camera((2.5, 2.0, 1.0), 37, 71)]
+    targets = [np.zeros((c.height, c.width, 3), np.float32) for c in cams]
+    s = make_scene(x, targets, cams, 0)
+    for j, cam in enumerate(cams):
+        say("bin ragged camera", j)
+        ob = B.bin_view(x, cam)
+        assert ob.tiles_touched.max() > 8
+        _check_bins(s.bin(j), ob, f"ragged{j}")
+    s.close()
+
+
+def test_binning_bit_exact_object_scale():
+    sc = syn.config2_scene()
+    cams = sc.cameras[:3]
+    targets = [np.zeros((c.height, c.width, 3), np.float32) for c in cams]
+    for name, x in (("gt", sc.gt), ("init", sc.init)):
+        s = make_scene(x, targets, cams, 3)
+        for j, cam in enumerate(cams):
+            say("bin object-scale", name, "camera", j)
+            ob = B.bin_view(x, cam)
+            _check_bins(s.bin(j), ob, f"{name}{j}")
+        s.close()
+
+
+def test_render_parity_config1(c1):
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0)
+    xt = torch.tensor(x, dtype=torch.float64)
+    for j, cam in enumerate(sc.cameras):
+        say("render c1 camera", j)
+        want = R.render(xt, cam, 0).numpy()
+        got = s.render(j).cpu().numpy()
+        assert rel_l2(got, want) <= TOL, (j, rel_l2(got, want))
+    s.close()
+
+
+def test_render_parity_background_and_empty_view():
+    sc = syn.config1_scene()
+    x = sc.gt.astype(np.float32)
+    cams = [sc.cameras[0], syn.make_camera((0.0, 0.0, 30.0), 48, 40, target=(0.0, 0.0, 60.0))]
+    targets = [np.zeros((c.height, c.width, 3), np.float32) for c in cams]
+    bg = (0.2, 0.5, 0.9)
+    s = make_scene(x, targets, cams, 0, bg=bg)
+    got = s.render(0).cpu().numpy()
+    want = R.render(torch.tensor(x, dtype=torch.float64), cams[0], 0, background=bg).numpy()
+    assert rel_l2(got, want) <= TOL
+    empty = s.render(1).cpu().numpy()  # looking away from every Gaussian
+    assert np.allclose(empty, np.broadcast_to(np.array(bg, np.float32), empty.shape))
+    g = s.grad([1]).cpu().numpy()
+    assert np.all(g == 0)
+    s.close()
+
+
+def test_render_parity_object_scale_sampled_tiles():
+    sc = syn.config2_scene()
+    cam = sc.cameras[5]
+    x = sc.init.astype(np.float32)
+    s = make_scene(x, [np.zeros((cam.height, cam.width, 3), np.float32)], [cam], 3)
+    got = s.render(0).cpu().numpy()
+    ob = B.bin_view(x, cam)
+    counts = ob.ranges[:, 1] - ob.ranges[:, 0]
+    rng = np.random.default_rng(7)
+    busy = np.argsort(counts)[-3:]
+    pick = set(int(t) for t in busy) | set(int(t) for t in rng.choice(len(counts), 5, replace=False))
+    say("render object-scale tiles", sorted(pick), "longest list", int(counts.max()))
+    want = R.render(torch.tensor(x, dtype=torch.float64), cam, 3, ob, tiles=pick).numpy()
+    m = ~np.isnan(want[..., 0])
+    assert m.sum() >= 6 * 256
+    assert rel_l2(got[m], want[m]) <= TOL
+    s.close()
+
+
+@pytest.mark.parametrize("lam", [0.2, 0.0])
+def test_grad_parity_config1(c1, lam):
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0, lam=lam)
+    prob = Mth.Problem(sc.cameras, targets, 0, lam=lam)
+    for S1 in ([1], [0, 5]):
+        say("grad c1 lam", lam, "S1", S1)
+        want, f_want = Mth.gradient(x, prob, S1)
+        got, f_got = s.grad(S1, want_loss=True)
+        errs = group_errors(got.cpu().numpy(), want, 14)
+        say("  rel-L2 per group", errs)
+        assert all(e <= TOL for e in errs.values()), errs
+        assert abs(f_got - f_want) <= 1e-5 * abs(f_want)
+    s.close()
+
+
+def test_grad_is_deterministic(c1):
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0)
+    a = s.grad([2]).cpu()
+    b = s.grad([2]).cpu()
+    assert torch.equal(a, b)
+    s.close()
+
+
+def test_hvp_diag_parity_config1(c1):
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0)
+    prob = Mth.Problem(sc.cameras, targets, 0, lam=0.2)
+    S2, nu, seed = [2], 2, 5001
+    say("hvp_diag c1 S2", S2, "nu", nu)
+    want = Mth.hutchinson(x, prob, S2, nu, seed)
+    got = s.hvp_diag(S2, nu, seed).cpu().numpy()
+    errs = group_errors(got, want, 14)
+    say("  rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
+def test_render_vjp_and_jvp_parity(c1):
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0)
+    cam = sc.cameras[4]
+    rng = np.random.default_rng(11)
+    cot = rng.normal(size=(cam.height, cam.width, 3))
+    tan = rng.normal(size=x.shape)
+    xt = torch.tensor(x, dtype=torch.float64)
+    bins = B.bin_view(x, cam)
+    f = lambda xx: R.render(xx, cam, 0, bins)  # noqa: E731
+    img, vjp_fn = torch.func.vjp(f, xt)
+    want_g = vjp_fn(torch.tensor(cot))[0].numpy()
+    got_g = s.render_vjp(4, torch.tensor(cot, dtype=torch.float32, device=DEV)).cpu().numpy()
+    errs = group_errors(got_g, want_g, 14)
+    say("vjp rel-L2", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    _, want_t = torch.func.jvp(f, (xt,), (torch.tensor(tan),))
+    rgb, got_t = s.render_jvp(4, torch.tensor(tan, dtype=torch.float32, device=DEV))
+    assert rel_l2(rgb.cpu().numpy(), img.detach().numpy()) <= TOL
+    assert rel_l2(got_t.cpu().numpy(), want_t.numpy()) <= TOL, rel_l2(got_t.cpu().numpy(), want_t.numpy())
+    s.close()
+
+
+def test_grad_parity_object_scale_crop():
+    """The 500 Gaussians nearest the origin of the object-scale scene, SH degree 3,
+    rendered at 800x800 from two cameras."""
+    sc = syn.config2_scene()
+    d = np.linalg.norm(sc.init[0:3].T, axis=1)
+    keep = np.argsort(d)[:500]
+    x = sc.init[:, keep].copy()
+    x[11 + 3:] = sc.gt[11 + 3:, keep]  # non-zero higher-order SH so every row is exercised
+    cams = [sc.cameras[0], sc.cameras[17]]
+    targets = offset_targets(x, cams, 3, seed=4002)
+    s = make_scene(x, targets, cams, 3)
+    prob = Mth.Problem(cams, targets, 3, lam=0.2)
+    say("grad crop")
+    want, _ = Mth.gradient(x, prob, [1])
+    got = s.grad([1]).cpu().numpy()
+    errs = group_errors(got, want, 59)
+    say("  rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
+def test_tr_step_parity():
+    sc = syn.config2_scene(n=4000, n_cams=2, res=64)
+    x = sc.gt.astype(np.float32)
+    p, n = x.shape
+    rng = np.random.default_rng(12)
+    g = (rng.normal(size=x.shape) * 1e-3).astype(np.float32)
+    ghat = (rng.normal(size=x.shape) * 1e-3).astype(np.float32)
+    dhat = rng.uniform(-0.2, 1.0, size=x.shape).astype(np.float32)
+    dhat[:, :50] = 0.0  # the D <= 0 rule
+    D = rng.uniform(0.0, 2.0, size=x.shape).astype(np.float32)
+    x[10, :100] = -16.0  # eps >= alpha: unconstrained mean and rotation
+    x[3:6, 100:150] = math.log(0.07)  # isotropic: free rotation
+    targets = [np.zeros((c.height, c.width, 3), np.float32) for c in sc.cameras]
+    for hutch in (True, False):
+        say("tr_step hutch", hutch)
+        s = make_scene(x, targets, sc.cameras, 3)
+        gh_t = torch.tensor(ghat, device=DEV)
+        dh_t = torch.tensor(dhat, device=DEV)
+        s.import_(ghat=gh_t, dhat=dh_t)
+        eta_t = torch.empty_like(gh_t)
+        dx_t = torch.empty_like(gh_t)
+        eps = 3e-7
+        s.tr_step(torch.tensor(g, device=DEV), torch.tensor(D, device=DEV) if hutch else None, 0.9, 0.999, eps,
+                  eta_out=eta_t, dx_out=dx_t)
+        x_new = s.params().cpu().numpy()
+        eta_want = Mth.shd_eta(x.astype(np.float64), eps, 3)
+        xw, ghw, dhw, dxw, _ = Mth.tr_step(x, g, ghat, dhat, D if hutch else None, 0.9, 0.999, eps, 3,
+                                           eta=eta_want)
+        eta_got = eta_t.cpu().numpy()
+        assert np.array_equal(np.isinf(eta_got), np.isinf(eta_want))
+        fin = np.isfinite(eta_want)
+        assert rel_l2(eta_got[fin], eta_want[fin]) <= TOL
+        errs = group_errors(dx_t.cpu().numpy(), dxw, p)
+        say("  step rel-L2", errs)
+        assert all(e <= TOL for e in errs.values()), errs
+        # x' = x + step: its error is the step's error plus float32 rounding of x
+        assert np.linalg.norm(x_new - xw) <= TOL * np.linalg.norm(dxw) + 1e-6 * np.linalg.norm(x)
+        ghn, dhn = torch.empty_like(gh_t), torch.empty_like(gh_t)
+        s.export(ghat=ghn, dhat=dhn)
+        assert rel_l2(ghn.cpu().numpy(), ghw) <= 1e-6 and rel_l2(dhn.cpu().numpy(), dhw) <= 1e-6
+        s.close()
+
+
+def test_adam_and_adam_tr_parity():
+    sc = syn.config2_scene(n=3000, n_cams=2, res=64)
+    x = sc.init.astype(np.float32)
+    targets = [np.zeros((c.height, c.width, 3), np.float32) for c in sc.cameras]
+    rng = np.random.default_rng(13)
+    lrs = Mth.adam_lrs(10, 100, 2.0)
+    for eps in (None, 1e-6):
+        s = make_scene(x, targets, sc.cameras, 3)
+        xo, m, v = x.astype(np.float64), np.zeros(x.shape), np.zeros(x.shape)
+        for step in range(1, 4):
+            g = (rng.normal(size=x.shape) * 1e-3).astype(np.float32)
+            s.adam_step(torch.tensor(g, device=DEV), lrs, step, epsilon=eps)
+            if eps is None:
+                xo, m, v = Mth.adam_step(xo, g, m, v, step, lrs, 3)
+            else:
+                eta = Mth.shd_eta(xo, eps, 3)
+                xn, m, v = Mth.adam_step(xo, g, m, v, step, lrs, 3)
+                xo = xo + np.clip(xn - xo, -eta, eta)
+        got = s.params().cpu().numpy()
+        errs = group_errors(got - x, xo - x, 59)
+        say("adam eps", eps, errs)
+        assert all(e <= TOL for e in errs.values()), errs
+        s.close()
+
+
+def test_psnr_matches_oracle(c1):
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0)
+    want = R.render(torch.tensor(x, dtype=torch.float64), sc.cameras[3], 0)
+    from oracle.loss import psnr
+
+    assert abs(s.psnr(3) - psnr(want, torch.tensor(targets[3], dtype=torch.float64))) < 1e-3
+    s.close()

@@ -111,3 +111,25 @@ def test_float32_binning_agrees_with_float64_projection():
     a, b, c = pr32["cov2"]
     det64 = 1.0 / (pr64["conic"][:, 0] * pr64["conic"][:, 2] - pr64["conic"][:, 1] ** 2)
     assert np.allclose((a * c - b * b)[vis], det64.numpy()[vis], rtol=1e-4)
+
+
+def test_log_domain_skip_threshold_matches_the_opacity_threshold():
+    # alpha exp(power) < 1/255  <=>  power < -ln(255 alpha): the float32 form
+    # agrees with the exact float64 test except within rounding of the boundary
+    rng = np.random.default_rng(3)
+    logit = rng.normal(0, 2, size=200000).astype(np.float32)
+    alpha = (1.0 / (1.0 + np.exp(-logit.astype(np.float64)))).astype(np.float32)
+    tau = (-np.log(255.0 * alpha.astype(np.float64))).astype(np.float32)
+    power = rng.uniform(-9, 0, size=logit.size).astype(np.float32)
+    exact = alpha.astype(np.float64) * np.exp(power.astype(np.float64)) < 1.0 / 255.0
+    f32 = power < tau
+    margin = np.abs(np.log(255.0 * alpha.astype(np.float64)) + power.astype(np.float64))
+    assert np.all(exact[margin > 1e-6] == f32[margin > 1e-6])
+    assert (exact != f32).mean() < 1e-4
+    # bins carry the float32 decision inputs
+    sc = syn.config1_scene()
+    b = B.bin_view(sc.gt, sc.cameras[0])
+    assert b.dec["tau"].dtype == np.float32 and b.dec["ca"].dtype == np.float32
+    pr = B.project_f32(sc.gt, sc.cameras[0])
+    a, bb, c = pr["cov2"]
+    assert np.array_equal(b.dec["ca"], c / (a * c - bb * bb))

@@ -58,18 +58,21 @@ def test_two_splats_closed_form_front_to_back():
     assert np.allclose(img[i, j], want, rtol=2e-6)
 
 
-def _brute_pixel(pr, gids, px, py):
-    """The blend rule read literally: one pixel, one splat at a time."""
+def _brute_pixel(pr, bins, gids, px, py):
+    """The blend rule read literally: one pixel, one splat at a time (the
+    skip decision in float32 from the binning's float32 splat values)."""
     T, C, used = 1.0, np.zeros(3), 0
+    f32 = np.float32
     for k, g in enumerate(gids):
+        d = bins.dec
+        dx32, dy32 = d["u"][g] - f32(px), d["v"][g] - f32(py)
+        p32 = f32(-0.5) * ((d["ca"][g] * dx32) * dx32 + (d["cc"][g] * dy32) * dy32) - (d["cb"][g] * dx32) * dy32
+        if p32 > 0 or p32 < d["tau"][g]:
+            continue
         dx, dy = float(pr["u"][g]) - px, float(pr["v"][g]) - py
         ca, cb, cc = (float(v) for v in pr["conic"][g])
         power = -0.5 * (ca * dx * dx + cc * dy * dy) - cb * dx * dy
-        if power > 0:
-            continue
         ab = min(0.99, float(pr["alpha"][g]) * math.exp(power))
-        if ab < 1.0 / 255.0:
-            continue
         if T * (1 - ab) < 1e-4:
             break
         C += pr["rgb"][g].numpy() * ab * T
@@ -91,7 +94,7 @@ def test_blend_matches_sequential_brute_force_with_early_stop():
     for i in range(cam.height):
         for j in range(cam.width):
             t = (i // 16) * bins.tiles_x + (j // 16)
-            C, T, used = _brute_pixel(pr, bins.tile_list(t), j + 0.5, i + 0.5)
+            C, T, used = _brute_pixel(pr, bins, bins.tile_list(t), j + 0.5, i + 0.5)
             assert np.allclose(img[i, j].numpy(), C, rtol=1e-12, atol=1e-14)
             assert abs(float(aux["T_final"][i, j]) - T) < 1e-14
             assert int(aux["n_contrib"][i, j]) == used
