@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=32, help="tiles in the oracle's timed sample")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB: first run one plain device-to-device copy of this size (counter calibration)")
     ap.add_argument("--fit", type=int, default=0,
                     help="also run Adam for 2x this many iterations and TR until Adam's PSNR (seconds to PSNR)")
     return ap.parse_args()
@@ -142,8 +144,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the image-parallel sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (the image-parallel "
+              "sharding is a design, not an implementation); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -154,6 +156,14 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty(n, device=dev)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     sc = syn.config2_scene()
     cams = sc.cameras
     train_ids, test_ids = sc.train_ids(), sc.test_ids()

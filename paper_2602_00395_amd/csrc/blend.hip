@@ -23,9 +23,9 @@
 // per-pixel state) and obtaining the weight of the splats behind splat i from
 // the stored output: sum_{j>i} c_j abar_j T_j + T_final bg = C_out - S_i,
 // S_i the running front-to-back sum.  Gradients of each (splat, tile) pair are
-// reduced over the workgroup (wave64 shuffles, then the four waves in LDS in
-// a fixed order) and written to the pair's own slot: no float atomics, so the
-// backward is deterministic.
+// reduced over the workgroup (wave64 DPP row shifts and broadcasts, then the
+// four waves in LDS in a fixed order) and written to the pair's own slot: no
+// float atomics, so the backward is deterministic.
 #include "gs3_internal.h"
 
 namespace {
@@ -215,9 +215,24 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   count_evals(ctr, nev, ncon);
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+// Data-parallel-primitive (DPP) move: lane i reads `v` from the lane selected
+// by CTRL; lanes without a source (or in rows outside ROW_MASK) read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum over the 64 lanes of a wave, valid in lane 63: an inclusive scan within
+// each 16-lane row (row_shr 1, 2, 4, 8), then row 0's total into row 1 and
+// row 2's into row 3 (row_bcast:15), then rows 0-1 into rows 2-3
+// (row_bcast:31).  Six VALU operations, no LDS traffic.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  v += dpp_move<0x111>(v);
+  v += dpp_move<0x112>(v);
+  v += dpp_move<0x114>(v);
+  v += dpp_move<0x118>(v);
+  v += dpp_move<0x142, 0xa>(v);
+  v += dpp_move<0x143, 0xc>(v);
   return v;
 }
 
@@ -327,9 +342,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
       }
       if (__ballot(contrib) != 0ull) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) gr[k] = wave_sum(gr[k]);
+        for (int k = 0; k < 9; ++k) gr[k] = wave_sum_lane63(gr[k]);
       }
-      if (lane == 0) {
+      if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) s.red[w][k][j] = gr[k];
       }

@@ -87,12 +87,17 @@ struct Proj {
   bool ok;  // in front of the near plane and a positive-definite screen covariance
 };
 
+// s = exp(log-scale) with its tangent, from a value computed once per Gaussian.
+__device__ __forceinline__ float scale_of(float, float sval) { return sval; }
+__device__ __forceinline__ Dual scale_of(Dual ls, float sval) { return Dual{sval, sval * ls.t}; }
+
 // Screen-space centre, conic, depth and radius of one Gaussian.  `src(r)`
-// returns row r of the raw parameters (as float or Dual).
+// returns row r of the raw parameters (as float or Dual); sv[i] is
+// exp_ls(log-scale i) evaluated once by the caller.
 template <class T, class Src>
-__device__ __forceinline__ void project_geo(const Src& src, const CamDev& cam, Proj<T>& o) {
+__device__ __forceinline__ void project_geo(const Src& src, const float sv[3], const CamDev& cam, Proj<T>& o) {
   const T mu0 = src(0), mu1 = src(1), mu2 = src(2);
-  const T s0 = exp_ls(src(3)), s1 = exp_ls(src(4)), s2 = exp_ls(src(5));
+  const T s0 = scale_of(src(3), sv[0]), s1 = scale_of(src(4), sv[1]), s2 = scale_of(src(5), sv[2]);
   const T qx = src(6), qy = src(7), qz = src(8), qw = src(9);
   const float two = 2.f;
   const T r2 = ((qx * qx + qy * qy) + qz * qz) + qw * qw;
@@ -153,21 +158,21 @@ __constant__ float kSH3[7] = {-0.5900435899266435f, 2.890611442640554f, -0.45704
                               0.3731763325901154f, -0.4570457994644658f, 1.445305721320277f,
                               -0.5900435899266435f};
 
-template <class T>
-__device__ __forceinline__ void sh_basis(T x, T y, T z, int deg, T* Y) {
+template <class T, int DEG>
+__device__ __forceinline__ void sh_basis(T x, T y, T z, T* Y) {
   Y[0] = cst<T>(SH_C0);
-  if (deg < 1) return;
+  if (DEG < 1) return;
   Y[1] = (-SH_C1) * y;
   Y[2] = SH_C1 * z;
   Y[3] = (-SH_C1) * x;
-  if (deg < 2) return;
+  if (DEG < 2) return;
   const T xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
   Y[4] = kSH2[0] * xy;
   Y[5] = kSH2[1] * yz;
   Y[6] = kSH2[2] * ((2.f * zz - xx) - yy);
   Y[7] = kSH2[3] * xz;
   Y[8] = kSH2[4] * (xx - yy);
-  if (deg < 3) return;
+  if (DEG < 3) return;
   Y[9] = kSH3[0] * y * (3.f * xx - yy);
   Y[10] = kSH3[1] * xy * z;
   Y[11] = kSH3[2] * y * ((4.f * zz - xx) - yy);
@@ -179,22 +184,26 @@ __device__ __forceinline__ void sh_basis(T x, T y, T z, int deg, T* Y) {
 
 // RGB = sum_k Y_k(dir) f_k + 0.5, clamped at 0; raw_pos[c] tells whether the
 // clamp is inactive (its derivative is then 1).
-template <class T, class Src>
-__device__ __forceinline__ void colour(const Src& src, const CamDev& cam, int deg, T rgb[3], bool raw_pos[3],
+template <class T, int DEG, class Src>
+__device__ __forceinline__ void colour(const Src& src, const CamDev& cam, T rgb[3], bool raw_pos[3],
                                        float* Yout = nullptr) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
   const T dx = src(0) - cam.campos[0], dy = src(1) - cam.campos[1], dz = src(2) - cam.campos[2];
   const T inv = cst<T>(1.f) / sqrt_((dx * dx + dy * dy) + dz * dz);
-  T Y[16];
-  sh_basis<T>(dx * inv, dy * inv, dz * inv, deg, Y);
-  const int K = (deg + 1) * (deg + 1);
+  T Y[K];
+  sh_basis<T, DEG>(dx * inv, dy * inv, dz * inv, Y);
+#pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     T acc = cst<T>(0.5f);
+#pragma unroll
     for (int k = 0; k < K; ++k) acc = acc + Y[k] * src(11 + 3 * k + ch);
     raw_pos[ch] = val(acc) >= 0.f;
     rgb[ch] = max_(acc, 0.f);
   }
-  if (Yout)
+  if (Yout) {
+#pragma unroll
     for (int k = 0; k < K; ++k) Yout[k] = val(Y[k]);
+  }
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t v) {
@@ -213,15 +222,17 @@ __device__ __forceinline__ float probe_sign(uint64_t inner, uint64_t k) {
 __device__ __forceinline__ float opacity_of(float logit) { return (float)(1.0 / (1.0 + exp(-(double)logit))); }
 __device__ __forceinline__ float skip_threshold(float op) { return (float)(-log(255.0 * (double)op)); }
 
-__global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x, int64_t n, int deg, CamDev cam,
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       Rec* __restrict__ rec, uint2* __restrict__ rect,
                                                       uint32_t* __restrict__ depth_key,
                                                       uint32_t* __restrict__ tiles) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   auto src = [&](int r) { return x[(int64_t)r * n + g]; };
+  const float sv[3] = {exp_ls(src(3)), exp_ls(src(4)), exp_ls(src(5))};
   Proj<float> p;
-  project_geo<float>(src, cam, p);
+  project_geo<float>(src, sv, cam, p);
   const float inv = 0.0625f;
   const float txf = (float)cam.tiles_x, tyf = (float)cam.tiles_y;
   const float x0 = fminf(fmaxf(floorf((p.u - p.radius) * inv), 0.f), txf);
@@ -239,7 +250,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
   }
   float rgb[3];
   bool pos[3];
-  colour<float>(src, cam, deg, rgb, pos);
+  colour<float, DEG>(src, cam, rgb, pos);
   const float op = opacity_of(src(10));
   Rec r;
   r.a = make_float4(p.u, p.v, p.ca, p.cb);
@@ -251,7 +262,8 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
   tiles[g] = (uint32_t)touched;
 }
 
-__global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x, int64_t n, int deg, CamDev cam,
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
                                                       int kind, uint64_t inner, const float* __restrict__ tangent,
                                                       TRec* __restrict__ trec) {
@@ -263,11 +275,12 @@ __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x
     float t = kind == PROBE_HASH ? probe_sign(inner, (uint64_t)k) : tangent[k];
     return Dual{x[k], t};
   };
+  const float sv[3] = {exp_ls(x[3 * n + g]), exp_ls(x[4 * n + g]), exp_ls(x[5 * n + g])};
   Proj<Dual> p;
-  project_geo<Dual>(src, cam, p);
+  project_geo<Dual>(src, sv, cam, p);
   Dual rgb[3];
   bool pos[3];
-  colour<Dual>(src, cam, deg, rgb, pos);
+  colour<Dual, DEG>(src, cam, rgb, pos);
   const Dual op = sigmoid_(src(10));
   TRec t;
   t.a = make_float4(p.u.t, p.v.t, p.ca.t, p.cb.t);
@@ -276,13 +289,15 @@ __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x
   trec[g] = t;
 }
 
-__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, int deg, CamDev cam,
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
                                                       const float* __restrict__ partials, int mode, int accumulate,
                                                       uint64_t inner, float scale, float* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  const int P = 11 + 3 * (deg + 1) * (deg + 1);
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr int P = 11 + 3 * K;
   const uint32_t cnt = tiles[g];
   auto emit = [&](int r, float v) {
     const int64_t k = (int64_t)r * n + g;
@@ -293,8 +308,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
     }
   };
   if (cnt == 0u) {
-    if (mode == 0 && !accumulate)
+    if (mode == 0 && !accumulate) {
+#pragma unroll
       for (int r = 0; r < P; ++r) out[(int64_t)r * n + g] = 0.f;
+    }
     return;
   }
   // sum the per-(Gaussian, tile) partials: contiguous slots [off, off + cnt)
@@ -306,15 +323,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
     for (int k = 0; k < 9; ++k) G[k] += pp[k];
   }
   // geometric rows: one forward-mode sweep each
+  const float sv[3] = {exp_ls(x[3 * n + g]), exp_ls(x[4 * n + g]), exp_ls(x[5 * n + g])};
   for (int k = 0; k < 10; ++k) {
     auto src = [&](int r) { return Dual{x[(int64_t)r * n + g], r == k ? 1.f : 0.f}; };
     Proj<Dual> p;
-    project_geo<Dual>(src, cam, p);
+    project_geo<Dual>(src, sv, cam, p);
     float d = G[0] * p.u.t + G[1] * p.v.t + G[2] * p.ca.t + G[3] * p.cb.t + G[4] * p.cc.t;
     if (k < 3) {
       Dual rgb[3];
       bool pos[3];
-      colour<Dual>(src, cam, deg, rgb, pos);
+      colour<Dual, DEG>(src, cam, rgb, pos);
       d += G[6] * rgb[0].t + G[7] * rgb[1].t + G[8] * rgb[2].t;
     }
     emit(k, d);
@@ -324,11 +342,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
   emit(10, G[5] * s * (1.f - s));
   // SH rows: d rgb_c / d f_kc = Y_k(dir) where the clamp is inactive
   auto srcf = [&](int r) { return x[(int64_t)r * n + g]; };
-  float rgb[3], Y[16];
+  float rgb[3], Y[K];
   bool pos[3];
-  colour<float>(srcf, cam, deg, rgb, pos, Y);
-  const int K = (deg + 1) * (deg + 1);
+  colour<float, DEG>(srcf, cam, rgb, pos, Y);
+#pragma unroll
   for (int k = 0; k < K; ++k)
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) emit(11 + 3 * k + ch, pos[ch] ? Y[k] * G[6 + ch] : 0.f);
 }
 
@@ -343,22 +362,30 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
+#define GS3_DEG_DISPATCH(deg, KERNEL, ...)                                                        \
+  switch (deg) {                                                                                  \
+    case 0: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;                                    \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                                    \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                                    \
+    default: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                                   \
+  }
+
 void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, Rec* rec, uint2* rect,
                         uint32_t* depth_key, uint32_t* tiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_project_fwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, deg, cam, rec, rect, depth_key,
-                     tiles);
+  GS3_DEG_DISPATCH(deg, k_project_fwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, rec, rect, depth_key,
+                   tiles);
 }
 
 void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
                         const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
                         const float* tangent, TRec* trec, hipStream_t st) {
-  hipLaunchKernelGGL(k_project_jvp, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, deg, cam, rec, tiles,
-                     probe_kind, probe_inner(seed, probe_index), tangent, trec);
+  GS3_DEG_DISPATCH(deg, k_project_jvp, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, rec, tiles, probe_kind,
+                   probe_inner(seed, probe_index), tangent, trec);
 }
 
 void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
                         const uint32_t* tiles, const float* partials, int mode, int accumulate, uint64_t seed,
                         uint32_t probe_index, float scale, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_project_bwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, deg, cam, rec, tiles,
-                     partials, mode, accumulate, probe_inner(seed, probe_index), scale, out);
+  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, rec, tiles, partials,
+                   mode, accumulate, probe_inner(seed, probe_index), scale, out);
 }
