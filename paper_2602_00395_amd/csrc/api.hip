@@ -125,6 +125,8 @@ struct gs3_scene {
   float* partials = nullptr;
   // per-view image scratch
   uint2* ranges = nullptr;
+  uint32_t* tile_order = nullptr;
+  bool have_order = false;
   float *img = nullptr, *cot = nullptr, *tan_img = nullptr, *ssim_tmp = nullptr;
   double *dpart = nullptr, *dsum = nullptr;
   uint32_t* host_u32 = nullptr;
@@ -209,6 +211,7 @@ void free_all(gs3_scene* s) {
   dfree(s->pg2);
   dfree(s->partials);
   dfree(s->ranges);
+  dfree(s->tile_order);
   dfree(s->img);
   dfree(s->cot);
   dfree(s->tan_img);
@@ -294,6 +297,7 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   auto p4 = prof::begin("pair_sort", st);
   radix_sort_u32(s->pt, s->pg, s->pt2, s->pg2, n_pairs, bits_for(n_tiles), s->rtmp, st, &tk, &tv);
   launch_tile_ranges(tk, n_pairs, s->ranges, n_tiles, st);
+  s->have_order = launch_tile_order(s->ranges, n_tiles, s->tile_order, st);
   prof::end(p4, st, n_pairs, bits_for(n_tiles));
   GS3_LAUNCHED();
   s->sorted_gid = tv;
@@ -312,19 +316,22 @@ const float* target_of(gs3_scene* s, int cam) { return s->targets + s->tgt_off[c
 
 void blend_fwd(gs3_scene* s, const CamDev& cd, float* out, hipStream_t st) {
   auto p = prof::begin("blend_fwd", st, true);
-  launch_blend_fwd(s->rec, s->sorted_gid, s->ranges, cd, s->bg, out, st, p.c);
+  launch_blend_fwd(s->rec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg, out, st,
+                   p.c);
   prof::end(p, st);
 }
 
 void blend_jvp(gs3_scene* s, const CamDev& cd, float* out, float* tan, hipStream_t st) {
   auto p = prof::begin("blend_jvp", st, true);
-  launch_blend_jvp(s->rec, s->trec, s->sorted_gid, s->ranges, cd, s->bg, out, tan, st, p.c);
+  launch_blend_jvp(s->rec, s->trec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg,
+                   out, tan, st, p.c);
   prof::end(p, st);
 }
 
 void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st) {
   auto p = prof::begin("blend_bwd", st, true);
-  launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, cd, s->img, cot, s->partials, st, p.c);
+  launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->img,
+                   cot, s->partials, st, p.c);
   prof::end(p, st);
 }
 
@@ -445,6 +452,7 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
   step(dalloc(&s->total_dev, 4));
   step(dalloc((char**)&s->stmp, scan_temp_bytes(s->N)));
   step(dalloc(&s->ranges, s->max_tiles));
+  step(dalloc(&s->tile_order, s->max_tiles));
   step(dalloc(&s->img, s->max_px * 3));
   step(dalloc(&s->cot, s->max_px * 3));
   step(dalloc(&s->tan_img, s->max_px * 3));

@@ -13,24 +13,29 @@
 // of the splat record, not a side effect of exp's rounding.
 //
 // Layout: one 256-thread workgroup per 16x16 tile, one pixel per thread;
-// records of 256 splats are staged in LDS per batch and every pixel walks the
-// batch.  Workgroups are mapped so that each of the 8 XCDs receives a
-// contiguous band of tiles (neighbouring tiles share splats, and each XCD has
-// its own L2).
+// records of a batch of splats are staged in LDS and every pixel walks the
+// batch.  Workgroups take tiles longest list first (a pixel's walk is serial,
+// so the tiles with the longest lists bound the kernel unless they start
+// early); without that order each of the 8 XCDs gets a contiguous band of
+// tiles (neighbouring tiles share splats, and each XCD has its own L2).
 //
 // The backward pass runs front to back as well, recomputing T exactly as the
 // forward did (so the stop decision repeats bit for bit without storing any
 // per-pixel state) and obtaining the weight of the splats behind splat i from
 // the stored output: sum_{j>i} c_j abar_j T_j + T_final bg = C_out - S_i,
 // S_i the running front-to-back sum.  Gradients of each (splat, tile) pair are
-// reduced over the workgroup (wave64 DPP row shifts and broadcasts, then the
-// four waves in LDS in a fixed order) and written to the pair's own slot: no
-// float atomics, so the backward is deterministic.
+// reduced over the workgroup (a transposed wave64 reduction with permlane
+// swaps and DPP row scans, then the four waves in LDS in a fixed order) and
+// written to the pair's own slot: no float atomics, so the backward is
+// deterministic.
 #include "gs3_internal.h"
 
 namespace {
 
-__device__ __forceinline__ int tile_of_block(int b, int n_tiles, int chunk) {
+// Tile of workgroup b: the longest-list-first order when given, else each of
+// the 8 XCDs (which receive workgroups round robin) gets a contiguous band.
+__device__ __forceinline__ int tile_of_block(int b, const uint32_t* order, int n_tiles, int chunk) {
+  if (order) return b < n_tiles ? (int)order[b] : n_tiles;
   return (b & 7) * chunk + (b >> 3);
 }
 
@@ -64,10 +69,11 @@ struct Stage {
 
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__ rec,
                                                           const uint32_t* __restrict__ pair_gid,
-                                                          const uint2* __restrict__ ranges, CamDev cam, float bg0,
+                                                          const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ order, CamDev cam, float bg0,
                                                           float bg1, float bg2, float* __restrict__ img, int n_tiles,
                                                           int chunk, unsigned long long* __restrict__ ctr) {
-  const int t = tile_of_block(blockIdx.x, n_tiles, chunk);
+  const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ Stage s;
   uint32_t nev = 0, ncon = 0;
@@ -134,11 +140,12 @@ struct StageJ {
 
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__ rec, const TRec* __restrict__ trec,
                                                           const uint32_t* __restrict__ pair_gid,
-                                                          const uint2* __restrict__ ranges, CamDev cam, float bg0,
+                                                          const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ order, CamDev cam, float bg0,
                                                           float bg1, float bg2, float* __restrict__ img,
                                                           float* __restrict__ tan_img, int n_tiles, int chunk,
                                                           unsigned long long* __restrict__ ctr) {
-  const int t = tile_of_block(blockIdx.x, n_tiles, chunk);
+  const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ StageJ s;
   uint32_t nev = 0, ncon = 0;
@@ -236,12 +243,36 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
   return v;
 }
 
+// Transposed reduction helpers (gfx950 permlane swaps).  fold32(a, b): lane
+// i < 32 gets a[i] + a[i+32], lane i >= 32 gets b[i-32] + b[i].  fold16(a, b):
+// with rows of 16 lanes, row pairs (0,1) and (2,3) are summed and the result
+// rows are [a01, b01, a23, b23].
+__device__ __forceinline__ float fold32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float fold16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// Inclusive scan within each 16-lane row: lane 15 of a row holds the row sum.
+__device__ __forceinline__ float row_sum_lane15(float v) {
+  v += dpp_move<0x111>(v);
+  v += dpp_move<0x112>(v);
+  v += dpp_move<0x114>(v);
+  v += dpp_move<0x118>(v);
+  return v;
+}
+
+// The backward stages 128 splats per batch: with the per-wave partial sums
+// this keeps the workgroup at ~24 KB of LDS (six workgroups per CU).
+constexpr int kBwdBatch = 128;
 struct StageB {
-  float4 a[GS3_BLOCK];
-  float4 b[GS3_BLOCK];
-  float2 c[GS3_BLOCK];  // b, tau
-  uint32_t slot[GS3_BLOCK];
-  float red[4][9][GS3_BLOCK];
+  float4 a[kBwdBatch];
+  float4 b[kBwdBatch];
+  float2 c[kBwdBatch];  // b, tau
+  uint32_t slot[kBwdBatch];
+  float red[4][9][kBwdBatch];
 };
 
 // Slot of the (Gaussian, tile) pair in the Gaussian-contiguous partials
@@ -255,11 +286,12 @@ __device__ __forceinline__ uint32_t pair_slot(uint32_t pair_off, uint2 rc, int t
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__ rec,
                                                           const uint2* __restrict__ rect,
                                                           const uint32_t* __restrict__ pair_gid,
-                                                          const uint2* __restrict__ ranges, CamDev cam,
+                                                          const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ order, CamDev cam,
                                                           const float* __restrict__ img, const float* __restrict__ cot,
                                                           float* __restrict__ partials, int n_tiles, int chunk,
                                                           unsigned long long* __restrict__ ctr) {
-  const int t = tile_of_block(blockIdx.x, n_tiles, chunk);
+  const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ StageB s;
   uint32_t nev = 0, ncon = 0;
@@ -283,10 +315,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   float T = 1.f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
   bool done = !inside;
   uint32_t start = range.x;
-  for (; start < range.y; start += GS3_BLOCK) {
+  for (; start < range.y; start += kBwdBatch) {
     if (__syncthreads_count(done) == GS3_BLOCK) break;
     const uint32_t i = start + tid;
-    if (i < range.y) {
+    if (tid < kBwdBatch && i < range.y) {
       const uint32_t g = pair_gid[i];
       const Rec r = rec[g];
       s.a[tid] = r.a;
@@ -295,7 +327,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
       s.slot[tid] = pair_slot(__float_as_uint(r.c.z), rect[g], tx, ty);
     }
     __syncthreads();
-    const int cnt = min((int)(range.y - start), GS3_BLOCK);
+    const int cnt = min((int)(range.y - start), kBwdBatch);
     for (int j = 0; j < cnt; ++j) {
       float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool contrib = false;
@@ -340,13 +372,22 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           }
         }
       }
+      // wave sums of the 9 partial derivatives: values 0-7 are folded in
+      // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
+      // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
+      // DPP reduction into lane 63.  26 VALU instructions in all.
+      float E = 0.f, F = 0.f, H = 0.f;
       if (__ballot(contrib) != 0ull) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) gr[k] = wave_sum_lane63(gr[k]);
+        E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
+        F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
+        H = wave_sum_lane63(gr[8]);
       }
-      if (lane == 63) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) s.red[w][k][j] = gr[k];
+      if ((lane & 15) == 15) {
+        const int row = lane >> 4;
+        const int k = (row & 1) * 2 + (row >> 1);
+        s.red[w][k][j] = E;
+        s.red[w][4 + k][j] = F;
+        if (lane == 63) s.red[w][8][j] = H;
       }
     }
     __syncthreads();
@@ -371,25 +412,25 @@ inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }
 
 }  // namespace
 
-void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const CamDev& cam,
-                      const float* bg, float* img, hipStream_t st, unsigned long long* ctr) {
+void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
+                      const CamDev& cam, const float* bg, float* img, hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
-  hipLaunchKernelGGL(k_blend_fwd, dim3(8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, cam, bg[0], bg[1],
-                     bg[2], img, nt, ch, ctr);
+  hipLaunchKernelGGL(k_blend_fwd, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, order,
+                     cam, bg[0], bg[1], bg[2], img, nt, ch, ctr);
 }
 
 void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
-                      const CamDev& cam, const float* bg, float* img, float* tan_img, hipStream_t st,
-                      unsigned long long* ctr) {
+                      const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
+                      hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
-  hipLaunchKernelGGL(k_blend_jvp, dim3(8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges, cam, bg[0],
-                     bg[1], bg[2], img, tan_img, nt, ch, ctr);
+  hipLaunchKernelGGL(k_blend_jvp, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges,
+                     order, cam, bg[0], bg[1], bg[2], img, tan_img, nt, ch, ctr);
 }
 
 void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const CamDev& cam, const float* img, const float* cot, float* partials, hipStream_t st,
-                      unsigned long long* ctr) {
+                      const uint32_t* order, const CamDev& cam, const float* img, const float* cot,
+                      float* partials, hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
-  hipLaunchKernelGGL(k_blend_bwd, dim3(8 * ch), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges, cam, img, cot,
-                     partials, nt, ch, ctr);
+  hipLaunchKernelGGL(k_blend_bwd, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges,
+                     order, cam, img, cot, partials, nt, ch, ctr);
 }

@@ -77,20 +77,26 @@ void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Re
                        const uint32_t* tiles, int64_t n, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
                        hipStream_t st);
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st);
+// Tile ids in descending order of their pair count (false: too many tiles,
+// the blends then use the XCD-banded order).
+bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, hipStream_t st);
 void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const uint32_t* depth_key,
                       int64_t n_pairs, uint64_t* keys, hipStream_t st);
 
 // blending
-// ctr (nullable): two u64 counters receiving the number of (pixel, splat)
-// evaluations and of contributing evaluations (measurement only).
-void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const CamDev& cam,
-                      const float* bg, float* img, hipStream_t st, unsigned long long* ctr = nullptr);
+// order (nullable): tile processed by workgroup b is order[b] (longest list
+// first); NULL = XCD-banded order.  ctr (nullable): two u64 counters
+// receiving the number of (pixel, splat) evaluations and of contributing
+// evaluations (measurement only).
+void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
+                      const CamDev& cam, const float* bg, float* img, hipStream_t st,
+                      unsigned long long* ctr = nullptr);
 void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
-                      const CamDev& cam, const float* bg, float* img, float* tan_img, hipStream_t st,
-                      unsigned long long* ctr = nullptr);
+                      const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
+                      hipStream_t st, unsigned long long* ctr = nullptr);
 void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const CamDev& cam, const float* img, const float* cot, float* partials, hipStream_t st,
-                      unsigned long long* ctr = nullptr);
+                      const uint32_t* order, const CamDev& cam, const float* img, const float* cot,
+                      float* partials, hipStream_t st, unsigned long long* ctr = nullptr);
 
 // loss
 // cot = scale * d(sum_k l_k)/dC; optional per-block loss partial sums (double).

@@ -232,6 +232,46 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
   if (i == n - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
+// Longest-list-first schedule of the tiles: one 1024-thread workgroup sorts
+// 64-bit keys (inverted pair count, tile id) in LDS with a bitonic network and
+// writes the tile ids in descending order of their pair count (ties by tile
+// id).  Blend workgroups take tiles in this order, so the tiles
+// with the longest serial lists start first instead of forming the tail.
+constexpr int kLptMax = 8192;
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, int n_tiles,
+                                                      uint32_t* __restrict__ order) {
+  __shared__ uint64_t key[kLptMax];
+  int n2 = 1;
+  while (n2 < n_tiles) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    if (i < n_tiles) {
+      const uint2 r = ranges[i];
+      // descending count, then ascending tile id
+      key[i] = ((uint64_t)(0xffffffffu - (r.y - r.x)) << 32) | (uint32_t)i;
+    } else {
+      key[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int p = i ^ j;
+        if (p > i) {
+          const uint64_t a = key[i], b = key[p];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            key[i] = b;
+            key[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) order[i] = (uint32_t)(key[i] & 0xffffffffu);
+}
+
 __global__ __launch_bounds__(256) void k_make_keys(const uint32_t* __restrict__ tile, const uint32_t* __restrict__ gid,
                                                     const uint32_t* __restrict__ depth_key, int64_t n,
                                                     uint64_t* __restrict__ keys) {
@@ -324,6 +364,12 @@ void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const
   if (n_pairs > 0)
     hipLaunchKernelGGL(k_make_keys, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, pair_tile, pair_gid, depth_key,
                        n_pairs, keys);
+}
+
+bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, hipStream_t st) {
+  if (n_tiles > kLptMax || n_tiles < 1) return false;
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, n_tiles, order);
+  return true;
 }
 
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
