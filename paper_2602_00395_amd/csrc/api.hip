@@ -290,7 +290,7 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   const int64_t n_pairs = s->host_u32[0];
   GS3_TRY(ensure_pairs(s, n_pairs));
   auto p3 = prof::begin("emit_pairs", st);
-  launch_emit_pairs(order, s->offsets, s->rec, s->rect, s->tiles, N, cd.tiles_x, s->pt, s->pg, st);
+  launch_emit_pairs(order, s->offsets, s->rec, s->rect, N, n_pairs, cd.tiles_x, s->pt, s->pg, st);
   prof::end(p3, st, N, n_pairs);
   const int n_tiles = cd.tiles_x * cd.tiles_y;
   uint32_t *tk, *tv;

@@ -55,10 +55,12 @@ __device__ __forceinline__ void count_evals(unsigned long long* ctr, uint32_t ne
   }
 }
 
-// -1/2 d^T conic d in float32, rounded exactly as written.
-__device__ __forceinline__ float splat_power(float ca, float cb, float cc, float dx, float dy) {
+// -1/2 d^T conic d in float32 from the pre-scaled conic (qa, qb, qc) =
+// (-a/2, -b, -c/2), rounded exactly as written: equal bit for bit to
+// -1/2 ((a dx) dx + (c dy) dy) - (b dx) dy.
+__device__ __forceinline__ float splat_power(float qa, float qb, float qc, float dx, float dy) {
 #pragma clang fp contract(off)
-  return -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy;
+  return ((qa * dx) * dx + (qc * dy) * dy) + (qb * dx) * dy;
 }
 
 struct Stage {
@@ -192,9 +194,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
         }
         ++ncon;
         const float4 TA = s.ta[j], TB = s.tb[j];
-        // d power along the tangent: d = (u - px, v - py), dd = (du, dv)
-        const float dpow = -(A.z * dx * TA.x + B.x * dy * TA.y) - 0.5f * (TA.z * dx * dx + TB.x * dy * dy) -
-                           A.w * (TA.x * dy + dx * TA.y) - TA.w * dx * dy;
+        // d power along the tangent: d = (u - px, v - py), dd = (du, dv); the
+        // record holds the pre-scaled conic, the tangent record the plain one
+        const float dpow = 2.f * (A.z * dx * TA.x + B.x * dy * TA.y) + A.w * (TA.x * dy + dx * TA.y) -
+                           0.5f * (TA.z * dx * dx + TB.x * dy * dy) - TA.w * dx * dy;
         const float da = araw > GS3_ALPHA_MAX ? 0.f : (TB.y * G + B.y * G * dpow);
         const float w = a * T;
         const float dw = da * T + a * dT;
@@ -356,8 +359,8 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
               const bool clamped = araw > GS3_ALPHA_MAX;
               const float dL_dG = clamped ? 0.f : B.y * dL_da;
               const float dL_dpow = dL_dG * G;
-              gr[0] = dL_dpow * (-(A.z * dx + A.w * dy));
-              gr[1] = dL_dpow * (-(B.x * dy + A.w * dx));
+              gr[0] = dL_dpow * (2.f * A.z * dx + A.w * dy);
+              gr[1] = dL_dpow * (2.f * B.x * dy + A.w * dx);
               gr[2] = dL_dpow * (-0.5f * dx * dx);
               gr[3] = dL_dpow * (-dx * dy);
               gr[4] = dL_dpow * (-0.5f * dy * dy);

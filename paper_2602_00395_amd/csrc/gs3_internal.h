@@ -30,7 +30,11 @@ struct CamDev {
 };
 
 // Per-Gaussian screen-space record, 12 words (three float4):
-//   {u, v, conic_a, conic_b}, {conic_c, opacity, r, g}, {b, tau, pair_off, 0}
+//   {u, v, qa, qb}, {qc, opacity, r, g}, {b, tau, pair_off, 0}
+// with the conic stored pre-scaled, qa = -a/2, qb = -b, qc = -c/2, so that
+// power = (qa dx) dx + (qc dy) dy + (qb dx) dy -- bit for bit the float32
+// value of -1/2 ((a dx) dx + (c dy) dy) - (b dx) dy, since scaling by powers of
+// two commutes with rounding.
 // tau = float32(-ln(255 opacity)): a splat is skipped at a pixel where its
 // float32 power is below tau (equivalently opacity exp(power) < 1/255).
 // The tile rectangle lives in a separate uint2 array:
@@ -74,11 +78,10 @@ void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t 
 void launch_iota(uint32_t* v, int64_t n, hipStream_t st);
 // writes each visible Gaussian's pair offset into its record (rec.c.w)
 void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Rec* rec, const uint2* rect,
-                       const uint32_t* tiles, int64_t n, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
+                       int64_t n, int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
                        hipStream_t st);
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st);
-// Tile ids in descending order of their pair count (false: too many tiles,
-// the blends then use the XCD-banded order).
+// Tile ids in (approximately) descending order of their pair count.
 bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, hipStream_t st);
 void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const uint32_t* depth_key,
                       int64_t n_pairs, uint64_t* keys, hipStream_t st);

@@ -41,13 +41,16 @@ __device__ __forceinline__ double block_sum_d(double v) {
 }
 
 // Gradient (GN = false) or Gauss-Newton (GN = true) coefficient maps of the
-// SSIM term, and (gradient mode) per-block loss sums.
+// SSIM term, and (gradient mode) per-block loss sums.  The 26x26 halo region
+// of all three channels is loaded in one pass (each region row is 78
+// consecutive floats); coefficient maps are stored planar, map m of channel c
+// at coef[(3 m + c) npix + pixel], so the combine pass reads whole rows.
 template <bool GN>
 __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict__ img, const float* __restrict__ tgt,
                                                           const float* __restrict__ u, int W, int H, float lam,
                                                           float scale, Win win, float* __restrict__ coef,
                                                           double* __restrict__ loss_partials) {
-  __shared__ float sx[HW][HW + 1], sy[HW][HW + 1], su[GN ? HW : 1][HW + 1];
+  __shared__ float sx[3][HW][HW + 1], sy[3][HW][HW + 1], su[GN ? 3 : 1][GN ? HW : 1][HW + 1];
   constexpr int NM = GN ? 8 : 5;
   __shared__ float hb[NM][HW][GS3_TILE];
   const int tid = threadIdx.x;
@@ -56,18 +59,19 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict
   const int px = blockIdx.x * GS3_TILE + j, py = blockIdx.y * GS3_TILE + i;
   const bool inside = px < W && py < H;
   const int64_t npix = (int64_t)W * H;
+  for (int e = tid; e < HW * HW * 3; e += GS3_BLOCK) {
+    const int r = e / (HW * 3), q = e % (HW * 3);
+    const int qq = q / 3, c = q % 3;
+    const int gx = ox + qq, gy = oy + r;
+    const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
+    const int64_t o = ((int64_t)gy * W + gx) * 3 + c;
+    sx[c][r][qq] = ok ? img[o] : 0.f;
+    sy[c][r][qq] = ok ? tgt[o] : 0.f;
+    if (GN) su[c][r][qq] = ok ? u[o] : 0.f;
+  }
+  __syncthreads();
   double lsum = 0.0;
   for (int c = 0; c < 3; ++c) {
-    for (int e = tid; e < HW * HW; e += GS3_BLOCK) {
-      const int r = e / HW, q = e % HW;
-      const int gx = ox + q, gy = oy + r;
-      const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
-      const int64_t o = ((int64_t)gy * W + gx) * 3 + c;
-      sx[r][q] = ok ? img[o] : 0.f;
-      sy[r][q] = ok ? tgt[o] : 0.f;
-      if (GN) su[r][q] = ok ? u[o] : 0.f;
-    }
-    __syncthreads();
     for (int e = tid; e < HW * GS3_TILE; e += GS3_BLOCK) {
       const int r = e / GS3_TILE, q = e % GS3_TILE;
       float m[NM];
@@ -75,14 +79,14 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict
       for (int k = 0; k < NM; ++k) m[k] = 0.f;
 #pragma unroll
       for (int k = 0; k < 11; ++k) {
-        const float xv = sx[r][q + k], yv = sy[r][q + k], wk = win.w[k];
+        const float xv = sx[c][r][q + k], yv = sy[c][r][q + k], wk = win.w[k];
         m[0] += wk * xv;
         m[1] += wk * yv;
         m[2] += wk * (xv * xv);
         m[3] += wk * (yv * yv);
         m[4] += wk * (xv * yv);
         if (GN) {
-          const float uv = su[r][q + k];
+          const float uv = su[c][r][q + k];
           m[5] += wk * uv;
           m[6] += wk * (2.f * xv * uv);
           m[7] += wk * (yv * uv);
@@ -118,15 +122,15 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict
     } else {
       wgt = -lam * scale;
       if (inside) {
-        const float xv = sx[i + R][j + R], yv = sy[i + R][j + R];
+        const float xv = sx[c][i + R][j + R], yv = sy[c][i + R][j + R];
         lsum += (double)((1.f - lam) * fabsf(xv - yv)) + (double)(lam * (1.f - S));
       }
     }
     if (inside) {
-      const int64_t o = ((int64_t)py * W + px) * 3 + c;
-      coef[o] = wgt * dS_dA;
-      coef[npix * 3 + o] = wgt * dS_dXX;
-      coef[2 * npix * 3 + o] = wgt * dS_dXY;
+      const int64_t o = (int64_t)py * W + px;
+      coef[(0 * 3 + c) * npix + o] = wgt * dS_dA;
+      coef[(1 * 3 + c) * npix + o] = wgt * dS_dXX;
+      coef[(2 * 3 + c) * npix + o] = wgt * dS_dXY;
     }
     __syncthreads();
   }
@@ -151,14 +155,24 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_combine(const float* __restr
   const int px = blockIdx.x * GS3_TILE + j, py = blockIdx.y * GS3_TILE + i;
   const bool inside = px < W && py < H;
   const int64_t npix = (int64_t)W * H;
+  const int64_t o3 = ((int64_t)py * W + px) * 3;
+  float xv[3] = {0.f, 0.f, 0.f}, yv[3] = {0.f, 0.f, 0.f}, uv[3] = {0.f, 0.f, 0.f}, out[3];
+  if (inside) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xv[c] = img[o3 + c];
+      yv[c] = tgt[o3 + c];
+      if (GN) uv[c] = u[o3 + c];
+    }
+  }
   for (int c = 0; c < 3; ++c) {
     for (int e = tid; e < HW * HW; e += GS3_BLOCK) {
       const int r = e / HW, q = e % HW;
       const int gx = ox + q, gy = oy + r;
       const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
-      const int64_t o = ((int64_t)gy * W + gx) * 3 + c;
+      const int64_t o = (int64_t)gy * W + gx;
 #pragma unroll
-      for (int m = 0; m < 3; ++m) sc[m][r][q] = ok ? coef[m * npix * 3 + o] : 0.f;
+      for (int m = 0; m < 3; ++m) sc[m][r][q] = ok ? coef[(m * 3 + c) * npix + o] : 0.f;
     }
     __syncthreads();
     for (int e = tid; e < HW * GS3_TILE; e += GS3_BLOCK) {
@@ -179,21 +193,21 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_combine(const float* __restr
       bXX += win.w[k] * hb[1][i + k][j];
       bXY += win.w[k] * hb[2][i + k][j];
     }
-    if (inside) {
-      const int64_t o = ((int64_t)py * W + px) * 3 + c;
-      const float xv = img[o], yv = tgt[o];
-      const float r = xv - yv, s = sgn(r);
-      float l1term;
-      if (GN) {
-        const float l1 = (1.f - lam) * fabsf(r);
-        const float w1 = (1.f - lam) * s * u[o] / (4.f * fmaxf(l1, GS3_GN_FLOOR));
-        l1term = scale * (1.f - lam) * s * w1;
-      } else {
-        l1term = scale * (1.f - lam) * s;
-      }
-      cot[o] = l1term + (bA + 2.f * xv * bXX + yv * bXY);
+    const float r = xv[c] - yv[c], sg = sgn(r);
+    float l1term;
+    if (GN) {
+      const float l1 = (1.f - lam) * fabsf(r);
+      const float w1 = (1.f - lam) * sg * uv[c] / (4.f * fmaxf(l1, GS3_GN_FLOOR));
+      l1term = scale * (1.f - lam) * sg * w1;
+    } else {
+      l1term = scale * (1.f - lam) * sg;
     }
+    out[c] = l1term + (bA + 2.f * xv[c] * bXX + yv[c] * bXY);
     __syncthreads();
+  }
+  if (inside) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cot[o3 + c] = out[c];
   }
 }
 

@@ -82,13 +82,15 @@ __device__ __forceinline__ float row_radius(const Radius& r, int row) {
 
 __device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
 
+template <int P>
 __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const float* __restrict__ grad,
                                                   float* __restrict__ ghat, float* __restrict__ dhat,
-                                                  const float* __restrict__ D, int64_t n, int P, TrArgs a,
+                                                  const float* __restrict__ D, int64_t n, TrArgs a,
                                                   float* __restrict__ eta_out, float* __restrict__ dx_out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const Radius rad = trust_radius(x, n, g, a.epsilon);
+#pragma unroll 8
   for (int r = 0; r < P; ++r) {
     const int64_t k = (int64_t)r * n + g;
     const float eta = row_radius(rad, r);
@@ -109,14 +111,16 @@ __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const fl
   }
 }
 
+template <int P>
 __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const float* __restrict__ grad,
-                                                    float* __restrict__ m, float* __restrict__ v, int64_t n, int P,
+                                                    float* __restrict__ m, float* __restrict__ v, int64_t n,
                                                     AdamArgs a) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   Radius rad;
   const bool clip = a.epsilon > 0.f;
   if (clip) rad = trust_radius(x, n, g, a.epsilon);
+#pragma unroll 8
   for (int r = 0; r < P; ++r) {
     const int64_t k = (int64_t)r * n + g;
     const float gr = grad[k];
@@ -135,15 +139,21 @@ __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const 
 
 }  // namespace
 
+#define GS3_P_DISPATCH(deg, KERNEL, ...)                   \
+  switch (deg) {                                           \
+    case 0: hipLaunchKernelGGL(KERNEL<14>, __VA_ARGS__); break; \
+    case 1: hipLaunchKernelGGL(KERNEL<23>, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL(KERNEL<38>, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL(KERNEL<59>, __VA_ARGS__); break; \
+  }
+
 void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
                     TrArgs a, float* eta_out, float* dx_out, hipStream_t st) {
-  const int P = 11 + 3 * (deg + 1) * (deg + 1);
-  hipLaunchKernelGGL(k_tr_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, ghat, dhat, D, n, P, a,
-                     eta_out, dx_out);
+  GS3_P_DISPATCH(deg, k_tr_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, ghat, dhat, D, n, a,
+                 eta_out, dx_out);
 }
 
 void launch_adam_step(float* x, const float* grad, float* m, float* v, int64_t n, int deg, const AdamArgs& a,
                       hipStream_t st) {
-  const int P = 11 + 3 * (deg + 1) * (deg + 1);
-  hipLaunchKernelGGL(k_adam_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, m, v, n, P, a);
+  GS3_P_DISPATCH(deg, k_adam_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, m, v, n, a);
 }

@@ -253,8 +253,8 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
   colour<float, DEG>(src, cam, rgb, pos);
   const float op = opacity_of(src(10));
   Rec r;
-  r.a = make_float4(p.u, p.v, p.ca, p.cb);
-  r.b = make_float4(p.cc, op, rgb[0], rgb[1]);
+  r.a = make_float4(p.u, p.v, -0.5f * p.ca, -p.cb);
+  r.b = make_float4(-0.5f * p.cc, op, rgb[0], rgb[1]);
   r.c = make_float4(rgb[2], skip_threshold(op), 0.f, 0.f);
   rec[g] = r;
   rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));

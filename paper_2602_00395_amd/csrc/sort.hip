@@ -201,26 +201,33 @@ __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* __restric
   if (i < n) counts[i] = tiles[order[i]];
 }
 
+// One thread per pair: the owning Gaussian (in depth order) is the last entry
+// whose exclusive offset is <= the pair index (a zero-count entry shares its
+// offset with the next one, so the last such entry is the owner).  Writes are
+// then contiguous across the wave.  The thread of a Gaussian's first pair also
+// records the Gaussian's first pair in its splat record.
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets, Rec* __restrict__ rec,
-                                                     const uint2* __restrict__ rect,
-                                                     const uint32_t* __restrict__ tiles, int64_t n, int tiles_x,
-                                                     uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_gid) {
+                                                     const uint2* __restrict__ rect, int64_t n, int64_t n_pairs,
+                                                     int tiles_x, uint32_t* __restrict__ pair_tile,
+                                                     uint32_t* __restrict__ pair_gid) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t g = order[i];
-  const uint32_t cnt = tiles[g];
-  if (cnt == 0u) return;
-  const uint32_t off = offsets[i];
+  if (i >= n_pairs) return;
+  int64_t lo = 0, hi = n;  // first index with offsets[idx] > i is in (lo, hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (offsets[mid] <= (uint32_t)i) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t g = order[lo];
+  const uint32_t k = (uint32_t)i - offsets[lo];
   const uint2 rc = rect[g];
   const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
   const int w = x1 - x0;
-  rec[g].c.z = __uint_as_float(off);
-  for (uint32_t k = 0; k < cnt; ++k) {
-    const int ty = y0 + (int)k / w, tx = x0 + (int)k % w;
-    pair_tile[off + k] = (uint32_t)(ty * tiles_x + tx);
-    pair_gid[off + k] = g;
-  }
+  const int ty = y0 + (int)k / w, tx = x0 + (int)k % w;
+  pair_tile[i] = (uint32_t)(ty * tiles_x + tx);
+  pair_gid[i] = g;
+  if (k == 0) rec[g].c.z = __uint_as_float((uint32_t)i);
 }
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ tile, int64_t n,
@@ -232,44 +239,38 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
   if (i == n - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
-// Longest-list-first schedule of the tiles: one 1024-thread workgroup sorts
-// 64-bit keys (inverted pair count, tile id) in LDS with a bitonic network and
-// writes the tile ids in descending order of their pair count (ties by tile
-// id).  Blend workgroups take tiles in this order, so the tiles
-// with the longest serial lists start first instead of forming the tail.
-constexpr int kLptMax = 8192;
+// Longest-list-first schedule of the tiles (approximate): one workgroup
+// buckets the tiles by pair count on a quarter-octave scale, scans the bucket
+// sizes from the longest down and scatters the tile ids.  The order inside a
+// bucket is whatever the LDS atomics give -- each tile's result does not
+// depend on when it runs, only the kernel's makespan does.
+constexpr int kOrderBuckets = 128;
+__device__ __forceinline__ int count_bucket(uint32_t c) {
+  return min(kOrderBuckets - 1, (int)(4.f * log2f((float)c + 1.f)));
+}
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, int n_tiles,
                                                       uint32_t* __restrict__ order) {
-  __shared__ uint64_t key[kLptMax];
-  int n2 = 1;
-  while (n2 < n_tiles) n2 <<= 1;
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-    if (i < n_tiles) {
-      const uint2 r = ranges[i];
-      // descending count, then ascending tile id
-      key[i] = ((uint64_t)(0xffffffffu - (r.y - r.x)) << 32) | (uint32_t)i;
-    } else {
-      key[i] = ~0ull;
+  __shared__ uint32_t cursor[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) cursor[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+    const uint2 r = ranges[i];
+    atomicAdd(&cursor[count_bucket(r.y - r.x)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+      const uint32_t c = cursor[b];
+      cursor[b] = run;
+      run += c;
     }
   }
   __syncthreads();
-  for (int k = 2; k <= n2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        const int p = i ^ j;
-        if (p > i) {
-          const uint64_t a = key[i], b = key[p];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            key[i] = b;
-            key[p] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+    const uint2 r = ranges[i];
+    order[atomicAdd(&cursor[count_bucket(r.y - r.x)], 1u)] = (uint32_t)i;
   }
-  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) order[i] = (uint32_t)(key[i] & 0xffffffffu);
 }
 
 __global__ __launch_bounds__(256) void k_make_keys(const uint32_t* __restrict__ tile, const uint32_t* __restrict__ gid,
@@ -345,11 +346,11 @@ void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t 
 }
 
 void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Rec* rec, const uint2* rect,
-                       const uint32_t* tiles, int64_t n, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
+                       int64_t n, int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
                        hipStream_t st) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_emit_pairs, dim3(nblk(n, 256)), dim3(256), 0, st, order, offsets_sorted, rec, rect, tiles, n,
-                       tiles_x, pair_tile, pair_gid);
+  if (n > 0 && n_pairs > 0)
+    hipLaunchKernelGGL(k_emit_pairs, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, order, offsets_sorted, rec, rect, n,
+                       n_pairs, tiles_x, pair_tile, pair_gid);
 }
 
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st) {
@@ -367,7 +368,7 @@ void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const
 }
 
 bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, hipStream_t st) {
-  if (n_tiles > kLptMax || n_tiles < 1) return false;
+  if (n_tiles < 1) return false;
   hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, n_tiles, order);
   return true;
 }
