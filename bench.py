@@ -32,11 +32,12 @@ HBM_PEAK_GBS = 8000.0
 # fp32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock)
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic arithmetic per (pixel, splat) evaluation of the blend kernels,
-# counted from the operations the method requires (add, mul, compare, exp and
-# divide each count 1): every evaluation forms the offset, the quadratic form
-# and the skip test; a contributing one also does the blend (and the JVP /
-# VJP arithmetic).
+# Algorithmic arithmetic of the blend kernels, counted from the operations the
+# method requires (add, mul, compare, exp and divide each count 1) for every
+# contributing (pixel, splat) pair -- the pairs whose blend any implementation
+# must compute: the offset, the quadratic form and the skip test (OPS_EVAL),
+# plus the blend and its JVP / VJP arithmetic.  Evaluations that end in a skip
+# are overhead of the tiling and count for nothing.
 OPS_EVAL = 14
 OPS_CONTRIB = {"blend_fwd": 12, "blend_jvp": 31, "blend_bwd": 47}
 
@@ -61,7 +62,7 @@ def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int) -> dict 
         return None
     sec = st["total_ms"] / 1e3
     if stage in OPS_CONTRIB:
-        ops = OPS_EVAL * st["work0"] + OPS_CONTRIB[stage] * st["work1"]
+        ops = (OPS_EVAL + OPS_CONTRIB[stage]) * st["work1"]
         ach = ops / sec / 1e12
         return dict(bound="alu", achieved=round(ach, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
                     frac=round(ach / ALU_PEAK_TOPS, 4), traffic=None, kernel=stage,

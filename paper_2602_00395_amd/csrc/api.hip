@@ -275,10 +275,8 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   prof::end(p0, st);
   GS3_LAUNCHED();
   auto p1 = prof::begin("depth_sort", st);
-  GS3_HIP(hipMemcpyAsync(s->ka, s->depth_key, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-  launch_iota(s->va, N, st);
   uint32_t *k_sorted, *order;
-  radix_sort_u32(s->ka, s->va, s->kb, s->vb, N, 32, s->rtmp, st, &k_sorted, &order);
+  radix_sort_u32(s->depth_key, nullptr, s->ka, s->va, s->kb, s->vb, N, 32, s->rtmp, st, &k_sorted, &order);
   prof::end(p1, st);
   auto p2 = prof::begin("scan", st);
   launch_gather_counts(order, s->tiles, N, s->counts, st);
@@ -295,7 +293,7 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   const int n_tiles = cd.tiles_x * cd.tiles_y;
   uint32_t *tk, *tv;
   auto p4 = prof::begin("pair_sort", st);
-  radix_sort_u32(s->pt, s->pg, s->pt2, s->pg2, n_pairs, bits_for(n_tiles), s->rtmp, st, &tk, &tv);
+  radix_sort_u32(s->pt, s->pg, s->pt2, s->pg2, s->pt, s->pg, n_pairs, bits_for(n_tiles), s->rtmp, st, &tk, &tv);
   launch_tile_ranges(tk, n_pairs, s->ranges, n_tiles, st);
   s->have_order = launch_tile_order(s->ranges, n_tiles, s->tile_order, st);
   prof::end(p4, st, n_pairs, bits_for(n_tiles));

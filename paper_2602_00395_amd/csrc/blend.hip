@@ -12,9 +12,13 @@
 // decision which splats contribute is then a reproducible float32 function
 // of the splat record, not a side effect of exp's rounding.
 //
-// Layout: one 256-thread workgroup per 16x16 tile, one pixel per thread;
-// records of a batch of splats are staged in LDS and every pixel walks the
-// batch.  Workgroups take tiles longest list first (a pixel's walk is serial,
+// Layout: one 256-thread workgroup per 16x16 tile, one pixel per thread,
+// each wave64 an 8x8 block of the tile; records of a batch of splats are
+// staged in LDS together with, per wave, a bit mask of the splats whose
+// skip test can pass somewhere in its block (a conservative bound on the
+// f32 skip ellipse), and every wave walks only the set bits.  Culled
+// evaluations are exactly the ones the skip test would reject, so the
+// result is the same bit for bit.  Workgroups take tiles longest list first (a pixel's walk is serial,
 // so the tiles with the longest lists bound the kernel unless they start
 // early); without that order each of the 8 XCDs gets a contiguous band of
 // tiles (neighbouring tiles share splats, and each XCD has its own L2).
@@ -63,10 +67,70 @@ __device__ __forceinline__ float splat_power(float qa, float qb, float qc, float
   return ((qa * dx) * dx + (qc * dy) * dy) + (qb * dx) * dy;
 }
 
+
+// Pixel of thread `tid` in tile (tx, ty): wave w = tid / 64 covers the 8x8
+// block (w & 1, w >> 1), lane l its pixel (l & 7, l >> 3).
+__device__ __forceinline__ int pixel_x(int tx, int tid) { return tx * GS3_TILE + ((tid >> 6) & 1) * 8 + (tid & 7); }
+__device__ __forceinline__ int pixel_y(int ty, int tid) { return ty * GS3_TILE + (tid >> 7) * 8 + ((tid >> 3) & 7); }
+
+// Which of the four 8x8 blocks of tile (tx, ty) may hold a pixel whose skip
+// test passes for the splat (u, v, pre-scaled conic qa, qb, qc, threshold
+// tau); bit b for block b.  With the plain conic Q = (a, b; b, c) =
+// (-2 qa, -qb; -qb, -2 qc), the test asks p >= tau for the float32 power p of
+// -1/2 d^T Q d, so it can pass only where d^T Q d <= k (1 + r) with k = -2 tau
+// and r the relative rounding error of p: with rho^2 = b^2 / (a c), r is at
+// most 4 u (1 + rho) / (1 - rho), below 1e-3 for rho^2 <= 0.999 (u = 2^-24).
+// The bounding box of d^T Q d <= 1.002 k has half-widths
+// sqrt(1.002 k c / det Q) and sqrt(1.002 k a / det Q); it is formed in double
+// (det Q of the float32 entries is then exact up to one rounding) and widened
+// by 1e-3 px.  Splats with rho^2 > 0.999 or non-finite entries are never
+// culled; tau > 0 passes nowhere.
+__device__ __forceinline__ uint32_t block_mask(float4 A, float4 B, float tau, int tx, int ty) {
+  if (tau > 0.f) return 0u;
+  const double a = -2.0 * (double)A.z, b = -(double)A.w, c = -2.0 * (double)B.x;
+  const double det = a * c - b * b;
+  if (!(a > 0.0 && c > 0.0 && det * 1000.0 >= a * c && det < INFINITY)) return 0xfu;
+  const double k = -2.004 * (double)tau;
+  const double ex = sqrt(k * c / det) + 1e-3, ey = sqrt(k * a / det) + 1e-3;
+  const double u = A.x, v = A.y;
+  const double x0 = tx * GS3_TILE + 0.5, y0 = ty * GS3_TILE + 0.5;
+  uint32_t m = 0u;
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const double bx = x0 + 8 * (blk & 1), by = y0 + 8 * (blk >> 1);
+    const bool hit = u + ex >= bx && u - ex <= bx + 7.0 && v + ey >= by && v - ey <= by + 7.0;
+    m |= hit ? (1u << blk) : 0u;
+  }
+  return m;
+}
+
+// Publish the block masks of the splats staged by this wave (one splat per
+// lane, `m` = 0 for empty slots): bits[b][wave] gets bit l for lane l.  Every
+// lane of the wave must call it.
+template <int NW>
+__device__ __forceinline__ void publish_masks(uint64_t (*bits)[NW], uint32_t m, int tid) {
+  const uint64_t b0 = __ballot(m & 1u), b1 = __ballot(m & 2u), b2 = __ballot(m & 4u), b3 = __ballot(m & 8u);
+  if ((tid & 63) == 0) {
+    const int sw = tid >> 6;
+    bits[0][sw] = b0;
+    bits[1][sw] = b1;
+    bits[2][sw] = b2;
+    bits[3][sw] = b3;
+  }
+}
+
+// A wave-uniform copy of a 64-bit LDS word (held in scalar registers).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 struct Stage {
   float4 a[GS3_BLOCK];
   float4 b[GS3_BLOCK];
   float2 c[GS3_BLOCK];  // b, tau
+  uint64_t bits[4][GS3_BLOCK / 64];
 };
 
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__ rec,
@@ -79,9 +143,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   if (t >= n_tiles) return;
   __shared__ Stage s;
   uint32_t nev = 0, ncon = 0;
-  const int tid = threadIdx.x;
-  const int px = (t % cam.tiles_x) * GS3_TILE + (tid & 15);
-  const int py = (t / cam.tiles_x) * GS3_TILE + (tid >> 4);
+  const int tid = threadIdx.x, w = tid >> 6;
+  const int tx = t % cam.tiles_x, ty = t / cam.tiles_x;
+  const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = ranges[t];
@@ -90,16 +154,22 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
     if (__syncthreads_count(done) == GS3_BLOCK) break;
     const uint32_t i = start + tid;
+    uint32_t m = 0u;
     if (i < range.y) {
       const Rec r = rec[pair_gid[i]];
       s.a[tid] = r.a;
       s.b[tid] = r.b;
       s.c[tid] = make_float2(r.c.x, r.c.y);
+      m = block_mask(r.a, r.b, r.c.y, tx, ty);
     }
+    publish_masks(s.bits, m, tid);
     __syncthreads();
-    const int cnt = min((int)(range.y - start), GS3_BLOCK);
-    if (!done) {
-      for (int j = 0; j < cnt; ++j) {
+    const int nwords = (min((int)(range.y - start), GS3_BLOCK) + 63) >> 6;
+    for (int q = 0; q < nwords && !done; ++q) {
+      uint64_t bits = uniform64(s.bits[w][q]);
+      while (bits) {
+        const int j = (q << 6) + __builtin_ctzll(bits);
+        bits &= bits - 1;
         ++nev;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
@@ -113,10 +183,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
           break;
         }
         ++ncon;
-        const float w = a * T;
-        C0 += B.z * w;
-        C1 += B.w * w;
-        C2 += Cc.x * w;
+        const float w8 = a * T;
+        C0 += B.z * w8;
+        C1 += B.w * w8;
+        C2 += Cc.x * w8;
         T = Tn;
       }
     }
@@ -138,6 +208,7 @@ struct StageJ {
   float4 tb[GS3_BLOCK];
   float2 c[GS3_BLOCK];  // b, tau
   float tc[GS3_BLOCK];
+  uint64_t bits[4][GS3_BLOCK / 64];
 };
 
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__ rec, const TRec* __restrict__ trec,
@@ -151,9 +222,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   if (t >= n_tiles) return;
   __shared__ StageJ s;
   uint32_t nev = 0, ncon = 0;
-  const int tid = threadIdx.x;
-  const int px = (t % cam.tiles_x) * GS3_TILE + (tid & 15);
-  const int py = (t / cam.tiles_x) * GS3_TILE + (tid >> 4);
+  const int tid = threadIdx.x, w = tid >> 6;
+  const int tx = t % cam.tiles_x, ty = t / cam.tiles_x;
+  const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = ranges[t];
@@ -163,6 +234,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
     if (__syncthreads_count(done) == GS3_BLOCK) break;
     const uint32_t i = start + tid;
+    uint32_t m = 0u;
     if (i < range.y) {
       const uint32_t g = pair_gid[i];
       const Rec r = rec[g];
@@ -173,11 +245,16 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
       s.ta[tid] = q.a;
       s.tb[tid] = q.b;
       s.tc[tid] = q.c.x;
+      m = block_mask(r.a, r.b, r.c.y, tx, ty);
     }
+    publish_masks(s.bits, m, tid);
     __syncthreads();
-    const int cnt = min((int)(range.y - start), GS3_BLOCK);
-    if (!done) {
-      for (int j = 0; j < cnt; ++j) {
+    const int nwords = (min((int)(range.y - start), GS3_BLOCK) + 63) >> 6;
+    for (int qw = 0; qw < nwords && !done; ++qw) {
+      uint64_t bits = uniform64(s.bits[w][qw]);
+      while (bits) {
+        const int j = (qw << 6) + __builtin_ctzll(bits);
+        bits &= bits - 1;
         ++nev;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
@@ -199,14 +276,14 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
         const float dpow = 2.f * (A.z * dx * TA.x + B.x * dy * TA.y) + A.w * (TA.x * dy + dx * TA.y) -
                            0.5f * (TA.z * dx * dx + TB.x * dy * dy) - TA.w * dx * dy;
         const float da = araw > GS3_ALPHA_MAX ? 0.f : (TB.y * G + B.y * G * dpow);
-        const float w = a * T;
+        const float wt = a * T;
         const float dw = da * T + a * dT;
-        C0 += B.z * w;
-        C1 += B.w * w;
-        C2 += Cc.x * w;
-        D0 += TB.z * w + B.z * dw;
-        D1 += TB.w * w + B.w * dw;
-        D2 += s.tc[j] * w + Cc.x * dw;
+        C0 += B.z * wt;
+        C1 += B.w * wt;
+        C2 += Cc.x * wt;
+        D0 += TB.z * wt + B.z * dw;
+        D1 += TB.w * wt + B.w * dw;
+        D2 += s.tc[j] * wt + Cc.x * dw;
         dT = dT * (1.f - a) - T * da;
         T = Tn;
       }
@@ -276,6 +353,7 @@ struct StageB {
   float2 c[kBwdBatch];  // b, tau
   uint32_t slot[kBwdBatch];
   float red[4][9][kBwdBatch];
+  uint64_t bits[4][kBwdBatch / 64];
 };
 
 // Slot of the (Gaussian, tile) pair in the Gaussian-contiguous partials
@@ -300,8 +378,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   uint32_t nev = 0, ncon = 0;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int tx = t % cam.tiles_x, ty = t / cam.tiles_x;
-  const int px = tx * GS3_TILE + (tid & 15);
-  const int py = ty * GS3_TILE + (tid >> 4);
+  const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = ranges[t];
@@ -321,83 +398,100 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   for (; start < range.y; start += kBwdBatch) {
     if (__syncthreads_count(done) == GS3_BLOCK) break;
     const uint32_t i = start + tid;
-    if (tid < kBwdBatch && i < range.y) {
-      const uint32_t g = pair_gid[i];
-      const Rec r = rec[g];
-      s.a[tid] = r.a;
-      s.b[tid] = r.b;
-      s.c[tid] = make_float2(r.c.x, r.c.y);
-      s.slot[tid] = pair_slot(__float_as_uint(r.c.z), rect[g], tx, ty);
+    if (tid < kBwdBatch) {
+      uint32_t m = 0u;
+      if (i < range.y) {
+        const uint32_t g = pair_gid[i];
+        const Rec r = rec[g];
+        s.a[tid] = r.a;
+        s.b[tid] = r.b;
+        s.c[tid] = make_float2(r.c.x, r.c.y);
+        s.slot[tid] = pair_slot(__float_as_uint(r.c.z), rect[g], tx, ty);
+        m = block_mask(r.a, r.b, r.c.y, tx, ty);
+      }
+      publish_masks(s.bits, m, tid);
     }
     __syncthreads();
     const int cnt = min((int)(range.y - start), kBwdBatch);
-    for (int j = 0; j < cnt; ++j) {
-      float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      bool contrib = false;
-      if (!done) {
-        ++nev;
-        const float4 A = s.a[j], B = s.b[j];
-        const float2 Cc = s.c[j];
-        const float dx = A.x - pxf, dy = A.y - pyf;
-        const float power = splat_power(A.z, A.w, B.x, dx, dy);
-        if (power <= 0.f && power >= Cc.y) {
-          const float G = __expf(power);
-          const float araw = B.y * G;
-          const float a = fminf(GS3_ALPHA_MAX, araw);
-          {
-            const float Tn = T * (1.f - a);
-            if (Tn < GS3_T_STOP) {
-              done = true;
-            } else {
-              const float cr = B.z, cg = B.w, cb = Cc.x;
-              const float wgt = a * T;
-              S0 += cr * wgt;
-              S1 += cg * wgt;
-              S2 += cb * wgt;
-              const float behind = (out0 - S0) * g0 + (out1 - S1) * g1 + (out2 - S2) * g2;
-              const float dL_da = T * (cr * g0 + cg * g1 + cb * g2) - behind / (1.f - a);
-              const bool clamped = araw > GS3_ALPHA_MAX;
-              const float dL_dG = clamped ? 0.f : B.y * dL_da;
-              const float dL_dpow = dL_dG * G;
-              gr[0] = dL_dpow * (2.f * A.z * dx + A.w * dy);
-              gr[1] = dL_dpow * (2.f * B.x * dy + A.w * dx);
-              gr[2] = dL_dpow * (-0.5f * dx * dx);
-              gr[3] = dL_dpow * (-dx * dy);
-              gr[4] = dL_dpow * (-0.5f * dy * dy);
-              gr[5] = clamped ? 0.f : G * dL_da;
-              gr[6] = wgt * g0;
-              gr[7] = wgt * g1;
-              gr[8] = wgt * g2;
-              contrib = true;
-              ++ncon;
-              T = Tn;
+    const int nwords = (cnt + 63) >> 6;
+    for (int q = 0; q < nwords; ++q) {
+      uint64_t bits = uniform64(s.bits[w][q]);
+      while (bits) {
+        const int j = (q << 6) + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        bool contrib = false;
+        if (!done) {
+          ++nev;
+          const float4 A = s.a[j], B = s.b[j];
+          const float2 Cc = s.c[j];
+          const float dx = A.x - pxf, dy = A.y - pyf;
+          const float power = splat_power(A.z, A.w, B.x, dx, dy);
+          if (power <= 0.f && power >= Cc.y) {
+            const float G = __expf(power);
+            const float araw = B.y * G;
+            const float a = fminf(GS3_ALPHA_MAX, araw);
+            {
+              const float Tn = T * (1.f - a);
+              if (Tn < GS3_T_STOP) {
+                done = true;
+              } else {
+                const float cr = B.z, cg = B.w, cb = Cc.x;
+                const float wgt = a * T;
+                S0 += cr * wgt;
+                S1 += cg * wgt;
+                S2 += cb * wgt;
+                const float behind = (out0 - S0) * g0 + (out1 - S1) * g1 + (out2 - S2) * g2;
+                const float dL_da = T * (cr * g0 + cg * g1 + cb * g2) - behind / (1.f - a);
+                const bool clamped = araw > GS3_ALPHA_MAX;
+                const float dL_dG = clamped ? 0.f : B.y * dL_da;
+                const float dL_dpow = dL_dG * G;
+                gr[0] = dL_dpow * (2.f * A.z * dx + A.w * dy);
+                gr[1] = dL_dpow * (2.f * B.x * dy + A.w * dx);
+                gr[2] = dL_dpow * (-0.5f * dx * dx);
+                gr[3] = dL_dpow * (-dx * dy);
+                gr[4] = dL_dpow * (-0.5f * dy * dy);
+                gr[5] = clamped ? 0.f : G * dL_da;
+                gr[6] = wgt * g0;
+                gr[7] = wgt * g1;
+                gr[8] = wgt * g2;
+                contrib = true;
+                ++ncon;
+                T = Tn;
+              }
             }
           }
         }
-      }
-      // wave sums of the 9 partial derivatives: values 0-7 are folded in
-      // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
-      // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
-      // DPP reduction into lane 63.  26 VALU instructions in all.
-      float E = 0.f, F = 0.f, H = 0.f;
-      if (__ballot(contrib) != 0ull) {
-        E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
-        F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
-        H = wave_sum_lane63(gr[8]);
-      }
-      if ((lane & 15) == 15) {
-        const int row = lane >> 4;
-        const int k = (row & 1) * 2 + (row >> 1);
-        s.red[w][k][j] = E;
-        s.red[w][4 + k][j] = F;
-        if (lane == 63) s.red[w][8][j] = H;
+        // wave sums of the 9 partial derivatives: values 0-7 are folded in
+        // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
+        // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
+        // DPP reduction into lane 63.  26 VALU instructions in all.
+        float E = 0.f, F = 0.f, H = 0.f;
+        if (__ballot(contrib) != 0ull) {
+          E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
+          F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
+          H = wave_sum_lane63(gr[8]);
+        }
+        if ((lane & 15) == 15) {
+          const int row = lane >> 4;
+          const int k = (row & 1) * 2 + (row >> 1);
+          s.red[w][k][j] = E;
+          s.red[w][4 + k][j] = F;
+          if (lane == 63) s.red[w][8][j] = H;
+        }
       }
     }
     __syncthreads();
     if (tid < cnt) {
+      // a wave that skipped the splat contributes exactly zero
       float* dst = partials + (int64_t)s.slot[tid] * 9;
+      const uint64_t bit = 1ull << (tid & 63);
+      const bool h0 = s.bits[0][tid >> 6] & bit, h1 = s.bits[1][tid >> 6] & bit;
+      const bool h2 = s.bits[2][tid >> 6] & bit, h3 = s.bits[3][tid >> 6] & bit;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) dst[k] = ((s.red[0][k][tid] + s.red[1][k][tid]) + s.red[2][k][tid]) + s.red[3][k][tid];
+      for (int k = 0; k < 9; ++k)
+        dst[k] = (((h0 ? s.red[0][k][tid] : 0.f) + (h1 ? s.red[1][k][tid] : 0.f)) + (h2 ? s.red[2][k][tid] : 0.f)) +
+                 (h3 ? s.red[3][k][tid] : 0.f);
     }
     __syncthreads();
   }

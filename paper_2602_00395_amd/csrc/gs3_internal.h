@@ -69,13 +69,17 @@ void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, c
 
 // sorting and binning
 size_t radix_temp_bytes(int64_t n);
-void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n, int bits,
-                    void* temp, hipStream_t st, uint32_t** keys_out, uint32_t** vals_out);
+// Stable LSD radix sort of n (key, value) pairs on the low `bits` key bits
+// (8 per pass).  The first pass reads (keys_in, vals_in) -- vals_in null means
+// value = index -- and passes alternate between (ka, va) and (kb, vb), so
+// keys_in must not alias ka; *keys_out / *vals_out name the result buffers.
+void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* ka, uint32_t* va, uint32_t* kb,
+                    uint32_t* vb, int64_t n, int bits, void* temp, hipStream_t st, uint32_t** keys_out,
+                    uint32_t** vals_out);
 size_t scan_temp_bytes(int64_t n);
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st);
 void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
                           hipStream_t st);
-void launch_iota(uint32_t* v, int64_t n, hipStream_t st);
 // writes each visible Gaussian's pair offset into its record (rec.c.w)
 void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Rec* rec, const uint2* rect,
                        int64_t n, int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,

@@ -12,10 +12,15 @@
 // moves far fewer bytes: the pair sort needs 2 passes instead of 6.
 //
 // Radix pass = upsweep (per-block digit histograms), per-digit scan across
-// blocks (one workgroup per digit), scatter (stable ranking with wave64
-// ballots: lanes holding the same digit are found with 8 ballots).  No
-// workgroup ever waits on another: every kernel is a plain data-parallel
-// launch.
+// blocks (one workgroup per digit), scatter.  In the scatter each wave64
+// ranks its own contiguous run of 1024 keys: lanes holding the same digit are
+// found with 8 ballots, and a per-wave running count per digit in LDS gives
+// each key its rank without any workgroup barrier inside the run; one barrier
+// then turns the four waves' counts into output offsets.  No workgroup ever
+// waits on another: every kernel is a plain data-parallel launch.  The first
+// pass may take its values implicitly as the key's index.
+#include <algorithm>
+
 #include "gs3_internal.h"
 
 namespace {
@@ -133,28 +138,36 @@ __global__ __launch_bounds__(kThreads) void k_rs_scan(uint32_t* __restrict__ his
   if (threadIdx.x == 0) digit_total[blockIdx.x] = running;
 }
 
+// Keys [blk + w * kWaveItems, + kWaveItems) belong to wave w of block blk,
+// 64 per round; `vals` null means value = index.
+constexpr int kWaveItems = kItems * 64;
+
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vals,
                                                           uint32_t* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, int64_t n, int shift,
                                                           const uint32_t* __restrict__ hist, int nb,
                                                           const uint32_t* __restrict__ digit_total) {
-  __shared__ uint32_t base[kRadix];
-  __shared__ uint32_t wcnt[4][kRadix];
+  __shared__ uint32_t cnt[4][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cnt[q][tid] = 0u;
+  uint32_t base;
   {
     uint32_t tot;
-    const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
-    base[tid] = dbase + hist[(int64_t)tid * nb + blockIdx.x];
+    base = block_excl_scan(digit_total[tid], &tot) + hist[(int64_t)tid * nb + blockIdx.x];
   }
+  __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t blk = (int64_t)blockIdx.x * kTileItems;
+  const int64_t wbase = (int64_t)blockIdx.x * kTileItems + (int64_t)w * kWaveItems;
+  uint32_t k[kItems], v[kItems], rk[kItems];
+#pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int64_t i = blk + r * kThreads + tid;
+    const int64_t i = wbase + r * 64 + lane;
     const bool valid = i < n;
-    const uint32_t k = valid ? keys[i] : 0u;
-    const uint32_t v = valid ? vals[i] : 0u;
-    const uint32_t d = (k >> shift) & 0xffu;
+    k[r] = valid ? keys[i] : 0u;
+    v[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;
+    const uint32_t d = (k[r] >> shift) & 0xffu;
     uint64_t same = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -162,37 +175,35 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
       const uint64_t m = __ballot(bit);
       same &= bit ? m : ~m;
     }
-    const uint32_t rank = (uint32_t)__popcll(same & lt_mask);
+    const uint32_t below = (uint32_t)__popcll(same & lt_mask);
+    uint32_t prior = 0u;
+    if (valid) prior = cnt[w][d];
+    // the lowest lane of each digit group advances the wave's running count;
+    // LDS accesses of one wave complete in order, so the next round reads it
+    if (valid && below == 0u) cnt[w][d] = prior + (uint32_t)__popcll(same);
+    rk[r] = prior + below;
+  }
+  __syncthreads();
+  {
+    const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid];
+    cnt[0][tid] = base;
+    cnt[1][tid] = base + c0;
+    cnt[2][tid] = base + c0 + c1;
+    cnt[3][tid] = base + c0 + c1 + c2;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wcnt[q][tid] = 0u;
-    __syncthreads();
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(same);
-    __syncthreads();
-    // per-digit prefix over the four waves (wave order == item order)
-    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-    __syncthreads();
-    wcnt[0][tid] = 0u;
-    wcnt[1][tid] = c0;
-    wcnt[2][tid] = c0 + c1;
-    wcnt[3][tid] = c0 + c1 + c2;
-    __syncthreads();
-    if (valid) {
-      const uint32_t pos = base[d] + wcnt[w][d] + rank;
-      keys_out[pos] = k;
-      vals_out[pos] = v;
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = wbase + r * 64 + lane;
+    if (i < n) {
+      const uint32_t pos = cnt[w][(k[r] >> shift) & 0xffu] + rk[r];
+      keys_out[pos] = k[r];
+      vals_out[pos] = v[r];
     }
-    __syncthreads();
-    base[tid] += c0 + c1 + c2 + c3;
-    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- binning
-
-__global__ __launch_bounds__(256) void k_iota(uint32_t* __restrict__ v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = (uint32_t)i;
-}
 
 __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ tiles, int64_t n,
@@ -313,31 +324,28 @@ size_t radix_temp_bytes(int64_t n) {
   return (size_t)(kRadix * nb + kRadix) * sizeof(uint32_t);
 }
 
-void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n, int bits,
-                    void* temp, hipStream_t st, uint32_t** keys_out, uint32_t** vals_out) {
-  uint32_t *ka = keys, *va = vals, *kb = keys_alt, *vb = vals_alt;
-  if (n > 1) {
-    const int nb = (int)nblk(n, kTileItems);
-    uint32_t* hist = (uint32_t*)temp;
-    uint32_t* dtot = hist + (size_t)kRadix * nb;
-    for (int shift = 0; shift < bits; shift += 8) {
-      hipLaunchKernelGGL(k_rs_upsweep, dim3(nb), dim3(kThreads), 0, st, ka, n, shift, hist, nb);
-      hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb, dtot);
-      hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, st, ka, va, kb, vb, n, shift, hist, nb, dtot);
-      uint32_t* t = ka;
-      ka = kb;
-      kb = t;
-      t = va;
-      va = vb;
-      vb = t;
-    }
-  }
+void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* ka, uint32_t* va, uint32_t* kb,
+                    uint32_t* vb, int64_t n, int bits, void* temp, hipStream_t st, uint32_t** keys_out,
+                    uint32_t** vals_out) {
   *keys_out = ka;
   *vals_out = va;
-}
-
-void launch_iota(uint32_t* v, int64_t n, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_iota, dim3(nblk(n, 256)), dim3(256), 0, st, v, n);
+  if (n <= 0) return;
+  const int nb = (int)nblk(n, kTileItems);
+  uint32_t* hist = (uint32_t*)temp;
+  uint32_t* dtot = hist + (size_t)kRadix * nb;
+  const uint32_t *kin = keys_in, *vin = vals_in;
+  const int passes = std::max(1, (bits + 7) / 8);
+  for (int p = 0; p < passes; ++p) {
+    uint32_t* ko = (p & 1) ? kb : ka;
+    uint32_t* vo = (p & 1) ? vb : va;
+    hipLaunchKernelGGL(k_rs_upsweep, dim3(nb), dim3(kThreads), 0, st, kin, n, 8 * p, hist, nb);
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb, dtot);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, st, kin, vin, ko, vo, n, 8 * p, hist, nb, dtot);
+    kin = ko;
+    vin = vo;
+    *keys_out = ko;
+    *vals_out = vo;
+  }
 }
 
 void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
