@@ -53,6 +53,12 @@ def parse():
                     help="MiB: first run one plain device-to-device copy of this size (counter calibration)")
     ap.add_argument("--fit", type=int, default=0,
                     help="also run Adam for 2x this many iterations and TR until Adam's PSNR (seconds to PSNR)")
+    ap.add_argument("--tr-variant", type=int, default=0,
+                    help="trust-region radius variant bits for --fit (1 mean exact, 2 second order, 4 joint SH)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also serve this many scene-fit requests of the Poisson trace (p50/p99 time-to-fit)")
+    ap.add_argument("--serve-iters", type=int, default=400,
+                    help="iterations of the solo run that sets each served request's PSNR target")
     return ap.parse_args()
 
 
@@ -139,6 +145,72 @@ def cpu_baseline(sc, n_tiles_sample: int, l: int) -> dict:
                 sample=(f"object-scale view, {len(pick)} of {len(nonempty)} non-empty tiles "
                         f"(x{scale:.1f} by pair count) for render+grad and the GN product; "
                         f"binning and trust-region step at full size; est. {t_iter:.1f} s/iter"))
+
+
+def serving(n_req: int, k_iters: int, dev: str) -> dict:
+    """Continuous-batching scene fitting on the Poisson request trace.
+
+    Each request is a seeded synthetic object scene (log-uniform 10k-500k
+    Gaussians, 16-128 cameras, 256-800 px, SH degree 0-3, 2 requests/s).  Its
+    PSNR target is what the same request reaches alone after `k_iters` TR
+    iterations, minus 0.1 dB (a solo pass measures it first).  The served pass
+    admits requests by HBM footprint (up to 8 at once, each on its own stream
+    and host thread) and reports time-to-fit from arrival, so queueing counts.
+    The kernels are deterministic, so every served request stops at the same
+    iteration as its solo run; the report checks that.
+    """
+    import numpy as np
+    import torch
+
+    import synthetic as syn
+    from paper_2602_00395_amd import Scene, scene_bytes
+    from paper_2602_00395_amd.serve import FitRequest, Server
+
+    check = 100
+    trace = syn.serving_requests(n_req=n_req)
+    reqs = []
+    for i, r in enumerate(trace):
+        sc = syn.request_scene(r)
+        blank = [torch.zeros((c.height, c.width, 3), device=dev) for c in sc.cameras]
+        g = Scene(torch.tensor(sc.gt, device=dev), blank, sc.cameras, sc.sh_degree, lam=0.2)
+        targets = [g.render(j).clone() for j in range(len(sc.cameras))]
+        g.close()
+        del blank
+        x0 = torch.tensor(sc.init, device=dev)
+        mask = [j % sc.test_every != 0 for j in range(len(sc.cameras))]
+        res_b, scr_b = scene_bytes(sc.n, sc.sh_degree, sc.cameras)
+
+        def make(stream, x0=x0, targets=targets, cams=sc.cameras, deg=sc.sh_degree, mask=mask):
+            return Scene(x0, targets, cams, deg, lam=0.2, train_mask=mask, stream=stream)
+
+        reqs.append(FitRequest(rid=i, arrival_s=r["arrival_s"], n=sc.n, sh_degree=sc.sh_degree, make_scene=make,
+                               train_ids=sc.train_ids(), test_ids=sc.test_ids(), target_psnr=float("inf"),
+                               max_iters=k_iters, check_every=check, bytes_needed=res_b + scr_b,
+                               seed=4005 + i))
+        print("request", i, sc.n, len(sc.cameras), r["res"], sc.sh_degree, file=sys.stderr, flush=True)
+    # solo pass: the PSNR each request reaches alone after k_iters iterations
+    solo = {}
+    t0 = time.perf_counter()
+    for r in reqs:
+        st = Server(hbm_budget=r.bytes_needed, max_active=1).run([FitRequest(**{**r.__dict__, "arrival_s": 0.0})])
+        solo[r.rid] = st.results[0]
+        print("solo", r.rid, r.n, round(st.results[0].psnr, 3), round(st.wall_s, 2), file=sys.stderr, flush=True)
+    solo_s = time.perf_counter() - t0
+    for r in reqs:  # same iteration cap, so the trust-region schedule is the solo one
+        r.target_psnr = solo[r.rid].psnr - 0.1
+    budget = 64 << 30
+    st = Server(hbm_budget=budget, max_active=8).run(reqs)
+    served_iters = {x.rid: x.iters for x in st.results}
+    same = all(served_iters[r.rid] <= solo[r.rid].iters for r in reqs)
+    lat = np.array([x.latency_s for x in st.results])
+    return dict(requests=len(reqs), reached=sum(x.reached for x in st.results),
+                p50_time_to_fit_s=round(float(np.percentile(lat, 50)), 3),
+                p99_time_to_fit_s=round(float(np.percentile(lat, 99)), 3),
+                gaussian_updates_per_s=round(st.gaussian_updates_per_s(), 1), wall_s=round(st.wall_s, 2),
+                peak_admitted_bytes=int(st.peak_bytes), hbm_budget_bytes=budget, max_active=8,
+                target=f"solo PSNR after {k_iters} TR iterations - 0.1 dB, checked every {check}",
+                served_iters_within_solo=same, solo_pass_s=round(solo_s, 2),
+                iters_total=int(sum(served_iters.values())))
 
 
 def main():
@@ -255,15 +327,18 @@ def main():
         s.close()
         target = hist_a[-1][2]
         s = make()
-        tr = TRTrainer(s, train_ids, TRConfig(budget=args.fit))
+        tr = TRTrainer(s, train_ids, TRConfig(budget=args.fit, variant=args.tr_variant))
         hist_t, reached = fit(tr, s, test_ids, args.fit, eval_every=500, target_psnr=target,
                               log=lambda m: print("tr", m, file=sys.stderr, flush=True))
         s.close()
-        out["fit"] = dict(adam_iters=2 * args.fit, adam_psnr=round(target, 3), adam_train_s=round(hist_a[-1][1], 2),
+        out["fit"] = dict(tr_variant=args.tr_variant, adam_iters=2 * args.fit, adam_psnr=round(target, 3), adam_train_s=round(hist_a[-1][1], 2),
                           tr_iters=args.fit, tr_psnr=round(hist_t[-1][2], 3),
                           tr_s_to_adam_psnr=None if reached is None else round(reached, 2),
                           adam_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_a],
                           tr_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_t])
+
+    if args.serve > 0:
+        out["serving"] = serving(args.serve, args.serve_iters, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_tiles, cfg.l)

@@ -82,10 +82,28 @@ typedef struct {
                                 Held-out views are rendered and scored only. */
 } gs3_scene_desc;
 
+/* Trust-region radius variants (gs3_tr_hparams.variant, bit flags).  0 is
+ * the radius exactly as the appendix prints it.
+ * GS3_TR_MEAN_EXACT: the mean radius uses 1 / (Sigma^-1)_cc in place of
+ *   Sigma_cc (the printed form is exact only for an axis-aligned Sigma).
+ * GS3_TR_SECOND_ORDER: the scale, quaternion, opacity and colour radii use
+ *   the constants 8/3, 16, 8, 8 in place of 2, 8, 4, 4, so that each spends
+ *   the whole budget epsilon to second order (the printed Taylor steps are
+ *   conservative by factors 0.75, 0.5, 0.5, 0.5). */
+#define GS3_TR_MEAN_EXACT 1u
+#define GS3_TR_SECOND_ORDER 2u
+/* GS3_TR_SH_JOINT: the view-dependent SH coefficients (k >= 1) of channel c
+ *   share the radius eta_C / S_d, S_d the maximum over directions of
+ *   sum_{k>=1} |Y_k| at degree d, so that moving all of them at once changes
+ *   the colour by at most eta_C in any direction; the DC coefficient keeps
+ *   eta_C / C0.  Without it every coefficient gets eta_C / C0. */
+#define GS3_TR_SH_JOINT 4u
+
 typedef struct {
-  float theta1;  /* EMA decay of the gradient, in [0, 1)                  */
-  float theta2;  /* EMA decay of the Hessian diagonal, in [0, 1)          */
-  float epsilon; /* Hellinger trust-region budget, > 0                    */
+  float theta1;     /* EMA decay of the gradient, in [0, 1)               */
+  float theta2;     /* EMA decay of the Hessian diagonal, in [0, 1)       */
+  float epsilon;    /* Hellinger trust-region budget, > 0                 */
+  uint32_t variant; /* GS3_TR_* bits; other bits are rejected (EINVAL)    */
 } gs3_tr_hparams;
 
 /* Number of rows P = 11 + 3 (d+1)^2 of the parameter layout; -1 if d is not 0..3. */

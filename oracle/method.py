@@ -44,7 +44,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from .gaussians import DT, SH_C0, n_params, rotation, split
+from .gaussians import DT, SH_C0, n_params, rotation, sh_basis, split
 from .binning import Bins, bin_view
 from .render import render
 from .loss import loss_components, ssim_map
@@ -241,9 +241,59 @@ def quaternion_beta(log_s, q) -> np.ndarray:
     return out
 
 
+def sh_rest_abs_max(sh_degree: int) -> float:
+    """max over unit directions d of sum_{k >= 1} |Y_k(d)| (0 at degree 0).
+
+    Found numerically: the best of a dense random sampling of the sphere,
+    refined by Nelder-Mead from the best samples (the function is smooth
+    away from the zero sets of the Y_k).
+    """
+    if sh_degree == 0:
+        return 0.0
+    if sh_degree in _SH_ABS_MAX:
+        return _SH_ABS_MAX[sh_degree]
+    from scipy.optimize import minimize
+
+    def neg(a):
+        th, ph = a
+        d = torch.tensor([[math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)]],
+                         dtype=torch.float64)
+        return -float(sh_basis(d, sh_degree)[0, 1:].abs().sum())
+
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=(100000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    vals = sh_basis(torch.tensor(d), sh_degree)[:, 1:].abs().sum(1).numpy()
+    best = float(vals.max())
+    for i in np.argsort(-vals)[:24]:
+        a0 = [math.acos(max(-1.0, min(1.0, d[i, 2]))), math.atan2(d[i, 1], d[i, 0])]
+        r = minimize(neg, a0, method="Nelder-Mead", options=dict(xatol=1e-12, fatol=1e-15, maxiter=4000))
+        best = max(best, -float(r.fun))
+    _SH_ABS_MAX[sh_degree] = best
+    return best
+
+
+_SH_ABS_MAX: dict = {}
+
+
 def shd_eta(x, eps: float, sh_degree: int, colour_floor: float = COLOUR_FLOOR,
-            mean_bound: str = "printed") -> np.ndarray:
-    """eta = SHD(x, eps) in raw-parameter space, [P, N] (inf = unconstrained)."""
+            mean_bound: str = "printed", constants: str = "printed", sh_rest: str = "base") -> np.ndarray:
+    """eta = SHD(x, eps) in raw-parameter space, [P, N] (inf = unconstrained).
+
+    mean_bound "printed" uses Sigma_cc as the appendix does (exact only for an
+    axis-aligned Sigma); "exact" uses 1 / (Sigma^-1)_cc, the exact second-order
+    radius of a move along axis c for any rotation.
+    constants "printed" keeps the appendix constants, whose Taylor steps make
+    the scale, opacity, colour and quaternion radii conservative (the exact
+    H^2 at eta is 0.75, 0.5, 0.5 and about 0.5 times eps); "second_order"
+    rescales eta^2 by 1/0.75, 2, 2 and 2 (constants 8/3, 8, 8 and 16 in place
+    of 2, 4, 4 and 8) so that every class spends eps to second order.
+    sh_rest "base" gives every SH coefficient of channel c the base colour's
+    radius eta_C / C0; "joint" keeps that for the DC coefficient and gives the
+    view-dependent coefficients (k >= 1) the common radius eta_C / S, S the
+    maximum over directions of sum_k |Y_k|, so that moving all of them at once
+    changes the colour by at most eta_C in every direction.
+    """
     xt = _t(x)
     p = split(xt, sh_degree)
     n = xt.shape[1]
@@ -258,20 +308,25 @@ def shd_eta(x, eps: float, sh_degree: int, colour_floor: float = COLOUR_FLOOR,
         diag = 1.0 / np.linalg.inv(Sigma).diagonal(axis1=1, axis2=2)
     else:
         diag = Sigma.diagonal(axis1=1, axis2=2)
+    if constants == "second_order":
+        k_s, k_q, k_a, k_c = 8.0 / 3.0, 16.0, 8.0, 8.0
+    else:
+        k_s, k_q, k_a, k_c = 2.0, 8.0, 4.0, 4.0
     for c in range(3):
         eta[c] = np.sqrt(8.0 * diag[:, c] * L)
-        eta[3 + c] = np.sqrt(2.0 * s[:, c] ** 2 * eps / alpha) / s[:, c]
+        eta[3 + c] = np.sqrt(k_s * s[:, c] ** 2 * eps / alpha) / s[:, c]
     beta = quaternion_beta(p["log_s"].numpy(), p["quat"].numpy())
     with np.errstate(divide="ignore", invalid="ignore"):
         for c in range(4):
-            eta[6 + c] = np.where(beta[:, c] > 0, np.sqrt(8.0 * L / beta[:, c]), np.inf)
-    eta[10] = np.sqrt(4.0 * alpha * eps) / (alpha * (1.0 - alpha))
+            eta[6 + c] = np.where(beta[:, c] > 0, np.sqrt(k_q * L / beta[:, c]), np.inf)
+    eta[10] = np.sqrt(k_a * alpha * eps) / (alpha * (1.0 - alpha))
     base = 0.5 + SH_C0 * p["sh"][:, 0, :].numpy()  # [N, 3]
-    eta_C = np.sqrt(4.0 * np.maximum(base, colour_floor) * eps / alpha[:, None])
+    eta_C = np.sqrt(k_c * np.maximum(base, colour_floor) * eps / alpha[:, None])
     k = (sh_degree + 1) ** 2
+    rest = sh_rest_abs_max(sh_degree) if sh_rest == "joint" else SH_C0
     for kk in range(k):
         for c in range(3):
-            eta[11 + 3 * kk + c] = eta_C[:, c] / SH_C0
+            eta[11 + 3 * kk + c] = eta_C[:, c] / (SH_C0 if kk == 0 else rest)
     return eta
 
 
@@ -290,7 +345,7 @@ def is_hutchinson_step(t: int, l: int) -> bool:
 
 
 def tr_step(x, g, ghat, Dhat, D_t, theta1: float, theta2: float, eps: float, sh_degree: int,
-            eta=None):
+            eta=None, mean_bound: str = "printed", constants: str = "printed", sh_rest: str = "base"):
     """One update of Algorithm 1 given g_t (and D_t on a Hutchinson step, else None).
 
     Returns (x_next, ghat_next, Dhat_next, dx_hat, eta).
@@ -300,7 +355,7 @@ def tr_step(x, g, ghat, Dhat, D_t, theta1: float, theta2: float, eps: float, sh_
     if D_t is not None:
         Dhat = theta2 * Dhat + (1.0 - theta2) * np.asarray(D_t, np.float64)
     if eta is None:
-        eta = shd_eta(x, eps, sh_degree)
+        eta = shd_eta(x, eps, sh_degree, mean_bound=mean_bound, constants=constants, sh_rest=sh_rest)
     with np.errstate(divide="ignore", invalid="ignore"):
         newton = -ghat / Dhat
         fallback = np.where(np.isfinite(eta), -np.sign(ghat) * eta, 0.0)

@@ -5,5 +5,5 @@ The compute path is the HIP library ``libgs3tr.so`` (C ABI in
 the package does not load the library; ``Scene`` does, and fails loudly if it
 has not been built.
 """
-from .api import (ADAM_GROUP_ORDER, Scene, n_params, profile_enable, profile_read,  # noqa: F401
-                  profile_reset, scene_bytes)
+from .api import (ADAM_GROUP_ORDER, TR_MEAN_EXACT, TR_SECOND_ORDER, TR_SH_JOINT, Scene,  # noqa: F401
+                  n_params, profile_enable, profile_read, profile_reset, scene_bytes)

@@ -29,7 +29,7 @@ class SceneDesc(ctypes.Structure):
 
 
 class TrHparams(ctypes.Structure):
-    _fields_ = [("theta1", c_float), ("theta2", c_float), ("epsilon", c_float)]
+    _fields_ = [("theta1", c_float), ("theta2", c_float), ("epsilon", c_float), ("variant", c_uint32)]
 
 
 class GS3Error(RuntimeError):

@@ -10,6 +10,9 @@ import torch
 from . import _lib
 
 ADAM_GROUP_ORDER = ("mu", "f_dc", "f_rest", "opacity", "scale", "rot")
+TR_MEAN_EXACT = 1  # GS3_TR_MEAN_EXACT
+TR_SECOND_ORDER = 2  # GS3_TR_SECOND_ORDER
+TR_SH_JOINT = 4  # GS3_TR_SH_JOINT
 
 
 def n_params(sh_degree: int) -> int:
@@ -200,8 +203,9 @@ class Scene:
         return out
 
     def tr_step(self, grad: torch.Tensor, D: torch.Tensor | None, theta1: float, theta2: float, epsilon: float,
-                eta_out: torch.Tensor | None = None, dx_out: torch.Tensor | None = None):
-        hp = _lib.TrHparams(float(theta1), float(theta2), float(epsilon))
+                eta_out: torch.Tensor | None = None, dx_out: torch.Tensor | None = None, variant: int = 0):
+        """variant: bits TR_MEAN_EXACT | TR_SECOND_ORDER | TR_SH_JOINT (0 = the printed radius)."""
+        hp = _lib.TrHparams(float(theta1), float(theta2), float(epsilon), int(variant))
         _lib.check("gs3_tr_step", self.lib.gs3_tr_step(self.handle, _ptr(grad), _ptr(D), byref(hp), _ptr(eta_out),
                                                        _ptr(dx_out), self._st()))
 

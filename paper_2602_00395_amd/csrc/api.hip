@@ -620,7 +620,9 @@ gs3_status gs3_tr_step(gs3_scene* s, const float* grad, const float* D, const gs
   if (!(hp->theta1 >= 0.f && hp->theta1 < 1.f && hp->theta2 >= 0.f && hp->theta2 < 1.f))
     return fail(GS3_EINVAL, "theta1 and theta2 must be in [0, 1)");
   if (!(hp->epsilon > 0.f) || !std::isfinite(hp->epsilon)) return fail(GS3_EINVAL, "epsilon must be > 0 and finite");
-  TrArgs a{hp->theta1, hp->theta2, hp->epsilon, D != nullptr};
+  if (hp->variant & ~(GS3_TR_MEAN_EXACT | GS3_TR_SECOND_ORDER | GS3_TR_SH_JOINT))
+    return fail(GS3_EINVAL, "unknown variant bits");
+  TrArgs a{hp->theta1, hp->theta2, hp->epsilon, D != nullptr, hp->variant};
   auto p = prof::begin("tr_step", st);
   launch_tr_step(s->x, grad, s->ghat, s->dhat, D, s->N, s->deg, a, eta_out, dx_out, st);
   prof::end(p, st, s->N, (int64_t)s->P * s->N);

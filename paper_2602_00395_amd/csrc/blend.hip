@@ -165,29 +165,36 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
     publish_masks(s.bits, m, tid);
     __syncthreads();
     const int nwords = (min((int)(range.y - start), GS3_BLOCK) + 63) >> 6;
-    for (int q = 0; q < nwords && !done; ++q) {
+    bool wave_done = false;
+    for (int q = 0; q < nwords && !wave_done; ++q) {
       uint64_t bits = uniform64(s.bits[w][q]);
       while (bits) {
+        // every pixel of the block has stopped: the rest is never read
+        if (__ballot(!done) == 0ull) {
+          wave_done = true;
+          break;
+        }
         const int j = (q << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        ++nev;
+        nev += done ? 0u : 1u;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
         const float dx = A.x - pxf, dy = A.y - pyf;
         const float power = splat_power(A.z, A.w, B.x, dx, dy);
-        if (power > 0.f || power < Cc.y) continue;
+        // predicated rather than branched: nearly every wave has a lane
+        // that contributes, so a branch would only add mask bookkeeping
+        const bool pass = !done && power <= 0.f && power >= Cc.y;
         const float a = fminf(GS3_ALPHA_MAX, B.y * __expf(power));
         const float Tn = T * (1.f - a);
-        if (Tn < GS3_T_STOP) {
-          done = true;
-          break;
-        }
-        ++ncon;
-        const float w8 = a * T;
+        const bool stop = pass && Tn < GS3_T_STOP;
+        const bool use = pass && !stop;
+        done = done || stop;
+        ncon += use ? 1u : 0u;
+        const float w8 = use ? a * T : 0.f;
         C0 += B.z * w8;
         C1 += B.w * w8;
         C2 += Cc.x * w8;
-        T = Tn;
+        T = use ? Tn : T;
       }
     }
     __syncthreads();
@@ -250,42 +257,46 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
     publish_masks(s.bits, m, tid);
     __syncthreads();
     const int nwords = (min((int)(range.y - start), GS3_BLOCK) + 63) >> 6;
-    for (int qw = 0; qw < nwords && !done; ++qw) {
+    bool wave_done = false;
+    for (int qw = 0; qw < nwords && !wave_done; ++qw) {
       uint64_t bits = uniform64(s.bits[w][qw]);
       while (bits) {
+        if (__ballot(!done) == 0ull) {
+          wave_done = true;
+          break;
+        }
         const int j = (qw << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        ++nev;
+        nev += done ? 0u : 1u;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
         const float dx = A.x - pxf, dy = A.y - pyf;
         const float power = splat_power(A.z, A.w, B.x, dx, dy);
-        if (power > 0.f || power < Cc.y) continue;
+        const bool pass = !done && power <= 0.f && power >= Cc.y;
         const float G = __expf(power);
         const float araw = B.y * G;
         const float a = fminf(GS3_ALPHA_MAX, araw);
         const float Tn = T * (1.f - a);
-        if (Tn < GS3_T_STOP) {
-          done = true;
-          break;
-        }
-        ++ncon;
+        const bool stop = pass && Tn < GS3_T_STOP;
+        const bool use = pass && !stop;
+        done = done || stop;
+        ncon += use ? 1u : 0u;
         const float4 TA = s.ta[j], TB = s.tb[j];
         // d power along the tangent: d = (u - px, v - py), dd = (du, dv); the
         // record holds the pre-scaled conic, the tangent record the plain one
         const float dpow = 2.f * (A.z * dx * TA.x + B.x * dy * TA.y) + A.w * (TA.x * dy + dx * TA.y) -
                            0.5f * (TA.z * dx * dx + TB.x * dy * dy) - TA.w * dx * dy;
         const float da = araw > GS3_ALPHA_MAX ? 0.f : (TB.y * G + B.y * G * dpow);
-        const float wt = a * T;
-        const float dw = da * T + a * dT;
+        const float wt = use ? a * T : 0.f;
+        const float dw = use ? da * T + a * dT : 0.f;
         C0 += B.z * wt;
         C1 += B.w * wt;
         C2 += Cc.x * wt;
         D0 += TB.z * wt + B.z * dw;
         D1 += TB.w * wt + B.w * dw;
         D2 += s.tc[j] * wt + Cc.x * dw;
-        dT = dT * (1.f - a) - T * da;
-        T = Tn;
+        dT = use ? dT * (1.f - a) - T * da : dT;
+        T = use ? Tn : T;
       }
     }
     __syncthreads();
@@ -414,60 +425,60 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
     __syncthreads();
     const int cnt = min((int)(range.y - start), kBwdBatch);
     const int nwords = (cnt + 63) >> 6;
-    for (int q = 0; q < nwords; ++q) {
-      uint64_t bits = uniform64(s.bits[w][q]);
+    int q = 0;
+    for (; q < nwords; ++q) {
+      const uint64_t word = uniform64(s.bits[w][q]);
+      uint64_t bits = word;
+      bool wave_done = false;
       while (bits) {
+        if (__ballot(!done) == 0ull) {
+          wave_done = true;
+          break;
+        }
         const int j = (q << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        float gr[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        bool contrib = false;
-        if (!done) {
-          ++nev;
-          const float4 A = s.a[j], B = s.b[j];
-          const float2 Cc = s.c[j];
-          const float dx = A.x - pxf, dy = A.y - pyf;
-          const float power = splat_power(A.z, A.w, B.x, dx, dy);
-          if (power <= 0.f && power >= Cc.y) {
-            const float G = __expf(power);
-            const float araw = B.y * G;
-            const float a = fminf(GS3_ALPHA_MAX, araw);
-            {
-              const float Tn = T * (1.f - a);
-              if (Tn < GS3_T_STOP) {
-                done = true;
-              } else {
-                const float cr = B.z, cg = B.w, cb = Cc.x;
-                const float wgt = a * T;
-                S0 += cr * wgt;
-                S1 += cg * wgt;
-                S2 += cb * wgt;
-                const float behind = (out0 - S0) * g0 + (out1 - S1) * g1 + (out2 - S2) * g2;
-                const float dL_da = T * (cr * g0 + cg * g1 + cb * g2) - behind / (1.f - a);
-                const bool clamped = araw > GS3_ALPHA_MAX;
-                const float dL_dG = clamped ? 0.f : B.y * dL_da;
-                const float dL_dpow = dL_dG * G;
-                gr[0] = dL_dpow * (2.f * A.z * dx + A.w * dy);
-                gr[1] = dL_dpow * (2.f * B.x * dy + A.w * dx);
-                gr[2] = dL_dpow * (-0.5f * dx * dx);
-                gr[3] = dL_dpow * (-dx * dy);
-                gr[4] = dL_dpow * (-0.5f * dy * dy);
-                gr[5] = clamped ? 0.f : G * dL_da;
-                gr[6] = wgt * g0;
-                gr[7] = wgt * g1;
-                gr[8] = wgt * g2;
-                contrib = true;
-                ++ncon;
-                T = Tn;
-              }
-            }
-          }
-        }
+        nev += done ? 0u : 1u;
+        const float4 A = s.a[j], B = s.b[j];
+        const float2 Cc = s.c[j];
+        const float dx = A.x - pxf, dy = A.y - pyf;
+        const float power = splat_power(A.z, A.w, B.x, dx, dy);
+        // predicated like the forward: lanes that do not contribute end with
+        // zero partials and unchanged T and S
+        const bool pass = !done && power <= 0.f && power >= Cc.y;
+        const float G = __expf(power);
+        const float araw = B.y * G;
+        const float a = fminf(GS3_ALPHA_MAX, araw);
+        const float Tn = T * (1.f - a);
+        const bool stop = pass && Tn < GS3_T_STOP;
+        const bool use = pass && !stop;
+        done = done || stop;
+        ncon += use ? 1u : 0u;
+        const float cr = B.z, cg = B.w, cb = Cc.x;
+        const float wgt = use ? a * T : 0.f;
+        S0 += cr * wgt;
+        S1 += cg * wgt;
+        S2 += cb * wgt;
+        const float behind = (out0 - S0) * g0 + (out1 - S1) * g1 + (out2 - S2) * g2;
+        const float dL_da = T * (cr * g0 + cg * g1 + cb * g2) - behind * __builtin_amdgcn_rcpf(1.f - a);
+        const bool open = use && araw <= GS3_ALPHA_MAX;  // the 0.99 clamp passes no gradient
+        const float dL_dpow = open ? B.y * dL_da * G : 0.f;
+        float gr[9];
+        gr[0] = dL_dpow * (2.f * A.z * dx + A.w * dy);
+        gr[1] = dL_dpow * (2.f * B.x * dy + A.w * dx);
+        gr[2] = dL_dpow * (-0.5f * dx * dx);
+        gr[3] = dL_dpow * (-dx * dy);
+        gr[4] = dL_dpow * (-0.5f * dy * dy);
+        gr[5] = open ? G * dL_da : 0.f;
+        gr[6] = wgt * g0;
+        gr[7] = wgt * g1;
+        gr[8] = wgt * g2;
+        T = use ? Tn : T;
         // wave sums of the 9 partial derivatives: values 0-7 are folded in
         // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
         // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
         // DPP reduction into lane 63.  26 VALU instructions in all.
         float E = 0.f, F = 0.f, H = 0.f;
-        if (__ballot(contrib) != 0ull) {
+        if (__ballot(use) != 0ull) {
           E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
           F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
           H = wave_sum_lane63(gr[8]);
@@ -480,7 +491,15 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           if (lane == 63) s.red[w][8][j] = H;
         }
       }
+      if (wave_done) {
+        // splats of this batch the wave did not walk: drop them from its
+        // mask, so the epilogue counts them as zero
+        if (lane == 0) s.bits[w][q] = word & ~bits;
+        break;
+      }
     }
+    if (lane == 0)
+      for (int q2 = q + 1; q2 < nwords; ++q2) s.bits[w][q2] = 0ull;
     __syncthreads();
     if (tid < cnt) {
       // a wave that skipped the splat contributes exactly zero

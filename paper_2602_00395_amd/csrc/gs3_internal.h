@@ -120,6 +120,7 @@ void launch_sum_partials(const double* partials, int n, double* out, hipStream_t
 struct TrArgs {
   float theta1, theta2, epsilon;
   int hutch;
+  uint32_t variant;  // GS3_TR_* bits
 };
 void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
                     TrArgs a, float* eta_out, float* dx_out, hipStream_t st);

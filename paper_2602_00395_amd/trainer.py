@@ -47,6 +47,7 @@ class TRConfig:
     budget: int = 30000
     seed: int = 4002
     probe_seed: int = 5002
+    variant: int = 0  # trust-region radius variant bits (0 = as printed)
 
 
 class TRTrainer:
@@ -71,9 +72,9 @@ class TRTrainer:
         if (t - 1) % c.l == 0:
             S2 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s2)]
             self.scene.hvp_diag(S2, c.nu, c.probe_seed + t, out=self.D)
-            self.scene.tr_step(self.g, self.D, c.theta1, c.theta2, eps)
+            self.scene.tr_step(self.g, self.D, c.theta1, c.theta2, eps, variant=c.variant)
         else:
-            self.scene.tr_step(self.g, None, c.theta1, c.theta2, eps)
+            self.scene.tr_step(self.g, None, c.theta1, c.theta2, eps, variant=c.variant)
 
 
 class AdamTrainer:

@@ -269,6 +269,42 @@ def test_tr_step_parity():
         s.close()
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 7])
+def test_tr_step_radius_variants(variant):
+    # GS3_TR_MEAN_EXACT (1), GS3_TR_SECOND_ORDER (2), GS3_TR_SH_JOINT (4) and
+    # combinations, against the oracle's mean_bound="exact",
+    # constants="second_order" and sh_rest="joint"
+    sc = syn.config2_scene(n=3000, n_cams=2, res=64)
+    x = sc.gt.astype(np.float32)
+    p, n = x.shape
+    rng = np.random.default_rng(31)
+    g = (rng.normal(size=x.shape) * 1e-3).astype(np.float32)
+    ghat = (rng.normal(size=x.shape) * 1e-3).astype(np.float32)
+    dhat = rng.uniform(-0.2, 1.0, size=x.shape).astype(np.float32)
+    x[10, :60] = -16.0
+    targets = [np.zeros((c.height, c.width, 3), np.float32) for c in sc.cameras]
+    say("tr_step variant", variant)
+    s = make_scene(x, targets, sc.cameras, 3)
+    s.import_(ghat=torch.tensor(ghat, device=DEV), dhat=torch.tensor(dhat, device=DEV))
+    eta_t = torch.empty((p, n), device=DEV)
+    dx_t = torch.empty((p, n), device=DEV)
+    eps = 3e-7
+    s.tr_step(torch.tensor(g, device=DEV), None, 0.9, 0.999, eps, eta_out=eta_t, dx_out=dx_t, variant=variant)
+    mb = "exact" if variant & 1 else "printed"
+    ko = "second_order" if variant & 2 else "printed"
+    sr = "joint" if variant & 4 else "base"
+    eta_want = Mth.shd_eta(x.astype(np.float64), eps, 3, mean_bound=mb, constants=ko, sh_rest=sr)
+    _, _, _, dxw, _ = Mth.tr_step(x, g, ghat, dhat, None, 0.9, 0.999, eps, 3, eta=eta_want)
+    eta_got = eta_t.cpu().numpy()
+    assert np.array_equal(np.isinf(eta_got), np.isinf(eta_want))
+    fin = np.isfinite(eta_want)
+    assert rel_l2(eta_got[fin], eta_want[fin]) <= TOL
+    errs = group_errors(dx_t.cpu().numpy(), dxw, p)
+    say("  step rel-L2", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
 def test_adam_and_adam_tr_parity():
     sc = syn.config2_scene(n=3000, n_cams=2, res=64)
     x = sc.init.astype(np.float32)

@@ -317,6 +317,29 @@ def test_trust_region_radius_meets_its_hellinger_budget(eps):
         assert abs(_ratio(col, c, eta_x[c], eps) - 1.0) < 1e-3
 
 
+@pytest.mark.parametrize("eps", [1e-7, 1e-9])
+def test_second_order_constants_spend_the_whole_budget(eps):
+    # with the second-order constants every class lands on H^2 = eps (to
+    # second order), for an axis-aligned and a rotated anisotropic Gaussian
+    col = np.zeros(14)
+    col[3:6] = np.log([0.3, 0.1, 0.05])
+    col[10] = -0.7
+    col[11:14] = [0.5, -0.3, 1.0]
+    for quat in ([0, 0, 0, 1], [0.3, -0.5, 0.2, 0.7]):
+        col[6:10] = quat
+        eta = Mth.shd_eta(col[:, None], eps, 0, mean_bound="exact", constants="second_order")[:, 0]
+        printed = Mth.shd_eta(col[:, None], eps, 0)[:, 0]
+        for c in range(3):
+            assert abs(_ratio(col, c, eta[c], eps) - 1.0) < 1e-3
+            assert abs(_ratio(col, 3 + c, eta[3 + c], eps) - 1.0) < 3e-3
+            assert abs(_ratio(col, 11 + c, eta[11 + c], eps, channel=c) - 1.0) < 3e-3
+            assert eta[3 + c] > printed[3 + c] and eta[11 + c] > printed[11 + c]
+        assert abs(_ratio(col, 10, eta[10], eps) - 1.0) < 3e-3
+        for c in range(4):
+            if np.isfinite(eta[6 + c]):
+                assert abs(_ratio(col, 6 + c, eta[6 + c], eps) - 1.0) < 1e-2
+
+
 def test_quaternion_beta_matches_second_difference_of_T():
     rng = np.random.default_rng(8)
     for _ in range(5):
@@ -433,3 +456,44 @@ def test_adam_learning_rate_schedule():
     assert lr0["mu"] == pytest.approx(3.2e-4) and lr1["mu"] == pytest.approx(3.2e-6)
     assert Mth.adam_lrs(50, 100, 2.0)["mu"] == pytest.approx(3.2e-5)
     assert lr0["f_rest"] == pytest.approx(1.25e-4)
+
+
+def test_sh_rest_abs_max_pins():
+    # degree 1: max over the sphere of C1 (|x| + |y| + |z|) = C1 sqrt(3) in closed form
+    assert abs(Mth.sh_rest_abs_max(1) - math.sqrt(3.0) * math.sqrt(3.0 / (4.0 * math.pi))) < 1e-9
+    assert Mth.sh_rest_abs_max(0) == 0.0
+    # brute force over a dense independent sampling never exceeds the maximum
+    # and comes close to it
+    rng = np.random.default_rng(77)
+    d = rng.normal(size=(200000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    for deg in (1, 2, 3):
+        v = G.sh_basis(torch.tensor(d), deg)[:, 1:].abs().sum(1).numpy()
+        S = Mth.sh_rest_abs_max(deg)
+        assert v.max() <= S + 1e-12 and v.max() >= S - 1e-4
+
+
+def test_joint_sh_radius_bounds_the_colour_change():
+    # moving every view-dependent coefficient of a channel by its full radius,
+    # with the worst signs for a direction, changes that direction's colour by
+    # at most eta_C; the DC radius is unchanged
+    rng = np.random.default_rng(78)
+    x = np.zeros((59, 1))
+    x[3:6, 0] = np.log([0.2, 0.1, 0.05])
+    x[6:10, 0] = [0.1, 0.2, -0.3, 0.9]
+    x[10, 0] = 0.3
+    x[11:14, 0] = [0.4, -0.2, 0.9]
+    eps = 1e-6
+    base = Mth.shd_eta(x, eps, 3)[:, 0]
+    joint = Mth.shd_eta(x, eps, 3, sh_rest="joint")[:, 0]
+    assert np.array_equal(base[:14], joint[:14])
+    d = rng.normal(size=(20000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = G.sh_basis(torch.tensor(d), 3).numpy()  # [n, 16]
+    for c in range(3):
+        eta_c = joint[11 + c] * G.SH_C0  # eta_C of the channel
+        rest = joint[11 + 3 + c::3][:15]
+        assert np.allclose(rest, rest[0])
+        worst = (np.abs(Y[:, 1:]) * rest[None, :]).sum(1)
+        assert worst.max() <= eta_c * (1 + 1e-9)
+        assert worst.max() >= 0.999 * eta_c
