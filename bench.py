@@ -62,6 +62,35 @@ def parse():
     return ap.parse_args()
 
 
+# stage -> (kernel name in the profile summaries, source file of the kernel)
+_KERNEL_OF = {"blend_bwd": ("k_blend_bwd", "blend.hip"), "blend_fwd": ("k_blend_fwd", "blend.hip"),
+              "blend_jvp": ("k_blend_jvp", "blend.hip"), "tr_step": ("k_tr_step<59>", "optim.hip"),
+              "adam_step": ("k_adam_step<59>", "optim.hip")}
+
+
+def measured_traffic(stage: str) -> int | None:
+    """HBM bytes per launch (read + written) of a stage's kernel, from the committed
+    FETCH_SIZE / WRITE_SIZE summary; None when that kernel's source (or the shared
+    header) has changed since the counters were taken."""
+    import hashlib
+
+    if stage not in _KERNEL_OF:
+        return None
+    kern, src = _KERNEL_OF[stage]
+    try:
+        with open(os.path.join(ROOT, "profiles", "object_scale_hbm_traffic.json")) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    csrc = os.path.join(ROOT, "paper_2602_00395_amd", "csrc")
+    for fn in (src, "gs3_internal.h"):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"].get(fn):
+                return None
+    k = rec["kernels"].get(kern)
+    return None if k is None else int(k["read_bytes"] + k["write_bytes"])
+
+
 def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int) -> dict | None:
     """Algorithmic work of one stage over the timed launches -> roofline entry."""
     if st["launches"] == 0 or st["total_ms"] <= 0:
@@ -71,7 +100,7 @@ def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int) -> dict 
         ops = (OPS_EVAL + OPS_CONTRIB[stage]) * st["work1"]
         ach = ops / sec / 1e12
         return dict(bound="alu", achieved=round(ach, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
-                    frac=round(ach / ALU_PEAK_TOPS, 4), traffic=None, kernel=stage,
+                    frac=round(ach / ALU_PEAK_TOPS, 4), traffic=measured_traffic(stage), kernel=stage,
                     avg_launch_ms=round(st["total_ms"] / st["launches"], 4),
                     evaluations_per_launch=st["work0"] // st["launches"],
                     contributing_per_launch=st["work1"] // st["launches"])
@@ -82,7 +111,7 @@ def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int) -> dict 
         bytes_ = per * p * n * st["launches"] + (8 * p * n * hutch_launches if stage == "tr_step" else 0)
         ach = bytes_ / sec / 1e9
         return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=stage,
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=measured_traffic(stage), kernel=stage,
                     avg_launch_ms=round(st["total_ms"] / st["launches"], 4),
                     bytes_per_launch=bytes_ // st["launches"])
     return dict(bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None, kernel=stage,

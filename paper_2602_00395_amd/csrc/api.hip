@@ -47,7 +47,8 @@ struct Entry {
   int64_t w0 = 0, w1 = 0;
 };
 std::vector<Entry> entries;
-constexpr int kSlots = 1 << 15;
+constexpr int kSlots = 1 << 12;
+constexpr size_t kSlotWords = 2 * GS3_PROF_SUB;
 unsigned long long* ctr = nullptr;
 int slots_used = 0;
 
@@ -68,7 +69,7 @@ Scope begin(const char* name, hipStream_t st, bool counted = false) {
   (void)hipEventRecord(e.a, st);
   if (counted && ctr && slots_used < kSlots) {
     e.slot = slots_used++;
-    sc.c = ctr + 2 * e.slot;
+    sc.c = ctr + kSlotWords * e.slot;
   }
   entries.push_back(e);
   sc.idx = (int)entries.size() - 1;
@@ -123,6 +124,7 @@ struct gs3_scene {
   int64_t pair_cap = 0;
   uint32_t *pt = nullptr, *pg = nullptr, *pt2 = nullptr, *pg2 = nullptr;
   float* partials = nullptr;
+  float* gsum = nullptr;  // float[9][N]: each Gaussian's summed partials
   // per-view image scratch
   uint2* ranges = nullptr;
   uint32_t* tile_order = nullptr;
@@ -134,6 +136,7 @@ struct gs3_scene {
   hipEvent_t done_ev = nullptr;
   // state of the last binned view
   const uint32_t* sorted_gid = nullptr;
+  const uint32_t* order = nullptr;  // Gaussians in depth order
   const uint32_t* sorted_tile = nullptr;
   int64_t n_pairs = 0;
 };
@@ -210,6 +213,7 @@ void free_all(gs3_scene* s) {
   dfree(s->pt2);
   dfree(s->pg2);
   dfree(s->partials);
+  dfree(s->gsum);
   dfree(s->ranges);
   dfree(s->tile_order);
   dfree(s->img);
@@ -300,6 +304,7 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   GS3_LAUNCHED();
   s->sorted_gid = tv;
   s->sorted_tile = tk;
+  s->order = order;
   s->n_pairs = n_pairs;
   return GS3_OK;
 }
@@ -336,7 +341,8 @@ void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st)
 void project_bwd(gs3_scene* s, const CamDev& cd, int mode, int acc, uint64_t seed, uint32_t i, float scale,
                  float* out, hipStream_t st) {
   auto p = prof::begin("project_bwd", st);
-  launch_project_bwd(s->x, s->N, s->deg, cd, s->rec, s->tiles, s->partials, mode, acc, seed, i, scale, out, st);
+  launch_project_bwd(s->x, s->N, s->deg, cd, s->order, s->offsets, s->counts, s->tiles, s->partials, s->gsum, mode,
+                     acc, seed, i, scale, out, st);
   prof::end(p, st, s->N, 0);
 }
 
@@ -386,10 +392,10 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
     max_px = std::max(max_px, px);
   }
   *resident = 4 * P * N * 5 + 12 * px_total;
-  // records, tangent records, eight u32 arrays, and pair buffers for about
+  // records, tangent records, eight u32 arrays, the summed partials, and pair buffers for about
   // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair, +25% slack)
   const int64_t pairs = 20 * N;
-  *peak_scratch = 96 * N + 32 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px;
+  *peak_scratch = 96 * N + 32 * N + 36 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px;
   return GS3_OK;
 }
 
@@ -446,6 +452,7 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
   step(dalloc(&s->kb, s->N));
   step(dalloc(&s->vb, s->N));
   step(dalloc(&s->counts, s->N));
+  step(dalloc(&s->gsum, 9 * s->N));
   step(dalloc(&s->offsets, s->N));
   step(dalloc(&s->total_dev, 4));
   step(dalloc((char**)&s->stmp, scan_temp_bytes(s->N)));
@@ -738,11 +745,11 @@ gs3_status gs3_profile_enable(const char* names) {
     return GS3_OK;
   }
   if (!prof::ctr) {
-    if (hipMalloc((void**)&prof::ctr, sizeof(unsigned long long) * 2 * prof::kSlots) != hipSuccess) {
+    if (hipMalloc((void**)&prof::ctr, sizeof(unsigned long long) * prof::kSlotWords * prof::kSlots) != hipSuccess) {
       prof::ctr = nullptr;
       return fail(GS3_ENOMEM, "profiler counter allocation failed");
     }
-    GS3_HIP(hipMemset(prof::ctr, 0, sizeof(unsigned long long) * 2 * prof::kSlots));
+    GS3_HIP(hipMemset(prof::ctr, 0, sizeof(unsigned long long) * prof::kSlotWords * prof::kSlots));
   }
   prof::names = "," + std::string(names) + ",";
   prof::active.store(true);
@@ -754,7 +761,7 @@ gs3_status gs3_profile_reset(void) {
   for (auto& e : prof::entries)
     if (e.b) (void)hipEventSynchronize(e.b);
   prof::clear_locked();
-  if (prof::ctr) GS3_HIP(hipMemset(prof::ctr, 0, sizeof(unsigned long long) * 2 * prof::kSlots));
+  if (prof::ctr) GS3_HIP(hipMemset(prof::ctr, 0, sizeof(unsigned long long) * prof::kSlotWords * prof::kSlots));
   return GS3_OK;
 }
 
@@ -777,14 +784,15 @@ gs3_status gs3_profile_read(const char* name, int64_t* launches, double* total_m
       need_ctr |= e.slot >= 0;
     }
   if (need_ctr) {
-    host.resize(2 * (size_t)prof::slots_used);
+    host.resize(prof::kSlotWords * (size_t)prof::slots_used);
     if (!host.empty())
       GS3_HIP(hipMemcpy(host.data(), prof::ctr, host.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     for (auto& e : prof::entries)
-      if (e.name == name && e.slot >= 0) {
-        w0 += (int64_t)host[2 * e.slot];
-        w1 += (int64_t)host[2 * e.slot + 1];
-      }
+      if (e.name == name && e.slot >= 0)
+        for (int k = 0; k < GS3_PROF_SUB; ++k) {
+          w0 += (int64_t)host[prof::kSlotWords * e.slot + 2 * k];
+          w1 += (int64_t)host[prof::kSlotWords * e.slot + 2 * k + 1];
+        }
   }
   if (launches) *launches = n;
   if (total_ms) *total_ms = ms;

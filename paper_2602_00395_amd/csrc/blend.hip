@@ -43,8 +43,9 @@ __device__ __forceinline__ int tile_of_block(int b, const uint32_t* order, int n
   return (b & 7) * chunk + (b >> 3);
 }
 
-// Measurement hook: when `ctr` is not null, adds this workgroup's number of
-// (pixel, splat) evaluations and of contributing evaluations to ctr[0], ctr[1].
+// Measurement hook: when `ctr` is not null, adds this wave's number of
+// (pixel, splat) evaluations and of contributing evaluations to one of the
+// launch's GS3_PROF_SUB counter pairs (ctr[2 s], ctr[2 s + 1]).
 __device__ __forceinline__ void count_evals(unsigned long long* ctr, uint32_t nev, uint32_t ncon) {
   if (ctr == nullptr) return;
   unsigned long long a = nev, b = ncon;
@@ -54,8 +55,9 @@ __device__ __forceinline__ void count_evals(unsigned long long* ctr, uint32_t ne
     b += __shfl_xor(b, m, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(ctr, a);
-    atomicAdd(ctr + 1, b);
+    const int sub = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % GS3_PROF_SUB);
+    atomicAdd(ctr + 2 * sub, a);
+    atomicAdd(ctr + 2 * sub + 1, b);
   }
 }
 

@@ -5,6 +5,10 @@
 #include <stdint.h>
 
 #define GS3_TILE 16
+// measurement counters of one profiled launch are spread over this many
+// (evaluations, contributions) pairs, so the waves' atomics do not all hit
+// one address
+#define GS3_PROF_SUB 64
 #define GS3_BLOCK (GS3_TILE * GS3_TILE)
 
 // Rasteriser constants of the original 3DGS design (the paper states only the
@@ -63,8 +67,11 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
                         const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
                         const float* tangent, TRec* trec, hipStream_t st);
 // mode 0: grad[r][g] = (accumulate ? grad : 0) + dL/dx; mode 1: out[r][g] += scale * z_r * dL/dx
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
-                        const uint32_t* tiles, const float* partials, int mode, int accumulate, uint64_t seed,
+// order / offsets / counts: the view's depth order, first pair and tile count
+// per depth rank; gsum: float[9][n] scratch for the summed partials
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const uint32_t* order,
+                        const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
+                        const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
                         uint32_t probe_index, float scale, float* out, hipStream_t st);
 
 // sorting and binning

@@ -25,9 +25,6 @@
 //   beta_c = 2 sum_{i<j} A_ij^2 (s_i/s_j - s_j/s_i)^2,
 // with A_01 = -w_2, A_02 = w_1, A_12 = -w_0; it vanishes for isotropic s.
 //
-// One thread per Gaussian: the radius needs the whole Gaussian, and rows are
-// read and written row-major across threads, so every access is a coalesced
-// 256-byte wave load/store (the kernel is HBM-bound).
 #include "gs3_internal.h"
 #include "gs3tr.h"
 
@@ -112,16 +109,32 @@ __device__ __forceinline__ float row_radius(const Radius& r, int row) {
 
 __device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
 
+// Work split: a workgroup takes 64 consecutive Gaussians and its four waves
+// take a quarter of the rows each (wave w: rows [w R, (w+1) R), R = ceil(P/4)),
+// so every row access of a wave is one coalesced 256-byte transaction and four
+// times more waves keep HBM busy than with one thread per Gaussian.  Every
+// thread evaluates its Gaussian's radius from the parameters before the
+// update; the barrier keeps the rows the radius reads unchanged until all
+// four waves have read them.
+constexpr int kGaussPerBlock = 64;
+
 template <int P>
 __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const float* __restrict__ grad,
                                                   float* __restrict__ ghat, float* __restrict__ dhat,
                                                   const float* __restrict__ D, int64_t n, TrArgs a,
                                                   float* __restrict__ eta_out, float* __restrict__ dx_out) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const Radius rad = trust_radius(x, n, g, a.epsilon, a.variant, P == 14 ? 0 : (P == 23 ? 1 : (P == 38 ? 2 : 3)));
-#pragma unroll 8
-  for (int r = 0; r < P; ++r) {
+  constexpr int R = (P + 3) / 4;
+  const int64_t g = (int64_t)blockIdx.x * kGaussPerBlock + (threadIdx.x & 63);
+  const int r0 = (threadIdx.x >> 6) * R;
+  const bool live = g < n;
+  Radius rad;
+  if (live) rad = trust_radius(x, n, g, a.epsilon, a.variant, P == 14 ? 0 : (P == 23 ? 1 : (P == 38 ? 2 : 3)));
+  __syncthreads();
+  if (!live) return;
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) {
+    const int r = r0 + rr;
+    if (r >= P) break;
     const int64_t k = (int64_t)r * n + g;
     const float eta = row_radius(rad, r);
     const float gh = a.theta1 * ghat[k] + (1.f - a.theta1) * grad[k];
@@ -145,13 +158,21 @@ template <int P>
 __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const float* __restrict__ grad,
                                                     float* __restrict__ m, float* __restrict__ v, int64_t n,
                                                     AdamArgs a) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  Radius rad;
+  constexpr int R = (P + 3) / 4;
+  const int64_t g = (int64_t)blockIdx.x * kGaussPerBlock + (threadIdx.x & 63);
+  const int r0 = (threadIdx.x >> 6) * R;
+  const bool live = g < n;
   const bool clip = a.epsilon > 0.f;
-  if (clip) rad = trust_radius(x, n, g, a.epsilon, 0u, 0);
-#pragma unroll 8
-  for (int r = 0; r < P; ++r) {
+  Radius rad;
+  if (clip) {
+    if (live) rad = trust_radius(x, n, g, a.epsilon, 0u, 0);
+    __syncthreads();
+  }
+  if (!live) return;
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) {
+    const int r = r0 + rr;
+    if (r >= P) break;
     const int64_t k = (int64_t)r * n + g;
     const float gr = grad[k];
     const float mm = a.b1 * m[k] + (1.f - a.b1) * gr;
@@ -179,11 +200,12 @@ __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const 
 
 void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
                     TrArgs a, float* eta_out, float* dx_out, hipStream_t st) {
-  GS3_P_DISPATCH(deg, k_tr_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, ghat, dhat, D, n, a,
-                 eta_out, dx_out);
+  const dim3 grid((unsigned)((n + kGaussPerBlock - 1) / kGaussPerBlock));
+  GS3_P_DISPATCH(deg, k_tr_step, grid, dim3(256), 0, st, x, grad, ghat, dhat, D, n, a, eta_out, dx_out);
 }
 
 void launch_adam_step(float* x, const float* grad, float* m, float* v, int64_t n, int deg, const AdamArgs& a,
                       hipStream_t st) {
-  GS3_P_DISPATCH(deg, k_adam_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, grad, m, v, n, a);
+  const dim3 grid((unsigned)((n + kGaussPerBlock - 1) / kGaussPerBlock));
+  GS3_P_DISPATCH(deg, k_adam_step, grid, dim3(256), 0, st, x, grad, m, v, n, a);
 }

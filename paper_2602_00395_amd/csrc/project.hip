@@ -289,16 +289,63 @@ __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x
   trec[g] = t;
 }
 
+// Sum of each Gaussian's per-(Gaussian, tile) partials, which sit in the
+// contiguous slots [offsets[i], offsets[i] + counts[i]) of the Gaussian of
+// depth rank i (order[i]): G[k][order[i]], k < 9, summed in slot order.  A
+// workgroup takes 28 consecutive depth ranks, whose slots form one contiguous
+// run; the run is streamed through LDS in chunks with coalesced loads, and
+// thread (j, k) adds component k of rank j's slots in order.  Invisible
+// Gaussians (count 0) get zeros.
+constexpr int kSumRanks = 28;      // 28 x 9 = 252 of the 256 threads
+constexpr int kSumChunk = 4096;    // floats per LDS chunk
+
+__global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __restrict__ order,
+                                                            const uint32_t* __restrict__ offsets,
+                                                            const uint32_t* __restrict__ counts,
+                                                            const float* __restrict__ partials, int64_t n,
+                                                            float* __restrict__ G) {
+  __shared__ float buf[kSumChunk];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kSumRanks;
+  const int64_t i1 = i0 + kSumRanks < n ? i0 + kSumRanks : n;
+  const int j = tid / 9, k = tid % 9;
+  const int64_t i = i0 + j;
+  const bool mine = tid < 9 * kSumRanks && i < i1;
+  const int64_t lo = (int64_t)offsets[i0] * 9;
+  const int64_t hi = ((int64_t)offsets[i1 - 1] + counts[i1 - 1]) * 9;
+  int64_t first = 0, last = 0;  // my float indices: first, first + 9, ..., < last
+  if (mine) {
+    first = (int64_t)offsets[i] * 9 + k;
+    last = ((int64_t)offsets[i] + counts[i]) * 9;
+  }
+  float acc = 0.f;
+  for (int64_t base = lo; base < hi; base += kSumChunk) {
+    const int64_t end = base + kSumChunk < hi ? base + kSumChunk : hi;
+    for (int64_t f = base + tid; f < end; f += 256) buf[f - base] = partials[f];
+    __syncthreads();
+    for (; first < last && first < end; first += 9) acc += buf[first - base];
+    __syncthreads();
+  }
+  if (mine) G[(int64_t)k * n + order[i]] = acc;
+}
+
+// Chain rule from the summed screen-space partials G (d/du, d/dv, d/dconic
+// a, b, c, d/dalpha, d/drgb) to the raw parameters.  blockIdx.y picks the
+// work of a thread: 0..9 one forward-mode sweep along geometric row y (mean,
+// log-scale, quaternion; the mean rows also move the SH view direction), 10
+// the opacity logit and the SH rows, d rgb_c / d f_kc = Y_k(dir) where the
+// colour clamp is inactive.  One thread per (Gaussian, role) keeps ten times
+// more waves in flight than one thread per Gaussian walking every sweep.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
-                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
-                                                      const float* __restrict__ partials, int mode, int accumulate,
+                                                      const uint32_t* __restrict__ tiles,
+                                                      const float* __restrict__ G, int mode, int accumulate,
                                                       uint64_t inner, float scale, float* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int P = 11 + 3 * K;
-  const uint32_t cnt = tiles[g];
+  const int role = blockIdx.y;
   auto emit = [&](int r, float v) {
     const int64_t k = (int64_t)r * n + g;
     if (mode == 0) {
@@ -307,48 +354,45 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
       out[k] += scale * probe_sign(inner, (uint64_t)k) * v;
     }
   };
-  if (cnt == 0u) {
+  if (tiles[g] == 0u) {
     if (mode == 0 && !accumulate) {
-#pragma unroll
-      for (int r = 0; r < P; ++r) out[(int64_t)r * n + g] = 0.f;
+      if (role < 10) {
+        out[(int64_t)role * n + g] = 0.f;
+      } else {
+        for (int r = 10; r < P; ++r) out[(int64_t)r * n + g] = 0.f;
+      }
     }
     return;
   }
-  // sum the per-(Gaussian, tile) partials: contiguous slots [off, off + cnt)
-  const uint32_t off = __float_as_uint(rec[g].c.z);
-  float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (uint32_t s = 0; s < cnt; ++s) {
-    const float* pp = partials + (int64_t)(off + s) * 9;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) G[k] += pp[k];
-  }
-  // geometric rows: one forward-mode sweep each
-  const float sv[3] = {exp_ls(x[3 * n + g]), exp_ls(x[4 * n + g]), exp_ls(x[5 * n + g])};
-  for (int k = 0; k < 10; ++k) {
-    auto src = [&](int r) { return Dual{x[(int64_t)r * n + g], r == k ? 1.f : 0.f}; };
+  auto Gk = [&](int k) { return G[(int64_t)k * n + g]; };
+  if (role < 10) {
+    const float sv[3] = {exp_ls(x[3 * n + g]), exp_ls(x[4 * n + g]), exp_ls(x[5 * n + g])};
+    auto src = [&](int r) { return Dual{x[(int64_t)r * n + g], r == role ? 1.f : 0.f}; };
     Proj<Dual> p;
     project_geo<Dual>(src, sv, cam, p);
-    float d = G[0] * p.u.t + G[1] * p.v.t + G[2] * p.ca.t + G[3] * p.cb.t + G[4] * p.cc.t;
-    if (k < 3) {
+    float d = Gk(0) * p.u.t + Gk(1) * p.v.t + Gk(2) * p.ca.t + Gk(3) * p.cb.t + Gk(4) * p.cc.t;
+    if (role < 3) {
       Dual rgb[3];
       bool pos[3];
       colour<Dual, DEG>(src, cam, rgb, pos);
-      d += G[6] * rgb[0].t + G[7] * rgb[1].t + G[8] * rgb[2].t;
+      d += Gk(6) * rgb[0].t + Gk(7) * rgb[1].t + Gk(8) * rgb[2].t;
     }
-    emit(k, d);
+    emit(role, d);
+    return;
   }
-  // opacity logit
   const float s = sigmoid_(x[10 * n + g]);
-  emit(10, G[5] * s * (1.f - s));
-  // SH rows: d rgb_c / d f_kc = Y_k(dir) where the clamp is inactive
+  emit(10, Gk(5) * s * (1.f - s));
   auto srcf = [&](int r) { return x[(int64_t)r * n + g]; };
   float rgb[3], Y[K];
   bool pos[3];
   colour<float, DEG>(srcf, cam, rgb, pos, Y);
+  const float G6 = Gk(6), G7 = Gk(7), G8 = Gk(8);
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) emit(11 + 3 * k + ch, pos[ch] ? Y[k] * G[6 + ch] : 0.f);
+  for (int k = 0; k < K; ++k) {
+    emit(11 + 3 * k, pos[0] ? Y[k] * G6 : 0.f);
+    emit(12 + 3 * k, pos[1] ? Y[k] * G7 : 0.f);
+    emit(13 + 3 * k, pos[2] ? Y[k] * G8 : 0.f);
+  }
 }
 
 uint64_t probe_inner(uint64_t seed, uint32_t i) {
@@ -383,9 +427,12 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
                    probe_inner(seed, probe_index), tangent, trec);
 }
 
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
-                        const uint32_t* tiles, const float* partials, int mode, int accumulate, uint64_t seed,
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const uint32_t* order,
+                        const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
+                        const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
                         uint32_t probe_index, float scale, float* out, hipStream_t st) {
-  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, rec, tiles, partials,
-                   mode, accumulate, probe_inner(seed, probe_index), scale, out);
+  hipLaunchKernelGGL(k_sum_pair_partials, dim3(blocks_for(n, kSumRanks)), dim3(256), 0, st, order, offsets, counts,
+                     partials, n, gsum);
+  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256), 11), dim3(256), 0, st, x, n, cam, tiles, gsum, mode,
+                   accumulate, probe_inner(seed, probe_index), scale, out);
 }

@@ -13,7 +13,7 @@
 //
 // Radix pass = upsweep (per-block digit histograms), per-digit scan across
 // blocks (one workgroup per digit), scatter.  In the scatter each wave64
-// ranks its own contiguous run of 1024 keys: lanes holding the same digit are
+// ranks its own contiguous run of 256 keys: lanes holding the same digit are
 // found with 8 ballots, and a per-wave running count per digit in LDS gives
 // each key its rank without any workgroup barrier inside the run; one barrier
 // then turns the four waves' counts into output offsets.  No workgroup ever
@@ -26,8 +26,10 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;  // items per thread per block
+constexpr int kItems = 16;  // scan: items per thread per block
 constexpr int kTileItems = kThreads * kItems;
+constexpr int kRsItems = 4;  // radix passes: keys per thread (per lane and round) per block
+constexpr int kRsTile = kThreads * kRsItems;
 constexpr int kRadix = 256;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -112,9 +114,9 @@ __global__ __launch_bounds__(kThreads) void k_rs_upsweep(const uint32_t* __restr
   __shared__ uint32_t h[kRadix];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kTileItems;
-#pragma unroll 4
-  for (int r = 0; r < kItems; ++r) {
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
     const int64_t i = base + r * kThreads + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xffu], 1u);
   }
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scan(uint32_t* __restrict__ his
 
 // Keys [blk + w * kWaveItems, + kWaveItems) belong to wave w of block blk,
 // 64 per round; `vals` null means value = index.
-constexpr int kWaveItems = kItems * 64;
+constexpr int kWaveItems = kRsItems * 64;
 
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vals,
@@ -159,10 +161,10 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
   }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t wbase = (int64_t)blockIdx.x * kTileItems + (int64_t)w * kWaveItems;
-  uint32_t k[kItems], v[kItems], rk[kItems];
+  const int64_t wbase = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kWaveItems;
+  uint32_t k[kRsItems], v[kRsItems], rk[kRsItems];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kRsItems; ++r) {
     const int64_t i = wbase + r * 64 + lane;
     const bool valid = i < n;
     k[r] = valid ? keys[i] : 0u;
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kRsItems; ++r) {
     const int64_t i = wbase + r * 64 + lane;
     if (i < n) {
       const uint32_t pos = cnt[w][(k[r] >> shift) & 0xffu] + rk[r];
@@ -320,7 +322,7 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
 }
 
 size_t radix_temp_bytes(int64_t n) {
-  const int64_t nb = nblk(n > 0 ? n : 1, kTileItems);
+  const int64_t nb = nblk(n > 0 ? n : 1, kRsTile);
   return (size_t)(kRadix * nb + kRadix) * sizeof(uint32_t);
 }
 
@@ -330,7 +332,7 @@ void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* 
   *keys_out = ka;
   *vals_out = va;
   if (n <= 0) return;
-  const int nb = (int)nblk(n, kTileItems);
+  const int nb = (int)nblk(n, kRsTile);
   uint32_t* hist = (uint32_t*)temp;
   uint32_t* dtot = hist + (size_t)kRadix * nb;
   const uint32_t *kin = keys_in, *vin = vals_in;
