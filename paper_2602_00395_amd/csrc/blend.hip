@@ -152,9 +152,11 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = ranges[t];
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  bool done = !inside;
+  // 1 while the pixel still blends; an integer rather than a bool, so the
+  // loop carries it in a vector register instead of a scalar lane mask
+  uint32_t live = inside ? 1u : 0u;
   for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
-    if (__syncthreads_count(done) == GS3_BLOCK) break;
+    if (__syncthreads_count(live) == 0) break;
     const uint32_t i = start + tid;
     uint32_t m = 0u;
     if (i < range.y) {
@@ -172,25 +174,25 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
       uint64_t bits = uniform64(s.bits[w][q]);
       while (bits) {
         // every pixel of the block has stopped: the rest is never read
-        if (__ballot(!done) == 0ull) {
+        if (__ballot(live) == 0ull) {
           wave_done = true;
           break;
         }
         const int j = (q << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        nev += done ? 0u : 1u;
+        nev += live;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
         const float dx = A.x - pxf, dy = A.y - pyf;
         const float power = splat_power(A.z, A.w, B.x, dx, dy);
         // predicated rather than branched: nearly every wave has a lane
         // that contributes, so a branch would only add mask bookkeeping
-        const bool pass = !done && power <= 0.f && power >= Cc.y;
+        const bool pass = live && power <= 0.f && power >= Cc.y;
         const float a = fminf(GS3_ALPHA_MAX, B.y * __expf(power));
         const float Tn = T * (1.f - a);
         const bool stop = pass && Tn < GS3_T_STOP;
         const bool use = pass && !stop;
-        done = done || stop;
+        live = stop ? 0u : live;
         ncon += use ? 1u : 0u;
         const float w8 = use ? a * T : 0.f;
         C0 += B.z * w8;
@@ -239,9 +241,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   const uint2 range = ranges[t];
   float T = 1.f, dT = 0.f;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
-  bool done = !inside;
+  uint32_t live = inside ? 1u : 0u;  // as in the forward
   for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
-    if (__syncthreads_count(done) == GS3_BLOCK) break;
+    if (__syncthreads_count(live) == 0) break;
     const uint32_t i = start + tid;
     uint32_t m = 0u;
     if (i < range.y) {
@@ -263,25 +265,25 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
     for (int qw = 0; qw < nwords && !wave_done; ++qw) {
       uint64_t bits = uniform64(s.bits[w][qw]);
       while (bits) {
-        if (__ballot(!done) == 0ull) {
+        if (__ballot(live) == 0ull) {
           wave_done = true;
           break;
         }
         const int j = (qw << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        nev += done ? 0u : 1u;
+        nev += live;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
         const float dx = A.x - pxf, dy = A.y - pyf;
         const float power = splat_power(A.z, A.w, B.x, dx, dy);
-        const bool pass = !done && power <= 0.f && power >= Cc.y;
+        const bool pass = live && power <= 0.f && power >= Cc.y;
         const float G = __expf(power);
         const float araw = B.y * G;
         const float a = fminf(GS3_ALPHA_MAX, araw);
         const float Tn = T * (1.f - a);
         const bool stop = pass && Tn < GS3_T_STOP;
         const bool use = pass && !stop;
-        done = done || stop;
+        live = stop ? 0u : live;
         ncon += use ? 1u : 0u;
         const float4 TA = s.ta[j], TB = s.tb[j];
         // d power along the tangent: d = (u - px, v - py), dd = (du, dv); the
@@ -406,10 +408,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
     g2 = cot[o + 2];
   }
   float T = 1.f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
-  bool done = !inside;
+  uint32_t live = inside ? 1u : 0u;  // as in the forward
   uint32_t start = range.x;
   for (; start < range.y; start += kBwdBatch) {
-    if (__syncthreads_count(done) == GS3_BLOCK) break;
+    if (__syncthreads_count(live) == 0) break;
     const uint32_t i = start + tid;
     if (tid < kBwdBatch) {
       uint32_t m = 0u;
@@ -433,27 +435,27 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
       uint64_t bits = word;
       bool wave_done = false;
       while (bits) {
-        if (__ballot(!done) == 0ull) {
+        if (__ballot(live) == 0ull) {
           wave_done = true;
           break;
         }
         const int j = (q << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        nev += done ? 0u : 1u;
+        nev += live;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
         const float dx = A.x - pxf, dy = A.y - pyf;
         const float power = splat_power(A.z, A.w, B.x, dx, dy);
         // predicated like the forward: lanes that do not contribute end with
         // zero partials and unchanged T and S
-        const bool pass = !done && power <= 0.f && power >= Cc.y;
+        const bool pass = live && power <= 0.f && power >= Cc.y;
         const float G = __expf(power);
         const float araw = B.y * G;
         const float a = fminf(GS3_ALPHA_MAX, araw);
         const float Tn = T * (1.f - a);
         const bool stop = pass && Tn < GS3_T_STOP;
         const bool use = pass && !stop;
-        done = done || stop;
+        live = stop ? 0u : live;
         ncon += use ? 1u : 0u;
         const float cr = B.z, cg = B.w, cb = Cc.x;
         const float wgt = use ? a * T : 0.f;
