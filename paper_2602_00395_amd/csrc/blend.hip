@@ -26,8 +26,11 @@
 // The backward pass runs front to back as well, recomputing T exactly as the
 // forward did (so the stop decision repeats bit for bit without storing any
 // per-pixel state) and obtaining the weight of the splats behind splat i from
-// the stored output: sum_{j>i} c_j abar_j T_j + T_final bg = C_out - S_i,
-// S_i the running front-to-back sum.  Gradients of each (splat, tile) pair are
+// the stored output: (sum_{j>i} c_j abar_j T_j + T_final bg) . dL/dC =
+// (C_out - S_i) . dL/dC, S_i the running front-to-back sum, kept as one
+// running dot product.  Per pixel it reduces dL/dpower times dx, dy, dx^2,
+// dx dy and dy^2; the conic coefficients are constant over the splat, so
+// the derivatives along u, v and the conic are formed once per splat.  Gradients of each (splat, tile) pair are
 // reduced over the workgroup (a transposed wave64 reduction with permlane
 // swaps and DPP row scans, then the four waves in LDS in a fixed order) and
 // written to the pair's own slot: no float atomics, so the backward is
@@ -407,7 +410,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
     g1 = cot[o + 1];
     g2 = cot[o + 2];
   }
-  float T = 1.f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
+  float T = 1.f;
+  // (C_out - S) . dL/dC: the colour of everything behind the current splat
+  float behind = out0 * g0 + out1 * g1 + out2 * g2;
   uint32_t live = inside ? 1u : 0u;  // as in the forward
   uint32_t start = range.x;
   for (; start < range.y; start += kBwdBatch) {
@@ -447,7 +452,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
         const float dx = A.x - pxf, dy = A.y - pyf;
         const float power = splat_power(A.z, A.w, B.x, dx, dy);
         // predicated like the forward: lanes that do not contribute end with
-        // zero partials and unchanged T and S
+        // zero partials and unchanged T and behind
         const bool pass = live && power <= 0.f && power >= Cc.y;
         const float G = __expf(power);
         const float araw = B.y * G;
@@ -457,21 +462,19 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
         const bool use = pass && !stop;
         live = stop ? 0u : live;
         ncon += use ? 1u : 0u;
-        const float cr = B.z, cg = B.w, cb = Cc.x;
+        const float cdot = B.z * g0 + B.w * g1 + Cc.x * g2;
         const float wgt = use ? a * T : 0.f;
-        S0 += cr * wgt;
-        S1 += cg * wgt;
-        S2 += cb * wgt;
-        const float behind = (out0 - S0) * g0 + (out1 - S1) * g1 + (out2 - S2) * g2;
-        const float dL_da = T * (cr * g0 + cg * g1 + cb * g2) - behind * __builtin_amdgcn_rcpf(1.f - a);
+        behind -= wgt * cdot;
+        const float dL_da = T * cdot - behind * __builtin_amdgcn_rcpf(1.f - a);
         const bool open = use && araw <= GS3_ALPHA_MAX;  // the 0.99 clamp passes no gradient
         const float dL_dpow = open ? B.y * dL_da * G : 0.f;
+        const float pt = dL_dpow * dx, pu = dL_dpow * dy;
         float gr[9];
-        gr[0] = dL_dpow * (2.f * A.z * dx + A.w * dy);
-        gr[1] = dL_dpow * (2.f * B.x * dy + A.w * dx);
-        gr[2] = dL_dpow * (-0.5f * dx * dx);
-        gr[3] = dL_dpow * (-dx * dy);
-        gr[4] = dL_dpow * (-0.5f * dy * dy);
+        gr[0] = pt;
+        gr[1] = pu;
+        gr[2] = pt * dx;
+        gr[3] = pt * dy;
+        gr[4] = pu * dy;
         gr[5] = open ? G * dL_da : 0.f;
         gr[6] = wgt * g0;
         gr[7] = wgt * g1;
@@ -511,10 +514,21 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
       const uint64_t bit = 1ull << (tid & 63);
       const bool h0 = s.bits[0][tid >> 6] & bit, h1 = s.bits[1][tid >> 6] & bit;
       const bool h2 = s.bits[2][tid >> 6] & bit, h3 = s.bits[3][tid >> 6] & bit;
+      float R[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k)
-        dst[k] = (((h0 ? s.red[0][k][tid] : 0.f) + (h1 ? s.red[1][k][tid] : 0.f)) + (h2 ? s.red[2][k][tid] : 0.f)) +
-                 (h3 ? s.red[3][k][tid] : 0.f);
+        R[k] = (((h0 ? s.red[0][k][tid] : 0.f) + (h1 ? s.red[1][k][tid] : 0.f)) + (h2 ? s.red[2][k][tid] : 0.f)) +
+               (h3 ? s.red[3][k][tid] : 0.f);
+      // power = qa dx^2 + qc dy^2 + qb dx dy, (qa, qb, qc) = (-a/2, -b, -c/2),
+      // dx = u - px, dy = v - py
+      const float qa = s.a[tid].z, qb = s.a[tid].w, qc = s.b[tid].x;
+      dst[0] = 2.f * qa * R[0] + qb * R[1];
+      dst[1] = 2.f * qc * R[1] + qb * R[0];
+      dst[2] = -0.5f * R[2];
+      dst[3] = -R[3];
+      dst[4] = -0.5f * R[4];
+#pragma unroll
+      for (int k = 5; k < 9; ++k) dst[k] = R[k];
     }
     __syncthreads();
   }

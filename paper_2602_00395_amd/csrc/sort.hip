@@ -217,23 +217,57 @@ __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* __restric
 // One thread per pair: the owning Gaussian (in depth order) is the last entry
 // whose exclusive offset is <= the pair index (a zero-count entry shares its
 // offset with the next one, so the last such entry is the owner).  Writes are
-// then contiguous across the wave.  The thread of a Gaussian's first pair also
-// records the Gaussian's first pair in its splat record.
+// then contiguous across the wave.  Zero-count (culled) Gaussians sort last,
+// so the owners of a workgroup's 256 pairs are at most 256 consecutive
+// entries: two threads find the first and last owner in global memory, the
+// offsets in between are staged in LDS and every thread searches those.  The
+// thread of a Gaussian's first pair also records the Gaussian's first pair in
+// its splat record.
+__device__ __forceinline__ int64_t last_le(const uint32_t* __restrict__ offsets, int64_t n, uint32_t target) {
+  int64_t lo = 0, hi = n;  // the first index with offsets[idx] > target is in (lo, hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (offsets[mid] <= target) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets, Rec* __restrict__ rec,
                                                      const uint2* __restrict__ rect, int64_t n, int64_t n_pairs,
                                                      int tiles_x, uint32_t* __restrict__ pair_tile,
                                                      uint32_t* __restrict__ pair_gid) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pairs) return;
-  int64_t lo = 0, hi = n;  // first index with offsets[idx] > i is in (lo, hi]
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (offsets[mid] <= (uint32_t)i) lo = mid;
-    else hi = mid;
+  __shared__ uint32_t soff[256];
+  __shared__ int64_t bounds[2];
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  if (tid < 2) {
+    const int64_t p = tid == 0 ? p0 : (p0 + 255 < n_pairs ? p0 + 255 : n_pairs - 1);
+    bounds[tid] = last_le(offsets, n, (uint32_t)p);
   }
-  const uint32_t g = order[lo];
-  const uint32_t k = (uint32_t)i - offsets[lo];
+  __syncthreads();
+  const int64_t first = bounds[0];
+  const int64_t span = bounds[1] - first + 1;
+  const bool staged = span <= 256;
+  if (staged && tid < span) soff[tid] = offsets[first + tid];
+  __syncthreads();
+  const int64_t i = p0 + tid;
+  if (i >= n_pairs) return;
+  int64_t own;
+  if (staged) {
+    int a = 0, b = (int)span;  // the last j with soff[j] <= i is in [a, b)
+    while (b - a > 1) {
+      const int mid = (a + b) >> 1;
+      if (soff[mid] <= (uint32_t)i) a = mid;
+      else b = mid;
+    }
+    own = first + a;
+  } else {
+    own = last_le(offsets, n, (uint32_t)i);
+  }
+  const uint32_t g = order[own];
+  const uint32_t k = (uint32_t)i - offsets[own];
   const uint2 rc = rect[g];
   const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
   const int w = x1 - x0;
