@@ -130,6 +130,8 @@ struct gs3_scene {
   uint32_t* tile_order = nullptr;
   bool have_order = false;
   float *img = nullptr, *cot = nullptr, *tan_img = nullptr, *ssim_tmp = nullptr;
+  uint32_t* pix_last = nullptr;  // per pixel: 1 + pair index of the last contributing splat
+  float* pix_T = nullptr;        // per pixel: final transmittance
   double *dpart = nullptr, *dsum = nullptr;
   uint32_t* host_u32 = nullptr;
   double* host_f64 = nullptr;
@@ -219,6 +221,8 @@ void free_all(gs3_scene* s) {
   dfree(s->img);
   dfree(s->cot);
   dfree(s->tan_img);
+  dfree(s->pix_last);
+  dfree(s->pix_T);
   dfree(s->ssim_tmp);
   dfree(s->dpart);
   dfree(s->dsum);
@@ -319,22 +323,22 @@ const float* target_of(gs3_scene* s, int cam) { return s->targets + s->tgt_off[c
 
 void blend_fwd(gs3_scene* s, const CamDev& cd, float* out, hipStream_t st) {
   auto p = prof::begin("blend_fwd", st, true);
-  launch_blend_fwd(s->rec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg, out, st,
-                   p.c);
+  launch_blend_fwd(s->rec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg, out,
+                   s->pix_last, s->pix_T, st, p.c);
   prof::end(p, st);
 }
 
 void blend_jvp(gs3_scene* s, const CamDev& cd, float* out, float* tan, hipStream_t st) {
   auto p = prof::begin("blend_jvp", st, true);
   launch_blend_jvp(s->rec, s->trec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg,
-                   out, tan, st, p.c);
+                   out, tan, s->pix_last, s->pix_T, st, p.c);
   prof::end(p, st);
 }
 
 void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st) {
   auto p = prof::begin("blend_bwd", st, true);
-  launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->img,
-                   cot, s->partials, st, p.c);
+  launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd,
+                   s->pix_last, s->pix_T, s->bg, cot, s->partials, st, p.c);
   prof::end(p, st);
 }
 
@@ -395,7 +399,7 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
   // records, tangent records, eight u32 arrays, the summed partials, and pair buffers for about
   // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair, +25% slack)
   const int64_t pairs = 20 * N;
-  *peak_scratch = 96 * N + 32 * N + 36 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px;
+  *peak_scratch = 96 * N + 32 * N + 36 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px + 8 * max_px;
   return GS3_OK;
 }
 
@@ -461,6 +465,8 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
   step(dalloc(&s->img, s->max_px * 3));
   step(dalloc(&s->cot, s->max_px * 3));
   step(dalloc(&s->tan_img, s->max_px * 3));
+  step(dalloc(&s->pix_last, s->max_px));
+  step(dalloc(&s->pix_T, s->max_px));
   step(dalloc(&s->ssim_tmp, ssim_tmp_floats(1, (int)s->max_px)));
   step(dalloc(&s->dpart, s->max_px * 3 / 256 + s->max_tiles + 1024));
   step(dalloc(&s->dsum, kMaxLossViews));

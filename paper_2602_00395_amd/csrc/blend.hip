@@ -1,5 +1,5 @@
-// Front-to-back alpha blending of depth-sorted splats, its JVP and its VJP,
-// for gfx950.
+// Alpha blending of depth-sorted splats (front to back), its JVP and its VJP
+// (back to front), for gfx950.
 //
 // Paper: Background, "Review of Gaussian Splatting": C = sum_i c_i abar_i T_i
 // with T_i = prod_{j<i} (1 - abar_j) over the splats of the pixel's tile in
@@ -18,23 +18,26 @@
 // skip test can pass somewhere in its block (a conservative bound on the
 // f32 skip ellipse), and every wave walks only the set bits.  Culled
 // evaluations are exactly the ones the skip test would reject, so the
-// result is the same bit for bit.  Workgroups take tiles longest list first (a pixel's walk is serial,
-// so the tiles with the longest lists bound the kernel unless they start
-// early); without that order each of the 8 XCDs gets a contiguous band of
-// tiles (neighbouring tiles share splats, and each XCD has its own L2).
+// result is the same bit for bit.  Workgroups take tiles longest list first
+// (a pixel's walk is serial, so the tiles with the longest lists bound the
+// kernel unless they start early); without that order each of the 8 XCDs
+// gets a contiguous band of tiles (neighbouring tiles share splats, and each
+// XCD has its own L2).
 //
-// The backward pass runs front to back as well, recomputing T exactly as the
-// forward did (so the stop decision repeats bit for bit without storing any
-// per-pixel state) and obtaining the weight of the splats behind splat i from
-// the stored output: (sum_{j>i} c_j abar_j T_j + T_final bg) . dL/dC =
-// (C_out - S_i) . dL/dC, S_i the running front-to-back sum, kept as one
-// running dot product.  Per pixel it reduces dL/dpower times dx, dy, dx^2,
-// dx dy and dy^2; the conic coefficients are constant over the splat, so
-// the derivatives along u, v and the conic are formed once per splat.  Gradients of each (splat, tile) pair are
-// reduced over the workgroup (a transposed wave64 reduction with permlane
-// swaps and DPP row scans, then the four waves in LDS in a fixed order) and
-// written to the pair's own slot: no float atomics, so the backward is
-// deterministic.
+// The backward pass walks each tile back to front: the forward stores, per
+// pixel, its final transmittance and the last splat that contributed; the
+// backward starts there, recovers T in front of each splat as T / (1 - abar)
+// and accumulates (sum over the splats behind of c w + T_final bg) . dL/dC
+// from zero, so no term comes from cancelling two large sums (a deep splat's
+// gradient keeps its relative precision).  Which splats contribute is taken
+// from the same float32 skip test and the stored last index, so the set is
+// exactly the forward's.  Per pixel it reduces dL/dpower times dx, dy, dx^2,
+// dx dy and dy^2; the conic coefficients are constant over the splat, so the
+// derivatives along u, v and the conic are formed once per splat.  Gradients
+// of each (splat, tile) pair are reduced over the workgroup (a transposed
+// wave64 reduction with permlane swaps and DPP row scans, then the four waves
+// in LDS in a fixed order) and written to the pair's own slot: no float
+// atomics, so the backward is deterministic.
 #include "gs3_internal.h"
 
 namespace {
@@ -142,8 +145,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
                                                           const uint32_t* __restrict__ pair_gid,
                                                           const uint2* __restrict__ ranges,
                                                           const uint32_t* __restrict__ order, CamDev cam, float bg0,
-                                                          float bg1, float bg2, float* __restrict__ img, int n_tiles,
-                                                          int chunk, unsigned long long* __restrict__ ctr) {
+                                                          float bg1, float bg2, float* __restrict__ img,
+                                                          uint32_t* __restrict__ pix_last, float* __restrict__ pix_T,
+                                                          int n_tiles, int chunk, unsigned long long* __restrict__ ctr) {
   const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ Stage s;
@@ -158,6 +162,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   // 1 while the pixel still blends; an integer rather than a bool, so the
   // loop carries it in a vector register instead of a scalar lane mask
   uint32_t live = inside ? 1u : 0u;
+  uint32_t lastp = 0u;  // 1 + pair index of the last contributing splat (0: none)
   for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
     if (__syncthreads_count(live) == 0) break;
     const uint32_t i = start + tid;
@@ -202,15 +207,19 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
         C1 += B.w * w8;
         C2 += Cc.x * w8;
         T = use ? Tn : T;
+        lastp = use ? start + (uint32_t)j + 1u : lastp;
       }
     }
     __syncthreads();
   }
   if (inside) {
-    float* o = img + ((int64_t)py * cam.width + px) * 3;
+    const int64_t pix = (int64_t)py * cam.width + px;
+    float* o = img + pix * 3;
     o[0] = C0 + T * bg0;
     o[1] = C1 + T * bg1;
     o[2] = C2 + T * bg2;
+    pix_last[pix] = lastp;
+    pix_T[pix] = T;
   }
   count_evals(ctr, nev, ncon);
 }
@@ -230,7 +239,8 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
                                                           const uint2* __restrict__ ranges,
                                                           const uint32_t* __restrict__ order, CamDev cam, float bg0,
                                                           float bg1, float bg2, float* __restrict__ img,
-                                                          float* __restrict__ tan_img, int n_tiles, int chunk,
+                                                          float* __restrict__ tan_img, uint32_t* __restrict__ pix_last,
+                                                          float* __restrict__ pix_T, int n_tiles, int chunk,
                                                           unsigned long long* __restrict__ ctr) {
   const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
@@ -245,6 +255,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   float T = 1.f, dT = 0.f;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
   uint32_t live = inside ? 1u : 0u;  // as in the forward
+  uint32_t lastp = 0u;
   for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
     if (__syncthreads_count(live) == 0) break;
     const uint32_t i = start + tid;
@@ -304,11 +315,14 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
         D2 += s.tc[j] * wt + Cc.x * dw;
         dT = use ? dT * (1.f - a) - T * da : dT;
         T = use ? Tn : T;
+        lastp = use ? start + (uint32_t)j + 1u : lastp;
       }
     }
     __syncthreads();
   }
   if (inside) {
+    pix_last[(int64_t)py * cam.width + px] = lastp;
+    pix_T[(int64_t)py * cam.width + px] = T;
     const int64_t o = ((int64_t)py * cam.width + px) * 3;
     img[o + 0] = C0 + T * bg0;
     img[o + 1] = C1 + T * bg1;
@@ -387,12 +401,15 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
                                                           const uint32_t* __restrict__ pair_gid,
                                                           const uint2* __restrict__ ranges,
                                                           const uint32_t* __restrict__ order, CamDev cam,
-                                                          const float* __restrict__ img, const float* __restrict__ cot,
+                                                          const uint32_t* __restrict__ pix_last,
+                                                          const float* __restrict__ pix_T, float bg0, float bg1,
+                                                          float bg2, const float* __restrict__ cot,
                                                           float* __restrict__ partials, int n_tiles, int chunk,
                                                           unsigned long long* __restrict__ ctr) {
   const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ StageB s;
+  __shared__ uint32_t tile_end;
   uint32_t nev = 0, ncon = 0;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int tx = t % cam.tiles_x, ty = t / cam.tiles_x;
@@ -400,144 +417,145 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = ranges[t];
-  float out0 = 0.f, out1 = 0.f, out2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f, T = 1.f;
+  uint32_t last = 0u;  // 1 + pair index of the pixel's last contributing splat (0: none)
   if (inside) {
-    const int64_t o = ((int64_t)py * cam.width + px) * 3;
-    out0 = img[o + 0];
-    out1 = img[o + 1];
-    out2 = img[o + 2];
-    g0 = cot[o + 0];
-    g1 = cot[o + 1];
-    g2 = cot[o + 2];
+    const int64_t pix = (int64_t)py * cam.width + px;
+    g0 = cot[pix * 3 + 0];
+    g1 = cot[pix * 3 + 1];
+    g2 = cot[pix * 3 + 2];
+    last = pix_last[pix];
+    T = pix_T[pix];
   }
-  float T = 1.f;
-  // (C_out - S) . dL/dC: the colour of everything behind the current splat
-  float behind = out0 * g0 + out1 * g1 + out2 * g2;
-  uint32_t live = inside ? 1u : 0u;  // as in the forward
-  uint32_t start = range.x;
-  for (; start < range.y; start += kBwdBatch) {
-    if (__syncthreads_count(live) == 0) break;
-    const uint32_t i = start + tid;
-    if (tid < kBwdBatch) {
-      uint32_t m = 0u;
-      if (i < range.y) {
-        const uint32_t g = pair_gid[i];
-        const Rec r = rec[g];
-        s.a[tid] = r.a;
-        s.b[tid] = r.b;
-        s.c[tid] = make_float2(r.c.x, r.c.y);
-        s.slot[tid] = pair_slot(__float_as_uint(r.c.z), rect[g], tx, ty);
-        m = block_mask(r.a, r.b, r.c.y, tx, ty);
-      }
-      publish_masks(s.bits, m, tid);
-    }
-    __syncthreads();
-    const int cnt = min((int)(range.y - start), kBwdBatch);
-    const int nwords = (cnt + 63) >> 6;
-    int q = 0;
-    for (; q < nwords; ++q) {
-      const uint64_t word = uniform64(s.bits[w][q]);
-      uint64_t bits = word;
-      bool wave_done = false;
-      while (bits) {
-        if (__ballot(live) == 0ull) {
-          wave_done = true;
-          break;
-        }
-        const int j = (q << 6) + __builtin_ctzll(bits);
-        bits &= bits - 1;
-        nev += live;
-        const float4 A = s.a[j], B = s.b[j];
-        const float2 Cc = s.c[j];
-        const float dx = A.x - pxf, dy = A.y - pyf;
-        const float power = splat_power(A.z, A.w, B.x, dx, dy);
-        // predicated like the forward: lanes that do not contribute end with
-        // zero partials and unchanged T and behind
-        const bool pass = live && power <= 0.f && power >= Cc.y;
-        const float G = __expf(power);
-        const float araw = B.y * G;
-        const float a = fminf(GS3_ALPHA_MAX, araw);
-        const float Tn = T * (1.f - a);
-        const bool stop = pass && Tn < GS3_T_STOP;
-        const bool use = pass && !stop;
-        live = stop ? 0u : live;
-        ncon += use ? 1u : 0u;
-        const float cdot = B.z * g0 + B.w * g1 + Cc.x * g2;
-        const float wgt = use ? a * T : 0.f;
-        behind -= wgt * cdot;
-        const float dL_da = T * cdot - behind * __builtin_amdgcn_rcpf(1.f - a);
-        const bool open = use && araw <= GS3_ALPHA_MAX;  // the 0.99 clamp passes no gradient
-        const float dL_dpow = open ? B.y * dL_da * G : 0.f;
-        const float pt = dL_dpow * dx, pu = dL_dpow * dy;
-        float gr[9];
-        gr[0] = pt;
-        gr[1] = pu;
-        gr[2] = pt * dx;
-        gr[3] = pt * dy;
-        gr[4] = pu * dy;
-        gr[5] = open ? G * dL_da : 0.f;
-        gr[6] = wgt * g0;
-        gr[7] = wgt * g1;
-        gr[8] = wgt * g2;
-        T = use ? Tn : T;
-        // wave sums of the 9 partial derivatives: values 0-7 are folded in
-        // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
-        // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
-        // DPP reduction into lane 63.  26 VALU instructions in all.
-        float E = 0.f, F = 0.f, H = 0.f;
-        if (__ballot(use) != 0ull) {
-          E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
-          F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
-          H = wave_sum_lane63(gr[8]);
-        }
-        if ((lane & 15) == 15) {
-          const int row = lane >> 4;
-          const int k = (row & 1) * 2 + (row >> 1);
-          s.red[w][k][j] = E;
-          s.red[w][4 + k][j] = F;
-          if (lane == 63) s.red[w][8][j] = H;
-        }
-      }
-      if (wave_done) {
-        // splats of this batch the wave did not walk: drop them from its
-        // mask, so the epilogue counts them as zero
-        if (lane == 0) s.bits[w][q] = word & ~bits;
-        break;
-      }
-    }
-    if (lane == 0)
-      for (int q2 = q + 1; q2 < nwords; ++q2) s.bits[w][q2] = 0ull;
-    __syncthreads();
-    if (tid < cnt) {
-      // a wave that skipped the splat contributes exactly zero
-      float* dst = partials + (int64_t)s.slot[tid] * 9;
-      const uint64_t bit = 1ull << (tid & 63);
-      const bool h0 = s.bits[0][tid >> 6] & bit, h1 = s.bits[1][tid >> 6] & bit;
-      const bool h2 = s.bits[2][tid >> 6] & bit, h3 = s.bits[3][tid >> 6] & bit;
-      float R[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k)
-        R[k] = (((h0 ? s.red[0][k][tid] : 0.f) + (h1 ? s.red[1][k][tid] : 0.f)) + (h2 ? s.red[2][k][tid] : 0.f)) +
-               (h3 ? s.red[3][k][tid] : 0.f);
-      // power = qa dx^2 + qc dy^2 + qb dx dy, (qa, qb, qc) = (-a/2, -b, -c/2),
-      // dx = u - px, dy = v - py
-      const float qa = s.a[tid].z, qb = s.a[tid].w, qc = s.b[tid].x;
-      dst[0] = 2.f * qa * R[0] + qb * R[1];
-      dst[1] = 2.f * qc * R[1] + qb * R[0];
-      dst[2] = -0.5f * R[2];
-      dst[3] = -R[3];
-      dst[4] = -0.5f * R[4];
-#pragma unroll
-      for (int k = 5; k < 9; ++k) dst[k] = R[k];
-    }
-    __syncthreads();
-  }
-  // pairs after the point where every pixel of the tile stopped: zero slots
-  for (uint32_t i = start + tid; i < range.y; i += GS3_BLOCK) {
+  // (sum over the contributing splats behind the current one of c w + T_final bg) . dL/dC,
+  // accumulated from the back
+  float acc = T * (bg0 * g0 + bg1 * g1 + bg2 * g2);
+  if (tid == 0) tile_end = 0u;
+  __syncthreads();
+  if (last > 0u) atomicMax(&tile_end, last);
+  __syncthreads();
+  // pairs at or after the tile's last contribution: zero slots
+  const uint32_t end = tile_end > range.x ? tile_end : range.x;
+  for (uint32_t i = end + tid; i < range.y; i += GS3_BLOCK) {
     const uint32_t g = pair_gid[i];
     float* dst = partials + (int64_t)pair_slot(__float_as_uint(rec[g].c.z), rect[g], tx, ty) * 9;
 #pragma unroll
     for (int k = 0; k < 9; ++k) dst[k] = 0.f;
+  }
+  // the wave's own last contribution bounds the splats it walks
+  uint32_t wave_end = last;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) wave_end = max(wave_end, (uint32_t)__shfl_xor((int)wave_end, m, 64));
+  wave_end = __builtin_amdgcn_readfirstlane(wave_end);
+  if (end > range.x) {
+    for (int64_t bstart = range.x + (int64_t)((end - 1 - range.x) / kBwdBatch) * kBwdBatch; bstart >= range.x;
+         bstart -= kBwdBatch) {
+      const int cnt = (int)min((int64_t)kBwdBatch, (int64_t)end - bstart);
+      const int64_t i = bstart + tid;
+      if (tid < kBwdBatch) {
+        uint32_t m = 0u;
+        if (tid < cnt) {
+          const uint32_t g = pair_gid[i];
+          const Rec r = rec[g];
+          s.a[tid] = r.a;
+          s.b[tid] = r.b;
+          s.c[tid] = make_float2(r.c.x, r.c.y);
+          s.slot[tid] = pair_slot(__float_as_uint(r.c.z), rect[g], tx, ty);
+          m = block_mask(r.a, r.b, r.c.y, tx, ty);
+        }
+        publish_masks(s.bits, m, tid);
+      }
+      __syncthreads();
+      const int nwords = (cnt + 63) >> 6;
+      // splats of this batch at or after the wave's last contribution add nothing for it
+      const int64_t lim = (int64_t)wave_end - bstart;  // walk j < lim
+      for (int q = nwords - 1; q >= 0; --q) {
+        const int64_t lq = lim - 64 * q;
+        const uint64_t keep = lq >= 64 ? ~0ull : (lq <= 0 ? 0ull : ((1ull << lq) - 1ull));
+        const uint64_t word = uniform64(s.bits[w][q]);
+        uint64_t bits = word & keep;
+        if (bits != word && lane == 0) s.bits[w][q] = bits;  // the epilogue counts dropped ones as zero
+        while (bits) {
+          const int hi = 63 - __builtin_clzll(bits);
+          const int j = (q << 6) + hi;
+          bits &= ~(1ull << hi);
+          const uint32_t pi = (uint32_t)bstart + (uint32_t)j;
+          const float4 A = s.a[j], B = s.b[j];
+          const float2 Cc = s.c[j];
+          const float dx = A.x - pxf, dy = A.y - pyf;
+          const float power = splat_power(A.z, A.w, B.x, dx, dy);
+          // predicated like the forward: lanes that do not contribute end
+          // with zero partials and unchanged T and acc
+          const bool use = pi < last && power <= 0.f && power >= Cc.y;
+          nev += pi < last ? 1u : 0u;
+          ncon += use ? 1u : 0u;
+          const float G = __expf(power);
+          const float araw = B.y * G;
+          const float a = fminf(GS3_ALPHA_MAX, araw);
+          const float r1 = __builtin_amdgcn_rcpf(1.f - a);
+          const float Tb = T * r1;  // transmittance in front of this splat
+          const float cdot = B.z * g0 + B.w * g1 + Cc.x * g2;
+          const float wgt = use ? a * Tb : 0.f;
+          const float dL_da = Tb * cdot - acc * r1;
+          const bool open = use && araw <= GS3_ALPHA_MAX;  // the 0.99 clamp passes no gradient
+          const float dL_dpow = open ? B.y * dL_da * G : 0.f;
+          const float pt = dL_dpow * dx, pu = dL_dpow * dy;
+          float gr[9];
+          gr[0] = pt;
+          gr[1] = pu;
+          gr[2] = pt * dx;
+          gr[3] = pt * dy;
+          gr[4] = pu * dy;
+          gr[5] = open ? G * dL_da : 0.f;
+          gr[6] = wgt * g0;
+          gr[7] = wgt * g1;
+          gr[8] = wgt * g2;
+          acc += wgt * cdot;
+          T = use ? Tb : T;
+          // wave sums of the 9 partial derivatives: values 0-7 are folded in
+          // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
+          // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
+          // DPP reduction into lane 63.  26 VALU instructions in all.
+          float E = 0.f, F = 0.f, H = 0.f;
+          if (__ballot(use) != 0ull) {
+            E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
+            F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
+            H = wave_sum_lane63(gr[8]);
+          }
+          if ((lane & 15) == 15) {
+            const int row = lane >> 4;
+            const int k = (row & 1) * 2 + (row >> 1);
+            s.red[w][k][j] = E;
+            s.red[w][4 + k][j] = F;
+            if (lane == 63) s.red[w][8][j] = H;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < cnt) {
+        // a wave that skipped the splat contributes exactly zero
+        float* dst = partials + (int64_t)s.slot[tid] * 9;
+        const uint64_t bit = 1ull << (tid & 63);
+        const bool h0 = s.bits[0][tid >> 6] & bit, h1 = s.bits[1][tid >> 6] & bit;
+        const bool h2 = s.bits[2][tid >> 6] & bit, h3 = s.bits[3][tid >> 6] & bit;
+        float R[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+          R[k] = (((h0 ? s.red[0][k][tid] : 0.f) + (h1 ? s.red[1][k][tid] : 0.f)) + (h2 ? s.red[2][k][tid] : 0.f)) +
+                 (h3 ? s.red[3][k][tid] : 0.f);
+        // power = qa dx^2 + qc dy^2 + qb dx dy, (qa, qb, qc) = (-a/2, -b, -c/2),
+        // dx = u - px, dy = v - py
+        const float qa = s.a[tid].z, qb = s.a[tid].w, qc = s.b[tid].x;
+        dst[0] = 2.f * qa * R[0] + qb * R[1];
+        dst[1] = 2.f * qc * R[1] + qb * R[0];
+        dst[2] = -0.5f * R[2];
+        dst[3] = -R[3];
+        dst[4] = -0.5f * R[4];
+#pragma unroll
+        for (int k = 5; k < 9; ++k) dst[k] = R[k];
+      }
+      __syncthreads();
+    }
   }
   count_evals(ctr, nev, ncon);
 }
@@ -547,24 +565,25 @@ inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }
 }  // namespace
 
 void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
-                      const CamDev& cam, const float* bg, float* img, hipStream_t st, unsigned long long* ctr) {
+                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T,
+                      hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
   hipLaunchKernelGGL(k_blend_fwd, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, order,
-                     cam, bg[0], bg[1], bg[2], img, nt, ch, ctr);
+                     cam, bg[0], bg[1], bg[2], img, pix_last, pix_T, nt, ch, ctr);
 }
 
 void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
                       const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
-                      hipStream_t st, unsigned long long* ctr) {
+                      uint32_t* pix_last, float* pix_T, hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
   hipLaunchKernelGGL(k_blend_jvp, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges,
-                     order, cam, bg[0], bg[1], bg[2], img, tan_img, nt, ch, ctr);
+                     order, cam, bg[0], bg[1], bg[2], img, tan_img, pix_last, pix_T, nt, ch, ctr);
 }
 
 void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint32_t* order, const CamDev& cam, const float* img, const float* cot,
-                      float* partials, hipStream_t st, unsigned long long* ctr) {
+                      const uint32_t* order, const CamDev& cam, const uint32_t* pix_last, const float* pix_T,
+                      const float* bg, const float* cot, float* partials, hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
   hipLaunchKernelGGL(k_blend_bwd, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges,
-                     order, cam, img, cot, partials, nt, ch, ctr);
+                     order, cam, pix_last, pix_T, bg[0], bg[1], bg[2], cot, partials, nt, ch, ctr);
 }

@@ -102,15 +102,19 @@ void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const
 // first); NULL = XCD-banded order.  ctr (nullable): two u64 counters
 // receiving the number of (pixel, splat) evaluations and of contributing
 // evaluations (measurement only).
+// pix_last / pix_T (float[H][W] each): 1 + pair index of each pixel's last
+// contributing splat (0: none) and its final transmittance, written by the
+// forward (or the JVP) and read by the backward
 void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
-                      const CamDev& cam, const float* bg, float* img, hipStream_t st,
-                      unsigned long long* ctr = nullptr);
+                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T,
+                      hipStream_t st, unsigned long long* ctr = nullptr);
 void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
                       const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
-                      hipStream_t st, unsigned long long* ctr = nullptr);
+                      uint32_t* pix_last, float* pix_T, hipStream_t st, unsigned long long* ctr = nullptr);
 void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint32_t* order, const CamDev& cam, const float* img, const float* cot,
-                      float* partials, hipStream_t st, unsigned long long* ctr = nullptr);
+                      const uint32_t* order, const CamDev& cam, const uint32_t* pix_last, const float* pix_T,
+                      const float* bg, const float* cot, float* partials, hipStream_t st,
+                      unsigned long long* ctr = nullptr);
 
 // loss
 // cot = scale * d(sum_k l_k)/dC; optional per-block loss partial sums (double).

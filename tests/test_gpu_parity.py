@@ -226,6 +226,83 @@ def test_grad_parity_object_scale_crop():
     s.close()
 
 
+def _sampled_gaussians(ob, rng, k, max_tiles):
+    """k visible Gaussians touching 1..max_tiles tiles, and the set of those tiles."""
+    cand = np.flatnonzero((ob.tiles_touched >= 1) & (ob.tiles_touched <= max_tiles))
+    pick = np.sort(rng.choice(cand, size=k, replace=False))
+    tiles = set()
+    for g in pick:
+        x0, y0, x1, y1 = (int(v) for v in ob.rect[g])
+        tiles |= {ty * ob.tiles_x + tx for ty in range(y0, y1) for tx in range(x0, x1)}
+    return pick, tiles
+
+
+def test_render_vjp_object_scale_sampled_gaussians():
+    """Full object scale (100k Gaussians, SH 3, 800x800): J^T cot for sampled
+    Gaussians; a Gaussian's gradient only involves the pixels of its own
+    tiles, so the oracle renders just those tiles (with every splat in them)."""
+    sc = syn.config2_scene()
+    cam = sc.cameras[3]
+    x = sc.init.astype(np.float32)
+    x[14:] = sc.gt[14:]  # non-zero higher-order SH so every row is exercised
+    s = make_scene(x, [np.zeros((cam.height, cam.width, 3), np.float32)], [cam], 3)
+    ob = B.bin_view(x, cam)
+    rng = np.random.default_rng(41)
+    pick, tiles = _sampled_gaussians(ob, rng, 5, 3)
+    say("vjp object scale: Gaussians", pick.tolist(), "tiles", len(tiles))
+    cot = rng.normal(size=(cam.height, cam.width, 3))
+    got = s.render_vjp(0, torch.tensor(cot, dtype=torch.float32, device=DEV)).cpu().numpy()[:, pick]
+    xg = torch.tensor(x, dtype=torch.float64).requires_grad_(True)
+    img = R.render(xg, cam, 3, ob, tiles=tiles)
+    m = ~torch.isnan(img)
+    (img[m] * torch.tensor(cot)[m]).sum().backward()
+    want = xg.grad.numpy()[:, pick]
+    errs = group_errors(got, want, 59)
+    say("  rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
+def test_hvp_diag_object_scale_sampled_gaussians():
+    """Full object scale: the Hutchinson diagonal (L1 loss, one probe) for
+    sampled Gaussians.  J z, the Gauss-Newton weights and J^T y of those
+    Gaussians only involve their own tiles; the targets there are the
+    oracle's render offset by +-U[0.05, 0.15] (every residual away from 0)."""
+    sc = syn.config2_scene()
+    cam = sc.cameras[11]
+    x = sc.init.astype(np.float32)
+    ob = B.bin_view(x, cam)
+    rng = np.random.default_rng(42)
+    pick, tiles = _sampled_gaussians(ob, rng, 4, 2)
+    say("hvp object scale: Gaussians", pick.tolist(), "tiles", len(tiles))
+    xt = torch.tensor(x, dtype=torch.float64)
+    f = lambda xx: R.render(xx, cam, 3, ob, tiles=tiles)  # noqa: E731
+    with torch.no_grad():
+        base = f(xt)
+    m = ~torch.isnan(base)
+    off = rng.uniform(0.05, 0.15, size=base.shape) * rng.choice([-1.0, 1.0], size=base.shape)
+    tgt = np.full(base.shape, 0.5)
+    tgt[m.numpy()] = base.numpy()[m.numpy()] + off[m.numpy()]
+    s = make_scene(x, [tgt.astype(np.float32)], [cam], 3, lam=0.0)
+    seed = 5077
+    got = s.hvp_diag([0], 1, seed).cpu().numpy()[:, pick]
+    p, n = x.shape
+    z = Mth.probe(seed, 0, p, n)
+    img, u = torch.func.jvp(f, (xt,), (torch.tensor(z),))
+    tg = torch.tensor(tgt)
+    y = torch.zeros_like(img)
+    y[m] = Mth.gn_cotangent(img[m], tg[m], u[m], 0.0)
+    xg = xt.clone().requires_grad_(True)
+    out = f(xg)
+    (out[m] * y[m]).sum().backward()
+    scale = 1.0 / (6.0 * cam.height * cam.width)  # M / (m |S2| nu) with one training view
+    want = (z * xg.grad.numpy() * scale)[:, pick]
+    errs = group_errors(got, want, 59)
+    say("  rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
 def test_tr_step_parity():
     sc = syn.config2_scene(n=4000, n_cams=2, res=64)
     x = sc.gt.astype(np.float32)
