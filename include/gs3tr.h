@@ -126,7 +126,8 @@ gs3_status gs3_scene_create(const gs3_scene_desc* desc, const float* params_dev,
 gs3_status gs3_scene_destroy(gs3_scene* scene);
 
 /* Borrowed device pointer to the scene's parameters float[P][N]; valid
- * until the scene is destroyed; updated in place by tr_step / adam_step. */
+ * until the scene is destroyed or the next gs3_tr_iteration (which swaps
+ * the two parameter buffers); updated in place by tr_step / adam_step. */
 gs3_status gs3_scene_params(gs3_scene* scene, float** params_dev);
 
 /* Overwrite the scene's parameters from params_dev (float[P][N], device). */
@@ -182,6 +183,21 @@ gs3_status gs3_hvp_diag(gs3_scene* scene, const int32_t* cams, int32_t n_cams, i
  * (+inf where unconstrained) and the clipped step. */
 gs3_status gs3_tr_step(gs3_scene* scene, const float* grad_dev, const float* D_dev, const gs3_tr_hparams* hp,
                        float* eta_out_dev, float* dx_out_dev, hipStream_t stream);
+
+/* One whole iteration of Algorithm 1 in one call: if n2 > 0 (a Hutchinson
+ * iteration) D_t over the views cams2[0..n2) with nu probes of `seed` (as
+ * gs3_hvp_diag); the stochastic gradient over cams1[0..n1) (as gs3_grad);
+ * then the update of gs3_tr_step with D_t on Hutchinson iterations.  The
+ * update is fused into the projection backward of the last gradient view,
+ * so the gradient of that view never goes through memory; the parameters
+ * are double-buffered (the update reads one copy and writes the other), so
+ * a pointer from gs3_scene_params is not valid after this call.  D_t and the
+ * other views' gradient live in scene-owned buffers.  loss_out (nullable,
+ * host) receives the mini-batch objective as in gs3_grad.  Same results as
+ * gs3_hvp_diag + gs3_grad + gs3_tr_step on the same views. */
+gs3_status gs3_tr_iteration(gs3_scene* scene, const int32_t* cams1, int32_t n1, const int32_t* cams2, int32_t n2,
+                            int32_t nu, uint64_t seed, const gs3_tr_hparams* hp, double* loss_out,
+                            hipStream_t stream);
 
 /* Adam baseline (Kingma and Ba) with bias correction, betas (0.9, 0.999),
  * eps 1e-15 and one learning rate per parameter group:

@@ -53,6 +53,8 @@ _SIGS = {
     "gs3_grad": (c_int32, [c_void_p, POINTER(c_int32), c_int32, c_void_p, POINTER(c_double), c_void_p]),
     "gs3_hvp_diag": (c_int32, [c_void_p, POINTER(c_int32), c_int32, c_int32, c_uint64, c_void_p, c_void_p]),
     "gs3_tr_step": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(TrHparams), c_void_p, c_void_p, c_void_p]),
+    "gs3_tr_iteration": (c_int32, [c_void_p, POINTER(c_int32), c_int32, POINTER(c_int32), c_int32, c_int32, c_uint64,
+                                   POINTER(TrHparams), POINTER(c_double), c_void_p]),
     "gs3_adam_step": (c_int32, [c_void_p, c_void_p, POINTER(c_float), c_int32, c_void_p]),
     "gs3_adam_tr_step": (c_int32, [c_void_p, c_void_p, POINTER(c_float), c_int32, c_float, c_void_p]),
     "gs3_psnr": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),

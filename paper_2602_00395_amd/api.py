@@ -209,6 +209,18 @@ class Scene:
         _lib.check("gs3_tr_step", self.lib.gs3_tr_step(self.handle, _ptr(grad), _ptr(D), byref(hp), _ptr(eta_out),
                                                        _ptr(dx_out), self._st()))
 
+    def tr_iteration(self, S1, S2, nu: int, seed: int, theta1: float, theta2: float, epsilon: float,
+                     variant: int = 0, want_loss: bool = False):
+        """One fused iteration of Algorithm 1 (gs3_tr_iteration); S2 empty = no Hutchinson step."""
+        a1 = (c_int32 * len(S1))(*[int(c) for c in S1])
+        a2 = (c_int32 * max(len(S2), 1))(*([int(c) for c in S2] or [0]))
+        hp = _lib.TrHparams(float(theta1), float(theta2), float(epsilon), int(variant))
+        loss = c_double()
+        _lib.check("gs3_tr_iteration", self.lib.gs3_tr_iteration(
+            self.handle, a1, len(S1), a2 if S2 else None, len(S2), int(nu), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+            byref(hp), byref(loss) if want_loss else None, self._st()))
+        return loss.value if want_loss else None
+
     def adam_step(self, grad: torch.Tensor, lrs: dict, step: int, epsilon: float | None = None):
         arr = (c_float * 6)(*[float(lrs[k]) for k in ADAM_GROUP_ORDER])
         if epsilon is None:

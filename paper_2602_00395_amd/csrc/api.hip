@@ -6,6 +6,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "gs3_internal.h"
@@ -111,6 +112,9 @@ struct gs3_scene {
   int max_tiles = 0;
   // resident state
   float *x = nullptr, *targets = nullptr, *ghat = nullptr, *dhat = nullptr, *am = nullptr, *av = nullptr;
+  // gs3_tr_iteration: the fused update writes x_alt (then the two swap); its
+  // Hutchinson diagonal and the gradient of all but the last view
+  float *x_alt = nullptr, *dbuf = nullptr, *gacc = nullptr, *rad = nullptr;
   // per-Gaussian scratch
   Rec* rec = nullptr;
   uint2* rect = nullptr;
@@ -191,6 +195,10 @@ void dfree(T*& p) {
 
 void free_all(gs3_scene* s) {
   dfree(s->x);
+  dfree(s->x_alt);
+  dfree(s->dbuf);
+  dfree(s->gacc);
+  dfree(s->rad);
   dfree(s->targets);
   dfree(s->ghat);
   dfree(s->dhat);
@@ -343,10 +351,10 @@ void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st)
 }
 
 void project_bwd(gs3_scene* s, const CamDev& cd, int mode, int acc, uint64_t seed, uint32_t i, float scale,
-                 float* out, hipStream_t st) {
+                 float* out, hipStream_t st, const FusedTr& ft = FusedTr{}) {
   auto p = prof::begin("project_bwd", st);
   launch_project_bwd(s->x, s->N, s->deg, cd, s->order, s->offsets, s->counts, s->tiles, s->partials, s->gsum, mode,
-                     acc, seed, i, scale, out, st);
+                     acc, seed, i, scale, out, ft, st);
   prof::end(p, st, s->N, 0);
 }
 
@@ -395,11 +403,13 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
     px_total += px;
     max_px = std::max(max_px, px);
   }
-  *resident = 4 * P * N * 5 + 12 * px_total;
-  // records, tangent records, eight u32 arrays, the summed partials, and pair buffers for about
+  *resident = 4 * P * N * 8 + 12 * px_total;
+  // records, tangent records, eight u32 arrays, the summed partials, the
+  // trust radius, per-pixel blend state, and pair buffers for about
   // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair, +25% slack)
   const int64_t pairs = 20 * N;
-  *peak_scratch = 96 * N + 32 * N + 36 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px + 8 * max_px;
+  *peak_scratch = 96 * N + 32 * N + 36 * N + 60 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px +
+                  8 * max_px;
   return GS3_OK;
 }
 
@@ -441,6 +451,10 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
     if (rc == GS3_OK) rc = r;
   };
   step(dalloc(&s->x, PN));
+  step(dalloc(&s->x_alt, PN));
+  step(dalloc(&s->dbuf, PN));
+  step(dalloc(&s->gacc, PN));
+  step(dalloc(&s->rad, 15 * s->N));
   step(dalloc(&s->targets, off));
   step(dalloc(&s->ghat, PN));
   step(dalloc(&s->dhat, PN));
@@ -567,12 +581,14 @@ gs3_status gs3_bin(gs3_scene* s, int32_t cam, uint64_t* keys, uint32_t* gids, ui
   return GS3_OK;
 }
 
-gs3_status gs3_grad(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* grad, double* loss_out,
-                    hipStream_t st) {
-  GS3_TRY(check_scene(s));
-  if (!cams || n_cams < 1 || n_cams > kMaxLossViews) return fail(GS3_EINVAL, "need 1..4096 camera indices");
-  if (!grad) return fail(GS3_EINVAL, "grad_dev is NULL");
-  for (int k = 0; k < n_cams; ++k) GS3_TRY(check_cam(s, cams[k]));
+namespace {
+
+// The gradient of Eq. objective over views cams[0..n) into grad (mode 0);
+// with `fuse` set, the last view's projection backward applies the update of
+// Algorithm 1 instead of writing its gradient (the other views' sum is in
+// grad, passed to the update as the accumulated part).
+gs3_status grad_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* grad, double* loss_out,
+                      const FusedTr* fuse, hipStream_t st) {
   const float scale = (float)((double)s->n_train / (2.0 * (double)s->m_comp * n_cams));
   for (int k = 0; k < n_cams; ++k) {
     const int j = cams[k];
@@ -586,7 +602,13 @@ gs3_status gs3_grad(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* gr
     prof::end(pl, st);
     if (loss_out) launch_sum_partials(s->dpart, np, s->dsum + k, st);
     blend_bwd(s, cd, s->cot, st);
-    project_bwd(s, cd, 0, k > 0, 0, 0, 0.f, grad, st);
+    if (fuse && k == n_cams - 1) {
+      FusedTr ft = *fuse;
+      ft.gacc = k > 0 ? grad : nullptr;
+      project_bwd(s, cd, 2, 0, 0, 0, 0.f, nullptr, st, ft);
+    } else {
+      project_bwd(s, cd, 0, k > 0, 0, 0, 0.f, grad, st);
+    }
     GS3_LAUNCHED();
   }
   if (loss_out) {
@@ -596,16 +618,11 @@ gs3_status gs3_grad(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* gr
     for (int k = 0; k < n_cams; ++k) tot += s->host_f64[k];
     *loss_out = tot / (2.0 * (double)s->m_comp);
   }
-  return finish(s, st);
+  return GS3_OK;
 }
 
-gs3_status gs3_hvp_diag(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed, float* D,
-                        hipStream_t st) {
-  GS3_TRY(check_scene(s));
-  if (!cams || n_cams < 1) return fail(GS3_EINVAL, "need at least one camera index");
-  if (nu < 1) return fail(GS3_EINVAL, "nu must be >= 1");
-  if (!D) return fail(GS3_EINVAL, "D_dev is NULL");
-  for (int k = 0; k < n_cams; ++k) GS3_TRY(check_cam(s, cams[k]));
+gs3_status hvp_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed, float* D,
+                     hipStream_t st) {
   launch_fill_f32(D, (int64_t)s->P * s->N, 0.f, st);
   const float scale = (float)((double)s->n_train / ((double)s->m_comp * n_cams * nu));
   for (int k = 0; k < n_cams; ++k) {
@@ -623,18 +640,71 @@ gs3_status gs3_hvp_diag(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32
       GS3_LAUNCHED();
     }
   }
+  return GS3_OK;
+}
+
+gs3_status check_views(gs3_scene* s, const int32_t* cams, int32_t n_cams) {
+  if (!cams || n_cams < 1 || n_cams > kMaxLossViews) return fail(GS3_EINVAL, "need 1..4096 camera indices");
+  for (int k = 0; k < n_cams; ++k) GS3_TRY(check_cam(s, cams[k]));
+  return GS3_OK;
+}
+
+gs3_status check_hparams(const gs3_tr_hparams* hp) {
+  if (!hp) return fail(GS3_EINVAL, "hp must not be NULL");
+  if (!(hp->theta1 >= 0.f && hp->theta1 < 1.f && hp->theta2 >= 0.f && hp->theta2 < 1.f))
+    return fail(GS3_EINVAL, "theta1 and theta2 must be in [0, 1)");
+  if (!(hp->epsilon > 0.f) || !std::isfinite(hp->epsilon)) return fail(GS3_EINVAL, "epsilon must be > 0 and finite");
+  if (hp->variant & ~(GS3_TR_MEAN_EXACT | GS3_TR_SECOND_ORDER | GS3_TR_SH_JOINT))
+    return fail(GS3_EINVAL, "unknown variant bits");
+  return GS3_OK;
+}
+
+}  // namespace
+
+gs3_status gs3_grad(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* grad, double* loss_out,
+                    hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_views(s, cams, n_cams));
+  if (!grad) return fail(GS3_EINVAL, "grad_dev is NULL");
+  GS3_TRY(grad_views(s, cams, n_cams, grad, loss_out, nullptr, st));
+  return finish(s, st);
+}
+
+gs3_status gs3_hvp_diag(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed, float* D,
+                        hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_views(s, cams, n_cams));
+  if (nu < 1) return fail(GS3_EINVAL, "nu must be >= 1");
+  if (!D) return fail(GS3_EINVAL, "D_dev is NULL");
+  GS3_TRY(hvp_views(s, cams, n_cams, nu, seed, D, st));
+  return finish(s, st);
+}
+
+gs3_status gs3_tr_iteration(gs3_scene* s, const int32_t* cams1, int32_t n1, const int32_t* cams2, int32_t n2,
+                            int32_t nu, uint64_t seed, const gs3_tr_hparams* hp, double* loss_out, hipStream_t st) {
+  GS3_TRY(check_scene(s));
+  GS3_TRY(check_views(s, cams1, n1));
+  if (n2 < 0 || (n2 > 0 && nu < 1)) return fail(GS3_EINVAL, "n2 must be >= 0 and nu >= 1 when n2 > 0");
+  if (n2 > 0) GS3_TRY(check_views(s, cams2, n2));
+  GS3_TRY(check_hparams(hp));
+  if (n2 > 0) GS3_TRY(hvp_views(s, cams2, n2, nu, seed, s->dbuf, st));
+  FusedTr ft;
+  ft.rad = s->rad;
+  ft.x_out = s->x_alt;
+  ft.ghat = s->ghat;
+  ft.dhat = s->dhat;
+  ft.D = n2 > 0 ? s->dbuf : nullptr;
+  ft.a = TrArgs{hp->theta1, hp->theta2, hp->epsilon, n2 > 0, hp->variant};
+  GS3_TRY(grad_views(s, cams1, n1, s->gacc, loss_out, &ft, st));
+  std::swap(s->x, s->x_alt);
   return finish(s, st);
 }
 
 gs3_status gs3_tr_step(gs3_scene* s, const float* grad, const float* D, const gs3_tr_hparams* hp, float* eta_out,
                        float* dx_out, hipStream_t st) {
   GS3_TRY(check_scene(s));
-  if (!grad || !hp) return fail(GS3_EINVAL, "grad_dev and hp must not be NULL");
-  if (!(hp->theta1 >= 0.f && hp->theta1 < 1.f && hp->theta2 >= 0.f && hp->theta2 < 1.f))
-    return fail(GS3_EINVAL, "theta1 and theta2 must be in [0, 1)");
-  if (!(hp->epsilon > 0.f) || !std::isfinite(hp->epsilon)) return fail(GS3_EINVAL, "epsilon must be > 0 and finite");
-  if (hp->variant & ~(GS3_TR_MEAN_EXACT | GS3_TR_SECOND_ORDER | GS3_TR_SH_JOINT))
-    return fail(GS3_EINVAL, "unknown variant bits");
+  if (!grad) return fail(GS3_EINVAL, "grad_dev must not be NULL");
+  GS3_TRY(check_hparams(hp));
   TrArgs a{hp->theta1, hp->theta2, hp->epsilon, D != nullptr, hp->variant};
   auto p = prof::begin("tr_step", st);
   launch_tr_step(s->x, grad, s->ghat, s->dhat, D, s->N, s->deg, a, eta_out, dx_out, st);

@@ -66,13 +66,33 @@ void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, R
 void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
                         const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
                         const float* tangent, TRec* trec, hipStream_t st);
-// mode 0: grad[r][g] = (accumulate ? grad : 0) + dL/dx; mode 1: out[r][g] += scale * z_r * dL/dx
+// the update of Algorithm 1: EMA decays, budget, whether this is a
+// Hutchinson iteration, radius variant
+struct TrArgs {
+  float theta1, theta2, epsilon;
+  int hutch;
+  uint32_t variant;  // GS3_TR_* bits
+};
+// the trust-region update fused into the projection backward (mode 2): the
+// summed gradient of a row is gacc (nullable) plus this view's part; the
+// update of Algorithm 1 writes x_out (x itself is only read), ghat, dhat
+struct FusedTr {
+  float* rad = nullptr;  // float[15][N] scratch for the radius
+  float* x_out = nullptr;
+  float* ghat = nullptr;
+  float* dhat = nullptr;
+  const float* D = nullptr;
+  const float* gacc = nullptr;
+  TrArgs a{};
+};
 // order / offsets / counts: the view's depth order, first pair and tile count
-// per depth rank; gsum: float[9][n] scratch for the summed partials
+// per depth rank; gsum: float[9][n] scratch for the summed partials.
+// mode 0: out = (accumulate ? out : 0) + dL/dx; mode 1: out += scale z dL/dx
+// for probe i of `seed`; mode 2: the fused update described by ft
 void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const uint32_t* order,
                         const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
                         const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
-                        uint32_t probe_index, float scale, float* out, hipStream_t st);
+                        uint32_t probe_index, float scale, float* out, const FusedTr& ft, hipStream_t st);
 
 // sorting and binning
 size_t radix_temp_bytes(int64_t n);
@@ -128,11 +148,6 @@ void launch_sq_err(const float* img, const float* tgt, int64_t n, double* partia
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
 
 // optimizer
-struct TrArgs {
-  float theta1, theta2, epsilon;
-  int hutch;
-  uint32_t variant;  // GS3_TR_* bits
-};
 void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
                     TrArgs a, float* eta_out, float* dx_out, hipStream_t st);
 struct AdamArgs {

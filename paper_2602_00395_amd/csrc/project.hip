@@ -20,7 +20,7 @@
 //    per geometric parameter (mean, log-scale, quaternion) -- exact and
 //    cheap next to the blend, and it keeps a single source for the
 //    projection's derivative.  Opacity and SH rows have closed forms.
-#include "gs3_internal.h"
+#include "gs3_trust.h"
 
 namespace {
 
@@ -329,39 +329,75 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
   if (mine) G[(int64_t)k * n + order[i]] = acc;
 }
 
+// Trust-region radius of every Gaussian from the parameters before the
+// update, for the fused update: rad[c][g] for the 15 components of
+// gs3trust::Radius (mu 0-2, log-scale 3, quaternion 4-7, logit 8, colour
+// 9-11, view-dependent SH 12-14).
+template <int DEG>
+__global__ __launch_bounds__(256) void k_trust_radius(const float* __restrict__ x, int64_t n, float eps,
+                                                       uint32_t variant, float* __restrict__ rad) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const gs3trust::Radius r = gs3trust::trust_radius(x, n, g, eps, variant, DEG);
+  const float v[15] = {r.mu[0], r.mu[1], r.mu[2], r.ls, r.q[0], r.q[1], r.q[2], r.q[3],
+                       r.logit, r.col[0], r.col[1], r.col[2], r.rest[0], r.rest[1], r.rest[2]};
+#pragma unroll
+  for (int c = 0; c < 15; ++c) rad[(int64_t)c * n + g] = v[c];
+}
+
+__device__ __forceinline__ int radius_component(int row) {
+  if (row < 3) return row;
+  if (row < 6) return 3;
+  if (row < 10) return row - 2;
+  if (row == 10) return 8;
+  if (row < 14) return row - 2;
+  return 12 + (row - 11) % 3;
+}
+
+// SH coefficients per role of the projection backward
+constexpr int kShPerRole = 4;
+template <int DEG>
+constexpr int bwd_roles() {
+  return 11 + ((DEG + 1) * (DEG + 1) + kShPerRole - 1) / kShPerRole;
+}
+
 // Chain rule from the summed screen-space partials G (d/du, d/dv, d/dconic
 // a, b, c, d/dalpha, d/drgb) to the raw parameters.  blockIdx.y picks the
 // work of a thread: 0..9 one forward-mode sweep along geometric row y (mean,
 // log-scale, quaternion; the mean rows also move the SH view direction), 10
-// the opacity logit and the SH rows, d rgb_c / d f_kc = Y_k(dir) where the
-// colour clamp is inactive.  One thread per (Gaussian, role) keeps ten times
-// more waves in flight than one thread per Gaussian walking every sweep.
+// the opacity logit, 11.. four SH coefficients each, d rgb_c / d f_kc =
+// Y_k(dir) where the colour clamp is inactive.  One thread per (Gaussian,
+// role) keeps many more waves in flight than one thread per Gaussian walking
+// every row.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       const uint32_t* __restrict__ tiles,
                                                       const float* __restrict__ G, int mode, int accumulate,
-                                                      uint64_t inner, float scale, float* __restrict__ out) {
+                                                      uint64_t inner, float scale, float* __restrict__ out,
+                                                      FusedTr ft) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   constexpr int K = (DEG + 1) * (DEG + 1);
-  constexpr int P = 11 + 3 * K;
   const int role = blockIdx.y;
+  // this role's rows: [r0, r1)
+  const int r0 = role <= 10 ? role : 11 + 3 * kShPerRole * (role - 11);
+  const int r1 = role <= 10 ? role + 1 : min(11 + 3 * K, r0 + 3 * kShPerRole);
   auto emit = [&](int r, float v) {
     const int64_t k = (int64_t)r * n + g;
     if (mode == 0) {
       out[k] = accumulate ? out[k] + v : v;
-    } else {
+    } else if (mode == 1) {
       out[k] += scale * probe_sign(inner, (uint64_t)k) * v;
+    } else {
+      // the update of Algorithm 1; x is only read, the update goes to x_out
+      const float gk = ft.gacc ? ft.gacc[k] + v : v;
+      const float eta = ft.rad[(int64_t)radius_component(r) * n + g];
+      ft.x_out[k] = x[k] + gs3trust::tr_update(ft.ghat, ft.dhat, ft.D, k, gk, eta, ft.a);
     }
   };
-  if (tiles[g] == 0u) {
-    if (mode == 0 && !accumulate) {
-      if (role < 10) {
-        out[(int64_t)role * n + g] = 0.f;
-      } else {
-        for (int r = 10; r < P; ++r) out[(int64_t)r * n + g] = 0.f;
-      }
-    }
+  if (tiles[g] == 0u) {  // no gradient from this view
+    if (mode == 2 || (mode == 0 && !accumulate))
+      for (int r = r0; r < r1; ++r) emit(r, 0.f);
     return;
   }
   auto Gk = [&](int k) { return G[(int64_t)k * n + g]; };
@@ -380,15 +416,21 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
     emit(role, d);
     return;
   }
-  const float s = sigmoid_(x[10 * n + g]);
-  emit(10, Gk(5) * s * (1.f - s));
+  if (role == 10) {
+    const float s = sigmoid_(x[10 * n + g]);
+    emit(10, Gk(5) * s * (1.f - s));
+    return;
+  }
   auto srcf = [&](int r) { return x[(int64_t)r * n + g]; };
   float rgb[3], Y[K];
   bool pos[3];
   colour<float, DEG>(srcf, cam, rgb, pos, Y);
   const float G6 = Gk(6), G7 = Gk(7), G8 = Gk(8);
+  const int k0 = kShPerRole * (role - 11);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int kk = 0; kk < kShPerRole; ++kk) {
+    const int k = k0 + kk;
+    if (k >= K) break;
     emit(11 + 3 * k, pos[0] ? Y[k] * G6 : 0.f);
     emit(12 + 3 * k, pos[1] ? Y[k] * G7 : 0.f);
     emit(13 + 3 * k, pos[2] ? Y[k] * G8 : 0.f);
@@ -430,9 +472,14 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
 void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const uint32_t* order,
                         const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
                         const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
-                        uint32_t probe_index, float scale, float* out, hipStream_t st) {
+                        uint32_t probe_index, float scale, float* out, const FusedTr& ft, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_pair_partials, dim3(blocks_for(n, kSumRanks)), dim3(256), 0, st, order, offsets, counts,
                      partials, n, gsum);
-  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256), 11), dim3(256), 0, st, x, n, cam, tiles, gsum, mode,
-                   accumulate, probe_inner(seed, probe_index), scale, out);
+  if (mode == 2)
+    GS3_DEG_DISPATCH(deg, k_trust_radius, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, ft.a.epsilon,
+                     ft.a.variant, ft.rad);
+  const unsigned roles = deg == 0 ? bwd_roles<0>() : (deg == 1 ? bwd_roles<1>() : (deg == 2 ? bwd_roles<2>()
+                                                                                            : bwd_roles<3>()));
+  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256), roles), dim3(256), 0, st, x, n, cam, tiles, gsum,
+                   mode, accumulate, probe_inner(seed, probe_index), scale, out, ft);
 }

@@ -48,6 +48,7 @@ class TRConfig:
     seed: int = 4002
     probe_seed: int = 5002
     variant: int = 0  # trust-region radius variant bits (0 = as printed)
+    fused: bool = True  # one gs3_tr_iteration call per step (else grad / hvp_diag / tr_step)
 
 
 class TRTrainer:
@@ -67,8 +68,14 @@ class TRTrainer:
         self.t += 1
         t = self.t
         S1 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s1)]
-        self.scene.grad(S1, out=self.g)
         eps = eps_schedule(t, c.budget)
+        if c.fused:
+            S2 = []
+            if (t - 1) % c.l == 0:
+                S2 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s2)]
+            self.scene.tr_iteration(S1, S2, c.nu, c.probe_seed + t, c.theta1, c.theta2, eps, variant=c.variant)
+            return
+        self.scene.grad(S1, out=self.g)
         if (t - 1) % c.l == 0:
             S2 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s2)]
             self.scene.hvp_diag(S2, c.nu, c.probe_seed + t, out=self.D)

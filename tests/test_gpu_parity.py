@@ -415,3 +415,32 @@ def test_psnr_matches_oracle(c1):
 
     assert abs(s.psnr(3) - psnr(want, torch.tensor(targets[3], dtype=torch.float64))) < 1e-3
     s.close()
+
+
+def test_fused_iteration_matches_separate_calls(c1):
+    """gs3_tr_iteration (Hutchinson + gradient + update fused into the last
+    view's projection backward) against gs3_hvp_diag + gs3_grad + gs3_tr_step,
+    bit for bit, over three iterations (with and without a Hutchinson step, one
+    and two gradient views).  Each of those calls is checked against the
+    oracle by its own test, so the fused iteration inherits their parity."""
+    sc, x, targets = c1
+    a = make_scene(x, targets, sc.cameras, 0)
+    b = make_scene(x, targets, sc.cameras, 0)
+    g = a._empty_like_params()
+    D = a._empty_like_params()
+    plan = [([1], [3], 2, 1e-6), ([1, 4], [], 1, 8e-7), ([2], [], 1, 6e-7)]
+    for it, (S1, S2, nu, eps) in enumerate(plan):
+        say("fused iteration", it, "S1", S1, "S2", S2)
+        seed = 7000 + it
+        if S2:
+            a.hvp_diag(S2, nu, seed, out=D)
+        a.grad(S1, out=g)
+        a.tr_step(g, D if S2 else None, 0.9, 0.999, eps, variant=4)
+        b.tr_iteration(S1, S2, nu, seed, 0.9, 0.999, eps, variant=4)
+        for name in ("x", "ghat", "dhat"):
+            ta, tb = a._empty_like_params(), b._empty_like_params()
+            a.export(**{name: ta})
+            b.export(**{name: tb})
+            assert torch.equal(ta, tb), (it, name, float((ta - tb).abs().max()))
+    a.close()
+    b.close()
