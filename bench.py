@@ -55,6 +55,8 @@ def parse():
                     help="also run Adam for 2x this many iterations and TR until Adam's PSNR (seconds to PSNR)")
     ap.add_argument("--tr-variant", type=int, default=0,
                     help="trust-region radius variant bits for --fit (1 mean exact, 2 second order, 4 joint SH)")
+    ap.add_argument("--large", default="",
+                    help="comma list of large workloads to measure (unbounded, city): iterations/s and device memory")
     ap.add_argument("--serve", type=int, default=0,
                     help="also serve this many scene-fit requests of the Poisson trace (p50/p99 time-to-fit)")
     ap.add_argument("--serve-iters", type=int, default=400,
@@ -242,6 +244,75 @@ def serving(n_req: int, k_iters: int, dev: str) -> dict:
                 iters_total=int(sum(served_iters.values())))
 
 
+def large_scale(names: list, steps: int, warmup: int, dev: str) -> dict:
+    """TR and Adam iterations/s and device memory at the large workloads.
+
+    unbounded: 1M Gaussians (mixture foreground + far shell), SH 3, 200
+    cameras 1600x1000; city: 6M Gaussians over a 200x200 grid, SH 3, 1,000
+    cameras 1920x1080.  Targets are renders of the seeded ground truth.
+    Device memory is the drop in free device memory from just before the
+    scene is created to after its warm-up iterations: everything the method
+    keeps resident (parameters, targets, optimizer state, per-view scratch).
+    """
+    import numpy as np
+    import torch
+
+    import synthetic as syn
+    from paper_2602_00395_amd import Scene
+    from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer
+
+    out = {}
+    for name in names:
+        t0 = time.perf_counter()
+        sc = syn.config3_scene() if name == "unbounded" else syn.config4_scene()
+        print("large", name, "built", sc.n, "Gaussians", len(sc.cameras), "cameras",
+              round(time.perf_counter() - t0, 1), "s", file=sys.stderr, flush=True)
+        cams = sc.cameras
+        sizes = [c.height * c.width * 3 for c in cams]
+        flat = torch.empty(sum(sizes), device=dev)
+        zeros = torch.zeros(sum(sizes), device=dev)
+        g = Scene(torch.tensor(sc.gt, device=dev), zeros, cams, sc.sh_degree, lam=0.2)
+        off = 0
+        for j, n in enumerate(sizes):
+            flat[off:off + n].copy_(g.render(j).reshape(-1))
+            off += n
+        g.close()
+        del zeros
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print("large", name, "targets rendered", file=sys.stderr, flush=True)
+        mask = [j % sc.test_every != 0 for j in range(len(cams))]
+        x0 = torch.tensor(sc.init, device=dev)
+        centres = np.array([c.centre() for c in cams])
+        extent = 1.1 * float(np.linalg.norm(centres - centres.mean(0), axis=1).max())  # Adam's mean learning rate
+        res = dict(gaussians=sc.n, cameras=len(cams), resolution=f"{cams[0].width}x{cams[0].height}")
+        for method in ("tr", "adam"):
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            free0 = torch.cuda.mem_get_info()[0]
+            s = Scene(x0, flat, cams, sc.sh_degree, lam=0.2, train_mask=mask)
+            tr = (TRTrainer(s, sc.train_ids(), TRConfig()) if method == "tr"
+                  else AdamTrainer(s, sc.train_ids(), extent=extent))
+            for _ in range(warmup):
+                tr.step()
+            torch.cuda.synchronize()
+            used = free0 - torch.cuda.mem_get_info()[0]
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                tr.step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            res[f"{method}_iters_per_s"] = round(steps / dt, 2)
+            res[f"{method}_device_bytes"] = int(used)
+            print("large", name, method, res[f"{method}_iters_per_s"], "it/s", used >> 20, "MiB",
+                  file=sys.stderr, flush=True)
+            del tr
+            s.close()
+        out[name] = res
+        del flat, x0
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -368,6 +439,9 @@ def main():
 
     if args.serve > 0:
         out["serving"] = serving(args.serve, args.serve_iters, dev)
+
+    if args.large:
+        out["large"] = large_scale([v for v in args.large.split(",") if v], 20, 5, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_tiles, cfg.l)

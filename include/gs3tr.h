@@ -114,9 +114,10 @@ const char* gs3_version(void);
 
 /* Create a scene: copies params_dev (float[P][N], device) and the training
  * targets targets_dev (device; camera j's float[H_j][W_j][3] images stored
- * back to back in camera order) on `stream`, zeroes the optimizer state
- * (gradient EMA, Hessian-diagonal EMA, Adam moments) and returns the
- * handle in *out.  Setting: the least-squares problem of Eq. objective, whose
+ * back to back in camera order) on `stream` and returns the handle in *out.
+ * The optimizer state (gradient EMA, Hessian-diagonal EMA, Adam moments,
+ * the fused iteration's buffers) is created, zeroed, by the first call that
+ * needs it, so a scene holds only its method's state.  Setting: the least-squares problem of Eq. objective, whose
  * M images are the given cameras.  Errors: EINVAL (NULL or bad sizes),
  * ENOMEM, EDEVICE.  The scene must be released with gs3_scene_destroy. */
 gs3_status gs3_scene_create(const gs3_scene_desc* desc, const float* params_dev, const float* targets_dev,
@@ -133,9 +134,10 @@ gs3_status gs3_scene_params(gs3_scene* scene, float** params_dev);
 /* Overwrite the scene's parameters from params_dev (float[P][N], device). */
 gs3_status gs3_scene_set_params(gs3_scene* scene, const float* params_dev, hipStream_t stream);
 
-/* Resident bytes (parameters, targets, optimizer state) and an estimate of
- * the peak per-view scratch for a scene described by desc; used to admit
- * scenes under an HBM budget.  No device work. */
+/* Resident bytes (parameters, targets and the trust-region method's state:
+ * six float[P][N] buffers in all, where Adam needs three) and
+ * an estimate of the peak per-view scratch for a scene described by desc;
+ * used to admit scenes under an HBM budget.  No device work. */
 gs3_status gs3_scene_bytes(const gs3_scene_desc* desc, int64_t* resident, int64_t* peak_scratch);
 
 /* Wait for all work the scene enqueued; reports deferred device errors. */
@@ -225,11 +227,13 @@ gs3_status gs3_render_jvp(gs3_scene* scene, int32_t cam, const float* tangent_de
                           hipStream_t stream);
 
 /* Copy the optimizer state out (device buffers float[P][N] each; any may be
- * NULL): parameters, gradient EMA, Hessian-diagonal EMA, Adam m and v. */
+ * NULL): parameters, gradient EMA, Hessian-diagonal EMA, Adam m and v (zeros
+ * for state not created yet). */
 gs3_status gs3_scene_export(gs3_scene* scene, float* x, float* ghat, float* Dhat, float* adam_m, float* adam_v,
                             hipStream_t stream);
 
-/* Restore the optimizer state exported by gs3_scene_export (NULL = keep). */
+/* Restore the optimizer state exported by gs3_scene_export (NULL = keep;
+ * creates the state it writes). */
 gs3_status gs3_scene_import(gs3_scene* scene, const float* x, const float* ghat, const float* Dhat,
                             const float* adam_m, const float* adam_v, hipStream_t stream);
 

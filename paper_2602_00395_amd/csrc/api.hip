@@ -242,6 +242,37 @@ void free_all(gs3_scene* s) {
   s->done_ev = nullptr;
 }
 
+// Optimizer state is allocated (and zeroed) on first use, so a scene holds
+// only what its method needs: the trust-region EMAs on the first TR call,
+// the Adam moments on the first Adam call, the fused iteration's second
+// parameter buffer, D_t, gradient accumulator and radius on the first
+// gs3_tr_iteration.
+gs3_status zeroed(gs3_scene* s, float** p, int64_t count, hipStream_t st) {
+  if (*p) return GS3_OK;
+  GS3_TRY(dalloc(p, (size_t)count));
+  launch_fill_f32(*p, count, 0.f, st);
+  return GS3_OK;
+}
+gs3_status need_tr_state(gs3_scene* s, hipStream_t st) {
+  const int64_t PN = (int64_t)s->P * s->N;
+  GS3_TRY(zeroed(s, &s->ghat, PN, st));
+  return zeroed(s, &s->dhat, PN, st);
+}
+gs3_status need_adam_state(gs3_scene* s, hipStream_t st) {
+  const int64_t PN = (int64_t)s->P * s->N;
+  GS3_TRY(zeroed(s, &s->am, PN, st));
+  return zeroed(s, &s->av, PN, st);
+}
+gs3_status need_fused_state(gs3_scene* s, hipStream_t st) {
+  const int64_t PN = (int64_t)s->P * s->N;
+  GS3_TRY(need_tr_state(s, st));
+  if (!s->x_alt) GS3_TRY(dalloc(&s->x_alt, (size_t)PN));
+  if (!s->dbuf) GS3_TRY(dalloc(&s->dbuf, (size_t)PN));
+  if (!s->gacc) GS3_TRY(dalloc(&s->gacc, (size_t)PN));
+  if (!s->rad) GS3_TRY(dalloc(&s->rad, (size_t)(15 * s->N)));
+  return GS3_OK;
+}
+
 gs3_status ensure_pairs(gs3_scene* s, int64_t n_pairs) {
   if (n_pairs <= s->pair_cap && s->rtmp) return GS3_OK;
   const int64_t cap = std::max<int64_t>(n_pairs + n_pairs / 4 + 4096, s->pair_cap);
@@ -403,7 +434,10 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
     px_total += px;
     max_px = std::max(max_px, px);
   }
-  *resident = 4 * P * N * 8 + 12 * px_total;
+  // parameters, both buffers of the fused iteration, the EMAs, D_t and the
+  // gradient accumulator (the trust-region method; Adam instead needs its two
+  // moments) and the targets
+  *resident = 4 * P * N * 6 + 12 * px_total;
   // records, tangent records, eight u32 arrays, the summed partials, the
   // trust radius, per-pixel blend state, and pair buffers for about
   // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair, +25% slack)
@@ -451,15 +485,7 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
     if (rc == GS3_OK) rc = r;
   };
   step(dalloc(&s->x, PN));
-  step(dalloc(&s->x_alt, PN));
-  step(dalloc(&s->dbuf, PN));
-  step(dalloc(&s->gacc, PN));
-  step(dalloc(&s->rad, 15 * s->N));
   step(dalloc(&s->targets, off));
-  step(dalloc(&s->ghat, PN));
-  step(dalloc(&s->dhat, PN));
-  step(dalloc(&s->am, PN));
-  step(dalloc(&s->av, PN));
   step(dalloc(&s->rec, s->N));
   step(dalloc(&s->rect, s->N));
   step(dalloc(&s->trec, s->N));
@@ -502,13 +528,7 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
   };
   rc = copy(s->x, params_dev, PN * sizeof(float));
   if (rc == GS3_OK) rc = copy(s->targets, targets_dev, off * sizeof(float));
-  if (rc == GS3_OK) {
-    launch_fill_f32(s->ghat, PN, 0.f, st);
-    launch_fill_f32(s->dhat, PN, 0.f, st);
-    launch_fill_f32(s->am, PN, 0.f, st);
-    launch_fill_f32(s->av, PN, 0.f, st);
-    rc = finish(s, st);
-  }
+  if (rc == GS3_OK) rc = finish(s, st);
   if (rc != GS3_OK) {
     (void)hipStreamSynchronize(st);
     free_all(s);
@@ -687,6 +707,7 @@ gs3_status gs3_tr_iteration(gs3_scene* s, const int32_t* cams1, int32_t n1, cons
   if (n2 < 0 || (n2 > 0 && nu < 1)) return fail(GS3_EINVAL, "n2 must be >= 0 and nu >= 1 when n2 > 0");
   if (n2 > 0) GS3_TRY(check_views(s, cams2, n2));
   GS3_TRY(check_hparams(hp));
+  GS3_TRY(need_fused_state(s, st));
   if (n2 > 0) GS3_TRY(hvp_views(s, cams2, n2, nu, seed, s->dbuf, st));
   FusedTr ft;
   ft.rad = s->rad;
@@ -705,6 +726,7 @@ gs3_status gs3_tr_step(gs3_scene* s, const float* grad, const float* D, const gs
   GS3_TRY(check_scene(s));
   if (!grad) return fail(GS3_EINVAL, "grad_dev must not be NULL");
   GS3_TRY(check_hparams(hp));
+  GS3_TRY(need_tr_state(s, st));
   TrArgs a{hp->theta1, hp->theta2, hp->epsilon, D != nullptr, hp->variant};
   auto p = prof::begin("tr_step", st);
   launch_tr_step(s->x, grad, s->ghat, s->dhat, D, s->N, s->deg, a, eta_out, dx_out, st);
@@ -736,6 +758,7 @@ static gs3_status adam_common(gs3_scene* s, const float* grad, const float* lr, 
   a.bc2 = (float)(1.0 - std::pow(0.999, step));
   a.epsilon = epsilon;
   auto p = prof::begin("adam_step", st);
+  GS3_TRY(need_adam_state(s, st));
   launch_adam_step(s->x, grad, s->am, s->av, s->N, s->deg, a, st);
   prof::end(p, st, s->N, (int64_t)s->P * s->N);
   return finish(s, st);
@@ -797,8 +820,14 @@ gs3_status gs3_scene_export(gs3_scene* s, float* x, float* ghat, float* dhat, fl
   const size_t bytes = (size_t)s->P * s->N * sizeof(float);
   const float* src[5] = {s->x, s->ghat, s->dhat, s->am, s->av};
   float* dst[5] = {x, ghat, dhat, m, v};
-  for (int i = 0; i < 5; ++i)
-    if (dst[i]) GS3_HIP(hipMemcpyAsync(dst[i], src[i], bytes, hipMemcpyDeviceToDevice, st));
+  for (int i = 0; i < 5; ++i) {
+    if (!dst[i]) continue;
+    if (src[i]) {
+      GS3_HIP(hipMemcpyAsync(dst[i], src[i], bytes, hipMemcpyDeviceToDevice, st));
+    } else {
+      launch_fill_f32(dst[i], (int64_t)s->P * s->N, 0.f, st);  // state not created yet: zero
+    }
+  }
   return finish(s, st);
 }
 
@@ -806,6 +835,8 @@ gs3_status gs3_scene_import(gs3_scene* s, const float* x, const float* ghat, con
                             const float* v, hipStream_t st) {
   GS3_TRY(check_scene(s));
   const size_t bytes = (size_t)s->P * s->N * sizeof(float);
+  if (ghat || dhat) GS3_TRY(need_tr_state(s, st));
+  if (m || v) GS3_TRY(need_adam_state(s, st));
   float* dst[5] = {s->x, s->ghat, s->dhat, s->am, s->av};
   const float* src[5] = {x, ghat, dhat, m, v};
   for (int i = 0; i < 5; ++i)

@@ -59,8 +59,10 @@ class TRTrainer:
         self.train = list(train_ids)
         self.cfg = cfg or TRConfig()
         self.rng = np.random.default_rng(self.cfg.seed)
-        self.g = scene._empty_like_params()
-        self.D = scene._empty_like_params()
+        # gradient and D_t buffers only for the unfused path (the fused
+        # iteration keeps them inside the scene)
+        self.g = None if self.cfg.fused else scene._empty_like_params()
+        self.D = None if self.cfg.fused else scene._empty_like_params()
         self.t = 0
 
     def step(self):

@@ -42,7 +42,7 @@ def test_scene_bytes_and_validation(lib):
     d, keep = make_desc(1000, 3, cams)
     res, scr = c_int64(), c_int64()
     assert lib.gs3_scene_bytes(byref(d), byref(res), byref(scr)) == 0
-    assert res.value == 4 * 59 * 1000 * 8 + 12 * (64 * 48 + 32 * 32)  # 8 state vectors + targets
+    assert res.value == 4 * 59 * 1000 * 6 + 12 * (64 * 48 + 32 * 32)  # 6 TR state vectors + targets
     assert scr.value > 0
     bad, keep2 = make_desc(1000, 5, cams)
     assert lib.gs3_scene_bytes(byref(bad), byref(res), byref(scr)) == _lib.GS3_EINVAL
