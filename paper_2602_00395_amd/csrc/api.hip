@@ -384,8 +384,8 @@ void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st)
 void project_bwd(gs3_scene* s, const CamDev& cd, int mode, int acc, uint64_t seed, uint32_t i, float scale,
                  float* out, hipStream_t st, const FusedTr& ft = FusedTr{}) {
   auto p = prof::begin("project_bwd", st);
-  launch_project_bwd(s->x, s->N, s->deg, cd, s->order, s->offsets, s->counts, s->tiles, s->partials, s->gsum, mode,
-                     acc, seed, i, scale, out, ft, st);
+  launch_project_bwd(s->x, s->N, s->deg, cd, s->rec, s->order, s->offsets, s->counts, s->tiles, s->partials, s->gsum,
+                     mode, acc, seed, i, scale, out, ft, st);
   prof::end(p, st, s->N, 0);
 }
 

@@ -34,7 +34,8 @@ struct CamDev {
 };
 
 // Per-Gaussian screen-space record, 12 words (three float4):
-//   {u, v, qa, qb}, {qc, opacity, r, g}, {b, tau, pair_off, 0}
+//   {u, v, qa, qb}, {qc, opacity, r, g}, {b, tau, pair_off, clamp}
+// clamp: bit c set where colour channel c is unclamped (its bits, not a float)
 // with the conic stored pre-scaled, qa = -a/2, qb = -b, qc = -c/2, so that
 // power = (qa dx) dx + (qc dy) dy + (qb dx) dy -- bit for bit the float32
 // value of -1/2 ((a dx) dx + (c dy) dy) - (b dx) dy, since scaling by powers of
@@ -89,7 +90,7 @@ struct FusedTr {
 // per depth rank; gsum: float[9][n] scratch for the summed partials.
 // mode 0: out = (accumulate ? out : 0) + dL/dx; mode 1: out += scale z dL/dx
 // for probe i of `seed`; mode 2: the fused update described by ft
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const uint32_t* order,
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* order,
                         const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
                         const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
                         uint32_t probe_index, float scale, float* out, const FusedTr& ft, hipStream_t st);

@@ -255,7 +255,9 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
   Rec r;
   r.a = make_float4(p.u, p.v, -0.5f * p.ca, -p.cb);
   r.b = make_float4(-0.5f * p.cc, op, rgb[0], rgb[1]);
-  r.c = make_float4(rgb[2], skip_threshold(op), 0.f, 0.f);
+  // spare word: which colour channels are unclamped (bit c), for the backward
+  const uint32_t posm = (pos[0] ? 1u : 0u) | (pos[1] ? 2u : 0u) | (pos[2] ? 4u : 0u);
+  r.c = make_float4(rgb[2], skip_threshold(op), 0.f, __uint_as_float(posm));
   rec[g] = r;
   rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
   depth_key[g] = __float_as_uint(p.depth);
@@ -371,7 +373,7 @@ constexpr int bwd_roles() {
 // every row.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
-                                                      const uint32_t* __restrict__ tiles,
+                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
                                                       const float* __restrict__ G, int mode, int accumulate,
                                                       uint64_t inner, float scale, float* __restrict__ out,
                                                       FusedTr ft) {
@@ -421,10 +423,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
     emit(10, Gk(5) * s * (1.f - s));
     return;
   }
-  auto srcf = [&](int r) { return x[(int64_t)r * n + g]; };
-  float rgb[3], Y[K];
-  bool pos[3];
-  colour<float, DEG>(srcf, cam, rgb, pos, Y);
+  // the SH basis at the view direction (same expressions as the forward's
+  // colour) and the forward's clamp mask: no SH coefficient is read
+  float Y[K];
+  {
+    const float dx = x[g] - cam.campos[0], dy = x[n + g] - cam.campos[1], dz = x[2 * n + g] - cam.campos[2];
+    const float inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
+    sh_basis<float, DEG>(dx * inv, dy * inv, dz * inv, Y);
+  }
+  const uint32_t posm = __float_as_uint(rec[g].c.w);
+  const bool pos[3] = {(posm & 1u) != 0u, (posm & 2u) != 0u, (posm & 4u) != 0u};
   const float G6 = Gk(6), G7 = Gk(7), G8 = Gk(8);
   const int k0 = kShPerRole * (role - 11);
 #pragma unroll
@@ -469,7 +477,7 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
                    probe_inner(seed, probe_index), tangent, trec);
 }
 
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const uint32_t* order,
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* order,
                         const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
                         const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
                         uint32_t probe_index, float scale, float* out, const FusedTr& ft, hipStream_t st) {
@@ -480,6 +488,6 @@ void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, c
                      ft.a.variant, ft.rad);
   const unsigned roles = deg == 0 ? bwd_roles<0>() : (deg == 1 ? bwd_roles<1>() : (deg == 2 ? bwd_roles<2>()
                                                                                             : bwd_roles<3>()));
-  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256), roles), dim3(256), 0, st, x, n, cam, tiles, gsum,
-                   mode, accumulate, probe_inner(seed, probe_index), scale, out, ft);
+  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256), roles), dim3(256), 0, st, x, n, cam, rec, tiles,
+                   gsum, mode, accumulate, probe_inner(seed, probe_index), scale, out, ft);
 }
