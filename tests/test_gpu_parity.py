@@ -444,3 +444,76 @@ def test_fused_iteration_matches_separate_calls(c1):
             assert torch.equal(ta, tb), (it, name, float((ta - tb).abs().max()))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_grad_and_hvp_parity_sh_degrees(deg):
+    """SH degrees 1 and 2 (the kernels are instantiated per degree; the other
+    tests cover 0 and 3): gradient and Hutchinson diagonal against the oracle."""
+    sc = syn.tiny_scene(300 + deg, n=60, sh_degree=deg, width=48, height=40, n_cams=3,
+                        log_scale_mean=np.log(0.08))
+    x = sc.gt.astype(np.float32)
+    x[0:3] += np.random.default_rng(deg).normal(0, 0.02, size=x[0:3].shape).astype(np.float32)
+    targets = offset_targets(x, sc.cameras, deg, seed=4100 + deg)
+    s = make_scene(x, targets, sc.cameras, deg)
+    prob = Mth.Problem(sc.cameras, targets, deg, lam=0.2)
+    p = x.shape[0]
+    say("grad sh degree", deg)
+    want, _ = Mth.gradient(x, prob, [1])
+    errs = group_errors(s.grad([1]).cpu().numpy(), want, p)
+    say("  rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    say("hvp sh degree", deg)
+    want = Mth.hutchinson(x, prob, [2], 1, 5200 + deg)
+    errs = group_errors(s.hvp_diag([2], 1, 5200 + deg).cpu().numpy(), want, p)
+    say("  rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2])
+def test_tr_step_parity_sh_degrees(deg):
+    """The update kernel for P = 14, 23, 38 rows (the object-scale test covers 59)."""
+    sc = syn.config2_scene(n=2000, n_cams=1, res=32)
+    p = Mth.n_params(deg)
+    x = np.concatenate([sc.gt[:11], sc.gt[11:11 + p - 11]]).astype(np.float32)
+    rng = np.random.default_rng(50 + deg)
+    g = (rng.normal(size=x.shape) * 1e-3).astype(np.float32)
+    ghat = (rng.normal(size=x.shape) * 1e-3).astype(np.float32)
+    dhat = rng.uniform(-0.2, 1.0, size=x.shape).astype(np.float32)
+    D = rng.uniform(0.0, 2.0, size=x.shape).astype(np.float32)
+    targets = [np.zeros((c.height, c.width, 3), np.float32) for c in sc.cameras]
+    s = make_scene(x, targets, sc.cameras, deg)
+    s.import_(ghat=torch.tensor(ghat, device=DEV), dhat=torch.tensor(dhat, device=DEV))
+    eta_t = torch.empty(x.shape, device=DEV)
+    dx_t = torch.empty(x.shape, device=DEV)
+    eps = 2e-7
+    say("tr_step sh degree", deg)
+    s.tr_step(torch.tensor(g, device=DEV), torch.tensor(D, device=DEV), 0.9, 0.999, eps, eta_out=eta_t, dx_out=dx_t,
+              variant=4)
+    eta_want = Mth.shd_eta(x.astype(np.float64), eps, deg, sh_rest="joint")
+    _, _, _, dxw, _ = Mth.tr_step(x, g, ghat, dhat, D, 0.9, 0.999, eps, deg, eta=eta_want)
+    eta_got = eta_t.cpu().numpy()
+    assert np.array_equal(np.isinf(eta_got), np.isinf(eta_want))
+    fin = np.isfinite(eta_want)
+    assert rel_l2(eta_got[fin], eta_want[fin]) <= TOL
+    errs = group_errors(dx_t.cpu().numpy(), dxw, p)
+    say("  step rel-L2", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
+def test_single_gaussian_render_and_grad():
+    """N = 1: one splat, one tile list of length one per tile it touches."""
+    sc = syn.tiny_scene(77, n=1, sh_degree=0, width=40, height=36, n_cams=2, log_scale_mean=np.log(0.3))
+    x = sc.gt.astype(np.float32)
+    targets = offset_targets(x, sc.cameras, 0, seed=4300)
+    s = make_scene(x, targets, sc.cameras, 0)
+    want_img = R.render(torch.tensor(x, dtype=torch.float64), sc.cameras[0], 0).numpy()
+    assert rel_l2(s.render(0).cpu().numpy(), want_img) <= TOL
+    prob = Mth.Problem(sc.cameras, targets, 0, lam=0.2)
+    want, _ = Mth.gradient(x, prob, [0])
+    errs = group_errors(s.grad([0]).cpu().numpy(), want, 14)
+    say("single Gaussian grad rel-L2", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
