@@ -15,8 +15,9 @@
 // Layout: one 256-thread workgroup per 16x16 tile, one pixel per thread,
 // each wave64 an 8x8 block of the tile; records of a batch of splats are
 // staged in LDS together with, per wave, a bit mask of the splats whose
-// skip test can pass somewhere in its block (a conservative bound on the
-// f32 skip ellipse), and every wave walks only the set bits.  Culled
+// skip test can pass somewhere in its block (the skip ellipse, widened by its
+// float32 rounding, against the block's rectangle of pixel centres), and
+// every wave walks only the set bits.  Culled
 // evaluations are exactly the ones the skip test would reject, so the
 // result is the same bit for bit.  Workgroups take tiles longest list first
 // (a pixel's walk is serial, so the tiles with the longest lists bound the
@@ -81,6 +82,19 @@ __device__ __forceinline__ float splat_power(float qa, float qb, float qc, float
 __device__ __forceinline__ int pixel_x(int tx, int tid) { return tx * GS3_TILE + ((tid >> 6) & 1) * 8 + (tid & 7); }
 __device__ __forceinline__ int pixel_y(int ty, int tid) { return ty * GS3_TILE + (tid >> 7) * 8 + ((tid >> 3) & 7); }
 
+// Minimum of q(x, y) = a x^2 + 2 b x y + c y^2 (positive definite) over the
+// rectangle [x0, x1] x [y0, y1]: 0 if the rectangle holds the origin, else
+// the least of the four edges' minima (each a 1D quadratic, its minimiser
+// clamped to the edge).
+__device__ __forceinline__ double quad_rect_min(double a, double b, double c, double x0, double x1, double y0,
+                                                double y1) {
+  if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) return 0.0;
+  auto q = [&](double x, double y) { return (a * x + 2.0 * b * y) * x + c * y * y; };
+  auto on_x = [&](double x) { return q(x, fmin(fmax(-b * x / c, y0), y1)); };
+  auto on_y = [&](double y) { return q(fmin(fmax(-b * y / a, x0), x1), y); };
+  return fmin(fmin(on_x(x0), on_x(x1)), fmin(on_y(y0), on_y(y1)));
+}
+
 // Which of the four 8x8 blocks of tile (tx, ty) may hold a pixel whose skip
 // test passes for the splat (u, v, pre-scaled conic qa, qb, qc, threshold
 // tau); bit b for block b.  With the plain conic Q = (a, b; b, c) =
@@ -88,26 +102,23 @@ __device__ __forceinline__ int pixel_y(int ty, int tid) { return ty * GS3_TILE +
 // -1/2 d^T Q d, so it can pass only where d^T Q d <= k (1 + r) with k = -2 tau
 // and r the relative rounding error of p: with rho^2 = b^2 / (a c), r is at
 // most 4 u (1 + rho) / (1 - rho), below 1e-3 for rho^2 <= 0.999 (u = 2^-24).
-// The bounding box of d^T Q d <= 1.002 k has half-widths
-// sqrt(1.002 k c / det Q) and sqrt(1.002 k a / det Q); it is formed in double
-// (det Q of the float32 entries is then exact up to one rounding) and widened
-// by 1e-3 px.  Splats with rho^2 > 0.999 or non-finite entries are never
-// culled; tau > 0 passes nowhere.
+// A block is kept when the minimum of d^T Q d over the rectangle spanned by
+// its pixel centres is at most 1.002 k + 1e-4, evaluated in double (det Q of
+// the float32 entries is then exact up to one rounding).  Splats with
+// rho^2 > 0.999 or non-finite entries are never culled; tau > 0 passes
+// nowhere.
 __device__ __forceinline__ uint32_t block_mask(float4 A, float4 B, float tau, int tx, int ty) {
   if (tau > 0.f) return 0u;
   const double a = -2.0 * (double)A.z, b = -(double)A.w, c = -2.0 * (double)B.x;
   const double det = a * c - b * b;
   if (!(a > 0.0 && c > 0.0 && det * 1000.0 >= a * c && det < INFINITY)) return 0xfu;
-  const double k = -2.004 * (double)tau;
-  const double ex = sqrt(k * c / det) + 1e-3, ey = sqrt(k * a / det) + 1e-3;
-  const double u = A.x, v = A.y;
-  const double x0 = tx * GS3_TILE + 0.5, y0 = ty * GS3_TILE + 0.5;
+  const double k = -2.004 * (double)tau + 1e-4;
+  const double x0 = tx * GS3_TILE + 0.5 - (double)A.x, y0 = ty * GS3_TILE + 0.5 - (double)A.y;
   uint32_t m = 0u;
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk) {
     const double bx = x0 + 8 * (blk & 1), by = y0 + 8 * (blk >> 1);
-    const bool hit = u + ex >= bx && u - ex <= bx + 7.0 && v + ey >= by && v - ey <= by + 7.0;
-    m |= hit ? (1u << blk) : 0u;
+    m |= quad_rect_min(a, b, c, bx, bx + 7.0, by, by + 7.0) <= k ? (1u << blk) : 0u;
   }
   return m;
 }
