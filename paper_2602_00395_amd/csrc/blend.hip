@@ -85,13 +85,14 @@ __device__ __forceinline__ int pixel_y(int ty, int tid) { return ty * GS3_TILE +
 // Minimum of q(x, y) = a x^2 + 2 b x y + c y^2 (positive definite) over the
 // rectangle [x0, x1] x [y0, y1]: 0 if the rectangle holds the origin, else
 // the least of the four edges' minima (each a 1D quadratic, its minimiser
-// clamped to the edge).
-__device__ __forceinline__ double quad_rect_min(double a, double b, double c, double x0, double x1, double y0,
-                                                double y1) {
+// clamped to the edge).  sx = -b / c and sy = -b / a give the minimisers
+// y = sx x on a vertical edge and x = sy y on a horizontal one.
+__device__ __forceinline__ double quad_rect_min(double a, double b, double c, double sx, double sy, double x0,
+                                                double x1, double y0, double y1) {
   if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) return 0.0;
   auto q = [&](double x, double y) { return (a * x + 2.0 * b * y) * x + c * y * y; };
-  auto on_x = [&](double x) { return q(x, fmin(fmax(-b * x / c, y0), y1)); };
-  auto on_y = [&](double y) { return q(fmin(fmax(-b * y / a, x0), x1), y); };
+  auto on_x = [&](double x) { return q(x, fmin(fmax(sx * x, y0), y1)); };
+  auto on_y = [&](double y) { return q(fmin(fmax(sy * y, x0), x1), y); };
   return fmin(fmin(on_x(x0), on_x(x1)), fmin(on_y(y0), on_y(y1)));
 }
 
@@ -104,7 +105,9 @@ __device__ __forceinline__ double quad_rect_min(double a, double b, double c, do
 // most 4 u (1 + rho) / (1 - rho), below 1e-3 for rho^2 <= 0.999 (u = 2^-24).
 // A block is kept when the minimum of d^T Q d over the rectangle spanned by
 // its pixel centres is at most 1.002 k + 1e-4, evaluated in double (det Q of
-// the float32 entries is then exact up to one rounding).  Splats with
+// the float32 entries is then exact up to one rounding; a minimiser off by a
+// few double roundings is still a point of the rectangle, and raises q by a
+// second-order amount far inside the 1e-4).  Splats with
 // rho^2 > 0.999 or non-finite entries are never culled; tau > 0 passes
 // nowhere.
 __device__ __forceinline__ uint32_t block_mask(float4 A, float4 B, float tau, int tx, int ty) {
@@ -114,11 +117,12 @@ __device__ __forceinline__ uint32_t block_mask(float4 A, float4 B, float tau, in
   if (!(a > 0.0 && c > 0.0 && det * 1000.0 >= a * c && det < INFINITY)) return 0xfu;
   const double k = -2.004 * (double)tau + 1e-4;
   const double x0 = tx * GS3_TILE + 0.5 - (double)A.x, y0 = ty * GS3_TILE + 0.5 - (double)A.y;
+  const double sx = -b / c, sy = -b / a;
   uint32_t m = 0u;
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk) {
     const double bx = x0 + 8 * (blk & 1), by = y0 + 8 * (blk >> 1);
-    m |= quad_rect_min(a, b, c, bx, bx + 7.0, by, by + 7.0) <= k ? (1u << blk) : 0u;
+    m |= quad_rect_min(a, b, c, sx, sy, bx, bx + 7.0, by, by + 7.0) <= k ? (1u << blk) : 0u;
   }
   return m;
 }
