@@ -10,8 +10,10 @@ timed region; targets are renders of a seeded ground-truth scene.
 
 Prints one JSON line: iterations/s, the roofline of the kernel that takes
 the most time (measured with HIP events around its launches during the timed
-region), the Adam baseline's iterations/s on the same views, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+region; its work counts come from an untimed replay of the same iterations
+with the counting kernel instances), the Adam baseline's iterations/s on the
+same views, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 
   python bench.py [--steps K] [--warmup W] [--fit TR_ITERS]
 """
@@ -324,7 +326,7 @@ def main():
     import torch
 
     import synthetic as syn
-    from paper_2602_00395_amd import Scene, profile_enable, profile_read, profile_reset
+    from paper_2602_00395_amd import Scene, profile_count, profile_enable, profile_read, profile_reset
     from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer, fit, mean_psnr
 
     dev = "cuda:0"
@@ -360,24 +362,28 @@ def main():
         tr.step()
     torch.cuda.synchronize()
     profile_reset()
+    profile_count(False)
     profile_enable("all")
     for _ in range(2 * cfg.l):
         tr.step()
     torch.cuda.synchronize()
     profile_enable("")
+    profile_count(True)
     stages = ["project_fwd", "depth_sort", "scan", "emit_pairs", "pair_sort", "blend_fwd", "loss", "blend_bwd",
               "project_bwd", "project_jvp", "blend_jvp", "tr_step"]
     stage_ms = {k: profile_read(k)["total_ms"] / (2 * cfg.l) for k in stages}
     dominant = max(stage_ms, key=stage_ms.get)
     s.close()
 
-    # ---- timed TR iterations
+    # ---- timed TR iterations: the dominant stage's launches are bracketed by
+    # events only, so they run the same kernels as every other launch
     s = make()
     tr = TRTrainer(s, train_ids, cfg)
     for _ in range(args.warmup):
         tr.step()
     torch.cuda.synchronize()
     profile_reset()
+    profile_count(False)
     profile_enable(dominant)
     first = tr.t + 1
     t0 = time.perf_counter()
@@ -386,10 +392,30 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     profile_enable("")
+    profile_count(True)
+    timed = profile_read(dominant)
     hutch = sum(1 for t in range(first, first + args.steps) if (t - 1) % cfg.l == 0)
-    roof = roofline(dominant, profile_read(dominant), N, P, hutch)
     psnr_tr = mean_psnr(s, test_ids)
     s.close()
+    # the same iterations again, untimed, with the work counters on: the
+    # evaluation counts of exactly the timed launches
+    s = make()
+    tr = TRTrainer(s, train_ids, cfg)
+    for _ in range(args.warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    profile_reset()
+    profile_enable(dominant)
+    for _ in range(args.steps):
+        tr.step()
+    torch.cuda.synchronize()
+    profile_enable("")
+    counted = profile_read(dominant)
+    s.close()
+    if counted["launches"] != timed["launches"]:
+        raise RuntimeError(f"counted replay made {counted['launches']} {dominant} launches, "
+                           f"the timed run {timed['launches']}")
+    roof = roofline(dominant, dict(timed, work0=counted["work0"], work1=counted["work1"]), N, P, hutch)
 
     # ---- Adam on the same views, same clock
     s = make()

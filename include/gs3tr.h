@@ -242,14 +242,19 @@ gs3_status gs3_scene_import(gs3_scene* scene, const float* x, const float* ghat,
  * (comma separated; "all" = every stage; NULL or "" disables): project_fwd,
  * depth_sort, scan, emit_pairs, pair_sort, blend_fwd, blend_jvp, blend_bwd,
  * project_jvp, project_bwd, loss, tr_step, adam_step.  Blend stages also
- * count their work on the device.  gs3_profile_read(name, ...) waits for the
+ * count their work on the device, with instrumented instances of their
+ * kernels, unless gs3_profile_count(0) has switched counting off (then the
+ * bracketed launches are the uninstrumented kernels every other call runs;
+ * counting is on initially).  gs3_profile_read(name, ...) waits for the
  * recorded events and returns the number of bracketed launches, their summed
  * duration in milliseconds and two work counters: for blend stages the
  * (pixel, splat) evaluations and the contributing evaluations, for tr_step
  * and adam_step the Gaussians and the parameters updated, else 0 (any output
- * pointer may be NULL).  gs3_profile_reset() forgets every record.  All three
- * are serialised by a process-wide lock. */
+ * pointer may be NULL; the blend counters read 0 for launches made with
+ * counting off).  gs3_profile_reset() forgets every record.  All four are
+ * serialised by a process-wide lock. */
 gs3_status gs3_profile_enable(const char* names);
+gs3_status gs3_profile_count(int32_t on);
 gs3_status gs3_profile_read(const char* name, int64_t* launches, double* total_ms, int64_t* work0,
                             int64_t* work1);
 gs3_status gs3_profile_reset(void);

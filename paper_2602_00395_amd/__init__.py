@@ -6,4 +6,4 @@ the package does not load the library; ``Scene`` does, and fails loudly if it
 has not been built.
 """
 from .api import (ADAM_GROUP_ORDER, TR_MEAN_EXACT, TR_SECOND_ORDER, TR_SH_JOINT, Scene,  # noqa: F401
-                  n_params, profile_enable, profile_read, profile_reset, scene_bytes)
+                  n_params, profile_count, profile_enable, profile_read, profile_reset, scene_bytes)

@@ -63,6 +63,7 @@ _SIGS = {
     "gs3_scene_export": (c_int32, [c_void_p] + [c_void_p] * 5 + [c_void_p]),
     "gs3_scene_import": (c_int32, [c_void_p] + [c_void_p] * 5 + [c_void_p]),
     "gs3_profile_enable": (c_int32, [c_char_p]),
+    "gs3_profile_count": (c_int32, [c_int32]),
     "gs3_profile_read": (c_int32, [c_char_p, POINTER(c_int64), POINTER(c_double), POINTER(c_int64),
                                    POINTER(c_int64)]),
     "gs3_profile_reset": (c_int32, []),

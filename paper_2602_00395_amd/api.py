@@ -81,6 +81,12 @@ def profile_enable(names: str):
     _lib.check("gs3_profile_enable", lib.gs3_profile_enable(names.encode() if names else None))
 
 
+def profile_count(on: bool):
+    """Whether bracketed blend launches count their work (see gs3_profile_count)."""
+    lib = _lib.load()
+    _lib.check("gs3_profile_count", lib.gs3_profile_count(1 if on else 0))
+
+
 def profile_reset():
     lib = _lib.load()
     _lib.check("gs3_profile_reset", lib.gs3_profile_reset())

@@ -40,6 +40,7 @@ constexpr int kMaxLossViews = 4096;
 namespace prof {
 std::mutex mu;
 std::atomic<bool> active{false};
+bool counting = true;  // blend stages launch their counting instances
 std::string names;  // ",name,name," or ",all,"
 struct Entry {
   std::string name;
@@ -68,7 +69,7 @@ Scope begin(const char* name, hipStream_t st, bool counted = false) {
   e.name = name;
   if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return sc;
   (void)hipEventRecord(e.a, st);
-  if (counted && ctr && slots_used < kSlots) {
+  if (counted && counting && ctr && slots_used < kSlots) {
     e.slot = slots_used++;
     sc.c = ctr + kSlotWords * e.slot;
   }
@@ -860,6 +861,12 @@ gs3_status gs3_profile_enable(const char* names) {
   }
   prof::names = "," + std::string(names) + ",";
   prof::active.store(true);
+  return GS3_OK;
+}
+
+gs3_status gs3_profile_count(int32_t on) {
+  std::lock_guard<std::mutex> lk(prof::mu);
+  prof::counting = on != 0;
   return GS3_OK;
 }
 

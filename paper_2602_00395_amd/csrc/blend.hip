@@ -50,11 +50,13 @@ __device__ __forceinline__ int tile_of_block(int b, const uint32_t* order, int n
   return (b & 7) * chunk + (b >> 3);
 }
 
-// Measurement hook: when `ctr` is not null, adds this wave's number of
+// Measurement hook of the COUNT instances: adds this wave's number of
 // (pixel, splat) evaluations and of contributing evaluations to one of the
-// launch's GS3_PROF_SUB counter pairs (ctr[2 s], ctr[2 s + 1]).
+// launch's GS3_PROF_SUB counter pairs (ctr[2 s], ctr[2 s + 1]).  The
+// instances launched without counters carry no counting instructions.
+template <bool COUNT>
 __device__ __forceinline__ void count_evals(unsigned long long* ctr, uint32_t nev, uint32_t ncon) {
-  if (ctr == nullptr) return;
+  if (!COUNT) return;
   unsigned long long a = nev, b = ncon;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
@@ -156,6 +158,7 @@ struct Stage {
   uint64_t bits[4][GS3_BLOCK / 64];
 };
 
+template <bool COUNT>
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__ rec,
                                                           const uint32_t* __restrict__ pair_gid,
                                                           const uint2* __restrict__ ranges,
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
         }
         const int j = (q << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        nev += live;
+        if (COUNT) nev += live;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
         const float dx = A.x - pxf, dy = A.y - pyf;
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
         const bool stop = pass && Tn < GS3_T_STOP;
         const bool use = pass && !stop;
         live = stop ? 0u : live;
-        ncon += use ? 1u : 0u;
+        if (COUNT) ncon += use ? 1u : 0u;
         const float w8 = use ? a * T : 0.f;
         C0 += B.z * w8;
         C1 += B.w * w8;
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
     pix_last[pix] = lastp;
     pix_T[pix] = T;
   }
-  count_evals(ctr, nev, ncon);
+  count_evals<COUNT>(ctr, nev, ncon);
 }
 
 struct StageJ {
@@ -249,6 +252,7 @@ struct StageJ {
   uint64_t bits[4][GS3_BLOCK / 64];
 };
 
+template <bool COUNT>
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__ rec, const TRec* __restrict__ trec,
                                                           const uint32_t* __restrict__ pair_gid,
                                                           const uint2* __restrict__ ranges,
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
         }
         const int j = (qw << 6) + __builtin_ctzll(bits);
         bits &= bits - 1;
-        nev += live;
+        if (COUNT) nev += live;
         const float4 A = s.a[j], B = s.b[j];
         const float2 Cc = s.c[j];
         const float dx = A.x - pxf, dy = A.y - pyf;
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
         const bool stop = pass && Tn < GS3_T_STOP;
         const bool use = pass && !stop;
         live = stop ? 0u : live;
-        ncon += use ? 1u : 0u;
+        if (COUNT) ncon += use ? 1u : 0u;
         const float4 TA = s.ta[j], TB = s.tb[j];
         // d power along the tangent: d = (u - px, v - py), dd = (du, dv); the
         // record holds the pre-scaled conic, the tangent record the plain one
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
     tan_img[o + 1] = D1 + dT * bg1;
     tan_img[o + 2] = D2 + dT * bg2;
   }
-  count_evals(ctr, nev, ncon);
+  count_evals<COUNT>(ctr, nev, ncon);
 }
 
 // Data-parallel-primitive (DPP) move: lane i reads `v` from the lane selected
@@ -411,6 +415,7 @@ __device__ __forceinline__ uint32_t pair_slot(uint32_t pair_off, uint2 rc, int t
   return pair_off + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__ rec,
                                                           const uint2* __restrict__ rect,
                                                           const uint32_t* __restrict__ pair_gid,
@@ -489,7 +494,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
         const uint64_t keep = lq >= 64 ? ~0ull : (lq <= 0 ? 0ull : ((1ull << lq) - 1ull));
         const uint64_t word = uniform64(s.bits[w][q]);
         uint64_t bits = word & keep;
-        if (bits != word && lane == 0) s.bits[w][q] = bits;  // the epilogue counts dropped ones as zero
+        uint64_t reduced = bits;  // less the splats no lane of the wave uses
         while (bits) {
           const int hi = 63 - __builtin_clzll(bits);
           const int j = (q << 6) + hi;
@@ -502,8 +507,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           // predicated like the forward: lanes that do not contribute end
           // with zero partials and unchanged T and acc
           const bool use = pi < last && power <= 0.f && power >= Cc.y;
-          nev += pi < last ? 1u : 0u;
-          ncon += use ? 1u : 0u;
+          if (COUNT) {
+            nev += pi < last ? 1u : 0u;
+            ncon += use ? 1u : 0u;
+          }
           const float G = __expf(power);
           const float araw = B.y * G;
           const float a = fminf(GS3_ALPHA_MAX, araw);
@@ -531,20 +538,23 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
           // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
           // DPP reduction into lane 63.  26 VALU instructions in all.
-          float E = 0.f, F = 0.f, H = 0.f;
           if (__ballot(use) != 0ull) {
-            E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
-            F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
-            H = wave_sum_lane63(gr[8]);
-          }
-          if ((lane & 15) == 15) {
-            const int row = lane >> 4;
-            const int k = (row & 1) * 2 + (row >> 1);
-            s.red[w][k][j] = E;
-            s.red[w][4 + k][j] = F;
-            if (lane == 63) s.red[w][8][j] = H;
+            const float E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
+            const float F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
+            const float H = wave_sum_lane63(gr[8]);
+            if ((lane & 15) == 15) {
+              const int row = lane >> 4;
+              const int k = (row & 1) * 2 + (row >> 1);
+              s.red[w][k][j] = E;
+              s.red[w][4 + k][j] = F;
+              if (lane == 63) s.red[w][8][j] = H;
+            }
+          } else {
+            reduced &= ~(1ull << hi);
           }
         }
+        // the epilogue counts the splats this wave did not reduce as zero
+        if (reduced != word && lane == 0) s.bits[w][q] = reduced;
       }
       __syncthreads();
       if (tid < cnt) {
@@ -572,7 +582,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
       __syncthreads();
     }
   }
-  count_evals(ctr, nev, ncon);
+  count_evals<COUNT>(ctr, nev, ncon);
 }
 
 inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }
@@ -583,7 +593,8 @@ void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ran
                       const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T,
                       hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
-  hipLaunchKernelGGL(k_blend_fwd, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, order,
+  auto kernel = ctr ? k_blend_fwd<true> : k_blend_fwd<false>;
+  hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, order,
                      cam, bg[0], bg[1], bg[2], img, pix_last, pix_T, nt, ch, ctr);
 }
 
@@ -591,7 +602,8 @@ void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid
                       const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
                       uint32_t* pix_last, float* pix_T, hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
-  hipLaunchKernelGGL(k_blend_jvp, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges,
+  auto kernel = ctr ? k_blend_jvp<true> : k_blend_jvp<false>;
+  hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges,
                      order, cam, bg[0], bg[1], bg[2], img, tan_img, pix_last, pix_T, nt, ch, ctr);
 }
 
@@ -599,6 +611,7 @@ void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gi
                       const uint32_t* order, const CamDev& cam, const uint32_t* pix_last, const float* pix_T,
                       const float* bg, const float* cot, float* partials, hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
-  hipLaunchKernelGGL(k_blend_bwd, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges,
+  auto kernel = ctr ? k_blend_bwd<true> : k_blend_bwd<false>;
+  hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges,
                      order, cam, pix_last, pix_T, bg[0], bg[1], bg[2], cot, partials, nt, ch, ctr);
 }
