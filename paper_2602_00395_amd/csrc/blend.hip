@@ -17,7 +17,10 @@
 // staged in LDS together with, per wave, a bit mask of the splats whose
 // skip test can pass somewhere in its block (the skip ellipse, widened by its
 // float32 rounding, against the block's rectangle of pixel centres), and
-// every wave walks only the set bits.  Culled
+// every wave walks only the set bits.  In the forward each wave stages its
+// own batches in a private LDS slice and never waits for the other three
+// (they differ in how far their pixels blend); the JVP and the backward
+// stage per workgroup.  Culled
 // evaluations are exactly the ones the skip test would reject, so the
 // result is the same bit for bit.  Workgroups take tiles longest list first
 // (a pixel's walk is serial, so the tiles with the longest lists bound the
@@ -112,21 +115,48 @@ __device__ __forceinline__ double quad_rect_min(double a, double b, double c, do
 // second-order amount far inside the 1e-4).  Splats with
 // rho^2 > 0.999 or non-finite entries are never culled; tau > 0 passes
 // nowhere.
+struct Cull {
+  int all;  // -1: no pixel passes, 1: never culled, 0: test each block
+  double a, b, c, sx, sy, k, x0, y0;
+};
+__device__ __forceinline__ Cull cull_setup(float4 A, float4 B, float tau, int tx, int ty) {
+  Cull q{};
+  if (tau > 0.f) {
+    q.all = -1;
+    return q;
+  }
+  q.a = -2.0 * (double)A.z;
+  q.b = -(double)A.w;
+  q.c = -2.0 * (double)B.x;
+  const double det = q.a * q.c - q.b * q.b;
+  q.all = (q.a > 0.0 && q.c > 0.0 && det * 1000.0 >= q.a * q.c && det < INFINITY) ? 0 : 1;
+  q.k = -2.004 * (double)tau + 1e-4;
+  q.x0 = tx * GS3_TILE + 0.5 - (double)A.x;
+  q.y0 = ty * GS3_TILE + 0.5 - (double)A.y;
+  q.sx = -q.b / q.c;
+  q.sy = -q.b / q.a;
+  return q;
+}
+__device__ __forceinline__ bool cull_keep(const Cull& q, int blk) {
+  if (q.all != 0) return q.all > 0;
+  const double bx = q.x0 + 8 * (blk & 1), by = q.y0 + 8 * (blk >> 1);
+  return quad_rect_min(q.a, q.b, q.c, q.sx, q.sy, bx, bx + 7.0, by, by + 7.0) <= q.k;
+}
+// all four blocks: bit b for block b
 __device__ __forceinline__ uint32_t block_mask(float4 A, float4 B, float tau, int tx, int ty) {
-  if (tau > 0.f) return 0u;
-  const double a = -2.0 * (double)A.z, b = -(double)A.w, c = -2.0 * (double)B.x;
-  const double det = a * c - b * b;
-  if (!(a > 0.0 && c > 0.0 && det * 1000.0 >= a * c && det < INFINITY)) return 0xfu;
-  const double k = -2.004 * (double)tau + 1e-4;
-  const double x0 = tx * GS3_TILE + 0.5 - (double)A.x, y0 = ty * GS3_TILE + 0.5 - (double)A.y;
-  const double sx = -b / c, sy = -b / a;
+  const Cull q = cull_setup(A, B, tau, tx, ty);
   uint32_t m = 0u;
 #pragma unroll
-  for (int blk = 0; blk < 4; ++blk) {
-    const double bx = x0 + 8 * (blk & 1), by = y0 + 8 * (blk >> 1);
-    m |= quad_rect_min(a, b, c, sx, sy, bx, bx + 7.0, by, by + 7.0) <= k ? (1u << blk) : 0u;
-  }
+  for (int blk = 0; blk < 4; ++blk) m |= cull_keep(q, blk) ? (1u << blk) : 0u;
   return m;
+}
+
+// Orders this wave's LDS writes before its later LDS reads and the reads
+// before later writes (its lanes exchange data through a wave-private slice).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Publish the block masks of the splats staged by this wave (one splat per
@@ -151,11 +181,12 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-struct Stage {
-  float4 a[GS3_BLOCK];
-  float4 b[GS3_BLOCK];
-  float2 c[GS3_BLOCK];  // b, tau
-  uint64_t bits[4][GS3_BLOCK / 64];
+// One wave's batch of 64 splats (the forward's waves never wait for each
+// other: each stages, culls for its own 8x8 block and walks on its own).
+struct StageW {
+  float4 a[64];
+  float4 b[64];
+  float2 c[64];  // b, tau
 };
 
 template <bool COUNT>
@@ -168,9 +199,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
                                                           int n_tiles, int chunk, unsigned long long* __restrict__ ctr) {
   const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
-  __shared__ Stage s;
+  __shared__ StageW stage[4];
   uint32_t nev = 0, ncon = 0;
-  const int tid = threadIdx.x, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  StageW& s = stage[w];
   const int tx = t % cam.tiles_x, ty = t / cam.tiles_x;
   const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
@@ -181,54 +213,46 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   // loop carries it in a vector register instead of a scalar lane mask
   uint32_t live = inside ? 1u : 0u;
   uint32_t lastp = 0u;  // 1 + pair index of the last contributing splat (0: none)
-  for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
-    if (__syncthreads_count(live) == 0) break;
-    const uint32_t i = start + tid;
-    uint32_t m = 0u;
+  for (uint32_t start = range.x; start < range.y; start += 64) {
+    // every pixel of the block has stopped: the rest is never read
+    if (__ballot(live) == 0ull) break;
+    const uint32_t i = start + lane;
+    bool keep = false;
     if (i < range.y) {
       const Rec r = rec[pair_gid[i]];
-      s.a[tid] = r.a;
-      s.b[tid] = r.b;
-      s.c[tid] = make_float2(r.c.x, r.c.y);
-      m = block_mask(r.a, r.b, r.c.y, tx, ty);
+      s.a[lane] = r.a;
+      s.b[lane] = r.b;
+      s.c[lane] = make_float2(r.c.x, r.c.y);
+      keep = cull_keep(cull_setup(r.a, r.b, r.c.y, tx, ty), w);
     }
-    publish_masks(s.bits, m, tid);
-    __syncthreads();
-    const int nwords = (min((int)(range.y - start), GS3_BLOCK) + 63) >> 6;
-    bool wave_done = false;
-    for (int q = 0; q < nwords && !wave_done; ++q) {
-      uint64_t bits = uniform64(s.bits[w][q]);
-      while (bits) {
-        // every pixel of the block has stopped: the rest is never read
-        if (__ballot(live) == 0ull) {
-          wave_done = true;
-          break;
-        }
-        const int j = (q << 6) + __builtin_ctzll(bits);
-        bits &= bits - 1;
-        if (COUNT) nev += live;
-        const float4 A = s.a[j], B = s.b[j];
-        const float2 Cc = s.c[j];
-        const float dx = A.x - pxf, dy = A.y - pyf;
-        const float power = splat_power(A.z, A.w, B.x, dx, dy);
-        // predicated rather than branched: nearly every wave has a lane
-        // that contributes, so a branch would only add mask bookkeeping
-        const bool pass = live && power <= 0.f && power >= Cc.y;
-        const float a = fminf(GS3_ALPHA_MAX, B.y * __expf(power));
-        const float Tn = T * (1.f - a);
-        const bool stop = pass && Tn < GS3_T_STOP;
-        const bool use = pass && !stop;
-        live = stop ? 0u : live;
-        if (COUNT) ncon += use ? 1u : 0u;
-        const float w8 = use ? a * T : 0.f;
-        C0 += B.z * w8;
-        C1 += B.w * w8;
-        C2 += Cc.x * w8;
-        T = use ? Tn : T;
-        lastp = use ? start + (uint32_t)j + 1u : lastp;
-      }
+    uint64_t bits = __ballot(keep);
+    wave_lds_sync();
+    while (bits) {
+      if (__ballot(live) == 0ull) break;
+      const int j = __builtin_ctzll(bits);
+      bits &= bits - 1;
+      if (COUNT) nev += live;
+      const float4 A = s.a[j], B = s.b[j];
+      const float2 Cc = s.c[j];
+      const float dx = A.x - pxf, dy = A.y - pyf;
+      const float power = splat_power(A.z, A.w, B.x, dx, dy);
+      // predicated rather than branched: nearly every wave has a lane
+      // that contributes, so a branch would only add mask bookkeeping
+      const bool pass = live && power <= 0.f && power >= Cc.y;
+      const float a = fminf(GS3_ALPHA_MAX, B.y * __expf(power));
+      const float Tn = T * (1.f - a);
+      const bool stop = pass && Tn < GS3_T_STOP;
+      const bool use = pass && !stop;
+      live = stop ? 0u : live;
+      if (COUNT) ncon += use ? 1u : 0u;
+      const float w8 = use ? a * T : 0.f;
+      C0 += B.z * w8;
+      C1 += B.w * w8;
+      C2 += Cc.x * w8;
+      T = use ? Tn : T;
+      lastp = use ? start + (uint32_t)j + 1u : lastp;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   if (inside) {
     const int64_t pix = (int64_t)py * cam.width + px;
