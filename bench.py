@@ -67,8 +67,8 @@ def parse():
 
 
 # stage -> (kernel name in the profile summaries, source file of the kernel)
-_KERNEL_OF = {"blend_bwd": ("k_blend_bwd", "blend.hip"), "blend_fwd": ("k_blend_fwd", "blend.hip"),
-              "blend_jvp": ("k_blend_jvp", "blend.hip"), "tr_step": ("k_tr_step<59>", "optim.hip"),
+_KERNEL_OF = {"blend_bwd": ("k_blend_bwd<false>", "blend.hip"), "blend_fwd": ("k_blend_fwd<false>", "blend.hip"),
+              "blend_jvp": ("k_blend_jvp<false>", "blend.hip"), "tr_step": ("k_tr_step<59>", "optim.hip"),
               "adam_step": ("k_adam_step<59>", "optim.hip")}
 
 
