@@ -174,6 +174,13 @@ __device__ __forceinline__ void publish_masks(uint64_t (*bits)[NW], uint32_t m, 
   }
 }
 
+// The tile's pair range, held in scalar registers (one value per workgroup),
+// so that the batch loops and the bit walks derived from it stay scalar.
+__device__ __forceinline__ uint2 uniform_range(const uint2* ranges, int t) {
+  const uint2 r = ranges[t];
+  return make_uint2(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y));
+}
+
 // A wave-uniform copy of a 64-bit LDS word (held in scalar registers).
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -207,24 +214,28 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
-  const uint2 range = ranges[t];
+  const uint2 range = uniform_range(ranges, t);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   // 1 while the pixel still blends; an integer rather than a bool, so the
   // loop carries it in a vector register instead of a scalar lane mask
   uint32_t live = inside ? 1u : 0u;
   uint32_t lastp = 0u;  // 1 + pair index of the last contributing splat (0: none)
+  // this lane's pair id of the batch about to be staged, loaded one batch
+  // ahead so that staging waits for one dependent load, not two
+  uint32_t g_next = range.x + lane < range.y ? pair_gid[range.x + lane] : 0u;
   for (uint32_t start = range.x; start < range.y; start += 64) {
     // every pixel of the block has stopped: the rest is never read
     if (__ballot(live) == 0ull) break;
     const uint32_t i = start + lane;
     bool keep = false;
     if (i < range.y) {
-      const Rec r = rec[pair_gid[i]];
+      const Rec r = rec[g_next];
       s.a[lane] = r.a;
       s.b[lane] = r.b;
       s.c[lane] = make_float2(r.c.x, r.c.y);
       keep = cull_keep(cull_setup(r.a, r.b, r.c.y, tx, ty), w);
     }
+    if (i + 64 < range.y) g_next = pair_gid[i + 64];
     uint64_t bits = __ballot(keep);
     wave_lds_sync();
     while (bits) {
@@ -294,7 +305,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
-  const uint2 range = ranges[t];
+  const uint2 range = uniform_range(ranges, t);
   float T = 1.f, dT = 0.f;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
   uint32_t live = inside ? 1u : 0u;  // as in the forward
@@ -460,7 +471,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
-  const uint2 range = ranges[t];
+  const uint2 range = uniform_range(ranges, t);
   float g0 = 0.f, g1 = 0.f, g2 = 0.f, T = 1.f;
   uint32_t last = 0u;  // 1 + pair index of the pixel's last contributing splat (0: none)
   if (inside) {
