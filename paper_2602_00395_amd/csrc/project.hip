@@ -15,11 +15,10 @@
 //    depths, radii and tile rectangles are reproducible bit for bit by any
 //    IEEE float32 evaluation of the same expressions;
 //  * Dual (value, tangent): the Jacobian-vector product along a Rademacher
-//    probe or a caller tangent;
-//  * Dual with one-hot tangents: the backward pass, one forward-mode sweep
-//    per geometric parameter (mean, log-scale, quaternion) -- exact and
-//    cheap next to the blend, and it keeps a single source for the
-//    projection's derivative.  Opacity and SH rows have closed forms.
+//    probe or a caller tangent.
+// The backward pass is the same chain written out in reverse (adjoint) mode,
+// one pass per Gaussian for the mean, log-scale, quaternion and opacity rows
+// (the view direction of the SH colour included); SH rows have closed forms.
 #include "gs3_trust.h"
 
 namespace {
@@ -356,21 +355,210 @@ __device__ __forceinline__ int radius_component(int row) {
   return 12 + (row - 11) % 3;
 }
 
-// SH coefficients per role of the projection backward
+// SH coefficients per role of the projection backward (role 0 takes the
+// eleven geometric and opacity rows)
 constexpr int kShPerRole = 4;
 template <int DEG>
 constexpr int bwd_roles() {
-  return 11 + ((DEG + 1) * (DEG + 1) + kShPerRole - 1) / kShPerRole;
+  return 1 + ((DEG + 1) * (DEG + 1) + kShPerRole - 1) / kShPerRole;
+}
+
+// Reverse-mode derivative of project_geo: from the summed screen-space
+// partials G[0..4] (d/du, d/dv, d/dconic a, b, c) to the mean (3),
+// log-scale (3) and quaternion (4) rows, out[0..9].  Every intermediate is
+// recomputed in float32 as in the forward; the adjoints are the transposed
+// local derivatives of each step (conic = inverse of the screen covariance,
+// V = T M, T = J W with the clamped Jacobian, M = R diag(s), R = Rn(q) /
+// |q|^2, p = W mu + t), so the result is the Jacobian a forward-mode sweep
+// per row would give, up to float32 rounding.
+__device__ __forceinline__ void geo_vjp(const float* __restrict__ x, int64_t n, int64_t g, const CamDev& cam,
+                                        const float G[5], float out[10]) {
+  auto xr = [&](int r) { return x[(int64_t)r * n + g]; };
+  const float mu[3] = {xr(0), xr(1), xr(2)};
+  const float sv[3] = {exp_ls(xr(3)), exp_ls(xr(4)), exp_ls(xr(5))};
+  const float qx = xr(6), qy = xr(7), qz = xr(8), qw = xr(9);
+  // ---- forward recomputation
+  const float r2 = ((qx * qx + qy * qy) + qz * qz) + qw * qw;
+  const float ir2 = 1.f / r2;
+  float Rn[3][3];
+  Rn[0][0] = ((qw * qw + qx * qx) - qy * qy) - qz * qz;
+  Rn[0][1] = 2.f * (qx * qy - qw * qz);
+  Rn[0][2] = 2.f * (qx * qz + qw * qy);
+  Rn[1][0] = 2.f * (qx * qy + qw * qz);
+  Rn[1][1] = ((qw * qw - qx * qx) + qy * qy) - qz * qz;
+  Rn[1][2] = 2.f * (qy * qz - qw * qx);
+  Rn[2][0] = 2.f * (qx * qz - qw * qy);
+  Rn[2][1] = 2.f * (qy * qz + qw * qx);
+  Rn[2][2] = ((qw * qw - qx * qx) - qy * qy) + qz * qz;
+  float R[3][3], M[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      R[i][j] = Rn[i][j] * ir2;
+      M[i][j] = R[i][j] * sv[j];
+    }
+  const float* W = cam.W;
+  float p[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) p[i] = ((W[3 * i] * mu[0] + W[3 * i + 1] * mu[1]) + W[3 * i + 2] * mu[2]) + cam.t[i];
+  const float ip2 = 1.f / p[2];
+  const float rx = p[0] * ip2, ry = p[1] * ip2;
+  const bool inx = rx >= -cam.limx && rx <= cam.limx, iny = ry >= -cam.limy && ry <= cam.limy;
+  const float txtz = fminf(fmaxf(rx, -cam.limx), cam.limx), tytz = fminf(fmaxf(ry, -cam.limy), cam.limy);
+  const float j00 = cam.fx * ip2, j02 = -(cam.fx * txtz) * ip2;
+  const float j11 = cam.fy * ip2, j12 = -(cam.fy * tytz) * ip2;
+  float Tm[2][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Tm[0][k] = j00 * W[k] + j02 * W[6 + k];
+    Tm[1][k] = j11 * W[3 + k] + j12 * W[6 + k];
+  }
+  float V[2][3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = (Tm[i][0] * M[0][j] + Tm[i][1] * M[1][j]) + Tm[i][2] * M[2][j];
+  const float a = ((V[0][0] * V[0][0] + V[0][1] * V[0][1]) + V[0][2] * V[0][2]) + GS3_DILATION;
+  const float b = (V[0][0] * V[1][0] + V[0][1] * V[1][1]) + V[0][2] * V[1][2];
+  const float c = ((V[1][0] * V[1][0] + V[1][1] * V[1][1]) + V[1][2] * V[1][2]) + GS3_DILATION;
+  const float idet = 1.f / (a * c - b * b);
+  // ---- adjoints: conic (c, -b, a) / det
+  const float ca = c * idet, cb = -b * idet, cc = a * idet;
+  const float gdet = -((G[2] * ca + G[3] * cb) + G[4] * cc) * idet;
+  const float ga = G[4] * idet + gdet * c;
+  const float gcv = G[2] * idet + gdet * a;
+  const float gb = -G[3] * idet - 2.f * gdet * b;
+  float gV[2][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    gV[0][k] = 2.f * ga * V[0][k] + gb * V[1][k];
+    gV[1][k] = gb * V[0][k] + 2.f * gcv * V[1][k];
+  }
+  // V = Tm M
+  float gT[2][3], gM[3][3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gT[i][k] = (gV[i][0] * M[k][0] + gV[i][1] * M[k][1]) + gV[i][2] * M[k][2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gM[k][j] = Tm[0][k] * gV[0][j] + Tm[1][k] * gV[1][j];
+  // Tm = J W
+  const float gj00 = (gT[0][0] * W[0] + gT[0][1] * W[1]) + gT[0][2] * W[2];
+  const float gj02 = (gT[0][0] * W[6] + gT[0][1] * W[7]) + gT[0][2] * W[8];
+  const float gj11 = (gT[1][0] * W[3] + gT[1][1] * W[4]) + gT[1][2] * W[5];
+  const float gj12 = (gT[1][0] * W[6] + gT[1][1] * W[7]) + gT[1][2] * W[8];
+  // J entries and the screen centre as functions of p
+  float gp0 = G[0] * cam.fx * ip2, gp1 = G[1] * cam.fy * ip2;
+  float gp2 = -((G[0] * cam.fx) * p[0] + (G[1] * cam.fy) * p[1]) * ip2 * ip2;
+  gp2 -= (((gj00 * j00 + gj02 * j02) + gj11 * j11) + gj12 * j12) * ip2;
+  const float gtx = -gj02 * cam.fx * ip2, gty = -gj12 * cam.fy * ip2;
+  if (inx) {
+    gp0 += gtx * ip2;
+    gp2 -= gtx * rx * ip2;
+  }
+  if (iny) {
+    gp1 += gty * ip2;
+    gp2 -= gty * ry * ip2;
+  }
+  float gmu[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gmu[k] = (W[k] * gp0 + W[3 + k] * gp1) + W[6 + k] * gp2;
+  // M = R diag(s), R = Rn / r2
+  float A[3][3], gr2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    float gs = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float gR = gM[k][j] * sv[j];
+      gs += gM[k][j] * R[k][j];
+      gr2 -= gR * R[k][j];
+      A[k][j] = gR * ir2;
+    }
+    out[3 + j] = gs * sv[j];  // d/d log-scale
+  }
+  gr2 *= ir2;
+  out[6] = 2.f * (((qx * ((A[0][0] - A[1][1]) - A[2][2]) + qy * (A[0][1] + A[1][0])) + qz * (A[0][2] + A[2][0])) +
+                  qw * (A[2][1] - A[1][2])) + 2.f * qx * gr2;
+  out[7] = 2.f * (((qy * ((A[1][1] - A[0][0]) - A[2][2]) + qx * (A[0][1] + A[1][0])) + qz * (A[1][2] + A[2][1])) +
+                  qw * (A[0][2] - A[2][0])) + 2.f * qy * gr2;
+  out[8] = 2.f * (((qz * ((A[2][2] - A[0][0]) - A[1][1]) + qx * (A[0][2] + A[2][0])) + qy * (A[1][2] + A[2][1])) +
+                  qw * (A[1][0] - A[0][1])) + 2.f * qz * gr2;
+  out[9] = 2.f * (((qw * ((A[0][0] + A[1][1]) + A[2][2]) + qz * (A[1][0] - A[0][1])) + qy * (A[0][2] - A[2][0])) +
+                  qx * (A[2][1] - A[1][2])) + 2.f * qw * gr2;
+  out[0] = gmu[0];
+  out[1] = gmu[1];
+  out[2] = gmu[2];
+}
+
+// Gradient of the basis polynomial Y_k (sh_basis) in its three arguments.
+__device__ __forceinline__ void sh_grad(int k, float x, float y, float z, float gr[3]) {
+  float a = 0.f, b = 0.f, c = 0.f;
+  switch (k) {
+    case 1: b = -SH_C1; break;
+    case 2: c = SH_C1; break;
+    case 3: a = -SH_C1; break;
+    case 4: a = kSH2[0] * y; b = kSH2[0] * x; break;
+    case 5: b = kSH2[1] * z; c = kSH2[1] * y; break;
+    case 6: a = -2.f * kSH2[2] * x; b = -2.f * kSH2[2] * y; c = 4.f * kSH2[2] * z; break;
+    case 7: a = kSH2[3] * z; c = kSH2[3] * x; break;
+    case 8: a = 2.f * kSH2[4] * x; b = -2.f * kSH2[4] * y; break;
+    case 9: a = 6.f * kSH3[0] * x * y; b = 3.f * kSH3[0] * (x * x - y * y); break;
+    case 10: a = kSH3[1] * y * z; b = kSH3[1] * x * z; c = kSH3[1] * x * y; break;
+    case 11:
+      a = -2.f * kSH3[2] * x * y;
+      b = kSH3[2] * ((4.f * z * z - x * x) - 3.f * y * y);
+      c = 8.f * kSH3[2] * y * z;
+      break;
+    case 12:
+      a = -6.f * kSH3[3] * x * z;
+      b = -6.f * kSH3[3] * y * z;
+      c = kSH3[3] * ((6.f * z * z - 3.f * x * x) - 3.f * y * y);
+      break;
+    case 13:
+      a = kSH3[4] * ((4.f * z * z - 3.f * x * x) - y * y);
+      b = -2.f * kSH3[4] * x * y;
+      c = 8.f * kSH3[4] * x * z;
+      break;
+    case 14: a = 2.f * kSH3[5] * x * z; b = -2.f * kSH3[5] * y * z; c = kSH3[5] * (x * x - y * y); break;
+    case 15: a = 3.f * kSH3[6] * (x * x - y * y); b = -6.f * kSH3[6] * x * y; break;
+    default: break;
+  }
+  gr[0] = a;
+  gr[1] = b;
+  gr[2] = c;
+}
+
+// Output of row r of Gaussian g (see launch_project_bwd for the modes).
+__device__ __forceinline__ void emit_row(const float* __restrict__ x, int64_t n, int64_t g, int r, float v, int mode,
+                                         int accumulate, uint64_t inner, float scale, float* __restrict__ out,
+                                         const FusedTr& ft) {
+  const int64_t k = (int64_t)r * n + g;
+  if (mode == 0) {
+    out[k] = accumulate ? out[k] + v : v;
+  } else if (mode == 1) {
+    out[k] += scale * probe_sign(inner, (uint64_t)k) * v;
+  } else {
+    // the update of Algorithm 1; x is only read, the update goes to x_out
+    const float gk = ft.gacc ? ft.gacc[k] + v : v;
+    const float eta = ft.rad[(int64_t)radius_component(r) * n + g];
+    ft.x_out[k] = x[k] + gs3trust::tr_update(ft.ghat, ft.dhat, ft.D, k, gk, eta, ft.a);
+  }
 }
 
 // Chain rule from the summed screen-space partials G (d/du, d/dv, d/dconic
 // a, b, c, d/dalpha, d/drgb) to the raw parameters.  blockIdx.y picks the
-// work of a thread: 0..9 one forward-mode sweep along geometric row y (mean,
-// log-scale, quaternion; the mean rows also move the SH view direction), 10
-// the opacity logit, 11.. four SH coefficients each, d rgb_c / d f_kc =
-// Y_k(dir) where the colour clamp is inactive.  One thread per (Gaussian,
-// role) keeps many more waves in flight than one thread per Gaussian walking
-// every row.
+// work of a thread: 0 the mean, log-scale, quaternion and opacity rows --
+// the reverse-mode pass (geo_vjp), the colour's dependence on the mean
+// through the view direction dir = (mu - campos) / |mu - campos| (sum_k
+// (sum_c g_c f_kc) grad Y_k(dir), projected on the plane normal to dir and
+// divided by |mu - campos|) and d alpha / d logit = s (1 - s); 1.. four SH
+// coefficients each, d rgb_c / d f_kc = Y_k(dir) where the colour clamp is
+// inactive.  One thread per (Gaussian, role) keeps more waves in flight
+// than one thread per Gaussian walking every row.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
@@ -382,66 +570,55 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int role = blockIdx.y;
   // this role's rows: [r0, r1)
-  const int r0 = role <= 10 ? role : 11 + 3 * kShPerRole * (role - 11);
-  const int r1 = role <= 10 ? role + 1 : min(11 + 3 * K, r0 + 3 * kShPerRole);
-  auto emit = [&](int r, float v) {
-    const int64_t k = (int64_t)r * n + g;
-    if (mode == 0) {
-      out[k] = accumulate ? out[k] + v : v;
-    } else if (mode == 1) {
-      out[k] += scale * probe_sign(inner, (uint64_t)k) * v;
-    } else {
-      // the update of Algorithm 1; x is only read, the update goes to x_out
-      const float gk = ft.gacc ? ft.gacc[k] + v : v;
-      const float eta = ft.rad[(int64_t)radius_component(r) * n + g];
-      ft.x_out[k] = x[k] + gs3trust::tr_update(ft.ghat, ft.dhat, ft.D, k, gk, eta, ft.a);
-    }
-  };
+  const int r0 = role == 0 ? 0 : 11 + 3 * kShPerRole * (role - 1);
+  const int r1 = role == 0 ? 11 : min(11 + 3 * K, r0 + 3 * kShPerRole);
   if (tiles[g] == 0u) {  // no gradient from this view
     if (mode == 2 || (mode == 0 && !accumulate))
-      for (int r = r0; r < r1; ++r) emit(r, 0.f);
+      for (int r = r0; r < r1; ++r) emit_row(x, n, g, r, 0.f, mode, accumulate, inner, scale, out, ft);
     return;
   }
   auto Gk = [&](int k) { return G[(int64_t)k * n + g]; };
-  if (role < 10) {
-    const float sv[3] = {exp_ls(x[3 * n + g]), exp_ls(x[4 * n + g]), exp_ls(x[5 * n + g])};
-    auto src = [&](int r) { return Dual{x[(int64_t)r * n + g], r == role ? 1.f : 0.f}; };
-    Proj<Dual> p;
-    project_geo<Dual>(src, sv, cam, p);
-    float d = Gk(0) * p.u.t + Gk(1) * p.v.t + Gk(2) * p.ca.t + Gk(3) * p.cb.t + Gk(4) * p.cc.t;
-    if (role < 3) {
-      Dual rgb[3];
-      bool pos[3];
-      colour<Dual, DEG>(src, cam, rgb, pos);
-      d += Gk(6) * rgb[0].t + Gk(7) * rgb[1].t + Gk(8) * rgb[2].t;
+  const uint32_t posm = __float_as_uint(rec[g].c.w);
+  const float gc[3] = {(posm & 1u) ? Gk(6) : 0.f, (posm & 2u) ? Gk(7) : 0.f, (posm & 4u) ? Gk(8) : 0.f};
+  const float dx = x[g] - cam.campos[0], dy = x[n + g] - cam.campos[1], dz = x[2 * n + g] - cam.campos[2];
+  const float inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
+  const float e[3] = {dx * inv, dy * inv, dz * inv};
+  if (role == 0) {
+    const float Gs[5] = {Gk(0), Gk(1), Gk(2), Gk(3), Gk(4)};
+    float d[10];
+    geo_vjp(x, n, g, cam, Gs, d);
+    if (DEG > 0) {
+      float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 1; k < K; ++k) {
+        const float gy = (gc[0] * x[(int64_t)(11 + 3 * k) * n + g] + gc[1] * x[(int64_t)(12 + 3 * k) * n + g]) +
+                         gc[2] * x[(int64_t)(13 + 3 * k) * n + g];
+        float gr[3];
+        sh_grad(k, e[0], e[1], e[2], gr);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) gdir[ax] += gy * gr[ax];
+      }
+      const float ed = (e[0] * gdir[0] + e[1] * gdir[1]) + e[2] * gdir[2];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) d[ax] += (gdir[ax] - e[ax] * ed) * inv;
     }
-    emit(role, d);
-    return;
-  }
-  if (role == 10) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) emit_row(x, n, g, r, d[r], mode, accumulate, inner, scale, out, ft);
     const float s = sigmoid_(x[10 * n + g]);
-    emit(10, Gk(5) * s * (1.f - s));
+    emit_row(x, n, g, 10, Gk(5) * s * (1.f - s), mode, accumulate, inner, scale, out, ft);
     return;
   }
   // the SH basis at the view direction (same expressions as the forward's
   // colour) and the forward's clamp mask: no SH coefficient is read
   float Y[K];
-  {
-    const float dx = x[g] - cam.campos[0], dy = x[n + g] - cam.campos[1], dz = x[2 * n + g] - cam.campos[2];
-    const float inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
-    sh_basis<float, DEG>(dx * inv, dy * inv, dz * inv, Y);
-  }
-  const uint32_t posm = __float_as_uint(rec[g].c.w);
-  const bool pos[3] = {(posm & 1u) != 0u, (posm & 2u) != 0u, (posm & 4u) != 0u};
-  const float G6 = Gk(6), G7 = Gk(7), G8 = Gk(8);
-  const int k0 = kShPerRole * (role - 11);
+  sh_basis<float, DEG>(e[0], e[1], e[2], Y);
+  const int k0 = kShPerRole * (role - 1);
 #pragma unroll
   for (int kk = 0; kk < kShPerRole; ++kk) {
     const int k = k0 + kk;
     if (k >= K) break;
-    emit(11 + 3 * k, pos[0] ? Y[k] * G6 : 0.f);
-    emit(12 + 3 * k, pos[1] ? Y[k] * G7 : 0.f);
-    emit(13 + 3 * k, pos[2] ? Y[k] * G8 : 0.f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) emit_row(x, n, g, 11 + 3 * k + c, gc[c] * Y[k], mode, accumulate, inner, scale, out, ft);
   }
 }
 
