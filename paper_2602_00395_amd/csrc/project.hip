@@ -292,42 +292,94 @@ __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x
 
 // Sum of each Gaussian's per-(Gaussian, tile) partials, which sit in the
 // contiguous slots [offsets[i], offsets[i] + counts[i]) of the Gaussian of
-// depth rank i (order[i]): G[k][order[i]], k < 9, summed in slot order.  A
-// workgroup takes 28 consecutive depth ranks, whose slots form one contiguous
-// run; the run is streamed through LDS in chunks with coalesced loads, and
-// thread (j, k) adds component k of rank j's slots in order.  Invisible
-// Gaussians (count 0) get zeros.
-constexpr int kSumRanks = 28;      // 28 x 9 = 252 of the 256 threads
-constexpr int kSumChunk = 4096;    // floats per LDS chunk
+// depth rank i (order[i]): G[k][order[i]], k < 9.  A workgroup takes 28
+// consecutive depth ranks.  Thread (j, k) sums component k of rank j when
+// the rank has at most kSumLong slots, with four interleaved partial sums
+// (slot t goes to sum t mod 4 in slot order, combined as (s0 + s1) +
+// (s2 + s3)); a rank
+// with more slots (a splat covering many tiles, which would hold its wave
+// for hundreds of serial steps) is summed by the whole workgroup: thread t
+// takes slots t, t + 256, ... and the 256 partial sums are combined in a
+// fixed tree.  Every order is fixed, so the result is deterministic.
+// Invisible Gaussians (count 0) get zeros.
+constexpr int kSumRanks = 28;  // 28 x 9 = 252 of the 256 threads
+constexpr uint32_t kSumLong = 48;
+
+__device__ __forceinline__ float wave_sum_xor(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
 
 __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __restrict__ order,
                                                             const uint32_t* __restrict__ offsets,
                                                             const uint32_t* __restrict__ counts,
                                                             const float* __restrict__ partials, int64_t n,
                                                             float* __restrict__ G) {
-  __shared__ float buf[kSumChunk];
+  __shared__ float wsum[4][9];
+  __shared__ uint32_t long_ranks;  // bit j: rank i0 + j is summed by the workgroup
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kSumRanks;
-  const int64_t i1 = i0 + kSumRanks < n ? i0 + kSumRanks : n;
+  const int nr = (int)(i0 + kSumRanks < n ? kSumRanks : n - i0);
   const int j = tid / 9, k = tid % 9;
-  const int64_t i = i0 + j;
-  const bool mine = tid < 9 * kSumRanks && i < i1;
-  const int64_t lo = (int64_t)offsets[i0] * 9;
-  const int64_t hi = ((int64_t)offsets[i1 - 1] + counts[i1 - 1]) * 9;
-  int64_t first = 0, last = 0;  // my float indices: first, first + 9, ..., < last
-  if (mine) {
-    first = (int64_t)offsets[i] * 9 + k;
-    last = ((int64_t)offsets[i] + counts[i]) * 9;
+  if (tid == 0) long_ranks = 0u;
+  __syncthreads();
+  if (tid < 9 * kSumRanks && j < nr) {
+    const int64_t i = i0 + j;
+    const uint32_t c = counts[i];
+    if (c <= kSumLong) {
+      const float* p = partials + (int64_t)offsets[i] * 9 + k;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+      uint32_t t = 0;
+      for (; t + 8 <= c; t += 8) {
+        const float v0 = p[9 * t], v1 = p[9 * (t + 1)], v2 = p[9 * (t + 2)], v3 = p[9 * (t + 3)];
+        const float v4 = p[9 * (t + 4)], v5 = p[9 * (t + 5)], v6 = p[9 * (t + 6)], v7 = p[9 * (t + 7)];
+        s0 += v0;
+        s1 += v1;
+        s2 += v2;
+        s3 += v3;
+        s0 += v4;
+        s1 += v5;
+        s2 += v6;
+        s3 += v7;
+      }
+      for (; t + 4 <= c; t += 4) {
+        s0 += p[9 * t];
+        s1 += p[9 * (t + 1)];
+        s2 += p[9 * (t + 2)];
+        s3 += p[9 * (t + 3)];
+      }
+      if (t < c) s0 += p[9 * t];
+      if (t + 1 < c) s1 += p[9 * (t + 1)];
+      if (t + 2 < c) s2 += p[9 * (t + 2)];
+      G[(int64_t)k * n + order[i]] = (s0 + s1) + (s2 + s3);
+    } else if (k == 0) {
+      atomicOr(&long_ranks, 1u << j);
+    }
   }
-  float acc = 0.f;
-  for (int64_t base = lo; base < hi; base += kSumChunk) {
-    const int64_t end = base + kSumChunk < hi ? base + kSumChunk : hi;
-    for (int64_t f = base + tid; f < end; f += 256) buf[f - base] = partials[f];
+  __syncthreads();
+  // long ranks, one at a time, by the whole workgroup
+  for (uint32_t m = long_ranks; m != 0u; m &= m - 1u) {
+    const int64_t i = i0 + __builtin_ctz(m);
+    const uint32_t c = counts[i];
+    const float* p = partials + (int64_t)offsets[i] * 9;
+    float acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    for (uint32_t t = tid; t < c; t += 256) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[q] += p[(int64_t)t * 9 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = wave_sum_xor(acc[q]);
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) wsum[tid >> 6][q] = acc[q];
+    }
     __syncthreads();
-    for (; first < last && first < end; first += 9) acc += buf[first - base];
+    if (tid < 9) G[(int64_t)tid * n + order[i]] = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
     __syncthreads();
   }
-  if (mine) G[(int64_t)k * n + order[i]] = acc;
 }
 
 // Trust-region radius of every Gaussian from the parameters before the
