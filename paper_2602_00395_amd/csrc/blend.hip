@@ -35,8 +35,9 @@
 // from zero, so no term comes from cancelling two large sums (a deep splat's
 // gradient keeps its relative precision).  Which splats contribute is taken
 // from the same float32 skip test and the stored last index, so the set is
-// exactly the forward's.  Per pixel it reduces dL/dpower times dx, dy, dx^2,
-// dx dy and dy^2; the conic coefficients are constant over the splat, so the
+// exactly the forward's.  Per pixel it reduces dL/dopacity times dx, dy,
+// dx^2, dx dy and dy^2 (dL/dpower is the opacity times dL/dopacity); the
+// opacity and the conic coefficients are constant over the splat, so the
 // derivatives along u, v and the conic are formed once per splat.  Gradients
 // of each (splat, tile) pair are reduced over the workgroup (a transposed
 // wave64 reduction with permlane swaps and DPP row scans, then the four waves
@@ -530,13 +531,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
         const uint64_t word = uniform64(s.bits[w][q]);
         uint64_t bits = word & keep;
         uint64_t reduced = bits;  // less the splats no lane of the wave uses
-        while (bits) {
-          const int hi = 63 - __builtin_clzll(bits);
+        // one walked splat: j its index in the batch, hi its bit in the word
+        auto walk = [&](const float4 A, const float4 B, const float2 Cc, const int hi) {
           const int j = (q << 6) + hi;
-          bits &= ~(1ull << hi);
           const uint32_t pi = (uint32_t)bstart + (uint32_t)j;
-          const float4 A = s.a[j], B = s.b[j];
-          const float2 Cc = s.c[j];
           const float dx = A.x - pxf, dy = A.y - pyf;
           const float power = splat_power(A.z, A.w, B.x, dx, dy);
           // predicated like the forward: lanes that do not contribute end
@@ -555,15 +553,17 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           const float wgt = use ? a * Tb : 0.f;
           const float dL_da = Tb * cdot - acc * r1;
           const bool open = use && araw <= GS3_ALPHA_MAX;  // the 0.99 clamp passes no gradient
-          const float dL_dpow = open ? B.y * dL_da * G : 0.f;
-          const float pt = dL_dpow * dx, pu = dL_dpow * dy;
+          // dL/dopacity; dL/dpower is opacity times it, and that factor is
+          // applied once per splat after the reduction
+          const float h = open ? G * dL_da : 0.f;
+          const float pt = h * dx, pu = h * dy;
           float gr[9];
           gr[0] = pt;
           gr[1] = pu;
           gr[2] = pt * dx;
           gr[3] = pt * dy;
           gr[4] = pu * dy;
-          gr[5] = open ? G * dL_da : 0.f;
+          gr[5] = h;
           gr[6] = wgt * g0;
           gr[7] = wgt * g1;
           gr[8] = wgt * g2;
@@ -587,6 +587,29 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           } else {
             reduced &= ~(1ull << hi);
           }
+        };
+        // each splat's record is read from LDS one step ahead, into the other
+        // of two register sets
+        if (bits) {
+          int h0 = 63 - __builtin_clzll(bits), h1 = 0;
+          float4 A0 = s.a[(q << 6) + h0], B0 = s.b[(q << 6) + h0], A1, B1;
+          float2 C0 = s.c[(q << 6) + h0], C1;
+          while (true) {
+            bits &= ~(1ull << h0);
+            h1 = bits ? 63 - __builtin_clzll(bits) : h0;
+            A1 = s.a[(q << 6) + h1];
+            B1 = s.b[(q << 6) + h1];
+            C1 = s.c[(q << 6) + h1];
+            walk(A0, B0, C0, h0);
+            if (!bits) break;
+            bits &= ~(1ull << h1);
+            h0 = bits ? 63 - __builtin_clzll(bits) : h1;
+            A0 = s.a[(q << 6) + h0];
+            B0 = s.b[(q << 6) + h0];
+            C0 = s.c[(q << 6) + h0];
+            walk(A1, B1, C1, h1);
+            if (!bits) break;
+          }
         }
         // the epilogue counts the splats this wave did not reduce as zero
         if (reduced != word && lane == 0) s.bits[w][q] = reduced;
@@ -604,13 +627,14 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           R[k] = (((h0 ? s.red[0][k][tid] : 0.f) + (h1 ? s.red[1][k][tid] : 0.f)) + (h2 ? s.red[2][k][tid] : 0.f)) +
                  (h3 ? s.red[3][k][tid] : 0.f);
         // power = qa dx^2 + qc dy^2 + qb dx dy, (qa, qb, qc) = (-a/2, -b, -c/2),
-        // dx = u - px, dy = v - py
-        const float qa = s.a[tid].z, qb = s.a[tid].w, qc = s.b[tid].x;
-        dst[0] = 2.f * qa * R[0] + qb * R[1];
-        dst[1] = 2.f * qc * R[1] + qb * R[0];
-        dst[2] = -0.5f * R[2];
-        dst[3] = -R[3];
-        dst[4] = -0.5f * R[4];
+        // dx = u - px, dy = v - py; R[0..4] still lack the opacity factor
+        const float qa = s.a[tid].z, qb = s.a[tid].w, qc = s.b[tid].x, op = s.b[tid].y;
+        const float R0 = op * R[0], R1 = op * R[1];
+        dst[0] = 2.f * qa * R0 + qb * R1;
+        dst[1] = 2.f * qc * R1 + qb * R0;
+        dst[2] = (-0.5f * op) * R[2];
+        dst[3] = -op * R[3];
+        dst[4] = (-0.5f * op) * R[4];
 #pragma unroll
         for (int k = 5; k < 9; ++k) dst[k] = R[k];
       }
