@@ -239,13 +239,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
     if (i + 64 < range.y) g_next = pair_gid[i + 64];
     uint64_t bits = __ballot(keep);
     wave_lds_sync();
-    while (bits) {
-      if (__ballot(live) == 0ull) break;
-      const int j = __builtin_ctzll(bits);
-      bits &= bits - 1;
+    // one walked splat, j its index in the batch
+    auto walk = [&](const float4 A, const float4 B, const float2 Cc, const int j) {
       if (COUNT) nev += live;
-      const float4 A = s.a[j], B = s.b[j];
-      const float2 Cc = s.c[j];
       const float dx = A.x - pxf, dy = A.y - pyf;
       const float power = splat_power(A.z, A.w, B.x, dx, dy);
       // predicated rather than branched: nearly every wave has a lane
@@ -263,6 +259,29 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
       C2 += Cc.x * w8;
       T = use ? Tn : T;
       lastp = use ? start + (uint32_t)j + 1u : lastp;
+    };
+    // each splat's record is read from LDS one step ahead, into the other of
+    // two register sets; the walk ends early once every pixel has stopped
+    if (bits) {
+      int j0 = __builtin_ctzll(bits), j1 = 0;
+      float4 A0 = s.a[j0], B0 = s.b[j0], A1, B1;
+      float2 C0r = s.c[j0], C1r;
+      while (true) {
+        bits &= bits - 1;
+        j1 = bits ? __builtin_ctzll(bits) : j0;
+        A1 = s.a[j1];
+        B1 = s.b[j1];
+        C1r = s.c[j1];
+        walk(A0, B0, C0r, j0);
+        if (!bits || __ballot(live) == 0ull) break;
+        bits &= bits - 1;
+        j0 = bits ? __builtin_ctzll(bits) : j1;
+        A0 = s.a[j0];
+        B0 = s.b[j0];
+        C0r = s.c[j0];
+        walk(A1, B1, C1r, j1);
+        if (!bits || __ballot(live) == 0ull) break;
+      }
     }
     wave_lds_sync();
   }
