@@ -128,6 +128,10 @@ struct gs3_scene {
   // per-pair scratch
   int64_t pair_cap = 0;
   uint32_t *pt = nullptr, *pg = nullptr, *pt2 = nullptr, *pg2 = nullptr;
+  // depth rank owning pair 256 b, written by the offsets scan for the
+  // emission; sized from the pair capacity of earlier views
+  uint32_t* block_owner = nullptr;
+  int64_t owner_blocks = 0;
   float* partials = nullptr;
   float* gsum = nullptr;  // float[9][N]: each Gaussian's summed partials
   // per-view image scratch
@@ -224,6 +228,7 @@ void free_all(gs3_scene* s) {
   dfree(s->pt2);
   dfree(s->pg2);
   dfree(s->partials);
+  dfree(s->block_owner);
   dfree(s->gsum);
   dfree(s->ranges);
   dfree(s->tile_order);
@@ -318,6 +323,12 @@ int bits_for(int n_tiles) {
 gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   const CamDev cd = make_cam(s->cams[cam]);
   const int64_t N = s->N;
+  if (s->pair_cap > 0 && s->owner_blocks < s->pair_cap / 256 + 1) {
+    dfree(s->block_owner);
+    s->owner_blocks = 0;
+    GS3_TRY(dalloc(&s->block_owner, (size_t)(s->pair_cap / 256 + 1)));
+    s->owner_blocks = s->pair_cap / 256 + 1;
+  }
   auto p0 = prof::begin("project_fwd", st);
   launch_project_fwd(s->x, N, s->deg, cd, s->rec, s->rect, s->depth_key, s->tiles, st);
   prof::end(p0, st);
@@ -328,7 +339,7 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   prof::end(p1, st);
   auto p2 = prof::begin("scan", st);
   launch_gather_counts(order, s->tiles, N, s->counts, st);
-  scan_exclusive_u32(s->counts, s->offsets, N, s->total_dev, s->stmp, st);
+  scan_exclusive_u32(s->counts, s->offsets, N, s->total_dev, s->stmp, st, s->block_owner, s->owner_blocks);
   prof::end(p2, st);
   GS3_LAUNCHED();
   GS3_HIP(hipMemcpyAsync(s->host_u32, s->total_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -336,7 +347,8 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   const int64_t n_pairs = s->host_u32[0];
   GS3_TRY(ensure_pairs(s, n_pairs));
   auto p3 = prof::begin("emit_pairs", st);
-  launch_emit_pairs(order, s->offsets, s->rec, s->rect, N, n_pairs, cd.tiles_x, s->pt, s->pg, st);
+  launch_emit_pairs(order, s->offsets, s->block_owner, s->owner_blocks, s->rec, s->rect, N, n_pairs, cd.tiles_x,
+                    s->pt, s->pg, st);
   prof::end(p3, st, N, n_pairs);
   const int n_tiles = cd.tiles_x * cd.tiles_y;
   uint32_t *tk, *tv;
@@ -441,9 +453,10 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
   *resident = 4 * P * N * 6 + 12 * px_total;
   // records, tangent records, eight u32 arrays, the summed partials, the
   // trust radius, per-pixel blend state, and pair buffers for about
-  // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair, +25% slack)
+  // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair and an owner
+  // per 256 pairs, +25% slack)
   const int64_t pairs = 20 * N;
-  *peak_scratch = 96 * N + 32 * N + 36 * N + 60 * N + pairs * (16 + 36) + 4 * max_px * 3 * 3 + 36 * max_px +
+  *peak_scratch = 96 * N + 32 * N + 36 * N + 60 * N + pairs * (16 + 36) + pairs / 64 + 4 * max_px * 3 * 3 + 36 * max_px +
                   8 * max_px;
   return GS3_OK;
 }

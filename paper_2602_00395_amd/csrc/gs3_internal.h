@@ -105,13 +105,18 @@ void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* 
                     uint32_t* vb, int64_t n, int bits, void* temp, hipStream_t st, uint32_t** keys_out,
                     uint32_t** vals_out);
 size_t scan_temp_bytes(int64_t n);
-void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st);
+// owner (nullable): owner[b] = the item whose output range holds element
+// 256 b of the expanded sequence, for b < owner_blocks
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st,
+                        uint32_t* owner = nullptr, int64_t owner_blocks = 0);
 void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
                           hipStream_t st);
-// writes each visible Gaussian's pair offset into its record (rec.c.w)
-void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Rec* rec, const uint2* rect,
-                       int64_t n, int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
-                       hipStream_t st);
+// writes each visible Gaussian's pair offset into its record (rec.c.z);
+// owner (nullable, from scan_exclusive_u32) names the first pair's item of
+// each 256-pair block b < owner_blocks, the others search the offsets
+void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, const uint32_t* owner,
+                       int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, int64_t n_pairs, int tiles_x,
+                       uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st);
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st);
 // Tile ids in (approximately) descending order of their pair count.
 bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, hipStream_t st);

@@ -88,8 +88,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bl
   if (threadIdx.x == 0) *total = running;
 }
 
+// owner (nullable): for every b < owner_blocks with 256 b inside an item's
+// output range [out[i], out[i] + in[i]), owner[b] = i -- the item that owns
+// element 256 b of the expanded sequence
 __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                         int64_t n, const uint32_t* __restrict__ block_sums) {
+                                                         int64_t n, const uint32_t* __restrict__ block_sums,
+                                                         uint32_t* __restrict__ owner, int64_t owner_blocks) {
   const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
   uint32_t v[kItems];
   uint32_t s = 0;
@@ -102,7 +106,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restri
   uint32_t run = block_excl_scan(s, &tot) + block_sums[blockIdx.x];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    if (base + i < n) out[base + i] = run;
+    if (base + i < n) {
+      out[base + i] = run;
+      if (owner)
+        for (int64_t b = ((int64_t)run + 255) >> 8; b < owner_blocks && (b << 8) < (int64_t)run + v[i]; ++b)
+          owner[b] = (uint32_t)(base + i);
+    }
     run += v[i];
   }
 }
@@ -234,15 +243,24 @@ __device__ __forceinline__ int64_t last_le(const uint32_t* __restrict__ offsets,
 }
 
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ order,
-                                                     const uint32_t* __restrict__ offsets, Rec* __restrict__ rec,
-                                                     const uint2* __restrict__ rect, int64_t n, int64_t n_pairs,
-                                                     int tiles_x, uint32_t* __restrict__ pair_tile,
+                                                     const uint32_t* __restrict__ offsets,
+                                                     const uint32_t* __restrict__ owner, int64_t owner_blocks,
+                                                     Rec* __restrict__ rec, const uint2* __restrict__ rect, int64_t n,
+                                                     int64_t n_pairs, int tiles_x, uint32_t* __restrict__ pair_tile,
                                                      uint32_t* __restrict__ pair_gid) {
   __shared__ uint32_t soff[256];
   __shared__ int64_t bounds[2];
   const int tid = threadIdx.x;
   const int64_t p0 = (int64_t)blockIdx.x * 256;
-  if (tid < 2) {
+  if ((int64_t)blockIdx.x < owner_blocks) {
+    // the owner of the first pair, from the scan; every item has at least
+    // one pair up to the last visible one, so the block's 256 pairs belong
+    // to at most 256 consecutive items from there
+    if (tid == 0) {
+      bounds[0] = owner[blockIdx.x];
+      bounds[1] = min(bounds[0] + 255, n - 1);
+    }
+  } else if (tid < 2) {
     const int64_t p = tid == 0 ? p0 : (p0 + 255 < n_pairs ? p0 + 255 : n_pairs - 1);
     bounds[tid] = last_le(offsets, n, (uint32_t)p);
   }
@@ -343,7 +361,8 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 size_t scan_temp_bytes(int64_t n) { return (size_t)(nblk(n, kTileItems) + 1) * sizeof(uint32_t); }
 
-void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st) {
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st,
+                        uint32_t* owner, int64_t owner_blocks) {
   const int nb = (int)nblk(n, kTileItems);
   uint32_t* sums = (uint32_t*)temp;
   if (n <= 0) {
@@ -352,7 +371,7 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, st, in, n, sums);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, sums, nb, total);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, st, in, out, n, sums);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, st, in, out, n, sums, owner, owner_blocks);
 }
 
 size_t radix_temp_bytes(int64_t n) {
@@ -389,12 +408,12 @@ void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t 
   if (n > 0) hipLaunchKernelGGL(k_gather_counts, dim3(nblk(n, 256)), dim3(256), 0, st, order, tiles, n, counts_sorted);
 }
 
-void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, Rec* rec, const uint2* rect,
-                       int64_t n, int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid,
-                       hipStream_t st) {
+void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, const uint32_t* owner,
+                       int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, int64_t n_pairs, int tiles_x,
+                       uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st) {
   if (n > 0 && n_pairs > 0)
-    hipLaunchKernelGGL(k_emit_pairs, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, order, offsets_sorted, rec, rect, n,
-                       n_pairs, tiles_x, pair_tile, pair_gid);
+    hipLaunchKernelGGL(k_emit_pairs, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, order, offsets_sorted, owner,
+                       owner ? owner_blocks : (int64_t)0, rec, rect, n, n_pairs, tiles_x, pair_tile, pair_gid);
 }
 
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st) {
