@@ -221,6 +221,10 @@ __device__ __forceinline__ float probe_sign(uint64_t inner, uint64_t k) {
 __device__ __forceinline__ float opacity_of(float logit) { return (float)(1.0 / (1.0 + exp(-(double)logit))); }
 __device__ __forceinline__ float skip_threshold(float op) { return (float)(-log(255.0 * (double)op)); }
 
+// blockIdx.y = 0: geometry -- screen centre, conic, opacity, skip
+// threshold, tile rectangle, depth key, tile count; 1: the view-dependent
+// colour and its clamp bits.  The two roles write disjoint words of the
+// record, so the 48 SH rows are read by threads of their own.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       Rec* __restrict__ rec, uint2* __restrict__ rect,
@@ -229,6 +233,19 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   auto src = [&](int r) { return x[(int64_t)r * n + g]; };
+  float* rw = reinterpret_cast<float*>(rec + g);  // words of the record
+  if (blockIdx.y == 1) {
+    float rgb[3];
+    bool pos[3];
+    colour<float, DEG>(src, cam, rgb, pos);
+    // spare word: which colour channels are unclamped (bit c), for the backward
+    const uint32_t posm = (pos[0] ? 1u : 0u) | (pos[1] ? 2u : 0u) | (pos[2] ? 4u : 0u);
+    rw[6] = rgb[0];
+    rw[7] = rgb[1];
+    rw[8] = rgb[2];
+    rw[11] = __uint_as_float(posm);
+    return;
+  }
   const float sv[3] = {exp_ls(src(3)), exp_ls(src(4)), exp_ls(src(5))};
   Proj<float> p;
   project_geo<float>(src, sv, cam, p);
@@ -247,17 +264,12 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
     tiles[g] = 0u;
     return;
   }
-  float rgb[3];
-  bool pos[3];
-  colour<float, DEG>(src, cam, rgb, pos);
   const float op = opacity_of(src(10));
-  Rec r;
-  r.a = make_float4(p.u, p.v, -0.5f * p.ca, -p.cb);
-  r.b = make_float4(-0.5f * p.cc, op, rgb[0], rgb[1]);
-  // spare word: which colour channels are unclamped (bit c), for the backward
-  const uint32_t posm = (pos[0] ? 1u : 0u) | (pos[1] ? 2u : 0u) | (pos[2] ? 4u : 0u);
-  r.c = make_float4(rgb[2], skip_threshold(op), 0.f, __uint_as_float(posm));
-  rec[g] = r;
+  *reinterpret_cast<float4*>(rw) = make_float4(p.u, p.v, -0.5f * p.ca, -p.cb);
+  rw[4] = -0.5f * p.cc;
+  rw[5] = op;
+  rw[9] = skip_threshold(op);
+  rw[10] = 0.f;
   rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
   depth_key[g] = __float_as_uint(p.depth);
   tiles[g] = (uint32_t)touched;
@@ -695,8 +707,8 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, Rec* rec, uint2* rect,
                         uint32_t* depth_key, uint32_t* tiles, hipStream_t st) {
-  GS3_DEG_DISPATCH(deg, k_project_fwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, rec, rect, depth_key,
-                   tiles);
+  GS3_DEG_DISPATCH(deg, k_project_fwd, dim3(blocks_for(n, 256), 2), dim3(256), 0, st, x, n, cam, rec, rect,
+                   depth_key, tiles);
 }
 
 void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
