@@ -133,7 +133,7 @@ struct gs3_scene {
   uint32_t* block_owner = nullptr;
   int64_t owner_blocks = 0;
   float* partials = nullptr;
-  float* gsum = nullptr;  // float[9][N]: each Gaussian's summed partials
+  float* gsum = nullptr;  // float[N][9]: each Gaussian's summed partials
   // per-view image scratch
   uint2* ranges = nullptr;
   uint32_t* tile_order = nullptr;

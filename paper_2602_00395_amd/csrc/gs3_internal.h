@@ -87,7 +87,8 @@ struct FusedTr {
   TrArgs a{};
 };
 // order / offsets / counts: the view's depth order, first pair and tile count
-// per depth rank; gsum: float[9][n] scratch for the summed partials.
+// per depth rank; gsum: float[n][9] scratch for the summed partials (a
+// Gaussian's nine values contiguous).
 // mode 0: out = (accumulate ? out : 0) + dL/dx; mode 1: out += scale z dL/dx
 // for probe i of `seed`; mode 2: the fused update described by ft
 void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* order,

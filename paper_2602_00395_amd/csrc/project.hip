@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x
 
 // Sum of each Gaussian's per-(Gaussian, tile) partials, which sit in the
 // contiguous slots [offsets[i], offsets[i] + counts[i]) of the Gaussian of
-// depth rank i (order[i]): G[k][order[i]], k < 9.  A workgroup takes 28
+// depth rank i (order[i]): G[order[i]][k], k < 9.  A workgroup takes 28
 // consecutive depth ranks.  Thread (j, k) sums component k of rank j when
 // the rank has at most kSumLong slots, with four interleaved partial sums
 // (slot t goes to sum t mod 4 in slot order, combined as (s0 + s1) +
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
       if (t < c) s0 += p[9 * t];
       if (t + 1 < c) s1 += p[9 * (t + 1)];
       if (t + 2 < c) s2 += p[9 * (t + 2)];
-      G[(int64_t)k * n + order[i]] = (s0 + s1) + (s2 + s3);
+      G[(int64_t)order[i] * 9 + k] = (s0 + s1) + (s2 + s3);
     } else if (k == 0) {
       atomicOr(&long_ranks, 1u << j);
     }
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
       for (int q = 0; q < 9; ++q) wsum[tid >> 6][q] = acc[q];
     }
     __syncthreads();
-    if (tid < 9) G[(int64_t)tid * n + order[i]] = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
+    if (tid < 9) G[(int64_t)order[i] * 9 + tid] = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
     __syncthreads();
   }
 }
@@ -641,7 +641,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
       for (int r = r0; r < r1; ++r) emit_row(x, n, g, r, 0.f, mode, accumulate, inner, scale, out, ft);
     return;
   }
-  auto Gk = [&](int k) { return G[(int64_t)k * n + g]; };
+  auto Gk = [&](int k) { return G[(int64_t)g * 9 + k]; };
   const uint32_t posm = __float_as_uint(rec[g].c.w);
   const float gc[3] = {(posm & 1u) ? Gk(6) : 0.f, (posm & 2u) ? Gk(7) : 0.f, (posm & 4u) ? Gk(8) : 0.f};
   const float dx = x[g] - cam.campos[0], dy = x[n + g] - cam.campos[1], dz = x[2 * n + g] - cam.campos[2];
