@@ -29,6 +29,15 @@ struct Win {
 
 __device__ __forceinline__ float sgn(float r) { return r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f); }
 
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// (a prefetch) stay in flight across it.  For kernels whose threads share
+// data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ double block_sum_d(double v) {
   __shared__ double ws[4];
 #pragma unroll
@@ -165,16 +174,35 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_combine(const float* __restr
       if (GN) uv[c] = u[o3 + c];
     }
   }
-  for (int c = 0; c < 3; ++c) {
-    for (int e = tid; e < HW * HW; e += GS3_BLOCK) {
+  // the next channel's halo of the three maps is loaded into registers
+  // while this channel is filtered; the barriers inside order LDS only, so
+  // those loads stay in flight across them
+  constexpr int kPer = (HW * HW + GS3_BLOCK - 1) / GS3_BLOCK;
+  float pre[kPer][3];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = tid + t * GS3_BLOCK;
       const int r = e / HW, q = e % HW;
       const int gx = ox + q, gy = oy + r;
-      const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
+      const bool ok = e < HW * HW && gx >= 0 && gy >= 0 && gx < W && gy < H;
       const int64_t o = (int64_t)gy * W + gx;
 #pragma unroll
-      for (int m = 0; m < 3; ++m) sc[m][r][q] = ok ? coef[(m * 3 + c) * npix + o] : 0.f;
+      for (int m = 0; m < 3; ++m) pre[t][m] = ok ? coef[(m * 3 + c) * npix + o] : 0.f;
     }
-    __syncthreads();
+  };
+  load(0);
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = tid + t * GS3_BLOCK;
+      if (e < HW * HW) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sc[m][e / HW][e % HW] = pre[t][m];
+      }
+    }
+    lds_barrier();
+    if (c < 2) load(c + 1);
     for (int e = tid; e < HW * GS3_TILE; e += GS3_BLOCK) {
       const int r = e / GS3_TILE, q = e % GS3_TILE;
 #pragma unroll
@@ -185,7 +213,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_combine(const float* __restr
         hb[m][r][q] = acc;
       }
     }
-    __syncthreads();
+    lds_barrier();
     float bA = 0.f, bXX = 0.f, bXY = 0.f;
 #pragma unroll
     for (int k = 0; k < 11; ++k) {
@@ -203,7 +231,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_combine(const float* __restr
       l1term = scale * (1.f - lam) * sg;
     }
     out[c] = l1term + (bA + 2.f * xv[c] * bXX + yv[c] * bXY);
-    __syncthreads();
+    lds_barrier();
   }
   if (inside) {
 #pragma unroll
