@@ -81,28 +81,45 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict
   __syncthreads();
   double lsum = 0.0;
   for (int c = 0; c < 3; ++c) {
-    for (int e = tid; e < HW * GS3_TILE; e += GS3_BLOCK) {
-      const int r = e / GS3_TILE, q = e % GS3_TILE;
-      float m[NM];
+    // horizontal pass: a thread filters two adjacent outputs of a row, q0
+    // and q0 + 1, from one window of 12 inputs, so every product is formed
+    // once for both (same terms in the same order as one output at a time)
+    for (int e = tid; e < HW * (GS3_TILE / 2); e += GS3_BLOCK) {
+      const int r = e / (GS3_TILE / 2), q0 = 2 * (e % (GS3_TILE / 2));
+      float m0[NM], m1[NM];
 #pragma unroll
-      for (int k = 0; k < NM; ++k) m[k] = 0.f;
+      for (int k = 0; k < NM; ++k) m0[k] = m1[k] = 0.f;
 #pragma unroll
-      for (int k = 0; k < 11; ++k) {
-        const float xv = sx[c][r][q + k], yv = sy[c][r][q + k], wk = win.w[k];
-        m[0] += wk * xv;
-        m[1] += wk * yv;
-        m[2] += wk * (xv * xv);
-        m[3] += wk * (yv * yv);
-        m[4] += wk * (xv * yv);
+      for (int t = 0; t < 12; ++t) {
+        const float xv = sx[c][r][q0 + t], yv = sy[c][r][q0 + t];
+        float pr[NM];
+        pr[0] = xv;
+        pr[1] = yv;
+        pr[2] = xv * xv;
+        pr[3] = yv * yv;
+        pr[4] = xv * yv;
         if (GN) {
-          const float uv = su[c][r][q + k];
-          m[5] += wk * uv;
-          m[6] += wk * (2.f * xv * uv);
-          m[7] += wk * (yv * uv);
+          const float uv = su[c][r][q0 + t];
+          pr[5] = uv;
+          pr[6] = 2.f * xv * uv;
+          pr[7] = yv * uv;
+        }
+        if (t < 11) {
+          const float wk = win.w[t];
+#pragma unroll
+          for (int k = 0; k < NM; ++k) m0[k] += wk * pr[k];
+        }
+        if (t >= 1) {
+          const float wk = win.w[t - 1];
+#pragma unroll
+          for (int k = 0; k < NM; ++k) m1[k] += wk * pr[k];
         }
       }
 #pragma unroll
-      for (int k = 0; k < NM; ++k) hb[k][r][q] = m[k];
+      for (int k = 0; k < NM; ++k) {
+        hb[k][r][q0] = m0[k];
+        hb[k][r][q0 + 1] = m1[k];
+      }
     }
     __syncthreads();
     float f[NM];
