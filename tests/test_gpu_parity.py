@@ -168,6 +168,33 @@ def test_grad_is_deterministic(c1):
     s.close()
 
 
+def test_counting_kernels_match_plain_kernels(c1):
+    """The instrumented blend instances (profiling with work counters) give
+    the same gradient and Hutchinson diagonal bit for bit, and count work."""
+    from paper_2602_00395_amd import profile_count, profile_enable, profile_read, profile_reset
+
+    sc, x, targets = c1
+    s = make_scene(x, targets, sc.cameras, 0)
+    plain_g = s.grad([2]).cpu()
+    plain_d = s.hvp_diag([3], 1, 5003).cpu()
+    profile_reset()
+    profile_count(True)
+    profile_enable("blend_fwd,blend_bwd,blend_jvp")
+    try:
+        counted_g = s.grad([2]).cpu()
+        counted_d = s.hvp_diag([3], 1, 5003).cpu()
+        torch.cuda.synchronize()
+    finally:
+        profile_enable("")
+    st = {k: profile_read(k) for k in ("blend_fwd", "blend_bwd", "blend_jvp")}
+    profile_reset()
+    say("  counters", st)
+    assert torch.equal(plain_g, counted_g) and torch.equal(plain_d, counted_d)
+    for k, v in st.items():
+        assert v["launches"] >= 1 and v["work0"] >= v["work1"] > 0, (k, v)
+    s.close()
+
+
 def test_hvp_diag_parity_config1(c1):
     sc, x, targets = c1
     s = make_scene(x, targets, sc.cameras, 0)
