@@ -253,7 +253,7 @@ void free_all(gs3_scene* s) {
 // the Adam moments on the first Adam call, the fused iteration's second
 // parameter buffer, D_t, gradient accumulator and radius on the first
 // gs3_tr_iteration.
-gs3_status zeroed(gs3_scene* s, float** p, int64_t count, hipStream_t st) {
+gs3_status zeroed(float** p, int64_t count, hipStream_t st) {
   if (*p) return GS3_OK;
   GS3_TRY(dalloc(p, (size_t)count));
   launch_fill_f32(*p, count, 0.f, st);
@@ -261,13 +261,13 @@ gs3_status zeroed(gs3_scene* s, float** p, int64_t count, hipStream_t st) {
 }
 gs3_status need_tr_state(gs3_scene* s, hipStream_t st) {
   const int64_t PN = (int64_t)s->P * s->N;
-  GS3_TRY(zeroed(s, &s->ghat, PN, st));
-  return zeroed(s, &s->dhat, PN, st);
+  GS3_TRY(zeroed(&s->ghat, PN, st));
+  return zeroed(&s->dhat, PN, st);
 }
 gs3_status need_adam_state(gs3_scene* s, hipStream_t st) {
   const int64_t PN = (int64_t)s->P * s->N;
-  GS3_TRY(zeroed(s, &s->am, PN, st));
-  return zeroed(s, &s->av, PN, st);
+  GS3_TRY(zeroed(&s->am, PN, st));
+  return zeroed(&s->av, PN, st);
 }
 gs3_status need_fused_state(gs3_scene* s, hipStream_t st) {
   const int64_t PN = (int64_t)s->P * s->N;

@@ -38,7 +38,6 @@ __device__ __forceinline__ Dual operator*(float a, Dual b) { return {a * b.v, a 
 __device__ __forceinline__ Dual operator*(Dual a, float b) { return {a.v * b, a.t * b}; }
 __device__ __forceinline__ Dual operator+(Dual a, float b) { return {a.v + b, a.t}; }
 __device__ __forceinline__ Dual operator-(Dual a, float b) { return {a.v - b, a.t}; }
-__device__ __forceinline__ Dual operator-(float a, Dual b) { return {a - b.v, -b.t}; }
 __device__ __forceinline__ Dual operator/(float a, Dual b) {
   float q = a / b.v;
   return {q, -q * b.t / b.v};
@@ -54,10 +53,6 @@ __device__ __forceinline__ Dual sqrt_(Dual a) {
 // exp of a log-scale, evaluated in double and rounded once: reproducible in
 // float32 by any correctly rounded double exp.
 __device__ __forceinline__ float exp_ls(float a) { return (float)exp((double)a); }
-__device__ __forceinline__ Dual exp_ls(Dual a) {
-  float e = exp_ls(a.v);
-  return {e, e * a.t};
-}
 __device__ __forceinline__ float sigmoid_(float a) { return 1.f / (1.f + expf(-a)); }
 __device__ __forceinline__ Dual sigmoid_(Dual a) {
   float s = sigmoid_(a.v);
@@ -277,9 +272,8 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x, int64_t n, CamDev cam,
-                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
-                                                      int kind, uint64_t inner, const float* __restrict__ tangent,
-                                                      TRec* __restrict__ trec) {
+                                                      const uint32_t* __restrict__ tiles, int kind, uint64_t inner,
+                                                      const float* __restrict__ tangent, TRec* __restrict__ trec) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   if (tiles[g] == 0u) return;
@@ -714,7 +708,8 @@ void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, R
 void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
                         const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
                         const float* tangent, TRec* trec, hipStream_t st) {
-  GS3_DEG_DISPATCH(deg, k_project_jvp, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, rec, tiles, probe_kind,
+  (void)rec;
+  GS3_DEG_DISPATCH(deg, k_project_jvp, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, tiles, probe_kind,
                    probe_inner(seed, probe_index), tangent, trec);
 }
 
