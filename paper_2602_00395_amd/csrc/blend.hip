@@ -17,10 +17,10 @@
 // staged in LDS together with, per wave, a bit mask of the splats whose
 // skip test can pass somewhere in its block (the skip ellipse, widened by its
 // float32 rounding, against the block's rectangle of pixel centres), and
-// every wave walks only the set bits.  In the forward each wave stages its
-// own batches in a private LDS slice and never waits for the other three
-// (they differ in how far their pixels blend); the JVP and the backward
-// stage per workgroup.  Culled
+// every wave walks only the set bits.  In the forward and the JVP each wave
+// stages its own batches in a private LDS slice and never waits for the
+// other three (they differ in how far their pixels blend); the backward
+// stages per workgroup.  Culled
 // evaluations are exactly the ones the skip test would reject, so the
 // result is the same bit for bit.  Workgroups take tiles longest list first
 // (a pixel's walk is serial, so the tiles with the longest lists bound the
@@ -297,14 +297,15 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   count_evals<COUNT>(ctr, nev, ncon);
 }
 
-struct StageJ {
-  float4 a[GS3_BLOCK];
-  float4 b[GS3_BLOCK];
-  float4 ta[GS3_BLOCK];
-  float4 tb[GS3_BLOCK];
-  float2 c[GS3_BLOCK];  // b, tau
-  float tc[GS3_BLOCK];
-  uint64_t bits[4][GS3_BLOCK / 64];
+// One wave's batch of 64 splats with their tangent records (the JVP's
+// waves, like the forward's, never wait for each other).
+struct StageJW {
+  float4 a[64];
+  float4 b[64];
+  float4 ta[64];
+  float4 tb[64];
+  float2 c[64];  // b, tau
+  float tc[64];
 };
 
 template <bool COUNT>
@@ -318,9 +319,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
                                                           unsigned long long* __restrict__ ctr) {
   const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
-  __shared__ StageJ s;
+  __shared__ StageJW stage[4];
   uint32_t nev = 0, ncon = 0;
-  const int tid = threadIdx.x, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  StageJW& s = stage[w];
   const int tx = t % cam.tiles_x, ty = t / cam.tiles_x;
   const int px = pixel_x(tx, tid), py = pixel_y(ty, tid);
   const bool inside = px < cam.width && py < cam.height;
@@ -330,69 +332,63 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
   uint32_t live = inside ? 1u : 0u;  // as in the forward
   uint32_t lastp = 0u;
-  for (uint32_t start = range.x; start < range.y; start += GS3_BLOCK) {
-    if (__syncthreads_count(live) == 0) break;
-    const uint32_t i = start + tid;
-    uint32_t m = 0u;
+  // this lane's pair id of the batch about to be staged, loaded one batch ahead
+  uint32_t g_next = range.x + lane < range.y ? pair_gid[range.x + lane] : 0u;
+  for (uint32_t start = range.x; start < range.y; start += 64) {
+    if (__ballot(live) == 0ull) break;
+    const uint32_t i = start + lane;
+    bool keep = false;
     if (i < range.y) {
-      const uint32_t g = pair_gid[i];
-      const Rec r = rec[g];
-      const TRec q = trec[g];
-      s.a[tid] = r.a;
-      s.b[tid] = r.b;
-      s.c[tid] = make_float2(r.c.x, r.c.y);
-      s.ta[tid] = q.a;
-      s.tb[tid] = q.b;
-      s.tc[tid] = q.c.x;
-      m = block_mask(r.a, r.b, r.c.y, tx, ty);
+      const Rec r = rec[g_next];
+      const TRec q = trec[g_next];
+      s.a[lane] = r.a;
+      s.b[lane] = r.b;
+      s.c[lane] = make_float2(r.c.x, r.c.y);
+      s.ta[lane] = q.a;
+      s.tb[lane] = q.b;
+      s.tc[lane] = q.c.x;
+      keep = cull_keep(cull_setup(r.a, r.b, r.c.y, tx, ty), w);
     }
-    publish_masks(s.bits, m, tid);
-    __syncthreads();
-    const int nwords = (min((int)(range.y - start), GS3_BLOCK) + 63) >> 6;
-    bool wave_done = false;
-    for (int qw = 0; qw < nwords && !wave_done; ++qw) {
-      uint64_t bits = uniform64(s.bits[w][qw]);
-      while (bits) {
-        if (__ballot(live) == 0ull) {
-          wave_done = true;
-          break;
-        }
-        const int j = (qw << 6) + __builtin_ctzll(bits);
-        bits &= bits - 1;
-        if (COUNT) nev += live;
-        const float4 A = s.a[j], B = s.b[j];
-        const float2 Cc = s.c[j];
-        const float dx = A.x - pxf, dy = A.y - pyf;
-        const float power = splat_power(A.z, A.w, B.x, dx, dy);
-        const bool pass = live && power <= 0.f && power >= Cc.y;
-        const float G = __expf(power);
-        const float araw = B.y * G;
-        const float a = fminf(GS3_ALPHA_MAX, araw);
-        const float Tn = T * (1.f - a);
-        const bool stop = pass && Tn < GS3_T_STOP;
-        const bool use = pass && !stop;
-        live = stop ? 0u : live;
-        if (COUNT) ncon += use ? 1u : 0u;
-        const float4 TA = s.ta[j], TB = s.tb[j];
-        // d power along the tangent: d = (u - px, v - py), dd = (du, dv); the
-        // record holds the pre-scaled conic, the tangent record the plain one
-        const float dpow = 2.f * (A.z * dx * TA.x + B.x * dy * TA.y) + A.w * (TA.x * dy + dx * TA.y) -
-                           0.5f * (TA.z * dx * dx + TB.x * dy * dy) - TA.w * dx * dy;
-        const float da = araw > GS3_ALPHA_MAX ? 0.f : (TB.y * G + B.y * G * dpow);
-        const float wt = use ? a * T : 0.f;
-        const float dw = use ? da * T + a * dT : 0.f;
-        C0 += B.z * wt;
-        C1 += B.w * wt;
-        C2 += Cc.x * wt;
-        D0 += TB.z * wt + B.z * dw;
-        D1 += TB.w * wt + B.w * dw;
-        D2 += s.tc[j] * wt + Cc.x * dw;
-        dT = use ? dT * (1.f - a) - T * da : dT;
-        T = use ? Tn : T;
-        lastp = use ? start + (uint32_t)j + 1u : lastp;
-      }
+    if (i + 64 < range.y) g_next = pair_gid[i + 64];
+    uint64_t bits = __ballot(keep);
+    wave_lds_sync();
+    while (bits) {
+      if (__ballot(live) == 0ull) break;
+      const int j = __builtin_ctzll(bits);
+      bits &= bits - 1;
+      if (COUNT) nev += live;
+      const float4 A = s.a[j], B = s.b[j];
+      const float2 Cc = s.c[j];
+      const float dx = A.x - pxf, dy = A.y - pyf;
+      const float power = splat_power(A.z, A.w, B.x, dx, dy);
+      const bool pass = live && power <= 0.f && power >= Cc.y;
+      const float G = __expf(power);
+      const float araw = B.y * G;
+      const float a = fminf(GS3_ALPHA_MAX, araw);
+      const float Tn = T * (1.f - a);
+      const bool stop = pass && Tn < GS3_T_STOP;
+      const bool use = pass && !stop;
+      live = stop ? 0u : live;
+      if (COUNT) ncon += use ? 1u : 0u;
+      const float4 TA = s.ta[j], TB = s.tb[j];
+      // d power along the tangent: d = (u - px, v - py), dd = (du, dv); the
+      // record holds the pre-scaled conic, the tangent record the plain one
+      const float dpow = 2.f * (A.z * dx * TA.x + B.x * dy * TA.y) + A.w * (TA.x * dy + dx * TA.y) -
+                         0.5f * (TA.z * dx * dx + TB.x * dy * dy) - TA.w * dx * dy;
+      const float da = araw > GS3_ALPHA_MAX ? 0.f : (TB.y * G + B.y * G * dpow);
+      const float wt = use ? a * T : 0.f;
+      const float dw = use ? da * T + a * dT : 0.f;
+      C0 += B.z * wt;
+      C1 += B.w * wt;
+      C2 += Cc.x * wt;
+      D0 += TB.z * wt + B.z * dw;
+      D1 += TB.w * wt + B.w * dw;
+      D2 += s.tc[j] * wt + Cc.x * dw;
+      dT = use ? dT * (1.f - a) - T * da : dT;
+      T = use ? Tn : T;
+      lastp = use ? start + (uint32_t)j + 1u : lastp;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   if (inside) {
     pix_last[(int64_t)py * cam.width + px] = lastp;
