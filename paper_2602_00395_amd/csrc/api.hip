@@ -132,6 +132,10 @@ struct gs3_scene {
   // emission; sized from the pair capacity of earlier views
   uint32_t* block_owner = nullptr;
   int64_t owner_blocks = 0;
+  // the backward's (tile, depth segment) units and the long tiles' segment
+  // states, seg_slots(max_tiles, pair_cap) rows each
+  uint2* units = nullptr;
+  float4* seg = nullptr;
   float* partials = nullptr;
   float* gsum = nullptr;  // float[N][9]: each Gaussian's summed partials
   // per-view image scratch
@@ -229,6 +233,8 @@ void free_all(gs3_scene* s) {
   dfree(s->pg2);
   dfree(s->partials);
   dfree(s->block_owner);
+  dfree(s->units);
+  dfree(s->seg);
   dfree(s->gsum);
   dfree(s->ranges);
   dfree(s->tile_order);
@@ -288,12 +294,16 @@ gs3_status ensure_pairs(gs3_scene* s, int64_t n_pairs) {
   dfree(s->pg2);
   dfree(s->partials);
   dfree(s->rtmp);
+  dfree(s->units);
+  dfree(s->seg);
   s->pair_cap = 0;
   GS3_TRY(dalloc(&s->pt, cap));
   GS3_TRY(dalloc(&s->pg, cap));
   GS3_TRY(dalloc(&s->pt2, cap));
   GS3_TRY(dalloc(&s->pg2, cap));
   GS3_TRY(dalloc(&s->partials, (size_t)cap * 9));
+  GS3_TRY(dalloc(&s->units, (size_t)seg_slots(s->max_tiles, cap)));
+  GS3_TRY(dalloc(&s->seg, (size_t)seg_slots(s->max_tiles, cap) * GS3_BLOCK));
   s->rtmp_bytes = radix_temp_bytes(std::max<int64_t>(cap, s->N));
   GS3_TRY(dalloc((char**)&s->rtmp, s->rtmp_bytes));
   s->pair_cap = cap;
@@ -355,7 +365,7 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   auto p4 = prof::begin("pair_sort", st);
   radix_sort_u32(s->pt, s->pg, s->pt2, s->pg2, s->pt, s->pg, n_pairs, bits_for(n_tiles), s->rtmp, st, &tk, &tv);
   launch_tile_ranges(tk, n_pairs, s->ranges, n_tiles, st);
-  s->have_order = launch_tile_order(s->ranges, n_tiles, s->tile_order, st);
+  s->have_order = launch_tile_order(s->ranges, n_tiles, s->tile_order, s->units, seg_slots(n_tiles, n_pairs), st);
   prof::end(p4, st, n_pairs, bits_for(n_tiles));
   GS3_LAUNCHED();
   s->sorted_gid = tv;
@@ -376,21 +386,22 @@ const float* target_of(gs3_scene* s, int cam) { return s->targets + s->tgt_off[c
 void blend_fwd(gs3_scene* s, const CamDev& cd, float* out, hipStream_t st) {
   auto p = prof::begin("blend_fwd", st, true);
   launch_blend_fwd(s->rec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg, out,
-                   s->pix_last, s->pix_T, st, p.c);
+                   s->pix_last, s->pix_T, s->seg, st, p.c);
   prof::end(p, st);
 }
 
 void blend_jvp(gs3_scene* s, const CamDev& cd, float* out, float* tan, hipStream_t st) {
   auto p = prof::begin("blend_jvp", st, true);
   launch_blend_jvp(s->rec, s->trec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg,
-                   out, tan, s->pix_last, s->pix_T, st, p.c);
+                   out, tan, s->pix_last, s->pix_T, s->seg, st, p.c);
   prof::end(p, st);
 }
 
 void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st) {
   auto p = prof::begin("blend_bwd", st, true);
-  launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd,
-                   s->pix_last, s->pix_T, s->bg, cot, s->partials, st, p.c);
+  if (s->have_order)
+    launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, s->units, seg_slots(cd.tiles_x * cd.tiles_y, s->n_pairs),
+                     cd, s->pix_last, s->pix_T, s->seg, s->bg, cot, s->partials, st, p.c);
   prof::end(p, st);
 }
 
@@ -454,10 +465,14 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
   // records, tangent records, eight u32 arrays, the summed partials, the
   // trust radius, per-pixel blend state, and pair buffers for about
   // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair and an owner
-  // per 256 pairs, +25% slack)
+  // per 256 pairs, +25% slack) with the backward's segment units and states
   const int64_t pairs = 20 * N;
+  int64_t max_tiles = 0;
+  for (int j = 0; j < d->n_cameras; ++j)
+    max_tiles = std::max<int64_t>(max_tiles, (int64_t)((d->cameras[j].width + GS3_TILE - 1) / GS3_TILE) *
+                                                 ((d->cameras[j].height + GS3_TILE - 1) / GS3_TILE));
   *peak_scratch = 96 * N + 32 * N + 36 * N + 60 * N + pairs * (16 + 36) + pairs / 64 + 4 * max_px * 3 * 3 + 36 * max_px +
-                  8 * max_px;
+                  8 * max_px + seg_slots(max_tiles, pairs) * (8 + 16 * GS3_BLOCK);
   return GS3_OK;
 }
 

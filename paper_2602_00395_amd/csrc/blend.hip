@@ -28,6 +28,15 @@
 // gets a contiguous band of tiles (neighbouring tiles share splats, and each
 // XCD has its own L2).
 //
+// The backward cuts each tile's list into depth segments of GS3_SEG pairs and
+// runs one workgroup per (tile, segment), longest first: a few hundred tiles
+// hold most of the pairs, and whole tiles would leave some SIMDs with one
+// long walk more than others.  For tiles of more than one segment the
+// forward (and the JVP) store, at every segment boundary a pixel reaches, its
+// transmittance and the colour the segment added; the backward of segment m
+// starts from the transmittance after m and the colour of the later segments
+// up to the pixel's last contribution.
+//
 // The backward pass walks each tile back to front: the forward stores, per
 // pixel, its final transmittance and the last splat that contributed; the
 // backward starts there, recovers T in front of each splat as T / (1 - abar)
@@ -204,7 +213,8 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
                                                           const uint32_t* __restrict__ order, CamDev cam, float bg0,
                                                           float bg1, float bg2, float* __restrict__ img,
                                                           uint32_t* __restrict__ pix_last, float* __restrict__ pix_T,
-                                                          int n_tiles, int chunk, unsigned long long* __restrict__ ctr) {
+                                                          float4* __restrict__ seg, int n_tiles, int chunk,
+                                                          unsigned long long* __restrict__ ctr) {
   const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ StageW stage[4];
@@ -216,17 +226,29 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = uniform_range(ranges, t);
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  // C: colour added by the current depth segment, E: by the finished ones
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f;
   // 1 while the pixel still blends; an integer rather than a bool, so the
   // loop carries it in a vector register instead of a scalar lane mask
   uint32_t live = inside ? 1u : 0u;
   uint32_t lastp = 0u;  // 1 + pair index of the last contributing splat (0: none)
+  const bool split = range.y - range.x > GS3_SEG;
+  float4* seg_px = seg + ((int64_t)t + range.x / GS3_SEG) * GS3_BLOCK + tid;
+  uint32_t cur = 0;  // depth segment of the batch being walked
   // this lane's pair id of the batch about to be staged, loaded one batch
   // ahead so that staging waits for one dependent load, not two
   uint32_t g_next = range.x + lane < range.y ? pair_gid[range.x + lane] : 0u;
   for (uint32_t start = range.x; start < range.y; start += 64) {
     // every pixel of the block has stopped: the rest is never read
     if (__ballot(live) == 0ull) break;
+    if (split && start != range.x && (start - range.x) % GS3_SEG == 0) {
+      seg_px[(int64_t)cur * GS3_BLOCK] = make_float4(T, C0, C1, C2);
+      E0 += C0;
+      E1 += C1;
+      E2 += C2;
+      C0 = C1 = C2 = 0.f;
+      ++cur;
+    }
     const uint32_t i = start + lane;
     bool keep = false;
     if (i < range.y) {
@@ -285,12 +307,13 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
     }
     wave_lds_sync();
   }
+  if (split) seg_px[(int64_t)cur * GS3_BLOCK] = make_float4(T, C0, C1, C2);
   if (inside) {
     const int64_t pix = (int64_t)py * cam.width + px;
     float* o = img + pix * 3;
-    o[0] = C0 + T * bg0;
-    o[1] = C1 + T * bg1;
-    o[2] = C2 + T * bg2;
+    o[0] = (E0 + C0) + T * bg0;
+    o[1] = (E1 + C1) + T * bg1;
+    o[2] = (E2 + C2) + T * bg2;
     pix_last[pix] = lastp;
     pix_T[pix] = T;
   }
@@ -315,8 +338,8 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
                                                           const uint32_t* __restrict__ order, CamDev cam, float bg0,
                                                           float bg1, float bg2, float* __restrict__ img,
                                                           float* __restrict__ tan_img, uint32_t* __restrict__ pix_last,
-                                                          float* __restrict__ pix_T, int n_tiles, int chunk,
-                                                          unsigned long long* __restrict__ ctr) {
+                                                          float* __restrict__ pix_T, float4* __restrict__ seg,
+                                                          int n_tiles, int chunk, unsigned long long* __restrict__ ctr) {
   const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ StageJW stage[4];
@@ -329,13 +352,25 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = uniform_range(ranges, t);
   float T = 1.f, dT = 0.f;
-  float C0 = 0.f, C1 = 0.f, C2 = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f, E0 = 0.f, E1 = 0.f, E2 = 0.f;
   uint32_t live = inside ? 1u : 0u;  // as in the forward
   uint32_t lastp = 0u;
+  // depth segments of long tiles, as in the forward
+  const bool split = range.y - range.x > GS3_SEG;
+  float4* seg_px = seg + ((int64_t)t + range.x / GS3_SEG) * GS3_BLOCK + tid;
+  uint32_t cur = 0;
   // this lane's pair id of the batch about to be staged, loaded one batch ahead
   uint32_t g_next = range.x + lane < range.y ? pair_gid[range.x + lane] : 0u;
   for (uint32_t start = range.x; start < range.y; start += 64) {
     if (__ballot(live) == 0ull) break;
+    if (split && start != range.x && (start - range.x) % GS3_SEG == 0) {
+      seg_px[(int64_t)cur * GS3_BLOCK] = make_float4(T, C0, C1, C2);
+      E0 += C0;
+      E1 += C1;
+      E2 += C2;
+      C0 = C1 = C2 = 0.f;
+      ++cur;
+    }
     const uint32_t i = start + lane;
     bool keep = false;
     if (i < range.y) {
@@ -390,13 +425,14 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
     }
     wave_lds_sync();
   }
+  if (split) seg_px[(int64_t)cur * GS3_BLOCK] = make_float4(T, C0, C1, C2);
   if (inside) {
     pix_last[(int64_t)py * cam.width + px] = lastp;
     pix_T[(int64_t)py * cam.width + px] = T;
     const int64_t o = ((int64_t)py * cam.width + px) * 3;
-    img[o + 0] = C0 + T * bg0;
-    img[o + 1] = C1 + T * bg1;
-    img[o + 2] = C2 + T * bg2;
+    img[o + 0] = (E0 + C0) + T * bg0;
+    img[o + 1] = (E1 + C1) + T * bg1;
+    img[o + 2] = (E2 + C2) + T * bg2;
     tan_img[o + 0] = D0 + dT * bg0;
     tan_img[o + 1] = D1 + dT * bg1;
     tan_img[o + 2] = D2 + dT * bg2;
@@ -471,14 +507,17 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
                                                           const uint2* __restrict__ rect,
                                                           const uint32_t* __restrict__ pair_gid,
                                                           const uint2* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ order, CamDev cam,
+                                                          const uint2* __restrict__ units, CamDev cam,
                                                           const uint32_t* __restrict__ pix_last,
-                                                          const float* __restrict__ pix_T, float bg0, float bg1,
+                                                          const float* __restrict__ pix_T,
+                                                          const float4* __restrict__ seg, float bg0, float bg1,
                                                           float bg2, const float* __restrict__ cot,
-                                                          float* __restrict__ partials, int n_tiles, int chunk,
+                                                          float* __restrict__ partials, int n_tiles,
                                                           unsigned long long* __restrict__ ctr) {
-  const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
+  const uint2 unit = units[blockIdx.x];
+  const int t = (int)__builtin_amdgcn_readfirstlane(unit.x);
   if (t >= n_tiles) return;
+  const uint32_t m = __builtin_amdgcn_readfirstlane(unit.y);  // depth segment of the tile's list
   __shared__ StageB s;
   __shared__ uint32_t tile_end;
   uint32_t nev = 0, ncon = 0;
@@ -488,7 +527,9 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   const bool inside = px < cam.width && py < cam.height;
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const uint2 range = uniform_range(ranges, t);
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f, T = 1.f;
+  // this workgroup's pairs [lo, hi): segment m of the tile's list
+  const uint32_t lo = range.x + m * GS3_SEG, hi = min(range.y, lo + GS3_SEG);
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f, T = 1.f, acc = 0.f;
   uint32_t last = 0u;  // 1 + pair index of the pixel's last contributing splat (0: none)
   if (inside) {
     const int64_t pix = (int64_t)py * cam.width + px;
@@ -497,17 +538,29 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
     g2 = cot[pix * 3 + 2];
     last = pix_last[pix];
     T = pix_T[pix];
+    // (sum over the contributing splats behind the current one of c w +
+    // T_final bg) . dL/dC, accumulated from the back
+    acc = T * (bg0 * g0 + bg1 * g1 + bg2 * g2);
+    // the pixel's last contribution lies in a later segment k: start from
+    // the transmittance after segment m and add the colour of segments
+    // m+1..k (segments after k add nothing for this pixel)
+    const uint32_t k = last > range.x ? (last - 1u - range.x) / GS3_SEG : 0u;
+    if (range.y - range.x > GS3_SEG && k > m) {
+      const float4* sp = seg + ((int64_t)t + range.x / GS3_SEG) * GS3_BLOCK + tid;
+      T = sp[(int64_t)m * GS3_BLOCK].x;
+      for (uint32_t q = m + 1u; q <= k; ++q) {
+        const float4 v = sp[(int64_t)q * GS3_BLOCK];
+        acc += v.y * g0 + v.z * g1 + v.w * g2;
+      }
+    }
   }
-  // (sum over the contributing splats behind the current one of c w + T_final bg) . dL/dC,
-  // accumulated from the back
-  float acc = T * (bg0 * g0 + bg1 * g1 + bg2 * g2);
   if (tid == 0) tile_end = 0u;
   __syncthreads();
   if (last > 0u) atomicMax(&tile_end, last);
   __syncthreads();
   // pairs at or after the tile's last contribution: zero slots
-  const uint32_t end = tile_end > range.x ? tile_end : range.x;
-  for (uint32_t i = end + tid; i < range.y; i += GS3_BLOCK) {
+  const uint32_t end = min(max(tile_end, lo), hi);
+  for (uint32_t i = end + tid; i < hi; i += GS3_BLOCK) {
     const uint32_t g = pair_gid[i];
     float* dst = partials + (int64_t)pair_slot(__float_as_uint(rec[g].c.z), rect[g], tx, ty) * 9;
 #pragma unroll
@@ -518,8 +571,8 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) wave_end = max(wave_end, (uint32_t)__shfl_xor((int)wave_end, m, 64));
   wave_end = __builtin_amdgcn_readfirstlane(wave_end);
-  if (end > range.x) {
-    for (int64_t bstart = range.x + (int64_t)((end - 1 - range.x) / kBwdBatch) * kBwdBatch; bstart >= range.x;
+  if (end > lo) {
+    for (int64_t bstart = lo + (int64_t)((end - 1 - lo) / kBwdBatch) * kBwdBatch; bstart >= lo;
          bstart -= kBwdBatch) {
       const int cnt = (int)min((int64_t)kBwdBatch, (int64_t)end - bstart);
       const int64_t i = bstart + tid;
@@ -664,28 +717,30 @@ inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }
 }  // namespace
 
 void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
-                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T,
+                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T, float4* seg,
                       hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
   auto kernel = ctr ? k_blend_fwd<true> : k_blend_fwd<false>;
   hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, order,
-                     cam, bg[0], bg[1], bg[2], img, pix_last, pix_T, nt, ch, ctr);
+                     cam, bg[0], bg[1], bg[2], img, pix_last, pix_T, seg, nt, ch, ctr);
 }
 
 void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
                       const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
-                      uint32_t* pix_last, float* pix_T, hipStream_t st, unsigned long long* ctr) {
+                      uint32_t* pix_last, float* pix_T, float4* seg, hipStream_t st, unsigned long long* ctr) {
   const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
   auto kernel = ctr ? k_blend_jvp<true> : k_blend_jvp<false>;
   hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges,
-                     order, cam, bg[0], bg[1], bg[2], img, tan_img, pix_last, pix_T, nt, ch, ctr);
+                     order, cam, bg[0], bg[1], bg[2], img, tan_img, pix_last, pix_T, seg, nt, ch, ctr);
 }
 
 void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint32_t* order, const CamDev& cam, const uint32_t* pix_last, const float* pix_T,
-                      const float* bg, const float* cot, float* partials, hipStream_t st, unsigned long long* ctr) {
-  const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
+                      const uint2* units, int64_t n_units, const CamDev& cam, const uint32_t* pix_last,
+                      const float* pix_T, const float4* seg, const float* bg, const float* cot, float* partials,
+                      hipStream_t st, unsigned long long* ctr) {
+  const int nt = cam.tiles_x * cam.tiles_y;
+  if (n_units < 1) return;
   auto kernel = ctr ? k_blend_bwd<true> : k_blend_bwd<false>;
-  hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges,
-                     order, cam, pix_last, pix_T, bg[0], bg[1], bg[2], cot, partials, nt, ch, ctr);
+  hipLaunchKernelGGL(kernel, dim3((unsigned)n_units), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges, units,
+                     cam, pix_last, pix_T, seg, bg[0], bg[1], bg[2], cot, partials, nt, ctr);
 }

@@ -10,6 +10,9 @@
 // one address
 #define GS3_PROF_SUB 64
 #define GS3_BLOCK (GS3_TILE * GS3_TILE)
+// depth segment of a tile's pair list processed by one backward workgroup
+// (a multiple of the backward's 128-splat batch)
+#define GS3_SEG 512
 
 // Rasteriser constants of the original 3DGS design (the paper states only the
 // blend equation): near plane, screen-space dilation, frustum clamp of the
@@ -119,8 +122,13 @@ void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, co
                        int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, int64_t n_pairs, int tiles_x,
                        uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st);
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st);
-// Tile ids in (approximately) descending order of their pair count.
-bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, hipStream_t st);
+// Tile ids in (approximately) descending order of their pair count, and the
+// backward's work units: each non-empty tile's list cut into depth segments
+// of GS3_SEG pairs, unit = (tile, segment), also longest first; entries from
+// the unit count up to n_units hold (n_tiles, 0).  n_units must be at least
+// n_tiles + n_pairs / GS3_SEG + 1.
+bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, uint2* units, int64_t n_units,
+                       hipStream_t st);
 void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const uint32_t* depth_key,
                       int64_t n_pairs, uint64_t* keys, hipStream_t st);
 
@@ -131,17 +139,25 @@ void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const
 // evaluations (measurement only).
 // pix_last / pix_T (float[H][W] each): 1 + pair index of each pixel's last
 // contributing splat (0: none) and its final transmittance, written by the
-// forward (or the JVP) and read by the backward
+// forward (or the JVP) and read by the backward.
+// seg (float4[seg_slots(n_tiles, n_pairs)][256]): for tiles of more than
+// GS3_SEG pairs, per depth segment m and pixel of the tile, the transmittance
+// after the segment and the colour the segment added, at row
+// t + ranges[t].x / GS3_SEG + m; written by the forward (or the JVP) for the
+// segments its pixels reach, read by the backward's segment units.
+inline int64_t seg_slots(int64_t n_tiles, int64_t n_pairs) { return n_tiles + n_pairs / GS3_SEG + 1; }
 void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
-                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T,
+                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T, float4* seg,
                       hipStream_t st, unsigned long long* ctr = nullptr);
 void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
                       const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
-                      uint32_t* pix_last, float* pix_T, hipStream_t st, unsigned long long* ctr = nullptr);
-void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint32_t* order, const CamDev& cam, const uint32_t* pix_last, const float* pix_T,
-                      const float* bg, const float* cot, float* partials, hipStream_t st,
+                      uint32_t* pix_last, float* pix_T, float4* seg, hipStream_t st,
                       unsigned long long* ctr = nullptr);
+// units / n_units: from launch_tile_order (one workgroup per unit)
+void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
+                      const uint2* units, int64_t n_units, const CamDev& cam, const uint32_t* pix_last,
+                      const float* pix_T, const float4* seg, const float* bg, const float* cot, float* partials,
+                      hipStream_t st, unsigned long long* ctr = nullptr);
 
 // loss
 // cot = scale * d(sum_k l_k)/dC; optional per-block loss partial sums (double).

@@ -330,6 +330,83 @@ def test_hvp_diag_object_scale_sampled_gaussians():
     s.close()
 
 
+def _long_tile_picks(ob, rng, n_tiles, per_seg, seg=512):
+    """Gaussians from every depth segment of the `n_tiles` longest tile lists
+    (segments of `seg` pairs), each touching at most 4 tiles, and the tiles
+    they touch."""
+    counts = ob.ranges[:, 1] - ob.ranges[:, 0]
+    longest = np.argsort(counts)[-n_tiles:]
+    assert counts[longest].min() > 2 * seg, counts[longest]
+    pick = set()
+    for t in longest:
+        lo, hi = (int(v) for v in ob.ranges[t])
+        for q in range(lo, hi, seg):
+            g = ob.gids[q:min(q + seg, hi)]
+            g = g[ob.tiles_touched[g] <= 4]
+            pick |= set(int(v) for v in rng.choice(g, size=min(per_seg, len(g)), replace=False))
+    pick = np.array(sorted(pick))
+    tiles = set()
+    for g in pick:
+        x0, y0, x1, y1 = (int(v) for v in ob.rect[g])
+        tiles |= {ty * ob.tiles_x + tx for ty in range(y0, y1) for tx in range(x0, x1)}
+    return pick, tiles, longest
+
+
+def test_vjp_and_hvp_long_tiles_every_depth_segment():
+    """Full object scale: Gaussians from every 512-pair depth segment of the
+    two longest tile lists.  Each segment's backward starts from the
+    transmittance and colour the forward (or, for the Hutchinson diagonal,
+    the JVP) stored at the segment boundaries, so a wrong state shows up in
+    the gradients of the earlier segments' Gaussians."""
+    sc = syn.config2_scene()
+    cam = sc.cameras[3]
+    x = sc.init.astype(np.float32)
+    x[14:] = sc.gt[14:]
+    ob = B.bin_view(x, cam)
+    rng = np.random.default_rng(43)
+    pick, tiles, longest = _long_tile_picks(ob, rng, 2, 2)
+    say("long tiles", longest.tolist(), "lists", (ob.ranges[longest, 1] - ob.ranges[longest, 0]).tolist(),
+        "Gaussians", len(pick), "tiles", len(tiles))
+    xt = torch.tensor(x, dtype=torch.float64)
+    f = lambda xx: R.render(xx, cam, 3, ob, tiles=tiles)  # noqa: E731
+    with torch.no_grad():
+        base = f(xt)
+    m = ~torch.isnan(base)
+    # render VJP with a random cotangent
+    cot = rng.normal(size=(cam.height, cam.width, 3))
+    s = make_scene(x, [np.zeros((cam.height, cam.width, 3), np.float32)], [cam], 3)
+    got = s.render_vjp(0, torch.tensor(cot, dtype=torch.float32, device=DEV)).cpu().numpy()[:, pick]
+    s.close()
+    xg = xt.clone().requires_grad_(True)
+    (f(xg)[m] * torch.tensor(cot)[m]).sum().backward()
+    want = xg.grad.numpy()[:, pick]
+    # Gaussians behind every pixel's last contribution have zero gradient
+    assert np.count_nonzero(np.abs(want).sum(axis=0)) >= 4
+    errs = group_errors(got, want, 59)
+    say("  vjp rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    # Hutchinson diagonal (L1 loss, one probe) through the JVP's states
+    off = rng.uniform(0.05, 0.15, size=base.shape) * rng.choice([-1.0, 1.0], size=base.shape)
+    tgt = np.full(base.shape, 0.5)
+    tgt[m.numpy()] = base.numpy()[m.numpy()] + off[m.numpy()]
+    s = make_scene(x, [tgt.astype(np.float32)], [cam], 3, lam=0.0)
+    seed = 5081
+    got = s.hvp_diag([0], 1, seed).cpu().numpy()[:, pick]
+    s.close()
+    p, n = x.shape
+    z = Mth.probe(seed, 0, p, n)
+    img, u = torch.func.jvp(f, (xt,), (torch.tensor(z),))
+    y = torch.zeros_like(img)
+    y[m] = Mth.gn_cotangent(img[m], torch.tensor(tgt)[m], u[m], 0.0)
+    xg = xt.clone().requires_grad_(True)
+    (f(xg)[m] * y[m]).sum().backward()
+    scale = 1.0 / (6.0 * cam.height * cam.width)
+    want = (z * xg.grad.numpy() * scale)[:, pick]
+    errs = group_errors(got, want, 59)
+    say("  hvp rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+
+
 def test_tr_step_parity():
     sc = syn.config2_scene(n=4000, n_cams=2, res=64)
     x = sc.gt.astype(np.float32)
