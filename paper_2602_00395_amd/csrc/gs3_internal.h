@@ -12,7 +12,7 @@
 #define GS3_BLOCK (GS3_TILE * GS3_TILE)
 // depth segment of a tile's pair list processed by one backward workgroup
 // (a multiple of the backward's 128-splat batch)
-#define GS3_SEG 512
+#define GS3_SEG 256
 
 // Rasteriser constants of the original 3DGS design (the paper states only the
 // blend equation): near plane, screen-space dilation, frustum clamp of the

@@ -308,57 +308,62 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
 // buckets the tiles by pair count on a quarter-octave scale, scans the bucket
 // sizes from the longest down and scatters the tile ids.  The order inside a
 // bucket is whatever the LDS atomics give -- each tile's result does not
-// depend on when it runs, only the kernel's makespan does.  The same pass
-// orders the backward's units: a non-empty tile of c pairs gives c / GS3_SEG
-// full depth segments and, if c is not a multiple, one shorter last segment,
-// each bucketed by its own pair count.
+// depend on when it runs, only the kernel's makespan does.  A second
+// workgroup orders the backward's units the same way: a non-empty tile of c
+// pairs gives c / GS3_SEG full depth segments and, if c is not a multiple,
+// one shorter last segment, each bucketed by its own pair count.
 constexpr int kOrderBuckets = 128;
 __device__ __forceinline__ int count_bucket(uint32_t c) {
   return min(kOrderBuckets - 1, (int)(4.f * log2f((float)c + 1.f)));
 }
+// Workgroup 0 orders the tiles, workgroup 1 the units (independent, so the
+// two run side by side).
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, int n_tiles,
                                                       uint32_t* __restrict__ order, uint2* __restrict__ units,
                                                       int64_t n_units) {
   __shared__ uint32_t cursor[kOrderBuckets];
-  __shared__ uint32_t ucursor[kOrderBuckets];
-  __shared__ uint32_t u_total;
-  if (threadIdx.x < kOrderBuckets) {
-    cursor[threadIdx.x] = 0u;
-    ucursor[threadIdx.x] = 0u;
-  }
+  __shared__ uint32_t total;
+  const bool by_unit = blockIdx.x == 1;
+  if (threadIdx.x < kOrderBuckets) cursor[threadIdx.x] = 0u;
   __syncthreads();
   const int full_bucket = count_bucket(GS3_SEG);
   for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
     const uint2 r = ranges[i];
-    const uint32_t c = r.y - r.x, nfull = c / GS3_SEG, rem = c % GS3_SEG;
-    atomicAdd(&cursor[count_bucket(c)], 1u);
-    if (nfull) atomicAdd(&ucursor[full_bucket], nfull);
-    if (rem) atomicAdd(&ucursor[count_bucket(rem)], 1u);
+    const uint32_t c = r.y - r.x;
+    if (!by_unit) {
+      atomicAdd(&cursor[count_bucket(c)], 1u);
+    } else {
+      if (c >= GS3_SEG) atomicAdd(&cursor[full_bucket], c / GS3_SEG);
+      if (c % GS3_SEG) atomicAdd(&cursor[count_bucket(c % GS3_SEG)], 1u);
+    }
   }
   __syncthreads();
-  if (threadIdx.x < 2) {
-    uint32_t* cur = threadIdx.x == 0 ? cursor : ucursor;
+  if (threadIdx.x == 0) {
     uint32_t run = 0;
     for (int b = kOrderBuckets - 1; b >= 0; --b) {
-      const uint32_t c = cur[b];
-      cur[b] = run;
+      const uint32_t c = cursor[b];
+      cursor[b] = run;
       run += c;
     }
-    if (threadIdx.x == 1) u_total = run;
+    total = run;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
     const uint2 r = ranges[i];
     const uint32_t c = r.y - r.x, nfull = c / GS3_SEG, rem = c % GS3_SEG;
-    order[atomicAdd(&cursor[count_bucket(c)], 1u)] = (uint32_t)i;
-    if (nfull) {
-      const uint32_t p = atomicAdd(&ucursor[full_bucket], nfull);
-      for (uint32_t m = 0; m < nfull; ++m) units[p + m] = make_uint2((uint32_t)i, m);
+    if (!by_unit) {
+      order[atomicAdd(&cursor[count_bucket(c)], 1u)] = (uint32_t)i;
+    } else {
+      if (nfull) {
+        const uint32_t p = atomicAdd(&cursor[full_bucket], nfull);
+        for (uint32_t m = 0; m < nfull; ++m) units[p + m] = make_uint2((uint32_t)i, m);
+      }
+      if (rem) units[atomicAdd(&cursor[count_bucket(rem)], 1u)] = make_uint2((uint32_t)i, nfull);
     }
-    if (rem) units[atomicAdd(&ucursor[count_bucket(rem)], 1u)] = make_uint2((uint32_t)i, nfull);
   }
-  for (int64_t j = (int64_t)u_total + threadIdx.x; j < n_units; j += blockDim.x)
-    units[j] = make_uint2((uint32_t)n_tiles, 0u);
+  if (by_unit)
+    for (int64_t j = (int64_t)total + threadIdx.x; j < n_units; j += blockDim.x)
+      units[j] = make_uint2((uint32_t)n_tiles, 0u);
 }
 
 __global__ __launch_bounds__(256) void k_make_keys(const uint32_t* __restrict__ tile, const uint32_t* __restrict__ gid,
@@ -456,7 +461,7 @@ void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const
 bool launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* order, uint2* units, int64_t n_units,
                        hipStream_t st) {
   if (n_tiles < 1) return false;
-  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, n_tiles, order, units, n_units);
+  hipLaunchKernelGGL(k_tile_order, dim3(2), dim3(1024), 0, st, ranges, n_tiles, order, units, n_units);
   return true;
 }
 

@@ -330,7 +330,7 @@ def test_hvp_diag_object_scale_sampled_gaussians():
     s.close()
 
 
-def _long_tile_picks(ob, rng, n_tiles, per_seg, seg=512):
+def _long_tile_picks(ob, rng, n_tiles, per_seg, seg=256):
     """Gaussians from every depth segment of the `n_tiles` longest tile lists
     (segments of `seg` pairs), each touching at most 4 tiles, and the tiles
     they touch."""
@@ -353,7 +353,7 @@ def _long_tile_picks(ob, rng, n_tiles, per_seg, seg=512):
 
 
 def test_vjp_and_hvp_long_tiles_every_depth_segment():
-    """Full object scale: Gaussians from every 512-pair depth segment of the
+    """Full object scale: Gaussians from every 256-pair depth segment of the
     two longest tile lists.  Each segment's backward starts from the
     transmittance and colour the forward (or, for the Hutchinson diagonal,
     the JVP) stored at the segment boundaries, so a wrong state shows up in
@@ -364,7 +364,7 @@ def test_vjp_and_hvp_long_tiles_every_depth_segment():
     x[14:] = sc.gt[14:]
     ob = B.bin_view(x, cam)
     rng = np.random.default_rng(43)
-    pick, tiles, longest = _long_tile_picks(ob, rng, 2, 2)
+    pick, tiles, longest = _long_tile_picks(ob, rng, 2, 1)
     say("long tiles", longest.tolist(), "lists", (ob.ranges[longest, 1] - ob.ranges[longest, 0]).tolist(),
         "Gaussians", len(pick), "tiles", len(tiles))
     xt = torch.tensor(x, dtype=torch.float64)
