@@ -294,6 +294,8 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
         A1 = s.a[j1];
         B1 = s.b[j1];
         C1r = s.c[j1];
+        // keep the reads issued here, ahead of the walk that hides them
+        __builtin_amdgcn_sched_barrier(0);
         walk(A0, B0, C0r, j0);
         if (!bits || __ballot(live) == 0ull) break;
         bits &= bits - 1;
@@ -301,6 +303,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
         A0 = s.a[j0];
         B0 = s.b[j0];
         C0r = s.c[j0];
+        __builtin_amdgcn_sched_barrier(0);
         walk(A1, B1, C1r, j1);
         if (!bits || __ballot(live) == 0ull) break;
       }
