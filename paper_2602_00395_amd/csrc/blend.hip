@@ -390,13 +390,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
     if (i + 64 < range.y) g_next = pair_gid[i + 64];
     uint64_t bits = __ballot(keep);
     wave_lds_sync();
-    while (bits) {
-      if (__ballot(live) == 0ull) break;
-      const int j = __builtin_ctzll(bits);
-      bits &= bits - 1;
+    // one walked splat, j its index in the batch
+    auto walk = [&](const float4 A, const float4 B, const float2 Cc, const float4 TA, const float4 TB,
+                    const float tcj, const int j) {
       if (COUNT) nev += live;
-      const float4 A = s.a[j], B = s.b[j];
-      const float2 Cc = s.c[j];
       const float dx = A.x - pxf, dy = A.y - pyf;
       const float power = splat_power(A.z, A.w, B.x, dx, dy);
       const bool pass = live && power <= 0.f && power >= Cc.y;
@@ -408,7 +405,6 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
       const bool use = pass && !stop;
       live = stop ? 0u : live;
       if (COUNT) ncon += use ? 1u : 0u;
-      const float4 TA = s.ta[j], TB = s.tb[j];
       // d power along the tangent: d = (u - px, v - py), dd = (du, dv); the
       // record holds the pre-scaled conic, the tangent record the plain one
       const float dpow = 2.f * (A.z * dx * TA.x + B.x * dy * TA.y) + A.w * (TA.x * dy + dx * TA.y) -
@@ -421,10 +417,42 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
       C2 += Cc.x * wt;
       D0 += TB.z * wt + B.z * dw;
       D1 += TB.w * wt + B.w * dw;
-      D2 += s.tc[j] * wt + Cc.x * dw;
+      D2 += tcj * wt + Cc.x * dw;
       dT = use ? dT * (1.f - a) - T * da : dT;
       T = use ? Tn : T;
       lastp = use ? start + (uint32_t)j + 1u : lastp;
+    };
+    // as in the forward: each splat's records are read from LDS one step
+    // ahead, into the other of two register sets
+    if (bits) {
+      int j0 = __builtin_ctzll(bits), j1 = 0;
+      float4 A0 = s.a[j0], B0 = s.b[j0], TA0 = s.ta[j0], TB0 = s.tb[j0], A1, B1, TA1, TB1;
+      float2 C0r = s.c[j0], C1r;
+      float t0 = s.tc[j0], t1;
+      while (true) {
+        bits &= bits - 1;
+        j1 = bits ? __builtin_ctzll(bits) : j0;
+        A1 = s.a[j1];
+        B1 = s.b[j1];
+        C1r = s.c[j1];
+        TA1 = s.ta[j1];
+        TB1 = s.tb[j1];
+        t1 = s.tc[j1];
+        __builtin_amdgcn_sched_barrier(0);
+        walk(A0, B0, C0r, TA0, TB0, t0, j0);
+        if (!bits || __ballot(live) == 0ull) break;
+        bits &= bits - 1;
+        j0 = bits ? __builtin_ctzll(bits) : j1;
+        A0 = s.a[j0];
+        B0 = s.b[j0];
+        C0r = s.c[j0];
+        TA0 = s.ta[j0];
+        TB0 = s.tb[j0];
+        t0 = s.tc[j0];
+        __builtin_amdgcn_sched_barrier(0);
+        walk(A1, B1, C1r, TA1, TB1, t1, j1);
+        if (!bits || __ballot(live) == 0ull) break;
+      }
     }
     wave_lds_sync();
   }
@@ -444,24 +472,10 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
 }
 
 // Data-parallel-primitive (DPP) move: lane i reads `v` from the lane selected
-// by CTRL; lanes without a source (or in rows outside ROW_MASK) read 0.
-template <int CTRL, int ROW_MASK = 0xf>
+// by CTRL; lanes without a source read 0.
+template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
-}
-
-// Sum over the 64 lanes of a wave, valid in lane 63: an inclusive scan within
-// each 16-lane row (row_shr 1, 2, 4, 8), then row 0's total into row 1 and
-// row 2's into row 3 (row_bcast:15), then rows 0-1 into rows 2-3
-// (row_bcast:31).  Six VALU operations, no LDS traffic.
-__device__ __forceinline__ float wave_sum_lane63(float v) {
-  v += dpp_move<0x111>(v);
-  v += dpp_move<0x112>(v);
-  v += dpp_move<0x114>(v);
-  v += dpp_move<0x118>(v);
-  v += dpp_move<0x142, 0xa>(v);
-  v += dpp_move<0x143, 0xc>(v);
-  return v;
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 
 // Transposed reduction helpers (gfx950 permlane swaps).  fold32(a, b): lane
@@ -476,12 +490,20 @@ __device__ __forceinline__ float fold16(float a, float b) {
   const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-// Inclusive scan within each 16-lane row: lane 15 of a row holds the row sum.
-__device__ __forceinline__ float row_sum_lane15(float v) {
+// fold8(a, b): within each 16-lane row, lanes 0-7 get a[l] + a[l+8] and
+// lanes 8-15 get b[l-8] + b[l] (a rotation by 8 within the row, then a
+// select on lane bit 3).
+__device__ __forceinline__ float fold8(float a, float b, bool hi8) {
+  const float ra = a + dpp_move<0x128>(a), rb = b + dpp_move<0x128>(b);
+  return hi8 ? rb : ra;
+}
+// Inclusive scan over 8 lanes within each 16-lane row (row_shr 1, 2, 4;
+// lanes shifted in from below the row read 0): lane 7 of a row holds the sum
+// of its lanes 0-7, lane 15 the sum of its lanes 8-15.
+__device__ __forceinline__ float half_row_sum(float v) {
   v += dpp_move<0x111>(v);
   v += dpp_move<0x112>(v);
   v += dpp_move<0x114>(v);
-  v += dpp_move<0x118>(v);
   return v;
 }
 
@@ -569,6 +591,11 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
 #pragma unroll
     for (int k = 0; k < 9; ++k) dst[k] = 0.f;
   }
+  // where this lane's wave sums land in the reduction rows (lanes 7 and 15
+  // of each 16-lane row; see the reduction in the walk)
+  const bool hi8 = (lane & 8) != 0;
+  float* red_w = &s.red[w][0][0];
+  const int red_lane = (((lane >> 4) & 1) * 2 + (lane >> 5) + (hi8 ? 4 : 0)) * kBwdBatch;
   // the wave's own last contribution bounds the splats it walks
   uint32_t wave_end = last;
 #pragma unroll
@@ -640,20 +667,19 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
           gr[8] = wgt * g2;
           acc += wgt * cdot;
           T = use ? Tb : T;
-          // wave sums of the 9 partial derivatives: values 0-7 are folded in
-          // pairs across half-waves and row pairs, leaving value {0,2,1,3} (E)
-          // and {4,6,5,7} (F) summed in lane 15 of rows 0..3; value 8 by a full
-          // DPP reduction into lane 63.  26 VALU instructions in all.
+          // wave sums of the 9 partial derivatives, transposed: values 0-7
+          // are folded in pairs across half-waves, row pairs and half-rows,
+          // leaving in row r value k(r) = {0,2,1,3}[r] in lanes 0-7 and value
+          // 4 + k(r) in lanes 8-15, each then summed into lane 7 and lane 15;
+          // value 8 (folded with zeros) ends summed in lane 7 of row 0.
           if (__ballot(use) != 0ull) {
-            const float E = row_sum_lane15(fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3])));
-            const float F = row_sum_lane15(fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7])));
-            const float H = wave_sum_lane63(gr[8]);
-            if ((lane & 15) == 15) {
-              const int row = lane >> 4;
-              const int k = (row & 1) * 2 + (row >> 1);
-              s.red[w][k][j] = E;
-              s.red[w][4 + k][j] = F;
-              if (lane == 63) s.red[w][8][j] = H;
+            const float E = fold16(fold32(gr[0], gr[1]), fold32(gr[2], gr[3]));
+            const float F = fold16(fold32(gr[4], gr[5]), fold32(gr[6], gr[7]));
+            const float M = half_row_sum(fold8(E, F, hi8));
+            const float H = half_row_sum(fold8(fold16(fold32(gr[8], 0.f), 0.f), 0.f, false));
+            if ((lane & 7) == 7) {
+              red_w[red_lane + j] = M;
+              if (lane == 7) s.red[w][8][j] = H;
             }
           } else {
             reduced &= ~(1ull << hi);
