@@ -133,17 +133,28 @@ __global__ __launch_bounds__(kThreads) void k_rs_upsweep(const uint32_t* __restr
   hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// One workgroup per digit: exclusive scan of hist[d][0..nb) in place.
+// One workgroup per digit: exclusive scan of hist[d][0..nb) in place, 2048
+// entries per round (8 consecutive per thread, all loaded before the scan).
+constexpr int kRsScanPer = 8;
 __global__ __launch_bounds__(kThreads) void k_rs_scan(uint32_t* __restrict__ hist, int nb,
                                                        uint32_t* __restrict__ digit_total) {
   uint32_t* row = hist + (int64_t)blockIdx.x * nb;
   uint32_t running = 0;
-  for (int base = 0; base < nb; base += kThreads) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < nb ? row[i] : 0u;
+  for (int base = 0; base < nb; base += kThreads * kRsScanPer) {
+    const int i0 = base + (int)threadIdx.x * kRsScanPer;
+    uint32_t v[kRsScanPer], s = 0;
+#pragma unroll
+    for (int q = 0; q < kRsScanPer; ++q) {
+      v[q] = i0 + q < nb ? row[i0 + q] : 0u;
+      s += v[q];
+    }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(v, &tot);
-    if (i < nb) row[i] = running + ex;
+    uint32_t r = running + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int q = 0; q < kRsScanPer; ++q) {
+      if (i0 + q < nb) row[i0 + q] = r;
+      r += v[q];
+    }
     running += tot;
   }
   if (threadIdx.x == 0) digit_total[blockIdx.x] = running;
@@ -161,6 +172,17 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
                                                           const uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t cnt[4][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t wbase = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kWaveItems;
+  // the keys and values are read first, so their latency overlaps that of
+  // the digit offsets below
+  uint32_t k[kRsItems], v[kRsItems], rk[kRsItems];
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    const int64_t i = wbase + r * 64 + lane;
+    const bool valid = i < n;
+    k[r] = valid ? keys[i] : 0u;
+    v[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) cnt[q][tid] = 0u;
   uint32_t base;
@@ -170,14 +192,10 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
   }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t wbase = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kWaveItems;
-  uint32_t k[kRsItems], v[kRsItems], rk[kRsItems];
 #pragma unroll
   for (int r = 0; r < kRsItems; ++r) {
     const int64_t i = wbase + r * 64 + lane;
     const bool valid = i < n;
-    k[r] = valid ? keys[i] : 0u;
-    v[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;
     const uint32_t d = (k[r] >> shift) & 0xffu;
     uint64_t same = __ballot(valid);
 #pragma unroll
