@@ -261,14 +261,15 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
     if (i + 64 < range.y) g_next = pair_gid[i + 64];
     uint64_t bits = __ballot(keep);
     wave_lds_sync();
-    // one walked splat, j its index in the batch
-    auto walk = [&](const float4 A, const float4 B, const float2 Cc, const int j) {
-      if (COUNT) nev += live;
+    // one walked splat, j its index in the batch; `valid` false: no splat
+    // (the odd slot of a pair), nothing changes
+    auto walk = [&](const float4 A, const float4 B, const float2 Cc, const int j, const bool valid) {
+      if (COUNT) nev += valid ? live : 0u;
       const float dx = A.x - pxf, dy = A.y - pyf;
       const float power = splat_power(A.z, A.w, B.x, dx, dy);
       // predicated rather than branched: nearly every wave has a lane
       // that contributes, so a branch would only add mask bookkeeping
-      const bool pass = live && power <= 0.f && power >= Cc.y;
+      const bool pass = valid && live && power <= 0.f && power >= Cc.y;
       const float a = fminf(GS3_ALPHA_MAX, B.y * __expf(power));
       const float Tn = T * (1.f - a);
       const bool stop = pass && Tn < GS3_T_STOP;
@@ -282,30 +283,48 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
       T = use ? Tn : T;
       lastp = use ? start + (uint32_t)j + 1u : lastp;
     };
-    // each splat's record is read from LDS one step ahead, into the other of
-    // two register sets; the walk ends early once every pixel has stopped
+    // splats are walked in pairs: both walks of a pair sit in one scheduling
+    // region, so the second's transmittance-free part (offset, power, alpha)
+    // overlaps the first's transmittance update, and the stop test runs once
+    // per pair.  The records of the next pair are read from LDS one pair
+    // ahead, into the other of two register sets.
     if (bits) {
-      int j0 = __builtin_ctzll(bits), j1 = 0;
-      float4 A0 = s.a[j0], B0 = s.b[j0], A1, B1;
-      float2 C0r = s.c[j0], C1r;
+      auto take = [&](int& j, bool& v, int dflt) {
+        v = bits != 0ull;
+        j = v ? __builtin_ctzll(bits) : dflt;
+        bits &= bits - 1;
+      };
+      int j0, j1, j2, j3;
+      bool v0, v1, v2, v3;
+      take(j0, v0, 0);
+      take(j1, v1, j0);
+      float4 A0 = s.a[j0], B0 = s.b[j0], A1 = s.a[j1], B1 = s.b[j1], A2, B2, A3, B3;
+      float2 D0 = s.c[j0], D1 = s.c[j1], D2, D3;
       while (true) {
-        bits &= bits - 1;
-        j1 = bits ? __builtin_ctzll(bits) : j0;
-        A1 = s.a[j1];
-        B1 = s.b[j1];
-        C1r = s.c[j1];
-        // keep the reads issued here, ahead of the walk that hides them
+        take(j2, v2, j1);
+        take(j3, v3, j2);
+        A2 = s.a[j2];
+        B2 = s.b[j2];
+        D2 = s.c[j2];
+        A3 = s.a[j3];
+        B3 = s.b[j3];
+        D3 = s.c[j3];
         __builtin_amdgcn_sched_barrier(0);
-        walk(A0, B0, C0r, j0);
-        if (!bits || __ballot(live) == 0ull) break;
-        bits &= bits - 1;
-        j0 = bits ? __builtin_ctzll(bits) : j1;
+        walk(A0, B0, D0, j0, true);
+        walk(A1, B1, D1, j1, v1);
+        if (!v2 || __ballot(live) == 0ull) break;
+        take(j0, v0, j3);
+        take(j1, v1, j0);
         A0 = s.a[j0];
         B0 = s.b[j0];
-        C0r = s.c[j0];
+        D0 = s.c[j0];
+        A1 = s.a[j1];
+        B1 = s.b[j1];
+        D1 = s.c[j1];
         __builtin_amdgcn_sched_barrier(0);
-        walk(A1, B1, C1r, j1);
-        if (!bits || __ballot(live) == 0ull) break;
+        walk(A2, B2, D2, j2, true);
+        walk(A3, B3, D3, j3, v3);
+        if (!v0 || __ballot(live) == 0ull) break;
       }
     }
     wave_lds_sync();
