@@ -2,10 +2,12 @@
 // argument validation, per-view binning and the orchestration of one
 // optimizer iteration of 3DGS^2-TR (Algorithm 1) on a caller stream.
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -322,6 +324,32 @@ gs3_status check_cam(gs3_scene* s, int32_t cam) {
   return GS3_OK;
 }
 
+// Value of the pinned pair-count word until the scan has written it (a pair
+// count never reaches it: pair indices are 32-bit).
+constexpr uint32_t kCountPending = 0xffffffffu;
+
+// Waits until the scan has written the pinned word: a short busy poll, then
+// polls that yield the thread; after 10 s, or if the stream reports an
+// error, the stream is synchronised and its status returned.
+gs3_status wait_count(volatile uint32_t* word, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t k = 0; *word == kCountPending; ++k) {
+    if ((k & 1023u) == 1023u) {
+      const hipError_t q = hipStreamQuery(st);
+      if (q != hipErrorNotReady && q != hipSuccess) break;
+      if (q == hipSuccess && *word == kCountPending) break;  // stream done, word never written
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(10)) break;
+      if (k > (1u << 16)) std::this_thread::yield();
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  if (*word == kCountPending) {
+    GS3_HIP(hipStreamSynchronize(st));
+    if (*word == kCountPending) return fail(GS3_EDEVICE, "pair count was not written by the scan");
+  }
+  return GS3_OK;
+}
+
 int bits_for(int n_tiles) {
   int b = 1;
   while ((1 << b) < n_tiles) ++b;
@@ -349,12 +377,18 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   prof::end(p1, st);
   auto p2 = prof::begin("scan", st);
   launch_gather_counts(order, s->tiles, N, s->counts, st);
-  scan_exclusive_u32(s->counts, s->offsets, N, s->total_dev, s->stmp, st, s->block_owner, s->owner_blocks);
+  // the scan stores the pair count into a pinned host word as soon as it is
+  // known; the host waits for that word (not for the stream), so the
+  // launches below are queued while the scan's last kernel still runs
+  volatile uint32_t* count_word = s->host_u32;
+  *count_word = kCountPending;
+  std::atomic_thread_fence(std::memory_order_seq_cst);
+  scan_exclusive_u32(s->counts, s->offsets, N, s->total_dev, s->stmp, st, s->block_owner, s->owner_blocks,
+                     s->host_u32);
   prof::end(p2, st);
   GS3_LAUNCHED();
-  GS3_HIP(hipMemcpyAsync(s->host_u32, s->total_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  GS3_HIP(hipStreamSynchronize(st));
-  const int64_t n_pairs = s->host_u32[0];
+  GS3_TRY(wait_count(count_word, st));
+  const int64_t n_pairs = *count_word;
   GS3_TRY(ensure_pairs(s, n_pairs));
   auto p3 = prof::begin("emit_pairs", st);
   launch_emit_pairs(order, s->offsets, s->block_owner, s->owner_blocks, s->rec, s->rect, N, n_pairs, cd.tiles_x,

@@ -110,9 +110,11 @@ void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* 
                     uint32_t** vals_out);
 size_t scan_temp_bytes(int64_t n);
 // owner (nullable): owner[b] = the item whose output range holds element
-// 256 b of the expanded sequence, for b < owner_blocks
+// 256 b of the expanded sequence, for b < owner_blocks.  total_host
+// (nullable): pinned host word that receives the total as soon as it is
+// known (before the last kernel of the scan ends)
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st,
-                        uint32_t* owner = nullptr, int64_t owner_blocks = 0);
+                        uint32_t* owner = nullptr, int64_t owner_blocks = 0, uint32_t* total_host = nullptr);
 void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
                           hipStream_t st);
 // writes each visible Gaussian's pair offset into its record (rec.c.z);

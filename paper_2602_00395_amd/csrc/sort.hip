@@ -74,8 +74,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __rest
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
+// total_host (nullable): pinned host word that also receives the total, with
+// a system-scope store (written through to memory; nothing else needs to be
+// visible with it), so the host can read it while the rest of
+// the scan still runs
 __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ block_sums, int nb,
-                                                        uint32_t* __restrict__ total) {
+                                                        uint32_t* __restrict__ total, uint32_t* total_host) {
   uint32_t running = 0;
   for (int base = 0; base < nb; base += kThreads) {
     const int i = base + threadIdx.x;
@@ -85,7 +89,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bl
     if (i < nb) block_sums[i] = running + ex;
     running += tot;
   }
-  if (threadIdx.x == 0) *total = running;
+  if (threadIdx.x == 0) {
+    *total = running;
+    if (total_host) __hip_atomic_store(total_host, running, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // owner (nullable): for every b < owner_blocks with 256 b inside an item's
@@ -334,48 +341,62 @@ constexpr int kOrderBuckets = 128;
 __device__ __forceinline__ int count_bucket(uint32_t c) {
   return min(kOrderBuckets - 1, (int)(4.f * log2f((float)c + 1.f)));
 }
+// Exclusive scan of the bucket sizes from the longest bucket down, by the
+// first wave (two buckets per lane): cur[b] becomes the number of entries in
+// buckets above b; *total gets the sum.  The caller synchronises.
+__device__ __forceinline__ void scan_buckets_desc(uint32_t* cur, uint32_t* total) {
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    const uint32_t c0 = cur[kOrderBuckets - 1 - 2 * l], c1 = cur[kOrderBuckets - 2 - 2 * l];
+    const uint32_t inc = wave_incl_scan(c0 + c1);
+    const uint32_t ex = inc - (c0 + c1);
+    cur[kOrderBuckets - 1 - 2 * l] = ex;
+    cur[kOrderBuckets - 2 - 2 * l] = ex + c0;
+    if (l == 63) *total = inc;
+  }
+}
 // Workgroup 0 orders the tiles, workgroup 1 the units (independent, so the
-// two run side by side).
+// two run side by side).  The full segments all share one bucket; their
+// counts are summed per wave first, so that bucket takes one LDS atomic per
+// wave instead of one per tile.
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, int n_tiles,
                                                       uint32_t* __restrict__ order, uint2* __restrict__ units,
                                                       int64_t n_units) {
   __shared__ uint32_t cursor[kOrderBuckets];
   __shared__ uint32_t total;
   const bool by_unit = blockIdx.x == 1;
+  const int lane = threadIdx.x & 63;
   if (threadIdx.x < kOrderBuckets) cursor[threadIdx.x] = 0u;
   __syncthreads();
   const int full_bucket = count_bucket(GS3_SEG);
-  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
-    const uint2 r = ranges[i];
+  for (int b0 = 0; b0 < n_tiles; b0 += blockDim.x) {
+    const int i = b0 + (int)threadIdx.x;
+    const uint2 r = i < n_tiles ? ranges[i] : make_uint2(0u, 0u);
     const uint32_t c = r.y - r.x;
     if (!by_unit) {
-      atomicAdd(&cursor[count_bucket(c)], 1u);
+      if (i < n_tiles) atomicAdd(&cursor[count_bucket(c)], 1u);
     } else {
-      if (c >= GS3_SEG) atomicAdd(&cursor[full_bucket], c / GS3_SEG);
+      const uint32_t nfull = wave_incl_scan(c / GS3_SEG);
+      if (lane == 63 && nfull) atomicAdd(&cursor[full_bucket], nfull);
       if (c % GS3_SEG) atomicAdd(&cursor[count_bucket(c % GS3_SEG)], 1u);
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = kOrderBuckets - 1; b >= 0; --b) {
-      const uint32_t c = cursor[b];
-      cursor[b] = run;
-      run += c;
-    }
-    total = run;
-  }
+  scan_buckets_desc(cursor, &total);
   __syncthreads();
-  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
-    const uint2 r = ranges[i];
+  for (int b0 = 0; b0 < n_tiles; b0 += blockDim.x) {
+    const int i = b0 + (int)threadIdx.x;
+    const uint2 r = i < n_tiles ? ranges[i] : make_uint2(0u, 0u);
     const uint32_t c = r.y - r.x, nfull = c / GS3_SEG, rem = c % GS3_SEG;
     if (!by_unit) {
-      order[atomicAdd(&cursor[count_bucket(c)], 1u)] = (uint32_t)i;
+      if (i < n_tiles) order[atomicAdd(&cursor[count_bucket(c)], 1u)] = (uint32_t)i;
     } else {
-      if (nfull) {
-        const uint32_t p = atomicAdd(&cursor[full_bucket], nfull);
-        for (uint32_t m = 0; m < nfull; ++m) units[p + m] = make_uint2((uint32_t)i, m);
-      }
+      // this lane's full segments follow those of the lanes below it
+      const uint32_t inc = wave_incl_scan(nfull);
+      uint32_t p = 0u;
+      if (lane == 63 && inc) p = atomicAdd(&cursor[full_bucket], inc);
+      p = (uint32_t)__shfl((int)p, 63, 64) + inc - nfull;
+      for (uint32_t m = 0; m < nfull; ++m) units[p + m] = make_uint2((uint32_t)i, m);
       if (rem) units[atomicAdd(&cursor[count_bucket(rem)], 1u)] = make_uint2((uint32_t)i, nfull);
     }
   }
@@ -408,15 +429,16 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 size_t scan_temp_bytes(int64_t n) { return (size_t)(nblk(n, kTileItems) + 1) * sizeof(uint32_t); }
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st,
-                        uint32_t* owner, int64_t owner_blocks) {
+                        uint32_t* owner, int64_t owner_blocks, uint32_t* total_host) {
   const int nb = (int)nblk(n, kTileItems);
   uint32_t* sums = (uint32_t*)temp;
   if (n <= 0) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, total, (int64_t)1, 0u);
+    if (total_host) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, total_host, (int64_t)1, 0u);
     return;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, st, in, n, sums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, sums, nb, total);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, sums, nb, total, total_host);
   hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, st, in, out, n, sums, owner, owner_blocks);
 }
 
