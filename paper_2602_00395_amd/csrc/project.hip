@@ -300,7 +300,8 @@ __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x
 // contiguous slots [offsets[i], offsets[i] + counts[i]) of the Gaussian of
 // depth rank i (order[i]): G[order[i]][k], k < 9.  A workgroup takes 28
 // consecutive depth ranks.  Thread (j, k) sums component k of rank j when
-// the rank has at most kSumLong slots, with four interleaved partial sums
+// the rank has at most kSumLong slots, in rounds of 16 loads issued together,
+// with four interleaved partial sums
 // (slot t goes to sum t mod 4 in slot order, combined as (s0 + s1) +
 // (s2 + s3)); a rank
 // with more slots (a splat covering many tiles, which would hold its wave
@@ -336,28 +337,21 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
     if (c <= kSumLong) {
       const float* p = partials + (int64_t)offsets[i] * 9 + k;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-      uint32_t t = 0;
-      for (; t + 8 <= c; t += 8) {
-        const float v0 = p[9 * t], v1 = p[9 * (t + 1)], v2 = p[9 * (t + 2)], v3 = p[9 * (t + 3)];
-        const float v4 = p[9 * (t + 4)], v5 = p[9 * (t + 5)], v6 = p[9 * (t + 6)], v7 = p[9 * (t + 7)];
-        s0 += v0;
-        s1 += v1;
-        s2 += v2;
-        s3 += v3;
-        s0 += v4;
-        s1 += v5;
-        s2 += v6;
-        s3 += v7;
+      // rounds of 16 slots, all loads of a round issued before any is added
+      // (one round for nine Gaussians in ten); slots past c read nothing
+      // and add an exact zero
+      for (uint32_t t = 0; t < c; t += 16) {
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = t + q < c ? p[9 * (t + q)] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; q += 4) {
+          s0 += v[q];
+          s1 += v[q + 1];
+          s2 += v[q + 2];
+          s3 += v[q + 3];
+        }
       }
-      for (; t + 4 <= c; t += 4) {
-        s0 += p[9 * t];
-        s1 += p[9 * (t + 1)];
-        s2 += p[9 * (t + 2)];
-        s3 += p[9 * (t + 3)];
-      }
-      if (t < c) s0 += p[9 * t];
-      if (t + 1 < c) s1 += p[9 * (t + 1)];
-      if (t + 2 < c) s2 += p[9 * (t + 2)];
       G[(int64_t)order[i] * 9 + k] = (s0 + s1) + (s2 + s3);
     } else if (k == 0) {
       atomicOr(&long_ranks, 1u << j);
