@@ -68,15 +68,30 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict
   const int px = blockIdx.x * GS3_TILE + j, py = blockIdx.y * GS3_TILE + i;
   const bool inside = px < W && py < H;
   const int64_t npix = (int64_t)W * H;
-  for (int e = tid; e < HW * HW * 3; e += GS3_BLOCK) {
-    const int r = e / (HW * 3), q = e % (HW * 3);
-    const int qq = q / 3, c = q % 3;
-    const int gx = ox + qq, gy = oy + r;
-    const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
-    const int64_t o = ((int64_t)gy * W + gx) * 3 + c;
-    sx[c][r][qq] = ok ? img[o] : 0.f;
-    sy[c][r][qq] = ok ? tgt[o] : 0.f;
-    if (GN) su[c][r][qq] = ok ? u[o] : 0.f;
+  {
+    // element e = tid + 256 k of the region (row r, column qq, channel c);
+    // 256 = 3 rows of 78 + 22 = 3 rows + 7 columns + 1 channel, so the
+    // indices advance by additions instead of divisions per element
+    int r = tid / (HW * 3), qq = (tid % (HW * 3)) / 3, c = tid % 3;
+    for (int e = tid; e < HW * HW * 3; e += GS3_BLOCK) {
+      const int gx = ox + qq, gy = oy + r;
+      const bool ok = gx >= 0 && gy >= 0 && gx < W && gy < H;
+      const int64_t o = ((int64_t)gy * W + gx) * 3 + c;
+      sx[c][r][qq] = ok ? img[o] : 0.f;
+      sy[c][r][qq] = ok ? tgt[o] : 0.f;
+      if (GN) su[c][r][qq] = ok ? u[o] : 0.f;
+      r += GS3_BLOCK / (HW * 3);
+      qq += (GS3_BLOCK % (HW * 3)) / 3;
+      c += GS3_BLOCK % 3;
+      if (c >= 3) {
+        c -= 3;
+        ++qq;
+      }
+      if (qq >= HW) {
+        qq -= HW;
+        ++r;
+      }
+    }
   }
   __syncthreads();
   double lsum = 0.0;
@@ -135,11 +150,12 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict
     const float sxx = f[2] - A * A, syy = f[3] - B * B, sxy = f[4] - A * B;
     const float n1 = 2.f * A * B + kC1, n2 = 2.f * sxy + kC2;
     const float d1 = A * A + B * B + kC1, d2 = sxx + syy + kC2;
-    const float den = d1 * d2;
-    const float S = (n1 * n2) / den;
-    const float dS_dA = (2.f * B * (n2 - n1) - S * 2.f * A * (d2 - d1)) / den;
-    const float dS_dXX = -S / d2;
-    const float dS_dXY = 2.f * n1 / den;
+    // one division: 1 / d2 = d1 / (d1 d2)
+    const float inv = 1.f / (d1 * d2);
+    const float S = (n1 * n2) * inv;
+    const float dS_dA = (2.f * B * (n2 - n1) - S * 2.f * A * (d2 - d1)) * inv;
+    const float dS_dXX = -S * (d1 * inv);
+    const float dS_dXY = 2.f * n1 * inv;
     float wgt;
     if (GN) {
       const float dS = dS_dA * f[5] + dS_dXX * f[6] + dS_dXY * f[7];
