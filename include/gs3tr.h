@@ -12,8 +12,10 @@
  *   work is enqueued, so GS3_EINVAL leaves the scene untouched.
  * Streams: all work is enqueued on the caller's hipStream_t (NULL = the
  *   default stream).  Functions that must know the number of (Gaussian,
- *   tile) pairs of a view before launching the blend synchronise that stream
- *   once per view; the others are asynchronous.  A scene must not be used
+ *   tile) pairs of a view before launching the blend block the calling
+ *   thread once per view until the stream has run up to that view's pair
+ *   count (a pinned host word written by the binning scan; the stream is
+ *   not drained); the others are asynchronous.  A scene must not be used
  *   from two host threads or two streams at once; different scenes may run
  *   concurrently on different streams.
  * Ownership: a scene owns its device copies of the parameters, the training

@@ -357,7 +357,7 @@ int bits_for(int n_tiles) {
 }
 
 // Project, sort by depth, emit pairs, sort pairs by tile, per-tile ranges.
-// Synchronises `st` once to learn the pair count.
+// Waits once for the pair count (see wait_count), not for the whole stream.
 gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   const CamDev cd = make_cam(s->cams[cam]);
   const int64_t N = s->N;
