@@ -407,6 +407,53 @@ def test_vjp_and_hvp_long_tiles_every_depth_segment():
     assert all(e <= TOL for e in errs.values()), errs
 
 
+def _stacked_tile_scene(L, seed):
+    """Exactly L small, faint Gaussians whose footprints lie inside tile 0 of a
+    32x32 view (so that tile's list holds L pairs and the other tiles none);
+    opacities ~0.1 keep every pixel blending through the whole list, a few
+    opaque ones stop some pixels early."""
+    from synthetic import scenes as S
+
+    cam = syn.make_camera((0.0, -3.0, 0.3), 32, 32)
+    rng = np.random.default_rng(seed)
+    parts, have = [], 0
+    while have < L:
+        x = S.random_scene(rng, 8 * L, 0, -0.9, 0.9, math.log(0.01), 0.2, 0.1)
+        ob = B.bin_view(x, cam)
+        ok = np.flatnonzero((ob.tiles_touched == 1) & (ob.rect[:, 0] == 0) & (ob.rect[:, 1] == 0))
+        parts.append(x[:, ok])
+        have += len(ok)
+    x = np.concatenate(parts, axis=1)[:, :L].copy()
+    x[10] = np.log(0.1 / 0.9) + rng.normal(0.0, 0.3, size=L)
+    x[10, rng.choice(L, size=max(1, L // 64), replace=False)] = 3.0
+    return x.astype(np.float32), cam
+
+
+@pytest.mark.parametrize("L", [256, 257, 512, 513])
+def test_grad_and_hvp_segment_boundaries(L):
+    """A tile list of exactly 256, 257, 512 or 513 pairs: one full depth
+    segment, a full one plus one pair, two full ones, two plus one.  The
+    whole view's gradient and Hutchinson diagonal against the oracle."""
+    x, cam = _stacked_tile_scene(L, 9100 + L)
+    ob = B.bin_view(x, cam)
+    assert int(ob.ranges[0, 1] - ob.ranges[0, 0]) == L
+    targets = offset_targets(x, [cam], 0, seed=9200 + L)
+    s = make_scene(x, targets, [cam], 0)
+    prob = Mth.Problem([cam], targets, 0, lam=0.2)
+    say("segment boundaries: list of", L, "pairs")
+    want, _ = Mth.gradient(x, prob, [0])
+    got = s.grad([0]).cpu().numpy()
+    errs = group_errors(got, want, 14)
+    say("  grad rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    want = Mth.hutchinson(x, prob, [0], 1, 5301)
+    got = s.hvp_diag([0], 1, 5301).cpu().numpy()
+    errs = group_errors(got, want, 14)
+    say("  hvp rel-L2 per group", errs)
+    assert all(e <= TOL for e in errs.values()), errs
+    s.close()
+
+
 def test_tr_step_parity():
     sc = syn.config2_scene(n=4000, n_cams=2, res=64)
     x = sc.gt.astype(np.float32)
