@@ -17,7 +17,8 @@
 // staged in LDS together with, per wave, a bit mask of the splats whose
 // skip test can pass somewhere in its block (the skip ellipse, widened by its
 // float32 rounding, against the block's rectangle of pixel centres), and
-// every wave walks only the set bits.  In the forward and the JVP each wave
+// every wave walks only the set bits (the forward compacts those splats to
+// the front of its slice and walks them in order).  In the forward and the JVP each wave
 // stages its own batches in a private LDS slice and never waits for the
 // other three (they differ in how far their pixels blend); the backward
 // stages per workgroup.  Culled
@@ -203,7 +204,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 struct StageW {
   float4 a[64];
   float4 b[64];
-  float2 c[64];  // b, tau
+  float4 c[64];  // b, tau, 1 + pair index (as bits), unused
 };
 
 template <bool COUNT>
@@ -250,20 +251,27 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
       ++cur;
     }
     const uint32_t i = start + lane;
+    // the splats this wave's block keeps are compacted to the front of its
+    // slice, in pair order, so the walk below steps through consecutive
+    // records with a counter instead of scanning a bit mask
     bool keep = false;
+    Rec r;
     if (i < range.y) {
-      const Rec r = rec[g_next];
-      s.a[lane] = r.a;
-      s.b[lane] = r.b;
-      s.c[lane] = make_float2(r.c.x, r.c.y);
+      r = rec[g_next];
       keep = cull_keep(cull_setup(r.a, r.b, r.c.y, tx, ty), w);
     }
     if (i + 64 < range.y) g_next = pair_gid[i + 64];
-    uint64_t bits = __ballot(keep);
+    const uint64_t kb = __ballot(keep);
+    const int cnt = __builtin_popcountll(kb);
+    if (keep) {
+      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(kb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u));
+      s.a[pos] = r.a;
+      s.b[pos] = r.b;
+      s.c[pos] = make_float4(r.c.x, r.c.y, __uint_as_float(i + 1u), 0.f);
+    }
     wave_lds_sync();
-    // one walked splat, j its index in the batch; `valid` false: no splat
-    // (the odd slot of a pair), nothing changes
-    auto walk = [&](const float4 A, const float4 B, const float2 Cc, const int j, const bool valid) {
+    // one walked splat; `valid` false: no splat (the odd slot of a pair)
+    auto walk = [&](const float4 A, const float4 B, const float4 Cc, const bool valid) {
       if (COUNT) nev += valid ? live : 0u;
       const float dx = A.x - pxf, dy = A.y - pyf;
       const float power = splat_power(A.z, A.w, B.x, dx, dy);
@@ -281,50 +289,42 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
       C1 += B.w * w8;
       C2 += Cc.x * w8;
       T = use ? Tn : T;
-      lastp = use ? start + (uint32_t)j + 1u : lastp;
+      lastp = use ? __float_as_uint(Cc.z) : lastp;
     };
     // splats are walked in pairs: both walks of a pair sit in one scheduling
     // region, so the second's transmittance-free part (offset, power, alpha)
     // overlaps the first's transmittance update, and the stop test runs once
     // per pair.  The records of the next pair are read from LDS one pair
-    // ahead, into the other of two register sets.
-    if (bits) {
-      auto take = [&](int& j, bool& v, int dflt) {
-        v = bits != 0ull;
-        j = v ? __builtin_ctzll(bits) : dflt;
-        bits &= bits - 1;
-      };
-      int j0, j1, j2, j3;
-      bool v0, v1, v2, v3;
-      take(j0, v0, 0);
-      take(j1, v1, j0);
-      float4 A0 = s.a[j0], B0 = s.b[j0], A1 = s.a[j1], B1 = s.b[j1], A2, B2, A3, B3;
-      float2 D0 = s.c[j0], D1 = s.c[j1], D2, D3;
-      while (true) {
-        take(j2, v2, j1);
-        take(j3, v3, j2);
-        A2 = s.a[j2];
-        B2 = s.b[j2];
-        D2 = s.c[j2];
-        A3 = s.a[j3];
-        B3 = s.b[j3];
-        D3 = s.c[j3];
+    // ahead, into the other of two register sets (slots past the count are
+    // read but not used).
+    if (cnt > 0) {
+      float4 A0 = s.a[0], B0 = s.b[0], D0 = s.c[0], A1 = s.a[1], B1 = s.b[1], D1 = s.c[1];
+      float4 A2, B2, D2, A3, B3, D3;
+      for (int j = 0;;) {
+        const int n2 = min(j + 2, 63), n3 = min(j + 3, 63);
+        A2 = s.a[n2];
+        B2 = s.b[n2];
+        D2 = s.c[n2];
+        A3 = s.a[n3];
+        B3 = s.b[n3];
+        D3 = s.c[n3];
         __builtin_amdgcn_sched_barrier(0);
-        walk(A0, B0, D0, j0, true);
-        walk(A1, B1, D1, j1, v1);
-        if (!v2 || __ballot(live) == 0ull) break;
-        take(j0, v0, j3);
-        take(j1, v1, j0);
-        A0 = s.a[j0];
-        B0 = s.b[j0];
-        D0 = s.c[j0];
-        A1 = s.a[j1];
-        B1 = s.b[j1];
-        D1 = s.c[j1];
+        walk(A0, B0, D0, true);
+        walk(A1, B1, D1, j + 1 < cnt);
+        j += 2;
+        if (j >= cnt || __ballot(live) == 0ull) break;
+        const int n0 = min(j + 2, 63), n1 = min(j + 3, 63);
+        A0 = s.a[n0];
+        B0 = s.b[n0];
+        D0 = s.c[n0];
+        A1 = s.a[n1];
+        B1 = s.b[n1];
+        D1 = s.c[n1];
         __builtin_amdgcn_sched_barrier(0);
-        walk(A2, B2, D2, j2, true);
-        walk(A3, B3, D3, j3, v3);
-        if (!v0 || __ballot(live) == 0ull) break;
+        walk(A2, B2, D2, true);
+        walk(A3, B3, D3, j + 1 < cnt);
+        j += 2;
+        if (j >= cnt || __ballot(live) == 0ull) break;
       }
     }
     wave_lds_sync();
