@@ -17,8 +17,8 @@
 // staged in LDS together with, per wave, a bit mask of the splats whose
 // skip test can pass somewhere in its block (the skip ellipse, widened by its
 // float32 rounding, against the block's rectangle of pixel centres), and
-// every wave walks only the set bits (the forward compacts those splats to
-// the front of its slice and walks them in order).  In the forward and the JVP each wave
+// every wave walks only the set bits (the forward and the JVP compact those
+// splats to the front of their slice and walk them in order).  In the forward and the JVP each wave
 // stages its own batches in a private LDS slice and never waits for the
 // other three (they differ in how far their pixels blend); the backward
 // stages per workgroup.  Culled
@@ -295,13 +295,16 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
     // region, so the second's transmittance-free part (offset, power, alpha)
     // overlaps the first's transmittance update, and the stop test runs once
     // per pair.  The records of the next pair are read from LDS one pair
-    // ahead, into the other of two register sets (slots past the count are
-    // read but not used).
+    // ahead, into the other of two register sets.  Every slot read is one
+    // of this batch's records (indices clamped to the count): the idle
+    // second walk of an odd count multiplies its colour by a zero weight,
+    // and a stale slot could hold an infinity.
     if (cnt > 0) {
-      float4 A0 = s.a[0], B0 = s.b[0], D0 = s.c[0], A1 = s.a[1], B1 = s.b[1], D1 = s.c[1];
+      const int f1 = min(1, cnt - 1);
+      float4 A0 = s.a[0], B0 = s.b[0], D0 = s.c[0], A1 = s.a[f1], B1 = s.b[f1], D1 = s.c[f1];
       float4 A2, B2, D2, A3, B3, D3;
       for (int j = 0;;) {
-        const int n2 = min(j + 2, 63), n3 = min(j + 3, 63);
+        const int n2 = min(j + 2, cnt - 1), n3 = min(j + 3, cnt - 1);
         A2 = s.a[n2];
         B2 = s.b[n2];
         D2 = s.c[n2];
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__
         walk(A1, B1, D1, j + 1 < cnt);
         j += 2;
         if (j >= cnt || __ballot(live) == 0ull) break;
-        const int n0 = min(j + 2, 63), n1 = min(j + 3, 63);
+        const int n0 = min(j + 2, cnt - 1), n1 = min(j + 3, cnt - 1);
         A0 = s.a[n0];
         B0 = s.b[n0];
         D0 = s.c[n0];
@@ -349,8 +352,7 @@ struct StageJW {
   float4 b[64];
   float4 ta[64];
   float4 tb[64];
-  float2 c[64];  // b, tau
-  float tc[64];
+  float4 c[64];  // b, tau, tangent of b, 1 + pair index (as bits)
 };
 
 template <bool COUNT>
@@ -394,28 +396,34 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
       ++cur;
     }
     const uint32_t i = start + lane;
+    // kept splats compacted to the front of the slice, as in the forward
     bool keep = false;
+    Rec r;
+    TRec q;
     if (i < range.y) {
-      const Rec r = rec[g_next];
-      const TRec q = trec[g_next];
-      s.a[lane] = r.a;
-      s.b[lane] = r.b;
-      s.c[lane] = make_float2(r.c.x, r.c.y);
-      s.ta[lane] = q.a;
-      s.tb[lane] = q.b;
-      s.tc[lane] = q.c.x;
+      r = rec[g_next];
+      q = trec[g_next];
       keep = cull_keep(cull_setup(r.a, r.b, r.c.y, tx, ty), w);
     }
     if (i + 64 < range.y) g_next = pair_gid[i + 64];
-    uint64_t bits = __ballot(keep);
+    const uint64_t kb = __ballot(keep);
+    const int cnt = __builtin_popcountll(kb);
+    if (keep) {
+      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(kb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u));
+      s.a[pos] = r.a;
+      s.b[pos] = r.b;
+      s.ta[pos] = q.a;
+      s.tb[pos] = q.b;
+      s.c[pos] = make_float4(r.c.x, r.c.y, q.c.x, __uint_as_float(i + 1u));
+    }
     wave_lds_sync();
-    // one walked splat, j its index in the batch
-    auto walk = [&](const float4 A, const float4 B, const float2 Cc, const float4 TA, const float4 TB,
-                    const float tcj, const int j) {
-      if (COUNT) nev += live;
+    // one walked splat; `valid` false: no splat (the odd slot of a pair)
+    auto walk = [&](const float4 A, const float4 B, const float4 Cc, const float4 TA, const float4 TB,
+                    const bool valid) {
+      if (COUNT) nev += valid ? live : 0u;
       const float dx = A.x - pxf, dy = A.y - pyf;
       const float power = splat_power(A.z, A.w, B.x, dx, dy);
-      const bool pass = live && power <= 0.f && power >= Cc.y;
+      const bool pass = valid && live && power <= 0.f && power >= Cc.y;
       const float G = __expf(power);
       const float araw = B.y * G;
       const float a = fminf(GS3_ALPHA_MAX, araw);
@@ -436,41 +444,51 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
       C2 += Cc.x * wt;
       D0 += TB.z * wt + B.z * dw;
       D1 += TB.w * wt + B.w * dw;
-      D2 += tcj * wt + Cc.x * dw;
+      D2 += Cc.z * wt + Cc.x * dw;
       dT = use ? dT * (1.f - a) - T * da : dT;
       T = use ? Tn : T;
-      lastp = use ? start + (uint32_t)j + 1u : lastp;
+      lastp = use ? __float_as_uint(Cc.w) : lastp;
     };
-    // as in the forward: each splat's records are read from LDS one step
-    // ahead, into the other of two register sets
-    if (bits) {
-      int j0 = __builtin_ctzll(bits), j1 = 0;
-      float4 A0 = s.a[j0], B0 = s.b[j0], TA0 = s.ta[j0], TB0 = s.tb[j0], A1, B1, TA1, TB1;
-      float2 C0r = s.c[j0], C1r;
-      float t0 = s.tc[j0], t1;
-      while (true) {
-        bits &= bits - 1;
-        j1 = bits ? __builtin_ctzll(bits) : j0;
-        A1 = s.a[j1];
-        B1 = s.b[j1];
-        C1r = s.c[j1];
-        TA1 = s.ta[j1];
-        TB1 = s.tb[j1];
-        t1 = s.tc[j1];
+    // walked in pairs, the next pair's records read one pair ahead (as in
+    // the forward)
+    if (cnt > 0) {
+      float4 A0 = s.a[0], B0 = s.b[0], D0r = s.c[0], P0 = s.ta[0], Q0 = s.tb[0];
+      const int f1 = min(1, cnt - 1);
+      float4 A1 = s.a[f1], B1 = s.b[f1], D1r = s.c[f1], P1 = s.ta[f1], Q1 = s.tb[f1];
+      float4 A2, B2, D2r, P2, Q2, A3, B3, D3r, P3, Q3;
+      for (int j = 0;;) {
+        const int n2 = min(j + 2, cnt - 1), n3 = min(j + 3, cnt - 1);
+        A2 = s.a[n2];
+        B2 = s.b[n2];
+        D2r = s.c[n2];
+        P2 = s.ta[n2];
+        Q2 = s.tb[n2];
+        A3 = s.a[n3];
+        B3 = s.b[n3];
+        D3r = s.c[n3];
+        P3 = s.ta[n3];
+        Q3 = s.tb[n3];
         __builtin_amdgcn_sched_barrier(0);
-        walk(A0, B0, C0r, TA0, TB0, t0, j0);
-        if (!bits || __ballot(live) == 0ull) break;
-        bits &= bits - 1;
-        j0 = bits ? __builtin_ctzll(bits) : j1;
-        A0 = s.a[j0];
-        B0 = s.b[j0];
-        C0r = s.c[j0];
-        TA0 = s.ta[j0];
-        TB0 = s.tb[j0];
-        t0 = s.tc[j0];
+        walk(A0, B0, D0r, P0, Q0, true);
+        walk(A1, B1, D1r, P1, Q1, j + 1 < cnt);
+        j += 2;
+        if (j >= cnt || __ballot(live) == 0ull) break;
+        const int n0 = min(j + 2, cnt - 1), n1 = min(j + 3, cnt - 1);
+        A0 = s.a[n0];
+        B0 = s.b[n0];
+        D0r = s.c[n0];
+        P0 = s.ta[n0];
+        Q0 = s.tb[n0];
+        A1 = s.a[n1];
+        B1 = s.b[n1];
+        D1r = s.c[n1];
+        P1 = s.ta[n1];
+        Q1 = s.tb[n1];
         __builtin_amdgcn_sched_barrier(0);
-        walk(A1, B1, C1r, TA1, TB1, t1, j1);
-        if (!bits || __ballot(live) == 0ull) break;
+        walk(A2, B2, D2r, P2, Q2, true);
+        walk(A3, B3, D3r, P3, Q3, j + 1 < cnt);
+        j += 2;
+        if (j >= cnt || __ballot(live) == 0ull) break;
       }
     }
     wave_lds_sync();

@@ -143,6 +143,38 @@ def test_render_parity_object_scale_sampled_tiles():
     s.close()
 
 
+def test_render_ignores_stale_lds_contents():
+    """Kernels that leave infinities and NaNs in LDS (block reductions over
+    such a tensor) run right before each render and gradient: the blend
+    kernels' idle walk slots must never read a stale slot, so the image and
+    the gradient stay finite and equal to the ones rendered after clean
+    kernels, bit for bit."""
+    sc = syn.config2_scene()
+    cams = sc.cameras[:2]
+    x = sc.init.astype(np.float32)
+    targets = [np.full((c.height, c.width, 3), 0.5, np.float32) for c in cams]
+    s = make_scene(x, targets, cams, 3)
+    ref_img = s.render(0).clone()
+    ref_g = s.grad([1]).clone()
+    junk = torch.full((1 << 22,), float("inf"), device=DEV)
+    junk[::7] = float("nan")
+    junk[::11] = -float("inf")
+    for rep in range(3):
+        say("stale LDS: repeat", rep)
+        for _ in range(4):
+            junk.sum()
+            junk.cumsum(0)
+        img = s.render(0)
+        for _ in range(4):
+            junk.sum()
+            junk.cumsum(0)
+        g = s.grad([1])
+        torch.cuda.synchronize()
+        assert torch.isfinite(img).all() and torch.isfinite(g).all()
+        assert torch.equal(img, ref_img) and torch.equal(g, ref_g)
+    s.close()
+
+
 @pytest.mark.parametrize("lam", [0.2, 0.0])
 def test_grad_parity_config1(c1, lam):
     sc, x, targets = c1
