@@ -398,11 +398,17 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
     const uint32_t i = start + lane;
     // kept splats compacted to the front of the slice, as in the forward
     bool keep = false;
-    Rec r;
-    TRec q;
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, qa = ra, qb = ra;
+    float qc = 0.f;
     if (i < range.y) {
-      r = rec[g_next];
-      q = trec[g_next];
+      const Rec r = rec[g_next];
+      const TRec q = trec[g_next];
+      ra = r.a;
+      rb = r.b;
+      rc = r.c;
+      qa = q.a;
+      qb = q.b;
+      qc = q.c.x;
       keep = cull_keep(cull_setup(r.a, r.b, r.c.y, tx, ty), w);
     }
     if (i + 64 < range.y) g_next = pair_gid[i + 64];
@@ -410,11 +416,11 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__
     const int cnt = __builtin_popcountll(kb);
     if (keep) {
       const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(kb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u));
-      s.a[pos] = r.a;
-      s.b[pos] = r.b;
-      s.ta[pos] = q.a;
-      s.tb[pos] = q.b;
-      s.c[pos] = make_float4(r.c.x, r.c.y, q.c.x, __uint_as_float(i + 1u));
+      s.a[pos] = ra;
+      s.b[pos] = rb;
+      s.ta[pos] = qa;
+      s.tb[pos] = qb;
+      s.c[pos] = make_float4(rc.x, rc.y, qc, __uint_as_float(i + 1u));
     }
     wave_lds_sync();
     // one walked splat; `valid` false: no splat (the odd slot of a pair)
