@@ -1,6 +1,8 @@
 // Parameter updates for gfx950: the trust-region step of Algorithm 1 and the
 // Adam baseline (optionally clipped by the same trust region, ADAM-TR).  The
 // radius and the row update are in gs3_trust.h.
+#include <type_traits>
+
 #include "gs3_trust.h"
 
 namespace {
@@ -29,16 +31,27 @@ __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const fl
   if (live) rad = trust_radius(x, n, g, a.epsilon, a.variant, degree_of_rows(P));
   __syncthreads();
   if (!live) return;
+  // the wave's rows as compile-time indices, so the radius components stay
+  // in registers (a run-time row index would place them in private memory)
+  auto rows = [&](auto wave) {
+    constexpr int W = decltype(wave)::value;
 #pragma unroll
-  for (int rr = 0; rr < R; ++rr) {
-    const int r = r0 + rr;
-    if (r >= P) break;
-    const int64_t k = (int64_t)r * n + g;
-    const float eta = row_radius(rad, r);
-    const float step = tr_update(ghat, dhat, D, k, grad[k], eta, a);
-    x[k] += step;
-    if (eta_out) eta_out[k] = eta;
-    if (dx_out) dx_out[k] = step;
+    for (int rr = 0; rr < R; ++rr) {
+      const int r = W * R + rr;
+      if (r >= P) break;
+      const int64_t k = (int64_t)r * n + g;
+      const float eta = row_radius(rad, r);
+      const float step = tr_update(ghat, dhat, D, k, grad[k], eta, a);
+      x[k] += step;
+      if (eta_out) eta_out[k] = eta;
+      if (dx_out) dx_out[k] = step;
+    }
+  };
+  switch (r0 / R) {
+    case 0: rows(std::integral_constant<int, 0>{}); break;
+    case 1: rows(std::integral_constant<int, 1>{}); break;
+    case 2: rows(std::integral_constant<int, 2>{}); break;
+    default: rows(std::integral_constant<int, 3>{}); break;
   }
 }
 
@@ -57,22 +70,32 @@ __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const 
     __syncthreads();
   }
   if (!live) return;
+  // compile-time rows per wave, as in the trust-region step
+  auto rows = [&](auto wave) {
+    constexpr int W = decltype(wave)::value;
 #pragma unroll
-  for (int rr = 0; rr < R; ++rr) {
-    const int r = r0 + rr;
-    if (r >= P) break;
-    const int64_t k = (int64_t)r * n + g;
-    const float gr = grad[k];
-    const float mm = a.b1 * m[k] + (1.f - a.b1) * gr;
-    const float vv = a.b2 * v[k] + (1.f - a.b2) * gr * gr;
-    m[k] = mm;
-    v[k] = vv;
-    float step = -a.lr_row[r] * (mm / a.bc1) / (sqrtf(vv / a.bc2) + a.eps);
-    if (clip) {
-      const float eta = row_radius(rad, r);
-      step = fminf(fmaxf(step, -eta), eta);
+    for (int rr = 0; rr < R; ++rr) {
+      const int r = W * R + rr;
+      if (r >= P) break;
+      const int64_t k = (int64_t)r * n + g;
+      const float gr = grad[k];
+      const float mm = a.b1 * m[k] + (1.f - a.b1) * gr;
+      const float vv = a.b2 * v[k] + (1.f - a.b2) * gr * gr;
+      m[k] = mm;
+      v[k] = vv;
+      float step = -a.lr_row[r] * (mm / a.bc1) / (sqrtf(vv / a.bc2) + a.eps);
+      if (clip) {
+        const float eta = row_radius(rad, r);
+        step = fminf(fmaxf(step, -eta), eta);
+      }
+      x[k] += step;
     }
-    x[k] += step;
+  };
+  switch (r0 / R) {
+    case 0: rows(std::integral_constant<int, 0>{}); break;
+    case 1: rows(std::integral_constant<int, 1>{}); break;
+    case 2: rows(std::integral_constant<int, 2>{}); break;
+    default: rows(std::integral_constant<int, 3>{}); break;
   }
 }
 
