@@ -38,6 +38,19 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Output tile of this workgroup on a gx-wide grid of nt tiles.  Workgroups
+// go to the 8 XCDs round robin and each XCD has its own L2, so workgroup b
+// takes tile (b mod 8) ceil(nt / 8) + b / 8: every XCD works through one
+// contiguous band of tiles and neighbouring tiles read their shared halo
+// rows through the same L2.  False for the padding workgroups past nt.
+__device__ __forceinline__ bool ssim_tile(int gx, int nt, int& bx, int& by, int& t) {
+  const int per = (nt + 7) / 8;
+  t = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  bx = t % gx;
+  by = t / gx;
+  return t < nt;
+}
+
 __device__ __forceinline__ double block_sum_d(double v) {
   __shared__ double ws[4];
 #pragma unroll
@@ -58,14 +71,16 @@ template <bool GN>
 __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict__ img, const float* __restrict__ tgt,
                                                           const float* __restrict__ u, int W, int H, float lam,
                                                           float scale, Win win, float* __restrict__ coef,
-                                                          double* __restrict__ loss_partials) {
+                                                          double* __restrict__ loss_partials, int gx, int nt) {
+  int bx, by, t;
+  if (!ssim_tile(gx, nt, bx, by, t)) return;
   __shared__ float sx[3][HW][HW + 1], sy[3][HW][HW + 1], su[GN ? 3 : 1][GN ? HW : 1][HW + 1];
   constexpr int NM = GN ? 8 : 5;
   __shared__ float hb[NM][HW][GS3_TILE];
   const int tid = threadIdx.x;
-  const int ox = blockIdx.x * GS3_TILE - R, oy = blockIdx.y * GS3_TILE - R;
+  const int ox = bx * GS3_TILE - R, oy = by * GS3_TILE - R;
   const int i = tid >> 4, j = tid & 15;
-  const int px = blockIdx.x * GS3_TILE + j, py = blockIdx.y * GS3_TILE + i;
+  const int px = bx * GS3_TILE + j, py = by * GS3_TILE + i;
   const bool inside = px < W && py < H;
   const int64_t npix = (int64_t)W * H;
   {
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_coef(const float* __restrict
   }
   if (!GN) {
     const double tot = block_sum_d(lsum);
-    if (tid == 0) loss_partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (tid == 0) loss_partials[t] = tot;
   }
 }
 
@@ -188,13 +203,16 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_ssim_combine(const float* __restr
                                                              const float* __restrict__ tgt,
                                                              const float* __restrict__ u,
                                                              const float* __restrict__ coef, int W, int H, float lam,
-                                                             float scale, Win win, float* __restrict__ cot) {
+                                                             float scale, Win win, float* __restrict__ cot, int gx,
+                                                             int nt) {
+  int bx, by, t;
+  if (!ssim_tile(gx, nt, bx, by, t)) return;
   __shared__ float sc[3][HW][HW + 1];
   __shared__ float hb[3][HW][GS3_TILE];
   const int tid = threadIdx.x;
-  const int ox = blockIdx.x * GS3_TILE - R, oy = blockIdx.y * GS3_TILE - R;
+  const int ox = bx * GS3_TILE - R, oy = by * GS3_TILE - R;
   const int i = tid >> 4, j = tid & 15;
-  const int px = blockIdx.x * GS3_TILE + j, py = blockIdx.y * GS3_TILE + i;
+  const int px = bx * GS3_TILE + j, py = by * GS3_TILE + i;
   const bool inside = px < W && py < H;
   const int64_t npix = (int64_t)W * H;
   const int64_t o3 = ((int64_t)py * W + px) * 3;
@@ -339,13 +357,14 @@ void launch_loss_grad(const float* img, const float* tgt, int w, int h, float la
     *n_partials = (int)nb;
     return;
   }
-  const dim3 grid((w + GS3_TILE - 1) / GS3_TILE, (h + GS3_TILE - 1) / GS3_TILE);
+  const int gx = (w + GS3_TILE - 1) / GS3_TILE, nt = gx * ((h + GS3_TILE - 1) / GS3_TILE);
+  const dim3 grid((unsigned)(8 * ((nt + 7) / 8)));
   const Win win = make_window();
   hipLaunchKernelGGL(k_ssim_coef<false>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, nullptr, w, h, lam, scale, win,
-                     ssim_tmp, loss_partials);
+                     ssim_tmp, loss_partials, gx, nt);
   hipLaunchKernelGGL(k_ssim_combine<false>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, nullptr, ssim_tmp, w, h, lam,
-                     scale, win, cot);
-  *n_partials = (int)(grid.x * grid.y);
+                     scale, win, cot, gx, nt);
+  *n_partials = nt;
 }
 
 void launch_loss_gn(const float* img, const float* tgt, const float* u, int w, int h, float lam, float scale,
@@ -356,12 +375,13 @@ void launch_loss_gn(const float* img, const float* tgt, const float* u, int w, i
                        cot, nullptr);
     return;
   }
-  const dim3 grid((w + GS3_TILE - 1) / GS3_TILE, (h + GS3_TILE - 1) / GS3_TILE);
+  const int gx = (w + GS3_TILE - 1) / GS3_TILE, nt = gx * ((h + GS3_TILE - 1) / GS3_TILE);
+  const dim3 grid((unsigned)(8 * ((nt + 7) / 8)));
   const Win win = make_window();
   hipLaunchKernelGGL(k_ssim_coef<true>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, u, w, h, lam, scale, win, ssim_tmp,
-                     nullptr);
+                     nullptr, gx, nt);
   hipLaunchKernelGGL(k_ssim_combine<true>, grid, dim3(GS3_BLOCK), 0, st, img, tgt, u, ssim_tmp, w, h, lam, scale,
-                     win, cot);
+                     win, cot, gx, nt);
 }
 
 void launch_sq_err(const float* img, const float* tgt, int64_t n, double* partials, int* n_partials, hipStream_t st) {
