@@ -18,7 +18,8 @@ Layout (each module cites the paper passages it follows):
   (Eq. pixel_loss) and the least-squares objective (Eq. objective).
 * ``method``    -- stochastic gradient, Gauss-Newton HVP, Hutchinson estimate,
   squared Hellinger distance, the trust-region radius SHD, the TR step of
-  Algorithm 1, the Adam baseline, the epsilon schedule and PSNR.
+  Algorithm 1, Algorithm 1 as a plain loop over t (``run_tr``), the Adam
+  baseline, the epsilon schedule and PSNR.
 
 Parity status of each function is listed in its docstring; every function has
 at least one pin in ``tests/test_oracle_*.py`` except those marked

@@ -6,7 +6,9 @@ Paper passages followed (section / equation / algorithm):
   (1/m)(M/|S1|); EMA of g with theta1; Hutchinson estimate D_t with the scale
   (1/m)(M/|S2|)(1/nu) and Rademacher probes; EMA of D with theta2 on every
   l-th iteration; step -D^-1 g; parameter-wise clip by eta = SHD(x, eps).
-* Algorithm 1 for the order of the steps.
+* Algorithm 1 for the order of the steps; ``run_tr`` is the algorithm as a
+  plain loop over t = 1..T (pinned on a separable quadratic, where the
+  Gauss-Newton matrix and the EMAs have closed forms).
 * Background, Eq. objective: J is the Jacobian of F = sqrt(loss components),
   so J^T F = 1/2 grad(sum of components) and J^T J z is formed from an image
   JVP, the loss Jacobian and an image VJP (Gauss-Newton).
@@ -392,3 +394,60 @@ def adam_step(x, g, m, v, step: int, lrs: dict, sh_degree: int, b1=0.9, b2=0.999
         rr = list(rr)
         x[rr] -= lrs[name] * mhat[rr] / (np.sqrt(vhat[rr]) + eps)
     return x, m, v
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 as a plain loop
+
+
+def run_tr(x1, T: int, grad_fn, hutch_fn, eta_fn, l: int = 10, theta1: float = 0.9, theta2: float = 0.999,
+           eps0: float = 1e-6, eps1: float = 1e-8, keep_x: bool = True):
+    """Algorithm 1 for t = 1..T, with the iteration's pieces passed in.
+
+    grad_fn(x, t)  -> g_t, the stochastic gradient on iteration t's batch S1;
+    hutch_fn(x, t) -> D_t = Hutch(x_t, S2, nu) on iteration t's batch S2,
+                      called only on Hutchinson iterations, (t - 1) mod l = 0;
+    eta_fn(x, eps) -> eta = SHD(x, eps) at the current parameters.
+    The budget of iteration t is eps_schedule(t, T, eps0, eps1) (the
+    evaluation's decay of epsilon over the run).  Both EMAs start at zero and
+    are not bias-corrected; on other iterations Dhat is kept.
+
+    Returns (x_{T+1}, ghat_T, Dhat_T, log): one record per iteration with t,
+    eps, whether it was a Hutchinson iteration, copies of x_{t+1}, ghat_t,
+    Dhat_t and the clipped step (x_{t+1} only when keep_x), and the step's
+    diagnostics: the share of coordinates whose step was clipped to the
+    radius, the share taking the rule for Dhat <= 0, and the step norm.
+    """
+    x = np.asarray(x1, np.float64).copy()
+    ghat = np.zeros_like(x)
+    Dhat = np.zeros_like(x)
+    log = []
+    for t in range(1, T + 1):
+        eps = eps_schedule(t, T, eps0, eps1)
+        g = np.asarray(grad_fn(x, t), np.float64)
+        D = np.asarray(hutch_fn(x, t), np.float64) if is_hutchinson_step(t, l) else None
+        eta = np.asarray(eta_fn(x, eps), np.float64)
+        x_next, ghat, Dhat, dx_hat, _ = tr_step(x, g, ghat, Dhat, D, theta1, theta2, eps, 0, eta=eta)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            newton = -ghat / Dhat
+            curved = (Dhat > 0) & np.isfinite(Dhat) & np.isfinite(newton)
+            clipped = curved & (np.abs(newton) > eta)
+        log.append(dict(t=t, eps=eps, hutch=D is not None, x=x_next.copy() if keep_x else None, ghat=ghat.copy(),
+                        Dhat=Dhat.copy(), dx=dx_hat.copy(), clipped=float(clipped.mean()),
+                        nonpos=float((~curved).mean()), step_norm=float(np.linalg.norm(dx_hat))))
+        x = x_next
+    return x, ghat, Dhat, log
+
+
+def run_tr_problem(x1, prob: Problem, T: int, S1s, S2s, nu: int, seeds, l: int = 10, theta1: float = 0.9,
+                   theta2: float = 0.999, eps0: float = 1e-6, eps1: float = 1e-8, mean_bound: str = "printed",
+                   constants: str = "printed", sh_rest: str = "base"):
+    """run_tr on the objective of Eq. objective: S1s[t-1] and S2s[t-1] are
+    iteration t's image batches, seeds[t-1] its probe seed (only Hutchinson
+    iterations use S2 and the seed)."""
+    return run_tr(x1, T,
+                  lambda x, t: gradient(x, prob, S1s[t - 1])[0],
+                  lambda x, t: hutchinson(x, prob, S2s[t - 1], nu, seeds[t - 1]),
+                  lambda x, eps: shd_eta(x, eps, prob.sh_degree, mean_bound=mean_bound, constants=constants,
+                                         sh_rest=sh_rest),
+                  l=l, theta1=theta1, theta2=theta2, eps0=eps0, eps1=eps1)

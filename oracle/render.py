@@ -160,3 +160,65 @@ def decisions_equal(d1: dict, d2: dict) -> bool:
             if not torch.equal(a, b):
                 return False
     return True
+
+
+def decision_flips(x, cam, sh_degree: int, bins: Bins | None = None, tiles=None) -> dict:
+    """How many blend decisions float32 arithmetic takes differently from
+    exact float64 arithmetic on one view (a report beside a parity figure;
+    the render itself takes the skip decision in float32, see above).
+
+    skip:  the float32 log-domain rule (``binning.contributes_f32``) against
+           power <= 0 and alpha exp(power) >= 1/255 from the float64 splat;
+    clamp: float32 alpha exp(power) >= 0.99 against float64;
+    stop:  the index where a pixel's walk stops, float32 transmittance and
+           opacities against float64.
+    skip and clamp count (pixel, splat) evaluations up to the pixel's float64
+    stop (the splat that stops the walk included); stop counts pixels.  ``evaluations`` and ``pixels`` are the totals.
+    """
+    x = torch.as_tensor(np.asarray(x, np.float64))
+    if bins is None:
+        bins = bin_view(x.numpy().astype(np.float32), cam)
+    with torch.no_grad():
+        pr = project(x, cam, sh_degree)
+    u, v = pr["u"].numpy(), pr["v"].numpy()
+    con = pr["conic"].numpy()
+    alpha = pr["alpha"].numpy()
+    f32 = np.float32
+    out = dict(skip=0, clamp=0, stop=0, evaluations=0, pixels=0)
+    H, Wd = cam.height, cam.width
+    for t in range(bins.tiles_x * bins.tiles_y):
+        if tiles is not None and t not in tiles:
+            continue
+        gids = bins.tile_list(t)
+        if len(gids) == 0:
+            continue
+        ty, tx = divmod(t, bins.tiles_x)
+        gy, gx = np.meshgrid(np.arange(ty * TILE, min((ty + 1) * TILE, H)) + 0.5,
+                             np.arange(tx * TILE, min((tx + 1) * TILE, Wd)) + 0.5, indexing="ij")
+        px, py = gx.reshape(-1, 1), gy.reshape(-1, 1)
+        dx, dy = u[gids][None, :] - px, v[gids][None, :] - py
+        p64 = -0.5 * (con[gids, 0][None, :] * dx * dx + con[gids, 2][None, :] * dy * dy) - con[gids, 1][None, :] * dx * dy
+        a64 = alpha[gids][None, :] * np.exp(p64)
+        valid64 = (p64 <= 0) & (a64 >= 1.0 / 255.0)
+        valid32 = contributes_f32(bins.dec, gids, gx.reshape(-1), gy.reshape(-1))
+        from .binning import power_f32
+
+        with np.errstate(all="ignore"):
+            p32 = power_f32(bins.dec, gids, gx.reshape(-1), gy.reshape(-1))
+            al32 = alpha[gids].astype(f32)[None, :]
+            a32 = al32 * np.exp(p32)
+        ab64 = np.where(valid64, np.minimum(a64, ALPHA_MAX), 0.0)
+        ab32 = np.where(valid32, np.minimum(a32, f32(ALPHA_MAX)), f32(0.0)).astype(f32)
+        T64 = np.cumprod(1.0 - ab64, axis=1)
+        T32 = np.cumprod((f32(1.0) - ab32).astype(f32), axis=1, dtype=f32)
+        L = len(gids)
+        stop64 = np.where((T64 < T_STOP).any(1), (T64 < T_STOP).argmax(1), L)
+        stop32 = np.where((T32 < f32(T_STOP)).any(1), (T32 < f32(T_STOP)).argmax(1), L)
+        before = np.arange(L)[None, :] <= stop64[:, None]  # the stopping splat is evaluated too
+        out["skip"] += int(((valid64 != valid32) & before).sum())
+        both = valid64 & valid32 & before
+        out["clamp"] += int(((a64 >= ALPHA_MAX) != (a32 >= f32(ALPHA_MAX)))[both].sum())
+        out["stop"] += int((stop64 != stop32).sum())
+        out["evaluations"] += int(before.sum())
+        out["pixels"] += int(px.shape[0])
+    return out

@@ -497,3 +497,116 @@ def test_joint_sh_radius_bounds_the_colour_change():
         worst = (np.abs(Y[:, 1:]) * rest[None, :]).sum(1)
         assert worst.max() <= eta_c * (1 + 1e-9)
         assert worst.max() >= 0.999 * eta_c
+
+
+def test_adam_group_map_matches_torch_optim_with_six_groups():
+    # one learning rate per 3DGS parameter group, all different: the rows of
+    # each group are taken from the layout's named views, not from the
+    # oracle's row table, and torch's Adam updates each group separately
+    rng = np.random.default_rng(12)
+    deg = 2
+    x0 = rng.normal(size=(G.n_params(deg), 7))
+    lrs = dict(mu=1.3e-3, f_dc=2.9e-3, f_rest=3.7e-4, opacity=5.3e-2, scale=7.1e-3, rot=1.1e-2)
+    views = G.split(torch.tensor(x0), deg)
+    named = dict(mu=views["mu"], scale=views["log_s"], rot=views["quat"], opacity=views["logit"],
+                 f_dc=views["sh"][:, 0, :], f_rest=views["sh"][:, 1:, :])
+    params = {k: torch.nn.Parameter(v.clone()) for k, v in named.items()}
+    opt = torch.optim.Adam([dict(params=[params[k]], lr=lrs[k]) for k in Mth.ADAM_GROUPS], betas=(0.9, 0.999),
+                           eps=1e-15)
+    x, m, v = x0.copy(), np.zeros_like(x0), np.zeros_like(x0)
+    for step in range(1, 6):
+        g = rng.normal(size=x0.shape)
+        gv = G.split(torch.tensor(g), deg)
+        gnamed = dict(mu=gv["mu"], scale=gv["log_s"], rot=gv["quat"], opacity=gv["logit"], f_dc=gv["sh"][:, 0, :],
+                      f_rest=gv["sh"][:, 1:, :])
+        for k in params:
+            params[k].grad = gnamed[k].clone()
+        opt.step()
+        x, m, v = Mth.adam_step(x, g, m, v, step, lrs, deg)
+    xv = G.split(torch.tensor(x), deg)
+    got = dict(mu=xv["mu"], scale=xv["log_s"], rot=xv["quat"], opacity=xv["logit"], f_dc=xv["sh"][:, 0, :],
+               f_rest=xv["sh"][:, 1:, :])
+    for k in params:
+        assert np.allclose(got[k].numpy(), params[k].detach().numpy(), rtol=1e-12, atol=1e-15), k
+    # every row moved by its own group's rate (the groups are told apart)
+    assert len(set(lrs.values())) == 6
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 as a loop: pinned on a separable quadratic, where the
+# Gauss-Newton matrix is diagonal and known, so every Rademacher probe gives
+# z (.) H z = diag(H) exactly
+
+
+def _quadratic(rng, shape):
+    d = rng.uniform(0.5, 3.0, size=shape)
+    c = rng.normal(size=shape)
+    grad = lambda x, t: d * (x - c)  # noqa: E731
+    # Hutchinson on H = diag(d): z (.) (H z) with a probe of the oracle's generator
+    hutch = lambda x, t: Mth.probe(77, t, *shape) * (d * Mth.probe(77, t, *shape))  # noqa: E731
+    return d, c, grad, hutch
+
+
+def test_run_tr_one_newton_step_solves_a_quadratic():
+    # theta1 = theta2 = 0, l = 1 and no radius: the plain diagonal Gauss-Newton
+    # (here Newton) step, which lands on the minimum of a separable quadratic
+    rng = np.random.default_rng(20)
+    d, c, grad, hutch = _quadratic(rng, (4, 6))
+    x1 = rng.normal(size=(4, 6))
+    inf = lambda x, eps: np.full(x.shape, np.inf)  # noqa: E731
+    x, gh, Dh, log = Mth.run_tr(x1, 3, grad, hutch, inf, l=1, theta1=0.0, theta2=0.0)
+    assert np.allclose(log[0]["x"], c, rtol=0, atol=1e-14)
+    assert np.allclose(x, c, atol=1e-14) and np.allclose(Dh, d)
+    assert all(r["hutch"] for r in log)
+
+
+def test_run_tr_emas_and_schedule_on_frozen_parameters():
+    # a zero radius freezes x, so g_t is constant: the EMAs are geometric sums,
+    # ghat_t = (1 - theta1^t) g and, after k Hutchinson iterations,
+    # Dhat = (1 - theta2^k) diag(H); Hutchinson runs at t = 1, 1 + l, 1 + 2l, ...
+    rng = np.random.default_rng(21)
+    d, c, grad, hutch = _quadratic(rng, (3, 5))
+    x1 = rng.normal(size=(3, 5))
+    seen_eps = []
+
+    def zero(x, eps):
+        seen_eps.append(eps)
+        return np.zeros(x.shape)
+
+    T, l, th1, th2 = 23, 10, 0.9, 0.999
+    x, gh, Dh, log = Mth.run_tr(x1, T, grad, hutch, zero, l=l, theta1=th1, theta2=th2)
+    g = d * (x1 - c)
+    assert np.array_equal(x, x1)
+    assert [r["t"] for r in log if r["hutch"]] == [1, 11, 21]
+    for r in log:
+        k = (r["t"] - 1) // l + 1
+        assert np.allclose(r["ghat"], (1 - th1 ** r["t"]) * g, rtol=1e-12)
+        assert np.allclose(r["Dhat"], (1 - th2 ** k) * d, rtol=1e-12)
+        assert np.all(r["dx"] == 0)
+    # epsilon: 1e-6 at t = 1, 1e-8 at t = T, a constant ratio in between
+    assert seen_eps[0] == pytest.approx(1e-6, rel=1e-14) and seen_eps[-1] == pytest.approx(1e-8, rel=1e-14)
+    ratios = np.array(seen_eps[1:]) / np.array(seen_eps[:-1])
+    assert np.allclose(ratios, (1e-2) ** (1.0 / (T - 1)), rtol=1e-12)
+
+
+def test_run_tr_clips_to_the_radius_and_reports_it():
+    rng = np.random.default_rng(22)
+    d, c, grad, hutch = _quadratic(rng, (2, 50))
+    x1 = c + rng.choice([-1.0, 1.0], size=c.shape)  # every Newton step has size 1
+    eta = lambda x, eps: np.full(x.shape, 0.25)  # noqa: E731
+    x, gh, Dh, log = Mth.run_tr(x1, 2, grad, hutch, eta, l=1, theta1=0.0, theta2=0.0)
+    assert np.allclose(np.abs(log[0]["dx"]), 0.25) and log[0]["clipped"] == 1.0 and log[0]["nonpos"] == 0.0
+    assert np.allclose(np.abs(x - c), 0.5)
+
+
+def test_run_tr_on_the_objective_matches_its_first_step():
+    # the driver on the real objective: iteration 1 is the tr_step of the
+    # gradient and Hutchinson estimate at x_1 with eps_1 = 1e-6
+    x, prob = tiny_problem(seed=5, n=4, sh_degree=0, size=16)
+    S1s, S2s, seeds = [[0], [1]], [[1], [0]], [9, 10]
+    xT, gh, Dh, log = Mth.run_tr_problem(x, prob, 2, S1s, S2s, 2, seeds, l=1)
+    g1, _ = Mth.gradient(x, prob, [0])
+    D1 = Mth.hutchinson(x, prob, [1], 2, 9)
+    x2, _, _, dx, _ = Mth.tr_step(x, g1, np.zeros_like(x), np.zeros_like(x), D1, 0.9, 0.999, 1e-6, 0)
+    assert np.allclose(log[0]["x"], x2, rtol=0, atol=1e-15) and np.allclose(log[0]["dx"], dx, atol=1e-15)
+    assert log[1]["eps"] == pytest.approx(1e-8) and log[1]["hutch"]

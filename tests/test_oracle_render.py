@@ -125,3 +125,76 @@ def test_empty_tiles_give_background():
     img = R.render(torch.tensor(x, dtype=torch.float64), cam, 0, background=(0.1, 0.2, 0.3))
     assert np.allclose(img[0, 0].numpy(), [0.1, 0.2, 0.3])
     assert np.allclose(img[63, 63].numpy(), [0.1, 0.2, 0.3])
+
+
+def _brute_flips(x, cam, bins, tiles):
+    """The flip report taken literally: one pixel and one splat at a time."""
+    pr = R.project(torch.tensor(x), cam, 0)
+    f32 = np.float32
+    want = dict(skip=0, clamp=0, stop=0, evaluations=0, pixels=0)
+    d = bins.dec
+    for t in tiles:
+        gids = bins.tile_list(t)
+        if len(gids) == 0:
+            continue
+        ty, tx = divmod(t, bins.tiles_x)
+        for i in range(16 * ty, min(16 * ty + 16, cam.height)):
+            for j in range(16 * tx, min(16 * tx + 16, cam.width)):
+                want["pixels"] += 1
+                T64, T32, s64, s32 = 1.0, f32(1.0), None, None
+                for k, g in enumerate(gids):
+                    dx, dy = float(pr["u"][g]) - (j + 0.5), float(pr["v"][g]) - (i + 0.5)
+                    ca, cb, cc = (float(c) for c in pr["conic"][g])
+                    p64 = -0.5 * (ca * dx * dx + cc * dy * dy) - cb * dx * dy
+                    a64 = float(pr["alpha"][g]) * math.exp(p64)
+                    v64 = p64 <= 0 and a64 >= 1 / 255
+                    dx32, dy32 = d["u"][g] - f32(j + 0.5), d["v"][g] - f32(i + 0.5)
+                    p32 = (f32(-0.5) * ((d["ca"][g] * dx32) * dx32 + (d["cc"][g] * dy32) * dy32)
+                           - (d["cb"][g] * dx32) * dy32)
+                    v32 = bool(p32 <= 0 and p32 >= d["tau"][g])
+                    a32 = f32(pr["alpha"][g].item()) * np.exp(p32)
+                    if s64 is None:
+                        want["evaluations"] += 1
+                        want["skip"] += v64 != v32
+                        if v64 and v32:
+                            want["clamp"] += (a64 >= 0.99) != bool(a32 >= f32(0.99))
+                        if v64:
+                            T64 *= 1 - min(a64, 0.99)
+                            if T64 < 1e-4:
+                                s64 = k
+                    if s32 is None and v32:
+                        T32 = f32(T32 * (f32(1) - min(a32, f32(0.99))))
+                        if T32 < f32(1e-4):
+                            s32 = k
+                want["stop"] += (len(gids) if s64 is None else s64) != (len(gids) if s32 is None else s32)
+    return want
+
+
+def test_decision_flips_match_a_per_pixel_count():
+    # tiny view with opaque and faint splats (many stops, clamps and skips)
+    sc = syn.tiny_scene(9, n=30, width=32, height=32, spread=0.3, log_scale_mean=math.log(0.15))
+    x = sc.gt.astype(np.float64)
+    rng = np.random.default_rng(4)
+    x[10] = rng.choice([-4.0, 6.0, 0.3], size=x.shape[1])
+    cam = sc.cameras[1]
+    bins = B.bin_view(x.astype(np.float32), cam)
+    got = R.decision_flips(x, cam, 0, bins)
+    want = _brute_flips(x, cam, bins, range(bins.tiles_x * bins.tiles_y))
+    assert got == want, (got, want)
+    assert got["evaluations"] > 1000
+
+
+def test_decision_flips_find_a_real_flip():
+    # one view of the plain workload holds a splat whose float32 skip decision
+    # differs from float64 at one pixel: the report and the literal walk find it
+    sc = syn.config1_scene()
+    x = sc.init.astype(np.float64)
+    cam = sc.cameras[2]
+    bins = B.bin_view(x.astype(np.float32), cam)
+    per_tile = {t: R.decision_flips(x, cam, 0, bins, tiles={t}) for t in range(bins.tiles_x * bins.tiles_y)}
+    flipped = [t for t, r in per_tile.items() if r["skip"] + r["clamp"] + r["stop"] > 0]
+    assert flipped
+    got = R.decision_flips(x, cam, 0, bins, tiles=set(flipped))
+    want = _brute_flips(x, cam, bins, flipped)
+    assert got == want, (got, want)
+    assert got["skip"] + got["clamp"] + got["stop"] >= 1
