@@ -64,6 +64,8 @@ class TRTrainer:
         self.g = None if self.cfg.fused else scene._empty_like_params()
         self.D = None if self.cfg.fused else scene._empty_like_params()
         self.t = 0
+        # the last iteration's choices: (t, S1, S2, probe seed, epsilon)
+        self.last = None
 
     def step(self):
         c = self.cfg
@@ -71,15 +73,15 @@ class TRTrainer:
         t = self.t
         S1 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s1)]
         eps = eps_schedule(t, c.budget)
+        S2 = []
+        if (t - 1) % c.l == 0:
+            S2 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s2)]
+        self.last = (t, S1, S2, c.probe_seed + t, eps)
         if c.fused:
-            S2 = []
-            if (t - 1) % c.l == 0:
-                S2 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s2)]
             self.scene.tr_iteration(S1, S2, c.nu, c.probe_seed + t, c.theta1, c.theta2, eps, variant=c.variant)
             return
         self.scene.grad(S1, out=self.g)
-        if (t - 1) % c.l == 0:
-            S2 = [self.train[i] for i in self.rng.integers(len(self.train), size=c.s2)]
+        if S2:
             self.scene.hvp_diag(S2, c.nu, c.probe_seed + t, out=self.D)
             self.scene.tr_step(self.g, self.D, c.theta1, c.theta2, eps, variant=c.variant)
         else:

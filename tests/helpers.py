@@ -44,3 +44,33 @@ def offset_targets(x, cams, sh_degree, seed, lo=0.05, hi=0.15):
         sgn = rng.choice([-1.0, 1.0], size=img.shape)
         out.append((img + sgn * rng.uniform(lo, hi, size=img.shape)).astype(np.float32))
     return out
+
+
+def group_max_abs(a, b, p):
+    """Largest elementwise error per parameter group, relative to the group's
+    largest reference entry (the whole vector's when the group is ~zero):
+    a few bad entries can hide inside a group's L2 norm, not here."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    top = np.abs(b).max() if b.size else 0.0
+    out = {}
+    for k, sl in GROUPS.items():
+        if len(range(p)[sl]) == 0:
+            continue
+        ref = np.abs(b[sl]).max()
+        denom = ref if ref > 1e-6 * top else top
+        err = np.abs(a[sl] - b[sl]).max()
+        out[k] = float(err / denom) if denom > 0 else float(err)
+    return out
+
+
+def view_flips(x, cams, ids, sh_degree, tiles=None):
+    """Summed float32-vs-float64 decision flips (skip, clamp, stop) over views."""
+    from oracle import render as R
+
+    tot = dict(skip=0, clamp=0, stop=0, evaluations=0, pixels=0)
+    for j in ids:
+        r = R.decision_flips(np.asarray(x, np.float64), cams[j], sh_degree, tiles=tiles)
+        for k in tot:
+            tot[k] += r[k]
+    return tot

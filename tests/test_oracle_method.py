@@ -610,3 +610,16 @@ def test_run_tr_on_the_objective_matches_its_first_step():
     x2, _, _, dx, _ = Mth.tr_step(x, g1, np.zeros_like(x), np.zeros_like(x), D1, 0.9, 0.999, 1e-6, 0)
     assert np.allclose(log[0]["x"], x2, rtol=0, atol=1e-15) and np.allclose(log[0]["dx"], dx, atol=1e-15)
     assert log[1]["eps"] == pytest.approx(1e-8) and log[1]["hutch"]
+
+
+def test_trainer_schedules_match_the_oracle():
+    # the trainer computes the same epsilon decay and Adam learning rates on
+    # the host as the oracle does (two copies of one schedule, tied here)
+    from paper_2602_00395_amd import trainer as Tr
+
+    for T in (1, 2, 10, 15000):
+        for t in sorted({1, 2, T // 2 + 1, max(T - 1, 1), T}):
+            assert Tr.eps_schedule(t, T) == pytest.approx(Mth.eps_schedule(t, T), rel=1e-13), (t, T)
+    for t in (0, 1, 500, 29999, 30000):
+        a, b = Tr.adam_lrs(t, 30000, 4.4), Mth.adam_lrs(t, 30000, 4.4)
+        assert a.keys() == b.keys() and all(a[k] == pytest.approx(b[k], rel=1e-13) for k in a)
