@@ -1,25 +1,30 @@
 #!/usr/bin/env python3
 """Throughput of the 3DGS^2-TR optimizer iteration on one MI355X (gfx950).
 
-A step is one iteration of Algorithm 1 on the object-scale workload
-(100k Gaussians, SH degree 3, 48 cameras at 800x800, every 8th held out):
-the stochastic gradient on one training view, every l = 10 iterations the
-Hutchinson diagonal (one probe, one view), and the trust-region update of all
-5.9M parameters.  Inputs are seeded synthetic data resident in HBM before the
-timed region; targets are renders of a seeded ground-truth scene.
+A step is one iteration of Algorithm 1 on the city-scale workload (6M
+Gaussians over a 200x200 grid, SH degree 3, 1,000 cameras at 1920x1080 on
+straight tracks, every 8th held out): the stochastic gradient on one training
+view, every l = 10 iterations the Hutchinson diagonal (one probe, one view),
+and the trust-region update of all 354M parameters.  Inputs are seeded
+synthetic data resident in HBM before the timed region; targets are renders
+of a seeded ground-truth scene.
 
-Prints one JSON line: iterations/s, the roofline of the kernel that takes
+Prints one JSON line: TR iterations/s; the roofline of the kernel that takes
 the most time (measured with HIP events around its launches during the timed
-region; its work counts come from an untimed replay of the same iterations
-with the counting kernel instances), the Adam baseline's iterations/s on the
-same views, and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+region; the blend kernels' work counts come from an untimed replay of the same
+iterations with the counting kernel instances); Adam's iterations/s and the
+device memory of both methods on the same workload; the seconds TR takes to
+reach the Adam baseline's PSNR on the object-scale workload (TR with 15k
+iterations against Adam with 30k, both on the same GPU); and the FP64 CPU
+oracle timed on a bounded sample of the same city workload.
 
-  python bench.py [--steps K] [--warmup W] [--fit TR_ITERS]
+  python bench.py [--steps K] [--warmup W] [--workload city|unbounded|object]
+                  [--fit TR_ITERS] [--serve N] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -31,17 +36,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# fp32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock)
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# published fp32 vector peak (an FMA counts as two operations, packed fp32 as two lanes)
+FP32_PEAK_TFLOPS = 157.3
+# fp32 VALU issue rate without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+LANE_ISSUE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic arithmetic of the blend kernels, counted from the operations the
-# method requires (add, mul, compare, exp and divide each count 1) for every
-# contributing (pixel, splat) pair -- the pairs whose blend any implementation
-# must compute: the offset, the quadratic form and the skip test (OPS_EVAL),
-# plus the blend and its JVP / VJP arithmetic.  Evaluations that end in a skip
-# are overhead of the tiling and count for nothing.
-OPS_EVAL = 14
-OPS_CONTRIB = {"blend_fwd": 12, "blend_jvp": 31, "blend_bwd": 47}
+# Arithmetic the method requires per evaluated (pixel, splat) pair of a blend
+# kernel: the offset, the quadratic form and the skip test plus the blend
+# (forward), its tangent (JVP) or its nine partial derivatives (backward); an
+# exp and a divide count one operation each.
+OPS_PER_EVAL = {"blend_fwd": 16, "blend_jvp": 31, "blend_bwd": 47}
+# The same per contributing pair (the pairs any implementation must blend),
+# for the lane-issue fraction reported beside the headline one.
+OPS_PER_CONTRIB = {"blend_fwd": 26, "blend_jvp": 45, "blend_bwd": 61}
+
+WORKLOADS = {
+    "city": "city-scale TR iteration: 6M Gaussians over a 200x200 grid, SH degree 3, 1,000 cameras 1920x1080 "
+            "on 20 straight tracks (875 train, 125 held out), L1 + 0.2 D-SSIM, |S1|=|S2|=nu=1, l=10",
+    "unbounded": "unbounded-scene TR iteration: 1M Gaussians (mixture foreground + far shell), SH degree 3, "
+                 "200 cameras 1600x1000 (175 train, 25 held out), L1 + 0.2 D-SSIM, |S1|=|S2|=nu=1, l=10",
+    "object": "object-scale TR iteration: 100k Gaussians, SH degree 3, 48 cameras 800x800 (42 train, 6 held out), "
+              "L1 + 0.2 D-SSIM, |S1|=|S2|=nu=1, l=10",
+}
 
 
 def parse():
@@ -49,16 +65,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="city", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=32, help="tiles in the oracle's timed sample")
+    ap.add_argument("--cpu-tiles", type=int, default=12, help="tiles in the oracle's timed sample")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: first run one plain device-to-device copy of this size (counter calibration)")
-    ap.add_argument("--fit", type=int, default=0,
-                    help="also run Adam for 2x this many iterations and TR until Adam's PSNR (seconds to PSNR)")
-    ap.add_argument("--tr-variant", type=int, default=0,
-                    help="trust-region radius variant bits for --fit (1 mean exact, 2 second order, 4 joint SH)")
-    ap.add_argument("--large", default="",
-                    help="comma list of large workloads to measure (unbounded, city): iterations/s and device memory")
+    ap.add_argument("--fit", type=int, default=15000,
+                    help="TR iterations of the object-scale time-to-PSNR run (Adam runs twice as many); 0 skips it")
+    ap.add_argument("--tr-variant", type=int, default=None,
+                    help="trust-region radius variant bits (1 mean exact, 2 second order, 4 joint SH); "
+                         "default: the trainer's")
     ap.add_argument("--serve", type=int, default=0,
                     help="also serve this many scene-fit requests of the Poisson trace (p50/p99 time-to-fit)")
     ap.add_argument("--serve-iters", type=int, default=400,
@@ -66,28 +82,27 @@ def parse():
     return ap.parse_args()
 
 
-# stage -> (kernel name in the profile summaries, source file of the kernel)
+# stage -> (kernel name in the profile summaries, its source file)
 _KERNEL_OF = {"blend_bwd": ("k_blend_bwd<false>", "blend.hip"), "blend_fwd": ("k_blend_fwd<false>", "blend.hip"),
-              "blend_jvp": ("k_blend_jvp<false>", "blend.hip"), "tr_step": ("k_tr_step<59>", "optim.hip"),
-              "adam_step": ("k_adam_step<59>", "optim.hip")}
+              "blend_jvp": ("k_blend_jvp<false>", "blend.hip"), "tr_update": ("k_tr_update<3>", "project.hip"),
+              "tr_step": ("k_tr_step<59>", "optim.hip"), "adam_step": ("k_adam_step<59>", "optim.hip")}
 
 
-def measured_traffic(stage: str) -> int | None:
-    """HBM bytes per launch (read + written) of a stage's kernel, from the committed
-    FETCH_SIZE / WRITE_SIZE summary; None when that kernel's source (or the shared
-    header) has changed since the counters were taken."""
-    import hashlib
-
+def measured_traffic(stage: str, workload: str) -> int | None:
+    """HBM bytes per launch (read + written) of a stage's kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary of this workload; None when there is none, or
+    when that kernel's source (or a shared header) has changed since the counters
+    were taken."""
     if stage not in _KERNEL_OF:
         return None
     kern, src = _KERNEL_OF[stage]
     try:
-        with open(os.path.join(ROOT, "profiles", "object_scale_hbm_traffic.json")) as f:
+        with open(os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.json")) as f:
             rec = json.load(f)
     except OSError:
         return None
     csrc = os.path.join(ROOT, "paper_2602_00395_amd", "csrc")
-    for fn in (src, "gs3_internal.h"):
+    for fn in (src, "gs3_internal.h", "gs3_trust.h"):
         with open(os.path.join(csrc, fn), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"].get(fn):
                 return None
@@ -95,47 +110,102 @@ def measured_traffic(stage: str) -> int | None:
     return None if k is None else int(k["read_bytes"] + k["write_bytes"])
 
 
-def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int) -> dict | None:
+def update_bytes(p: int, n: int, hutch: bool) -> int:
+    """Algorithmic HBM bytes of one fused update launch: read x, ghat and Dhat
+    and write x' and ghat for every parameter (20 B; the gradient is formed in
+    registers from each Gaussian's nine summed screen-space partials, 36 B
+    read), plus D_t read and Dhat written on a Hutchinson iteration (8 B)."""
+    return (20 + (8 if hutch else 0)) * p * n + 36 * n
+
+
+def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int, workload: str) -> dict | None:
     """Algorithmic work of one stage over the timed launches -> roofline entry."""
     if st["launches"] == 0 or st["total_ms"] <= 0:
         return None
     sec = st["total_ms"] / 1e3
-    if stage in OPS_CONTRIB:
-        ops = (OPS_EVAL + OPS_CONTRIB[stage]) * st["work1"]
-        ach = ops / sec / 1e12
-        return dict(bound="alu", achieved=round(ach, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
-                    frac=round(ach / ALU_PEAK_TOPS, 4), traffic=measured_traffic(stage), kernel=stage,
-                    avg_launch_ms=round(st["total_ms"] / st["launches"], 4),
+    avg_ms = st["total_ms"] / st["launches"]
+    traffic = measured_traffic(stage, workload)
+    if stage in OPS_PER_EVAL:
+        flops = OPS_PER_EVAL[stage] * st["work0"]
+        ach = flops / sec / 1e12
+        lane = OPS_PER_CONTRIB[stage] * st["work1"] / sec / 1e12
+        return dict(bound="alu", achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=traffic, kernel=stage,
+                    ops_per_evaluation=OPS_PER_EVAL[stage], avg_launch_ms=round(avg_ms, 4),
                     evaluations_per_launch=st["work0"] // st["launches"],
-                    contributing_per_launch=st["work1"] // st["launches"])
-    if stage in ("tr_step", "adam_step"):
-        # tr_step reads x, g, ghat, Dhat and writes x, ghat (+ D read, Dhat write on Hutchinson steps);
-        # Adam reads x, g, m, v and writes x, m, v
-        per = 24 if stage == "tr_step" else 28
-        bytes_ = per * p * n * st["launches"] + (8 * p * n * hutch_launches if stage == "tr_step" else 0)
+                    contributing_per_launch=st["work1"] // st["launches"],
+                    lane_issue_frac=dict(value=round(lane / LANE_ISSUE_PEAK_TOPS, 4), peak_tops=LANE_ISSUE_PEAK_TOPS,
+                                         ops_per_contributing_pair=OPS_PER_CONTRIB[stage],
+                                         note="algorithmic ops on contributing pairs over the non-packed "
+                                              "VALU issue rate (an FMA as one op)"))
+    if stage in ("tr_update", "tr_step", "adam_step"):
+        launches = st["launches"]
+        if stage == "tr_update":
+            bytes_ = update_bytes(p, n, False) * (launches - hutch_launches) + update_bytes(p, n, True) * hutch_launches
+        elif stage == "tr_step":
+            bytes_ = 24 * p * n * launches + 8 * p * n * hutch_launches
+        else:
+            bytes_ = 28 * p * n * launches
         ach = bytes_ / sec / 1e9
         return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=measured_traffic(stage), kernel=stage,
-                    avg_launch_ms=round(st["total_ms"] / st["launches"], 4),
-                    bytes_per_launch=bytes_ // st["launches"])
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic, kernel=stage,
+                    avg_launch_ms=round(avg_ms, 4), bytes_per_launch=bytes_ // launches)
     return dict(bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None, kernel=stage,
-                avg_launch_ms=round(st["total_ms"] / st["launches"], 4))
+                avg_launch_ms=round(avg_ms, 4))
+
+
+def build_workload(name: str, dev: str):
+    """Seeded scene inputs, flat targets on the device (renders of the ground
+    truth) and the train mask."""
+    import torch
+
+    import synthetic as syn
+    from paper_2602_00395_amd import Scene
+
+    sc = {"city": syn.config4_scene, "unbounded": syn.config3_scene, "object": syn.config2_scene}[name]()
+    cams = sc.cameras
+    sizes = [c.height * c.width * 3 for c in cams]
+    flat = torch.empty(sum(sizes), device=dev)
+    zeros = torch.zeros(sum(sizes), device=dev)
+    g = Scene(torch.tensor(sc.gt, device=dev), zeros, cams, sc.sh_degree, lam=0.2)
+    off = 0
+    for j, n in enumerate(sizes):
+        g.render(j, out=flat[off:off + n].view(cams[j].height, cams[j].width, 3))
+        off += n
+    g.sync()
+    g.close()
+    del zeros
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    mask = [j % sc.test_every != 0 for j in range(len(cams))]
+    return sc, flat, mask
+
+
+def extent_of(cams) -> float:
+    import numpy as np
+
+    centres = np.array([c.centre() for c in cams])
+    return 1.1 * float(np.linalg.norm(centres - centres.mean(0), axis=1).max())
 
 
 def cpu_baseline(sc, n_tiles_sample: int, l: int) -> dict:
     """The FP64 oracle, as it stands, on a bounded sample of the same workload.
 
-    Sample: one training view of the object-scale scene; the oracle's float32
-    binning of all Gaussians, its render + autograd gradient (L1 loss) and its
-    Gauss-Newton product (JVP, GN weights, VJP) on `n_tiles_sample` random
-    non-empty tiles, scaled to the whole view by (pairs in view) / (pairs in
-    sample); its trust-region radius and step at full size.  One iteration =
-    binning + gradient + step + (binning + GN product) / l.
+    Sample: one training view of the workload.  The oracle's float32 binning
+    of all Gaussians; its render + autograd gradient and its Gauss-Newton
+    product (JVP, GN weights, VJP) on `n_tiles_sample` random non-empty tiles,
+    scaled to the whole view by (pairs in view) / (pairs in sample), with the
+    L1 part of the loss on those tiles; the D-SSIM part (lambda = 0.2: SSIM
+    maps and their gradient) timed at full image size; the trust-region
+    radius and step on a slice of 500k Gaussians, scaled to all N.  One
+    iteration = binning + gradient + D-SSIM + step + (binning + GN product +
+    D-SSIM) / l.
     """
     import numpy as np
     import torch
 
     from oracle import binning as OB
+    from oracle import loss as OL
     from oracle import method as OM
     from oracle import render as OR
 
@@ -158,8 +228,14 @@ def cpu_baseline(sc, n_tiles_sample: int, l: int) -> dict:
     xg = xt.clone().requires_grad_(True)
     img = f(xg)
     m = ~torch.isnan(img)
-    torch.abs(img[m] - tgt[m]).sum().backward()
+    (0.8 * torch.abs(img[m] - tgt[m])).sum().backward()
     t_grad = (time.perf_counter() - t0) * scale
+    # the D-SSIM component and its gradient at full size
+    full = torch.rand((cam.height, cam.width, 3), dtype=torch.float64, requires_grad=True)
+    t0 = time.perf_counter()
+    _, ls = OL.loss_components(full, tgt, 0.2)
+    ls.sum().backward()
+    t_ssim = time.perf_counter() - t0
     z = torch.tensor(OM.probe(5002, 0, *x.shape))
     t0 = time.perf_counter()
     img, u = torch.func.jvp(f, (xt,), (z,))
@@ -169,15 +245,70 @@ def cpu_baseline(sc, n_tiles_sample: int, l: int) -> dict:
     _, vjp = torch.func.vjp(f, xt)
     vjp(y)
     t_hvp = (time.perf_counter() - t0) * scale
+    n_slice = min(500_000, x.shape[1])
+    xs = np.ascontiguousarray(x[:, :n_slice])
+    g = np.zeros(xs.shape)
     t0 = time.perf_counter()
-    g = np.zeros(x.shape)
-    OM.tr_step(x, g, g, g, None, 0.9, 0.999, 1e-6, sc.sh_degree)
-    t_step = time.perf_counter() - t0
-    t_iter = t_bin + t_grad + t_step + (t_bin + t_hvp) / l
+    OM.tr_step(xs, g, g, g, None, 0.9, 0.999, 1e-6, sc.sh_degree)
+    t_step = (time.perf_counter() - t0) * x.shape[1] / n_slice
+    t_iter = t_bin + t_grad + t_ssim + t_step + (t_bin + t_hvp + t_ssim) / l
     return dict(value=round(1.0 / t_iter, 6), unit="iter/s", cores=threads, kind="oracle",
-                sample=(f"object-scale view, {len(pick)} of {len(nonempty)} non-empty tiles "
-                        f"(x{scale:.1f} by pair count) for render+grad and the GN product; "
-                        f"binning and trust-region step at full size; est. {t_iter:.1f} s/iter"))
+                sample=(f"one view of the same workload: {len(pick)} of {len(nonempty)} non-empty tiles "
+                        f"(x{scale:.1f} by pair count) for render + gradient (L1 part) and the GN product; "
+                        f"D-SSIM (lambda 0.2) and its gradient at full image size; binning at full size; "
+                        f"trust-region radius and step on {n_slice} Gaussians x{x.shape[1] / n_slice:.0f}; "
+                        f"est. {t_iter:.1f} s/iter (bin {t_bin:.1f}, grad {t_grad:.1f}, ssim {t_ssim:.1f}, "
+                        f"step {t_step:.1f}, GN product {t_hvp:.1f} per Hutchinson view)"))
+
+
+def time_to_adam_psnr(tr_iters: int, variant, dev: str) -> dict:
+    """Seconds of training TR needs to reach the Adam baseline's final PSNR.
+
+    Object-scale workload (100k Gaussians, SH 3, 48 cameras 800x800, 6 held
+    out); same init, loss, views and GPU.  Adam runs 2 x tr_iters iterations
+    and sets the target P_A = its final held-out PSNR.  TR runs tr_iters
+    iterations; its held-out PSNR is evaluated every 100 iterations (the clock
+    counts training only), and its time to P_A is interpolated linearly
+    between the two evaluations that bracket the crossing.
+    """
+    import torch
+
+    from paper_2602_00395_amd import Scene
+    from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer, fit
+
+    sc, flat, mask = build_workload("object", dev)
+    x0 = torch.tensor(sc.init, device=dev)
+    train_ids, test_ids = sc.train_ids(), sc.test_ids()
+    extent = extent_of(sc.cameras)
+
+    def make():
+        return Scene(x0, flat, sc.cameras, sc.sh_degree, lam=0.2, train_mask=mask)
+
+    s = make()
+    ad = AdamTrainer(s, train_ids, extent, budget=2 * tr_iters)
+    hist_a, _ = fit(ad, s, test_ids, 2 * tr_iters, eval_every=1000,
+                    log=lambda m: print("adam", m, file=sys.stderr, flush=True))
+    s.close()
+    target = hist_a[-1][2]
+    s = make()
+    cfg = TRConfig(budget=tr_iters) if variant is None else TRConfig(budget=tr_iters, variant=variant)
+    tr = TRTrainer(s, train_ids, cfg)
+    hist_t, reached = fit(tr, s, test_ids, tr_iters, eval_every=100, target_psnr=target, interpolate=True,
+                          log=lambda m: print("tr", m, file=sys.stderr, flush=True))
+    s.close()
+    it_reached = None
+    if reached is not None:
+        it_reached = next(i for i, _, p in hist_t if p >= target)
+    best = max(hist_t, key=lambda h: h[2])
+    return dict(workload=WORKLOADS["object"], tr_variant=cfg.variant, adam_iters=2 * tr_iters,
+                adam_psnr=round(target, 3), adam_train_s=round(hist_a[-1][1], 3), tr_iters=tr_iters,
+                tr_final_psnr=round(hist_t[-1][2], 3), tr_best_psnr=round(best[2], 3), tr_best_at_iter=best[0],
+                tr_s_to_adam_psnr=("not reached" if reached is None else round(reached, 3)),
+                tr_iters_to_adam_psnr=it_reached,
+                speedup_vs_adam=(None if reached is None else round(hist_a[-1][1] / reached, 3)),
+                resolution="TR evaluated every 100 iterations, crossing time interpolated linearly",
+                adam_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_a],
+                tr_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_t[::10]])
 
 
 def serving(n_req: int, k_iters: int, dev: str) -> dict:
@@ -221,12 +352,13 @@ def serving(n_req: int, k_iters: int, dev: str) -> dict:
                                max_iters=k_iters, check_every=check, bytes_needed=res_b + scr_b,
                                seed=4005 + i))
         print("request", i, sc.n, len(sc.cameras), r["res"], sc.sh_degree, file=sys.stderr, flush=True)
-    # solo pass: the PSNR each request reaches alone after k_iters iterations
     solo = {}
     t0 = time.perf_counter()
     for r in reqs:
         st = Server(hbm_budget=r.bytes_needed, max_active=1).run([FitRequest(**{**r.__dict__, "arrival_s": 0.0})])
         solo[r.rid] = st.results[0]
+        if st.results[0].error:
+            raise RuntimeError(f"solo fit of request {r.rid} failed: {st.results[0].error}")
         print("solo", r.rid, r.n, round(st.results[0].psnr, 3), round(st.wall_s, 2), file=sys.stderr, flush=True)
     solo_s = time.perf_counter() - t0
     for r in reqs:  # same iteration cap, so the trust-region schedule is the solo one
@@ -235,10 +367,8 @@ def serving(n_req: int, k_iters: int, dev: str) -> dict:
     st = Server(hbm_budget=budget, max_active=8).run(reqs)
     served_iters = {x.rid: x.iters for x in st.results}
     same = all(served_iters[r.rid] <= solo[r.rid].iters for r in reqs)
-    lat = np.array([x.latency_s for x in st.results])
-    return dict(requests=len(reqs), reached=sum(x.reached for x in st.results),
-                p50_time_to_fit_s=round(float(np.percentile(lat, 50)), 3),
-                p99_time_to_fit_s=round(float(np.percentile(lat, 99)), 3),
+    return dict(requests=len(reqs), reached=sum(x.reached for x in st.results), failed=len(st.failed),
+                p50_time_to_fit_s=round(st.percentile(50), 3), p99_time_to_fit_s=round(st.percentile(99), 3),
                 gaussian_updates_per_s=round(st.gaussian_updates_per_s(), 1), wall_s=round(st.wall_s, 2),
                 peak_admitted_bytes=int(st.peak_bytes), hbm_budget_bytes=budget, max_active=8,
                 target=f"solo PSNR after {k_iters} TR iterations - 0.1 dB, checked every {check}",
@@ -246,73 +376,8 @@ def serving(n_req: int, k_iters: int, dev: str) -> dict:
                 iters_total=int(sum(served_iters.values())))
 
 
-def large_scale(names: list, steps: int, warmup: int, dev: str) -> dict:
-    """TR and Adam iterations/s and device memory at the large workloads.
-
-    unbounded: 1M Gaussians (mixture foreground + far shell), SH 3, 200
-    cameras 1600x1000; city: 6M Gaussians over a 200x200 grid, SH 3, 1,000
-    cameras 1920x1080.  Targets are renders of the seeded ground truth.
-    Device memory is the drop in free device memory from just before the
-    scene is created to after its warm-up iterations: everything the method
-    keeps resident (parameters, targets, optimizer state, per-view scratch).
-    """
-    import numpy as np
-    import torch
-
-    import synthetic as syn
-    from paper_2602_00395_amd import Scene
-    from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer
-
-    out = {}
-    for name in names:
-        t0 = time.perf_counter()
-        sc = syn.config3_scene() if name == "unbounded" else syn.config4_scene()
-        print("large", name, "built", sc.n, "Gaussians", len(sc.cameras), "cameras",
-              round(time.perf_counter() - t0, 1), "s", file=sys.stderr, flush=True)
-        cams = sc.cameras
-        sizes = [c.height * c.width * 3 for c in cams]
-        flat = torch.empty(sum(sizes), device=dev)
-        zeros = torch.zeros(sum(sizes), device=dev)
-        g = Scene(torch.tensor(sc.gt, device=dev), zeros, cams, sc.sh_degree, lam=0.2)
-        off = 0
-        for j, n in enumerate(sizes):
-            flat[off:off + n].copy_(g.render(j).reshape(-1))
-            off += n
-        g.close()
-        del zeros
-        torch.cuda.synchronize()
-        torch.cuda.empty_cache()
-        print("large", name, "targets rendered", file=sys.stderr, flush=True)
-        mask = [j % sc.test_every != 0 for j in range(len(cams))]
-        x0 = torch.tensor(sc.init, device=dev)
-        centres = np.array([c.centre() for c in cams])
-        extent = 1.1 * float(np.linalg.norm(centres - centres.mean(0), axis=1).max())  # Adam's mean learning rate
-        res = dict(gaussians=sc.n, cameras=len(cams), resolution=f"{cams[0].width}x{cams[0].height}")
-        for method in ("tr", "adam"):
-            torch.cuda.synchronize()
-            torch.cuda.empty_cache()
-            free0 = torch.cuda.mem_get_info()[0]
-            s = Scene(x0, flat, cams, sc.sh_degree, lam=0.2, train_mask=mask)
-            tr = (TRTrainer(s, sc.train_ids(), TRConfig()) if method == "tr"
-                  else AdamTrainer(s, sc.train_ids(), extent=extent))
-            for _ in range(warmup):
-                tr.step()
-            torch.cuda.synchronize()
-            used = free0 - torch.cuda.mem_get_info()[0]
-            t1 = time.perf_counter()
-            for _ in range(steps):
-                tr.step()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t1
-            res[f"{method}_iters_per_s"] = round(steps / dt, 2)
-            res[f"{method}_device_bytes"] = int(used)
-            print("large", name, method, res[f"{method}_iters_per_s"], "it/s", used >> 20, "MiB",
-                  file=sys.stderr, flush=True)
-            del tr
-            s.close()
-        out[name] = res
-        del flat, x0
-    return out
+STAGES = ["project_fwd", "depth_sort", "scan", "emit_pairs", "pair_sort", "blend_fwd", "loss", "blend_bwd",
+          "pair_sums", "project_bwd", "tr_update", "project_jvp", "blend_jvp"]
 
 
 def main():
@@ -322,12 +387,10 @@ def main():
         print("bench.py measures one GPU only: there is no multi-GPU path (the image-parallel "
               "sharding is a design, not an implementation); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    import synthetic as syn
     from paper_2602_00395_amd import Scene, profile_count, profile_enable, profile_read, profile_reset
-    from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer, fit, mean_psnr
+    from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer, mean_psnr
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
@@ -339,21 +402,18 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    sc = syn.config2_scene()
+    t_build = time.perf_counter()
+    sc, flat, mask = build_workload(args.workload, dev)
+    print("workload", args.workload, "ready in", round(time.perf_counter() - t_build, 1), "s", file=sys.stderr,
+          flush=True)
     cams = sc.cameras
     train_ids, test_ids = sc.train_ids(), sc.test_ids()
-    mask = [i % sc.test_every != 0 for i in range(len(cams))]
-    blank = [torch.zeros((c.height, c.width, 3), device=dev) for c in cams]
-    gt_scene = Scene(torch.tensor(sc.gt, device=dev), blank, cams, sc.sh_degree, lam=0.2)
-    targets = [gt_scene.render(j).clone() for j in range(len(cams))]
-    gt_scene.close()
-    del blank
     x0 = torch.tensor(sc.init, device=dev)
     N, P = sc.n, sc.p
-    cfg = TRConfig()
+    cfg = TRConfig() if args.tr_variant is None else TRConfig(variant=args.tr_variant)
 
     def make():
-        return Scene(x0, targets, cams, sc.sh_degree, lam=0.2, train_mask=mask)
+        return Scene(x0, flat, cams, sc.sh_degree, lam=0.2, train_mask=mask)
 
     # ---- stage breakdown (untimed) to find the dominant kernel
     s = make()
@@ -369,23 +429,27 @@ def main():
     torch.cuda.synchronize()
     profile_enable("")
     profile_count(True)
-    stages = ["project_fwd", "depth_sort", "scan", "emit_pairs", "pair_sort", "blend_fwd", "loss", "blend_bwd",
-              "project_bwd", "project_jvp", "blend_jvp", "tr_step"]
-    stage_ms = {k: profile_read(k)["total_ms"] / (2 * cfg.l) for k in stages}
+    stage_ms = {k: profile_read(k)["total_ms"] / (2 * cfg.l) for k in STAGES}
     dominant = max(stage_ms, key=stage_ms.get)
     s.close()
+    print("stages", {k: round(v, 3) for k, v in stage_ms.items()}, file=sys.stderr, flush=True)
 
     # ---- timed TR iterations: the dominant stage's launches are bracketed by
     # events only, so they run the same kernels as every other launch
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     s = make()
     tr = TRTrainer(s, train_ids, cfg)
     for _ in range(args.warmup):
         tr.step()
     torch.cuda.synchronize()
+    tr_bytes = free0 - torch.cuda.mem_get_info()[0]
+    tr_scene_bytes = s.device_bytes()
     profile_reset()
     profile_count(False)
     profile_enable(dominant)
     first = tr.t + 1
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         tr.step()
@@ -396,79 +460,70 @@ def main():
     timed = profile_read(dominant)
     hutch = sum(1 for t in range(first, first + args.steps) if (t - 1) % cfg.l == 0)
     psnr_tr = mean_psnr(s, test_ids)
+    s.sync()
     s.close()
-    # the same iterations again, untimed, with the work counters on: the
-    # evaluation counts of exactly the timed launches
-    s = make()
-    tr = TRTrainer(s, train_ids, cfg)
-    for _ in range(args.warmup):
-        tr.step()
-    torch.cuda.synchronize()
-    profile_reset()
-    profile_enable(dominant)
-    for _ in range(args.steps):
-        tr.step()
-    torch.cuda.synchronize()
-    profile_enable("")
-    counted = profile_read(dominant)
-    s.close()
-    if counted["launches"] != timed["launches"]:
-        raise RuntimeError(f"counted replay made {counted['launches']} {dominant} launches, "
-                           f"the timed run {timed['launches']}")
-    roof = roofline(dominant, dict(timed, work0=counted["work0"], work1=counted["work1"]), N, P, hutch)
+    print("timed", args.steps, "TR iterations", round(dt, 3), "s", file=sys.stderr, flush=True)
+    counted = timed
+    if dominant in OPS_PER_EVAL:
+        # the same iterations again, untimed, with the work counters on: the
+        # evaluation counts of exactly the timed launches
+        s = make()
+        tr = TRTrainer(s, train_ids, cfg)
+        for _ in range(args.warmup):
+            tr.step()
+        torch.cuda.synchronize()
+        profile_reset()
+        profile_enable(dominant)
+        for _ in range(args.steps):
+            tr.step()
+        torch.cuda.synchronize()
+        profile_enable("")
+        counted = profile_read(dominant)
+        s.close()
+        if counted["launches"] != timed["launches"]:
+            raise RuntimeError(f"counted replay made {counted['launches']} {dominant} launches, "
+                               f"the timed run {timed['launches']}")
+    roof = roofline(dominant, dict(timed, work0=counted["work0"], work1=counted["work1"]), N, P, hutch,
+                    args.workload)
 
     # ---- Adam on the same views, same clock
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
     s = make()
-    extent = 1.1 * 4.0
-    ad = AdamTrainer(s, train_ids, extent)
+    ad = AdamTrainer(s, train_ids, extent_of(cams))
     for _ in range(args.warmup):
         ad.step()
     torch.cuda.synchronize()
+    adam_bytes = free0 - torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ad.step()
     torch.cuda.synchronize()
     dt_adam = time.perf_counter() - t0
     s.close()
+    del flat, x0
+    torch.cuda.empty_cache()
 
     out = dict(
         metric="iters/s", value=round(args.steps / dt, 3), unit="iter/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(1e3 * dt / args.steps, 3), higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload="object-scale TR iteration: 100k Gaussians, SH degree 3, 48 cameras 800x800 "
-                             "(42 train, 6 held out), L1+0.2 D-SSIM, |S1|=|S2|=nu=1, l=10",
-                    gaussians=N, params_per_gaussian=P, cameras=len(cams), resolution="800x800"),
+        config=dict(workload=WORKLOADS[args.workload], gaussians=N, params_per_gaussian=P, cameras=len(cams),
+                    resolution=f"{cams[0].width}x{cams[0].height}", tr_variant=cfg.variant),
         roofline=roof,
         adam_iters_per_s=round(args.steps / dt_adam, 3),
+        device_bytes=dict(tr=int(tr_bytes), adam=int(adam_bytes), tr_scene_reported=int(tr_scene_bytes),
+                          note="drop in free device memory from before scene creation to after warm-up: "
+                               "parameters, targets, the method's optimizer state and per-view scratch"),
         stage_ms_per_iter={k: round(v, 4) for k, v in stage_ms.items()},
         psnr_after=round(psnr_tr, 3),
     )
-
+    print("throughput", out["value"], "it/s", file=sys.stderr, flush=True)
     if args.fit > 0:
-        # seconds to the Adam baseline's PSNR: Adam runs 2x the TR budget
-        s = make()
-        ad = AdamTrainer(s, train_ids, extent, budget=2 * args.fit)
-        hist_a, _ = fit(ad, s, test_ids, 2 * args.fit, eval_every=500,
-                        log=lambda m: print("adam", m, file=sys.stderr, flush=True))
-        s.close()
-        target = hist_a[-1][2]
-        s = make()
-        tr = TRTrainer(s, train_ids, TRConfig(budget=args.fit, variant=args.tr_variant))
-        hist_t, reached = fit(tr, s, test_ids, args.fit, eval_every=500, target_psnr=target,
-                              log=lambda m: print("tr", m, file=sys.stderr, flush=True))
-        s.close()
-        out["fit"] = dict(tr_variant=args.tr_variant, adam_iters=2 * args.fit, adam_psnr=round(target, 3), adam_train_s=round(hist_a[-1][1], 2),
-                          tr_iters=args.fit, tr_psnr=round(hist_t[-1][2], 3),
-                          tr_s_to_adam_psnr=None if reached is None else round(reached, 2),
-                          adam_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_a],
-                          tr_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_t])
-
+        out["time_to_adam_psnr"] = time_to_adam_psnr(args.fit, args.tr_variant, dev)
     if args.serve > 0:
         out["serving"] = serving(args.serve, args.serve_iters, dev)
-
-    if args.large:
-        out["large"] = large_scale([v for v in args.large.split(",") if v], 20, 5, dev)
-
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_tiles, cfg.l)
     print(json.dumps(out), flush=True)

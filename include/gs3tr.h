@@ -11,7 +11,7 @@
  *   failing call on the calling thread.  Arguments are validated before any
  *   work is enqueued, so GS3_EINVAL leaves the scene untouched.
  * Streams: all work is enqueued on the caller's hipStream_t (NULL = the
- *   default stream).  Functions that must know the number of (Gaussian,
+ *   default stream); no call waits for the whole device.  Functions that must know the number of (Gaussian,
  *   tile) pairs of a view before launching the blend block the calling
  *   thread once per view until the stream has run up to that view's pair
  *   count (a pinned host word written by the binning scan; the stream is
@@ -51,12 +51,15 @@ enum {
   GS3_EINVAL = -1,      /* bad argument: NULL, size, index or range        */
   GS3_ENOMEM = -2,      /* a device allocation failed                      */
   GS3_EDEVICE = -3,     /* a HIP runtime call or kernel launch failed      */
-  GS3_ENONFINITE = -4,  /* reserved: non-finite values detected            */
+  GS3_ENONFINITE = -4,  /* an update met a non-finite gradient entry or
+                           produced a non-finite parameter (gs3_scene_sync) */
   GS3_ESTATE = -5,      /* the scene is not in a state that allows the call */
   GS3_ENOTIMPL = -6     /* the requested variant is not implemented        */
 };
 
-/* Scene flags. */
+/* Scene flags: reserved; gs3_scene_desc.flags must be GS3_FLAG_NONE
+ * (anything else is EINVAL).  Method variants are chosen per call
+ * (gs3_tr_hparams.variant). */
 enum {
   GS3_FLAG_NONE = 0u
 };
@@ -64,7 +67,7 @@ enum {
 typedef struct gs3_scene gs3_scene; /* opaque */
 
 typedef struct {
-  int32_t width, height;   /* pixels; both >= 1                             */
+  int32_t width, height;   /* pixels; both in [1, 16368]                    */
   float fx, fy, cx, cy;    /* pinhole intrinsics in pixels                  */
   float R[9];              /* world-to-camera rotation, row-major           */
   float t[3];              /* world-to-camera translation                   */
@@ -77,7 +80,7 @@ typedef struct {
   const gs3_camera* cameras; /* host array of n_cameras cameras             */
   float background[3];       /* colour added with the final transmittance   */
   float lambda_dssim;        /* lambda of the L1 / D-SSIM mix, in [0, 1]    */
-  uint32_t flags;            /* GS3_FLAG_*                                  */
+  uint32_t flags;            /* reserved, must be GS3_FLAG_NONE             */
   const uint8_t* train_mask; /* host, n_cameras entries: nonzero marks a
                                 training view (the M images of the
                                 objective); NULL = every camera trains.
@@ -125,7 +128,11 @@ const char* gs3_version(void);
 gs3_status gs3_scene_create(const gs3_scene_desc* desc, const float* params_dev, const float* targets_dev,
                             hipStream_t stream, gs3_scene** out);
 
-/* Release every device buffer of the scene (after synchronising the device). */
+/* Release the scene.  Waits for the work the scene has enqueued (its own
+ * completion event, recorded by every call on that call's stream) and for
+ * nothing else; its device blocks go to a process-wide cache that later
+ * scenes draw from (see gs3_trim_cache), so tearing one scene down does not
+ * stall the streams of others. */
 gs3_status gs3_scene_destroy(gs3_scene* scene);
 
 /* Borrowed device pointer to the scene's parameters float[P][N]; valid
@@ -136,13 +143,29 @@ gs3_status gs3_scene_params(gs3_scene* scene, float** params_dev);
 /* Overwrite the scene's parameters from params_dev (float[P][N], device). */
 gs3_status gs3_scene_set_params(gs3_scene* scene, const float* params_dev, hipStream_t stream);
 
-/* Resident bytes (parameters, targets and the trust-region method's state:
- * six float[P][N] buffers in all, where Adam needs three) and
- * an estimate of the peak per-view scratch for a scene described by desc;
- * used to admit scenes under an HBM budget.  No device work. */
+/* Resident bytes (targets, parameters and the trust-region method's state:
+ * six float[P][N] buffers and the radius scratch, where Adam needs three
+ * buffers) and the scratch a scene described by desc allocates at creation:
+ * per-Gaussian and per-pixel buffers and pair buffers reserved for 20
+ * (Gaussian, tile) pairs per Gaussian with 25% slack.  A view with more pairs
+ * grows the pair buffers (stream-ordered, without waiting for the device);
+ * gs3_scene_device_bytes reports what a scene holds.  Used to admit scenes
+ * under an HBM budget.  No device work. */
 gs3_status gs3_scene_bytes(const gs3_scene_desc* desc, int64_t* resident, int64_t* peak_scratch);
 
-/* Wait for all work the scene enqueued; reports deferred device errors. */
+/* Device bytes the scene holds now: everything gs3_scene_bytes counts
+ * (optimizer state only once created) plus any growth of its pair buffers. */
+gs3_status gs3_scene_device_bytes(gs3_scene* scene, int64_t* bytes);
+
+/* Release the device blocks that destroyed scenes left in the process-wide
+ * cache (waiting for the device).  The cache keeps at most 16 GiB; blocks
+ * beyond that are released when they are given back. */
+gs3_status gs3_trim_cache(void);
+
+/* Wait for all work the scene enqueued; reports deferred device errors, and
+ * GS3_ENONFINITE (once, then cleared) if an update since the last sync read
+ * a non-finite gradient entry or wrote a non-finite parameter (the trust-
+ * region and Adam updates check every row they write). */
 gs3_status gs3_scene_sync(gs3_scene* scene);
 
 /* Render camera `cam` (0 <= cam < n_cameras) of the scene's current
@@ -156,7 +179,9 @@ gs3_status gs3_render(gs3_scene* scene, int32_t cam, float* rgb_dev, hipStream_t
  * keys_dev / gids_dev (capacity entries each, device; either may be NULL),
  * each tile's [start, end) into ranges_dev (uint32[tiles][2], device, may be
  * NULL) and the pair count into *n_pairs (host).  Fails with EINVAL when the
- * pair count exceeds capacity (n_pairs is still set).  Synchronises. */
+ * pair count exceeds capacity (n_pairs is still set).  Every call that bins
+ * a view (render, grad, hvp_diag, ...) fails with EINVAL for a view of
+ * 2^32 - 2 or more pairs.  Synchronises. */
 gs3_status gs3_bin(gs3_scene* scene, int32_t cam, uint64_t* keys_dev, uint32_t* gids_dev, uint32_t* ranges_dev,
                    int64_t capacity, int64_t* n_pairs, hipStream_t stream);
 
@@ -203,19 +228,23 @@ gs3_status gs3_tr_iteration(gs3_scene* scene, const int32_t* cams1, int32_t n1, 
                             int32_t nu, uint64_t seed, const gs3_tr_hparams* hp, double* loss_out,
                             hipStream_t stream);
 
-/* Adam baseline (Kingma and Ba) with bias correction, betas (0.9, 0.999),
+/* The ADAM baseline of the Evaluations section (the first-order method the
+ * paper compares against, run with the original 3DGS training settings):
+ * Adam (Kingma and Ba) with bias correction, betas (0.9, 0.999),
  * eps 1e-15 and one learning rate per parameter group:
  * lr_per_group = {mean, SH DC, SH rest, opacity, scale, rotation} (host).
  * `step` is the 1-based Adam step count. */
 gs3_status gs3_adam_step(gs3_scene* scene, const float* grad_dev, const float* lr_per_group, int32_t step,
                          hipStream_t stream);
 
-/* ADAM-TR of the evaluation: the Adam step clipped by eta = SHD(x, epsilon). */
+/* ADAM-TR, the ablation of the Evaluations section: the Adam step clipped
+ * by the parameter-wise Hellinger radius eta = SHD(x, epsilon). */
 gs3_status gs3_adam_tr_step(gs3_scene* scene, const float* grad_dev, const float* lr_per_group, int32_t step,
                             float epsilon, hipStream_t stream);
 
 /* PSNR 10 log10(1/MSE) of camera `cam`'s render against its target (host
- * double; synchronises). */
+ * double; synchronises): the reconstruction metric the Evaluations section
+ * reports on held-out views (the 3DGS train/test split). */
 gs3_status gs3_psnr(gs3_scene* scene, int32_t cam, double* psnr_out, hipStream_t stream);
 
 /* Image-space VJP for autograd: grad_dev (float[P][N]) = J_img^T cot_dev,
@@ -243,7 +272,10 @@ gs3_status gs3_scene_import(gs3_scene* scene, const float* x, const float* ghat,
  * named stages with HIP events on the stream each runs on.  Stage names
  * (comma separated; "all" = every stage; NULL or "" disables): project_fwd,
  * depth_sort, scan, emit_pairs, pair_sort, blend_fwd, blend_jvp, blend_bwd,
- * project_jvp, project_bwd, loss, tr_step, adam_step.  Blend stages also
+ * pair_sums (each Gaussian's backward partials summed), project_bwd (the
+ * chain rule into a gradient or Hutchinson diagonal), tr_update (the chain
+ * rule fused with the update in gs3_tr_iteration), project_jvp, loss,
+ * tr_step, adam_step.  Blend stages also
  * count their work on the device, with instrumented instances of their
  * kernels, unless gs3_profile_count(0) has switched counting off (then the
  * bracketed launches are the uninstrumented kernels every other call runs;

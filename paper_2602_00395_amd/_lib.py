@@ -47,6 +47,8 @@ _SIGS = {
     "gs3_scene_params": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "gs3_scene_set_params": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "gs3_scene_bytes": (c_int32, [POINTER(SceneDesc), POINTER(c_int64), POINTER(c_int64)]),
+    "gs3_scene_device_bytes": (c_int32, [c_void_p, POINTER(c_int64)]),
+    "gs3_trim_cache": (c_int32, []),
     "gs3_scene_sync": (c_int32, [c_void_p]),
     "gs3_render": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "gs3_bin": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int64, POINTER(c_int64), c_void_p]),

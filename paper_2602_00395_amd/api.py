@@ -75,6 +75,12 @@ def scene_bytes(n, sh_degree, cameras):
     return res.value, scr.value
 
 
+def trim_cache():
+    """Release the device blocks destroyed scenes left in the library's cache."""
+    lib = _lib.load()
+    _lib.check("gs3_trim_cache", lib.gs3_trim_cache())
+
+
 def profile_enable(names: str):
     """Bracket the named stages with HIP events (see gs3_profile_enable)."""
     lib = _lib.load()
@@ -171,6 +177,11 @@ class Scene:
 
     def sync(self):
         _lib.check("gs3_scene_sync", self.lib.gs3_scene_sync(self.handle))
+
+    def device_bytes(self) -> int:
+        out = c_int64()
+        _lib.check("gs3_scene_device_bytes", self.lib.gs3_scene_device_bytes(self.handle, byref(out)))
+        return int(out.value)
 
     # ------------------------------------------------------------------ the method
     def render(self, cam: int, out: torch.Tensor | None = None) -> torch.Tensor:

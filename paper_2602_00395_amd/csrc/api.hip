@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/gs3tr.h: scene ownership,
 // argument validation, per-view binning and the orchestration of one
 // optimizer iteration of 3DGS^2-TR (Algorithm 1) on a caller stream.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -9,6 +10,7 @@
 #include <string>
 #include <thread>
 #include <utility>
+#include <type_traits>
 #include <vector>
 
 #include "gs3_internal.h"
@@ -36,6 +38,13 @@ gs3_status fail(gs3_status code, const std::string& msg) {
   } while (0)
 
 constexpr int kMaxLossViews = 4096;
+// pinned host words of a scene: [0] the pair count of the view being binned,
+// [1] set by the update kernels when a gradient entry or an updated
+// parameter is not finite
+constexpr int kHostWords = 16;
+// Largest image side: fewer than 2^20 tiles per view, so that a scan block of
+// 4,096 Gaussians never sums to 2^32 tiles.
+constexpr int kMaxSide = 16368;
 
 // ---------------------------------------------------------------- profiler
 // HIP events around named stages, plus device work counters for the blends.
@@ -117,7 +126,7 @@ struct gs3_scene {
   float *x = nullptr, *targets = nullptr, *ghat = nullptr, *dhat = nullptr, *am = nullptr, *av = nullptr;
   // gs3_tr_iteration: the fused update writes x_alt (then the two swap); its
   // Hutchinson diagonal and the gradient of all but the last view
-  float *x_alt = nullptr, *dbuf = nullptr, *gacc = nullptr, *rad = nullptr;
+  float *x_alt = nullptr, *dbuf = nullptr, *gacc = nullptr;
   // per-Gaussian scratch
   Rec* rec = nullptr;
   uint2* rect = nullptr;
@@ -156,6 +165,8 @@ struct gs3_scene {
   const uint32_t* order = nullptr;  // Gaussians in depth order
   const uint32_t* sorted_tile = nullptr;
   int64_t n_pairs = 0;
+  // every buffer carved from the static scratch: nothing may be allocated
+  bool fixed_scratch = false;
 };
 
 namespace {
@@ -186,21 +197,165 @@ CamDev make_cam(const gs3_camera& c) {
   return d;
 }
 
-template <class T>
-gs3_status dalloc(T** p, size_t count) {
+// ---------------------------------------------------------------- memory
+// Device blocks that a scene gives back (its teardown, pair scratch it has
+// outgrown) stay in a process-wide cache instead of going back to the
+// runtime, whose free waits for every stream of the device; a block is handed
+// out again, to any scene, once the event recorded on the stream that last
+// used it has completed.  So neither a scene's teardown nor its growth waits
+// for another scene's stream.  The cache holds at most kCacheCap bytes (larger
+// surpluses are returned to the runtime at once) and gs3_trim_cache empties it.
+namespace mem {
+struct Block {
+  void* p;
+  size_t bytes;
+  int dev;
+  hipEvent_t ready;  // completed once the last user's work is done; NULL: ready
+};
+std::mutex mu;
+std::vector<Block> cached;
+size_t cached_bytes = 0;
+size_t cache_cap = (size_t)16 << 30;
+std::vector<std::pair<void*, size_t>> sizes;  // live block -> bytes
+
+size_t& live_size(void* p) {
+  for (auto& e : sizes)
+    if (e.first == p) return e.second;
+  sizes.emplace_back(p, 0);
+  return sizes.back().second;
+}
+
+bool is_ready(const Block& b) { return !b.ready || hipEventQuery(b.ready) == hipSuccess; }
+
+void drop(Block& b) {
+  if (b.ready) {
+    (void)hipEventSynchronize(b.ready);
+    (void)hipEventDestroy(b.ready);
+  }
+  (void)hipFree(b.p);
+}
+
+// smallest ready cached block of this device with bytes <= size <= 2 bytes
+void* take(size_t bytes, int dev) {
+  int best = -1;
+  for (int i = 0; i < (int)cached.size(); ++i) {
+    const Block& b = cached[i];
+    if (b.dev != dev || b.bytes < bytes || b.bytes > 2 * bytes) continue;
+    if (best >= 0 && cached[best].bytes <= b.bytes) continue;
+    if (!is_ready(b)) continue;
+    best = i;
+  }
+  if (best < 0) return nullptr;
+  Block b = cached[best];
+  cached.erase(cached.begin() + best);
+  cached_bytes -= b.bytes;
+  if (b.ready) (void)hipEventDestroy(b.ready);
+  live_size(b.p) = b.bytes;
+  return b.p;
+}
+
+void trim_locked(int dev) {
+  for (size_t i = 0; i < cached.size();) {
+    if (dev < 0 || cached[i].dev == dev) {
+      cached_bytes -= cached[i].bytes;
+      drop(cached[i]);
+      cached.erase(cached.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+gs3_status alloc(void** p, size_t bytes) {
   *p = nullptr;
-  if (count == 0) count = 1;
-  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GS3_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if ((*p = take(bytes, dev))) return GS3_OK;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    trim_locked(dev);  // the runtime may find room once the cache is empty
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+      return fail(GS3_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  live_size(*p) = bytes;
+  return GS3_OK;
+}
+
+// gives p back; `last_use` is the stream whose queued work may still use it
+// (NULL pointer: nothing in flight uses it any more)
+void release(void* p, const hipStream_t* last_use) {
+  if (!p) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  size_t bytes = 0;
+  for (size_t i = 0; i < sizes.size(); ++i)
+    if (sizes[i].first == p) {
+      bytes = sizes[i].second;
+      sizes.erase(sizes.begin() + i);
+      break;
+    }
+  Block b{p, bytes, dev, nullptr};
+  if (last_use) {
+    if (hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(b.ready, *last_use) != hipSuccess) {
+      if (b.ready) (void)hipEventDestroy(b.ready);
+      b.ready = nullptr;
+      (void)hipStreamSynchronize(*last_use);
+    }
+  }
+  if (bytes == 0 || cached_bytes + bytes > cache_cap) {
+    drop(b);
+    return;
+  }
+  cached.push_back(b);
+  cached_bytes += bytes;
+}
+// Pinned host buffers (the pair-count and non-finite words, loss sums) are
+// small; they are pooled by size and kept for the life of the process, since
+// freeing pinned memory can wait for the device as well.
+std::vector<std::pair<void*, size_t>> host_pool;
+
+gs3_status host_alloc(void** p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu);
+  for (size_t i = 0; i < host_pool.size(); ++i)
+    if (host_pool[i].second == bytes) {
+      *p = host_pool[i].first;
+      host_pool.erase(host_pool.begin() + i);
+      return GS3_OK;
+    }
+  if (hipHostMalloc(p, bytes, hipHostMallocDefault) != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
-    return fail(GS3_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    return fail(GS3_ENOMEM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed");
   }
   return GS3_OK;
 }
 
+void host_release(void* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(mu);
+  host_pool.emplace_back(p, bytes);
+}
+}  // namespace mem
+
 template <class T>
-void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+gs3_status dalloc(T** p, size_t count) {
+  void* v = nullptr;
+  const gs3_status rc = mem::alloc(&v, std::max<size_t>(count, 1) * sizeof(T));
+  *p = (T*)v;
+  return rc;
+}
+
+// frees p; st: the stream whose queued work may still read or write it
+template <class T>
+void dfree(T*& p, const hipStream_t* st = nullptr) {
+  mem::release((void*)p, st);
   p = nullptr;
 }
 
@@ -209,7 +364,6 @@ void free_all(gs3_scene* s) {
   dfree(s->x_alt);
   dfree(s->dbuf);
   dfree(s->gacc);
-  dfree(s->rad);
   dfree(s->targets);
   dfree(s->ghat);
   dfree(s->dhat);
@@ -248,8 +402,8 @@ void free_all(gs3_scene* s) {
   dfree(s->ssim_tmp);
   dfree(s->dpart);
   dfree(s->dsum);
-  if (s->host_u32) (void)hipHostFree(s->host_u32);
-  if (s->host_f64) (void)hipHostFree(s->host_f64);
+  mem::host_release(s->host_u32, kHostWords * sizeof(uint32_t));
+  mem::host_release(s->host_f64, sizeof(double) * kMaxLossViews);
   s->host_u32 = nullptr;
   s->host_f64 = nullptr;
   if (s->done_ev) (void)hipEventDestroy(s->done_ev);
@@ -283,21 +437,50 @@ gs3_status need_fused_state(gs3_scene* s, hipStream_t st) {
   if (!s->x_alt) GS3_TRY(dalloc(&s->x_alt, (size_t)PN));
   if (!s->dbuf) GS3_TRY(dalloc(&s->dbuf, (size_t)PN));
   if (!s->gacc) GS3_TRY(dalloc(&s->gacc, (size_t)PN));
-  if (!s->rad) GS3_TRY(dalloc(&s->rad, (size_t)(15 * s->N)));
   return GS3_OK;
 }
 
-gs3_status ensure_pairs(gs3_scene* s, int64_t n_pairs) {
+// Pair scratch reserved at scene creation: kPairsPerGaussian pairs per
+// Gaussian (the same estimate gs3_scene_bytes reports).  A view with more
+// pairs grows it; the outgrown blocks go back to the cache stream-ordered
+// (on `st`, behind the work that still reads them), so growing never waits
+// for the device.
+constexpr int64_t kPairsPerGaussian = 20;
+
+int64_t reserved_pairs(int64_t n) { return kPairsPerGaussian * n; }
+
+// bytes of pair scratch for a capacity of `cap` pairs on views of up to
+// max_tiles tiles: tile ids and Gaussian ids double-buffered, nine partials
+// per pair, the backward's units and segment states, the radix histograms
+int64_t pair_bytes(int64_t cap, int64_t max_tiles, int64_t n) {
+  return cap * (16 + 36) + seg_slots(max_tiles, cap) * (8 + 16 * GS3_BLOCK) +
+         (int64_t)radix_temp_bytes(std::max<int64_t>(cap, n)) + 4 * (cap / 256 + 1);
+}
+
+
+// capacity allocated for a view of n pairs: 25% slack
+int64_t pair_capacity(int64_t n_pairs) { return n_pairs + n_pairs / 4 + 4096; }
+
+// per-Gaussian and per-pixel scratch allocated at scene creation
+int64_t view_scratch_bytes(int64_t n, int64_t max_px, int64_t max_tiles) {
+  return 172 * n + (int64_t)scan_temp_bytes(n) + 16 + 12 * max_tiles + 44 * max_px +
+         4 * (int64_t)ssim_tmp_floats(1, (int)max_px) + 8 * (max_px * 3 / 256 + max_tiles + 1024) + 8 * kMaxLossViews;
+}
+
+gs3_status ensure_pairs(gs3_scene* s, int64_t n_pairs, const hipStream_t* st) {
   if (n_pairs <= s->pair_cap && s->rtmp) return GS3_OK;
-  const int64_t cap = std::max<int64_t>(n_pairs + n_pairs / 4 + 4096, s->pair_cap);
-  dfree(s->pt);
-  dfree(s->pg);
-  dfree(s->pt2);
-  dfree(s->pg2);
-  dfree(s->partials);
-  dfree(s->rtmp);
-  dfree(s->units);
-  dfree(s->seg);
+  if (s->fixed_scratch)
+    return fail(GS3_EINVAL, "the view has " + std::to_string(n_pairs) + " (Gaussian, tile) pairs; the static scratch holds " +
+                                std::to_string(s->pair_cap));
+  const int64_t cap = std::max<int64_t>(pair_capacity(n_pairs), s->pair_cap);
+  dfree(s->pt, st);
+  dfree(s->pg, st);
+  dfree(s->pt2, st);
+  dfree(s->pg2, st);
+  dfree(s->partials, st);
+  dfree(s->rtmp, st);
+  dfree(s->units, st);
+  dfree(s->seg, st);
   s->pair_cap = 0;
   GS3_TRY(dalloc(&s->pt, cap));
   GS3_TRY(dalloc(&s->pg, cap));
@@ -309,6 +492,18 @@ gs3_status ensure_pairs(gs3_scene* s, int64_t n_pairs) {
   s->rtmp_bytes = radix_temp_bytes(std::max<int64_t>(cap, s->N));
   GS3_TRY(dalloc((char**)&s->rtmp, s->rtmp_bytes));
   s->pair_cap = cap;
+  return GS3_OK;
+}
+
+// The offsets scan records the owner of every 256-pair block of the pair
+// capacity known before the view (the emission searches for the owners of
+// blocks beyond it), so this array follows the capacity one view later.
+gs3_status ensure_owner_blocks(gs3_scene* s, const hipStream_t* st) {
+  if (s->owner_blocks >= s->pair_cap / 256 + 1 || s->fixed_scratch) return GS3_OK;
+  dfree(s->block_owner, st);
+  s->owner_blocks = 0;
+  GS3_TRY(dalloc(&s->block_owner, (size_t)(s->pair_cap / 256 + 1)));
+  s->owner_blocks = s->pair_cap / 256 + 1;
   return GS3_OK;
 }
 
@@ -327,6 +522,8 @@ gs3_status check_cam(gs3_scene* s, int32_t cam) {
 // Value of the pinned pair-count word until the scan has written it (a pair
 // count never reaches it: pair indices are 32-bit).
 constexpr uint32_t kCountPending = 0xffffffffu;
+// Value the scan writes when the view's pair count does not fit 32 bits.
+constexpr uint32_t kCountOverflow = 0xfffffffeu;
 
 // Waits until the scan has written the pinned word: a short busy poll, then
 // polls that yield the thread; after 10 s, or if the stream reports an
@@ -358,15 +555,10 @@ int bits_for(int n_tiles) {
 
 // Project, sort by depth, emit pairs, sort pairs by tile, per-tile ranges.
 // Waits once for the pair count (see wait_count), not for the whole stream.
-gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
-  const CamDev cd = make_cam(s->cams[cam]);
+gs3_status bin_camera(gs3_scene* s, const gs3_camera& camera, int cam, hipStream_t st) {
+  const CamDev cd = make_cam(camera);
   const int64_t N = s->N;
-  if (s->pair_cap > 0 && s->owner_blocks < s->pair_cap / 256 + 1) {
-    dfree(s->block_owner);
-    s->owner_blocks = 0;
-    GS3_TRY(dalloc(&s->block_owner, (size_t)(s->pair_cap / 256 + 1)));
-    s->owner_blocks = s->pair_cap / 256 + 1;
-  }
+  GS3_TRY(ensure_owner_blocks(s, &st));
   auto p0 = prof::begin("project_fwd", st);
   launch_project_fwd(s->x, N, s->deg, cd, s->rec, s->rect, s->depth_key, s->tiles, st);
   prof::end(p0, st);
@@ -380,16 +572,26 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   // the scan stores the pair count into a pinned host word as soon as it is
   // known; the host waits for that word (not for the stream), so the
   // launches below are queued while the scan's last kernel still runs
-  volatile uint32_t* count_word = s->host_u32;
+  // (without a pinned word -- the allocation-free render -- the count is
+  // copied back and the stream synchronised)
+  uint32_t copied = kCountPending;
+  volatile uint32_t* count_word = s->host_u32 ? s->host_u32 : &copied;
   *count_word = kCountPending;
   std::atomic_thread_fence(std::memory_order_seq_cst);
   scan_exclusive_u32(s->counts, s->offsets, N, s->total_dev, s->stmp, st, s->block_owner, s->owner_blocks,
                      s->host_u32);
   prof::end(p2, st);
   GS3_LAUNCHED();
-  GS3_TRY(wait_count(count_word, st));
+  if (s->host_u32) {
+    GS3_TRY(wait_count(count_word, st));
+  } else {
+    GS3_HIP(hipMemcpyAsync(&copied, s->total_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GS3_HIP(hipStreamSynchronize(st));
+  }
+  if (*count_word == kCountOverflow)
+    return fail(GS3_EINVAL, "camera " + std::to_string(cam) + ": the view has 2^32 - 2 or more (Gaussian, tile) pairs");
   const int64_t n_pairs = *count_word;
-  GS3_TRY(ensure_pairs(s, n_pairs));
+  GS3_TRY(ensure_pairs(s, n_pairs, &st));
   auto p3 = prof::begin("emit_pairs", st);
   launch_emit_pairs(order, s->offsets, s->block_owner, s->owner_blocks, s->rec, s->rect, N, n_pairs, cd.tiles_x,
                     s->pt, s->pg, st);
@@ -409,11 +611,26 @@ gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) {
   return GS3_OK;
 }
 
+gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) { return bin_camera(s, s->cams[cam], cam, st); }
+
 gs3_status finish(gs3_scene* s, hipStream_t st) {
+  (void)s;
+  (void)st;
   GS3_LAUNCHED();
-  GS3_HIP(hipEventRecord(s->done_ev, st));
   return GS3_OK;
 }
+
+// Records the scene's completion event on the call's stream when an entry
+// point returns, whether it succeeded or failed after enqueuing work, so
+// that gs3_scene_sync and gs3_scene_destroy wait for everything the scene
+// has enqueued (and for nothing else).
+struct CallEnd {
+  gs3_scene* s;
+  hipStream_t st;
+  ~CallEnd() {
+    if (s && s->done_ev) (void)hipEventRecord(s->done_ev, st);
+  }
+};
 
 const float* target_of(gs3_scene* s, int cam) { return s->targets + s->tgt_off[cam]; }
 
@@ -441,9 +658,11 @@ void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st)
 
 void project_bwd(gs3_scene* s, const CamDev& cd, int mode, int acc, uint64_t seed, uint32_t i, float scale,
                  float* out, hipStream_t st, const FusedTr& ft = FusedTr{}) {
-  auto p = prof::begin("project_bwd", st);
-  launch_project_bwd(s->x, s->N, s->deg, cd, s->rec, s->order, s->offsets, s->counts, s->tiles, s->partials, s->gsum,
-                     mode, acc, seed, i, scale, out, ft, st);
+  auto ps = prof::begin("pair_sums", st);
+  launch_pair_sums(s->order, s->offsets, s->counts, s->partials, s->N, s->gsum, st);
+  prof::end(ps, st, s->N, s->n_pairs);
+  auto p = prof::begin(mode == 2 ? "tr_update" : "project_bwd", st);
+  launch_project_bwd(s->x, s->N, s->deg, cd, s->rec, s->tiles, s->gsum, mode, acc, seed, i, scale, out, ft, st);
   prof::end(p, st, s->N, 0);
 }
 
@@ -460,10 +679,11 @@ gs3_status validate_desc(const gs3_scene_desc* d) {
   if (params_for(d->sh_degree) < 0) return fail(GS3_EINVAL, "sh_degree must be 0..3");
   if (d->n_cameras < 1 || !d->cameras) return fail(GS3_EINVAL, "need at least one camera");
   if (!(d->lambda_dssim >= 0.f && d->lambda_dssim <= 1.f)) return fail(GS3_EINVAL, "lambda_dssim must be in [0, 1]");
+  if (d->flags != GS3_FLAG_NONE) return fail(GS3_EINVAL, "flags is reserved and must be 0");
   int n_train = 0;
   for (int j = 0; j < d->n_cameras; ++j) {
     const gs3_camera& c = d->cameras[j];
-    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+    if (c.width < 1 || c.height < 1 || c.width > kMaxSide || c.height > kMaxSide)
       return fail(GS3_EINVAL, "camera " + std::to_string(j) + " has an invalid size");
     if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(GS3_EINVAL, "camera " + std::to_string(j) + " has fx/fy <= 0");
     n_train += (!d->train_mask || d->train_mask[j]) ? 1 : 0;
@@ -486,27 +706,19 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
   GS3_TRY(validate_desc(d));
   if (!resident || !peak_scratch) return fail(GS3_EINVAL, "output pointers must not be NULL");
   const int64_t N = d->n_gaussians, P = params_for(d->sh_degree);
-  int64_t px_total = 0, max_px = 0;
+  int64_t px_total = 0, max_px = 0, max_tiles = 0;
   for (int j = 0; j < d->n_cameras; ++j) {
     const int64_t px = (int64_t)d->cameras[j].width * d->cameras[j].height;
     px_total += px;
     max_px = std::max(max_px, px);
-  }
-  // parameters, both buffers of the fused iteration, the EMAs, D_t and the
-  // gradient accumulator (the trust-region method; Adam instead needs its two
-  // moments) and the targets
-  *resident = 4 * P * N * 6 + 12 * px_total;
-  // records, tangent records, eight u32 arrays, the summed partials, the
-  // trust radius, per-pixel blend state, and pair buffers for about
-  // 16 tiles per Gaussian (4 u32 arrays + 9 partials per pair and an owner
-  // per 256 pairs, +25% slack) with the backward's segment units and states
-  const int64_t pairs = 20 * N;
-  int64_t max_tiles = 0;
-  for (int j = 0; j < d->n_cameras; ++j)
     max_tiles = std::max<int64_t>(max_tiles, (int64_t)((d->cameras[j].width + GS3_TILE - 1) / GS3_TILE) *
                                                  ((d->cameras[j].height + GS3_TILE - 1) / GS3_TILE));
-  *peak_scratch = 96 * N + 32 * N + 36 * N + 60 * N + pairs * (16 + 36) + pairs / 64 + 4 * max_px * 3 * 3 + 36 * max_px +
-                  8 * max_px + seg_slots(max_tiles, pairs) * (8 + 16 * GS3_BLOCK);
+  }
+  // the targets, the parameters, both buffers of the fused iteration, the
+  // EMAs, D_t and the gradient accumulator of the trust-region method (Adam
+  // instead holds two moments)
+  *resident = 12 * px_total + 4 * P * N * 6;
+  *peak_scratch = view_scratch_bytes(N, max_px, max_tiles) + pair_bytes(pair_capacity(reserved_pairs(N)), max_tiles, N);
   return GS3_OK;
 }
 
@@ -573,13 +785,13 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
   step(dalloc(&s->ssim_tmp, ssim_tmp_floats(1, (int)s->max_px)));
   step(dalloc(&s->dpart, s->max_px * 3 / 256 + s->max_tiles + 1024));
   step(dalloc(&s->dsum, kMaxLossViews));
-  if (rc == GS3_OK && hipHostMalloc((void**)&s->host_u32, 64, hipHostMallocDefault) != hipSuccess)
-    rc = fail(GS3_ENOMEM, "hipHostMalloc failed");
-  if (rc == GS3_OK && hipHostMalloc((void**)&s->host_f64, sizeof(double) * kMaxLossViews, hipHostMallocDefault) != hipSuccess)
-    rc = fail(GS3_ENOMEM, "hipHostMalloc failed");
+  if (rc == GS3_OK) rc = mem::host_alloc((void**)&s->host_u32, kHostWords * sizeof(uint32_t));
+  if (rc == GS3_OK) rc = mem::host_alloc((void**)&s->host_f64, sizeof(double) * kMaxLossViews);
+  if (rc == GS3_OK) s->host_u32[1] = 0u;
   if (rc == GS3_OK && hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming) != hipSuccess)
     rc = fail(GS3_EDEVICE, "hipEventCreate failed");
-  if (rc == GS3_OK) rc = ensure_pairs(s, 16 * s->N);
+  if (rc == GS3_OK) rc = ensure_pairs(s, reserved_pairs(s->N), nullptr);
+  if (rc == GS3_OK) rc = ensure_owner_blocks(s, nullptr);
   if (rc != GS3_OK) {
     free_all(s);
     delete s;
@@ -592,6 +804,7 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
   rc = copy(s->x, params_dev, PN * sizeof(float));
   if (rc == GS3_OK) rc = copy(s->targets, targets_dev, off * sizeof(float));
   if (rc == GS3_OK) rc = finish(s, st);
+  if (rc == GS3_OK && hipEventRecord(s->done_ev, st) != hipSuccess) rc = fail(GS3_EDEVICE, "hipEventRecord failed");
   if (rc != GS3_OK) {
     (void)hipStreamSynchronize(st);
     free_all(s);
@@ -604,10 +817,31 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
 
 gs3_status gs3_scene_destroy(gs3_scene* s) {
   if (!s) return fail(GS3_EINVAL, "scene is NULL");
+  // everything this scene enqueued precedes its completion event; its
+  // blocks go back to the cache, so nothing here waits for other streams
   if (s->done_ev) (void)hipEventSynchronize(s->done_ev);
-  (void)hipDeviceSynchronize();
   free_all(s);
   delete s;
+  return GS3_OK;
+}
+
+gs3_status gs3_scene_device_bytes(gs3_scene* s, int64_t* bytes) {
+  GS3_TRY(check_scene(s));
+  if (!bytes) return fail(GS3_EINVAL, "bytes is NULL");
+  const int64_t PN = (int64_t)s->P * s->N;
+  int64_t px_total = 0;
+  for (const auto& c : s->cams) px_total += (int64_t)c.width * c.height;
+  const float* state[7] = {s->ghat, s->dhat, s->am, s->av, s->x_alt, s->dbuf, s->gacc};
+  int64_t b = 12 * px_total + 4 * PN;
+  for (const float* v : state) b += v ? 4 * PN : 0;
+  b += view_scratch_bytes(s->N, s->max_px, s->max_tiles) + pair_bytes(s->pair_cap, s->max_tiles, s->N);
+  *bytes = b;
+  return GS3_OK;
+}
+
+gs3_status gs3_trim_cache(void) {
+  std::lock_guard<std::mutex> lk(mem::mu);
+  mem::trim_locked(-1);
   return GS3_OK;
 }
 
@@ -620,6 +854,7 @@ gs3_status gs3_scene_params(gs3_scene* s, float** p) {
 
 gs3_status gs3_scene_set_params(gs3_scene* s, const float* params_dev, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   if (!params_dev) return fail(GS3_EINVAL, "params_dev is NULL");
   GS3_HIP(hipMemcpyAsync(s->x, params_dev, (size_t)s->P * s->N * sizeof(float), hipMemcpyDeviceToDevice, st));
   return finish(s, st);
@@ -629,11 +864,17 @@ gs3_status gs3_scene_sync(gs3_scene* s) {
   GS3_TRY(check_scene(s));
   GS3_HIP(hipEventSynchronize(s->done_ev));
   GS3_HIP(hipGetLastError());
+  volatile uint32_t* flag = s->host_u32 + 1;
+  if (*flag) {
+    *flag = 0u;
+    return fail(GS3_ENONFINITE, "a gradient entry or an updated parameter was not finite since the last sync");
+  }
   return GS3_OK;
 }
 
 gs3_status gs3_render(gs3_scene* s, int32_t cam, float* rgb, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!rgb) return fail(GS3_EINVAL, "rgb_dev is NULL");
   GS3_TRY(bin_view(s, cam, st));
@@ -645,6 +886,7 @@ gs3_status gs3_render(gs3_scene* s, int32_t cam, float* rgb, hipStream_t st) {
 gs3_status gs3_bin(gs3_scene* s, int32_t cam, uint64_t* keys, uint32_t* gids, uint32_t* ranges, int64_t capacity,
                    int64_t* n_pairs, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!n_pairs) return fail(GS3_EINVAL, "n_pairs is NULL");
   GS3_TRY(bin_view(s, cam, st));
@@ -747,6 +989,7 @@ gs3_status check_hparams(const gs3_tr_hparams* hp) {
 gs3_status gs3_grad(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* grad, double* loss_out,
                     hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_views(s, cams, n_cams));
   if (!grad) return fail(GS3_EINVAL, "grad_dev is NULL");
   GS3_TRY(grad_views(s, cams, n_cams, grad, loss_out, nullptr, st));
@@ -756,6 +999,7 @@ gs3_status gs3_grad(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* gr
 gs3_status gs3_hvp_diag(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed, float* D,
                         hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_views(s, cams, n_cams));
   if (nu < 1) return fail(GS3_EINVAL, "nu must be >= 1");
   if (!D) return fail(GS3_EINVAL, "D_dev is NULL");
@@ -766,6 +1010,7 @@ gs3_status gs3_hvp_diag(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32
 gs3_status gs3_tr_iteration(gs3_scene* s, const int32_t* cams1, int32_t n1, const int32_t* cams2, int32_t n2,
                             int32_t nu, uint64_t seed, const gs3_tr_hparams* hp, double* loss_out, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_views(s, cams1, n1));
   if (n2 < 0 || (n2 > 0 && nu < 1)) return fail(GS3_EINVAL, "n2 must be >= 0 and nu >= 1 when n2 > 0");
   if (n2 > 0) GS3_TRY(check_views(s, cams2, n2));
@@ -773,11 +1018,11 @@ gs3_status gs3_tr_iteration(gs3_scene* s, const int32_t* cams1, int32_t n1, cons
   GS3_TRY(need_fused_state(s, st));
   if (n2 > 0) GS3_TRY(hvp_views(s, cams2, n2, nu, seed, s->dbuf, st));
   FusedTr ft;
-  ft.rad = s->rad;
   ft.x_out = s->x_alt;
   ft.ghat = s->ghat;
   ft.dhat = s->dhat;
   ft.D = n2 > 0 ? s->dbuf : nullptr;
+  ft.nonfinite = s->host_u32 + 1;
   ft.a = TrArgs{hp->theta1, hp->theta2, hp->epsilon, n2 > 0, hp->variant};
   GS3_TRY(grad_views(s, cams1, n1, s->gacc, loss_out, &ft, st));
   std::swap(s->x, s->x_alt);
@@ -787,12 +1032,13 @@ gs3_status gs3_tr_iteration(gs3_scene* s, const int32_t* cams1, int32_t n1, cons
 gs3_status gs3_tr_step(gs3_scene* s, const float* grad, const float* D, const gs3_tr_hparams* hp, float* eta_out,
                        float* dx_out, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   if (!grad) return fail(GS3_EINVAL, "grad_dev must not be NULL");
   GS3_TRY(check_hparams(hp));
   GS3_TRY(need_tr_state(s, st));
   TrArgs a{hp->theta1, hp->theta2, hp->epsilon, D != nullptr, hp->variant};
   auto p = prof::begin("tr_step", st);
-  launch_tr_step(s->x, grad, s->ghat, s->dhat, D, s->N, s->deg, a, eta_out, dx_out, st);
+  launch_tr_step(s->x, grad, s->ghat, s->dhat, D, s->N, s->deg, a, eta_out, dx_out, s->host_u32 + 1, st);
   prof::end(p, st, s->N, (int64_t)s->P * s->N);
   return finish(s, st);
 }
@@ -800,6 +1046,7 @@ gs3_status gs3_tr_step(gs3_scene* s, const float* grad, const float* D, const gs
 static gs3_status adam_common(gs3_scene* s, const float* grad, const float* lr, int32_t step, float epsilon,
                               hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   if (!grad || !lr) return fail(GS3_EINVAL, "grad_dev and lr_per_group must not be NULL");
   if (step < 1) return fail(GS3_EINVAL, "step is 1-based");
   AdamArgs a;
@@ -822,7 +1069,7 @@ static gs3_status adam_common(gs3_scene* s, const float* grad, const float* lr, 
   a.epsilon = epsilon;
   auto p = prof::begin("adam_step", st);
   GS3_TRY(need_adam_state(s, st));
-  launch_adam_step(s->x, grad, s->am, s->av, s->N, s->deg, a, st);
+  launch_adam_step(s->x, grad, s->am, s->av, s->N, s->deg, a, s->host_u32 + 1, st);
   prof::end(p, st, s->N, (int64_t)s->P * s->N);
   return finish(s, st);
 }
@@ -839,6 +1086,7 @@ gs3_status gs3_adam_tr_step(gs3_scene* s, const float* grad, const float* lr, in
 
 gs3_status gs3_psnr(gs3_scene* s, int32_t cam, double* out, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!out) return fail(GS3_EINVAL, "psnr_out is NULL");
   GS3_TRY(bin_view(s, cam, st));
@@ -857,6 +1105,7 @@ gs3_status gs3_psnr(gs3_scene* s, int32_t cam, double* out, hipStream_t st) {
 
 gs3_status gs3_render_vjp(gs3_scene* s, int32_t cam, const float* cot, float* grad, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!cot || !grad) return fail(GS3_EINVAL, "cot_dev and grad_dev must not be NULL");
   GS3_TRY(bin_view(s, cam, st));
@@ -869,6 +1118,7 @@ gs3_status gs3_render_vjp(gs3_scene* s, int32_t cam, const float* cot, float* gr
 
 gs3_status gs3_render_jvp(gs3_scene* s, int32_t cam, const float* tangent, float* rgb, float* tan, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!tangent || !rgb || !tan) return fail(GS3_EINVAL, "tangent_dev, rgb_dev and tan_dev must not be NULL");
   GS3_TRY(bin_view(s, cam, st));
@@ -880,6 +1130,7 @@ gs3_status gs3_render_jvp(gs3_scene* s, int32_t cam, const float* tangent, float
 
 gs3_status gs3_scene_export(gs3_scene* s, float* x, float* ghat, float* dhat, float* m, float* v, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   const size_t bytes = (size_t)s->P * s->N * sizeof(float);
   const float* src[5] = {s->x, s->ghat, s->dhat, s->am, s->av};
   float* dst[5] = {x, ghat, dhat, m, v};
@@ -897,6 +1148,7 @@ gs3_status gs3_scene_export(gs3_scene* s, float* x, float* ghat, float* dhat, fl
 gs3_status gs3_scene_import(gs3_scene* s, const float* x, const float* ghat, const float* dhat, const float* m,
                             const float* v, hipStream_t st) {
   GS3_TRY(check_scene(s));
+  CallEnd end_{s, st};
   const size_t bytes = (size_t)s->P * s->N * sizeof(float);
   if (ghat || dhat) GS3_TRY(need_tr_state(s, st));
   if (m || v) GS3_TRY(need_adam_state(s, st));

@@ -81,23 +81,25 @@ struct TrArgs {
 // summed gradient of a row is gacc (nullable) plus this view's part; the
 // update of Algorithm 1 writes x_out (x itself is only read), ghat, dhat
 struct FusedTr {
-  float* rad = nullptr;  // float[15][N] scratch for the radius
   float* x_out = nullptr;
   float* ghat = nullptr;
   float* dhat = nullptr;
   const float* D = nullptr;
   const float* gacc = nullptr;
+  uint32_t* nonfinite = nullptr;  // pinned host word set to 1 by a non-finite gradient or parameter
   TrArgs a{};
 };
-// order / offsets / counts: the view's depth order, first pair and tile count
-// per depth rank; gsum: float[n][9] scratch for the summed partials (a
-// Gaussian's nine values contiguous).
-// mode 0: out = (accumulate ? out : 0) + dL/dx; mode 1: out += scale z dL/dx
-// for probe i of `seed`; mode 2: the fused update described by ft
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* order,
-                        const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
-                        const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
-                        uint32_t probe_index, float scale, float* out, const FusedTr& ft, hipStream_t st);
+// Sum of each Gaussian's per-(Gaussian, tile) backward partials: order /
+// offsets / counts are the view's depth order, first pair and tile count per
+// depth rank; gsum: float[n][9] (a Gaussian's nine values contiguous).
+void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint32_t* counts, const float* partials,
+                      int64_t n, float* gsum, hipStream_t st);
+// Chain rule from gsum to the raw parameters.  mode 0: out = (accumulate ?
+// out : 0) + dL/dx; mode 1: out += scale z dL/dx for probe i of `seed`
+// (invisible Gaussians untouched); mode 2: the fused update described by ft.
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* tiles,
+                        const float* gsum, int mode, int accumulate, uint64_t seed, uint32_t probe_index, float scale,
+                        float* out, const FusedTr& ft, hipStream_t st);
 
 // sorting and binning
 size_t radix_temp_bytes(int64_t n);
@@ -173,14 +175,22 @@ void launch_sq_err(const float* img, const float* tgt, int64_t n, double* partia
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
 
 // optimizer
+// nonfinite (nullable): pinned host word that receives 1 where a gradient
+// entry or an updated parameter is not finite
 void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
-                    TrArgs a, float* eta_out, float* dx_out, hipStream_t st);
+                    TrArgs a, float* eta_out, float* dx_out, uint32_t* nonfinite, hipStream_t st);
 struct AdamArgs {
   float lr_row[64];
   float b1, b2, eps, bc1, bc2;
   float epsilon;  // > 0: clip by the trust-region radius (ADAM-TR)
 };
 void launch_adam_step(float* x, const float* grad, float* m, float* v, int64_t n, int deg, const AdamArgs& a,
-                      hipStream_t st);
+                      uint32_t* nonfinite, hipStream_t st);
+
+// Marks a non-finite value for the host: a system-scope store to a pinned
+// host word (several lanes storing the same 1 is harmless).
+__device__ __forceinline__ void note_nonfinite(uint32_t* word, float g, float x_new) {
+  if (word && !(isfinite(g) && isfinite(x_new))) __hip_atomic_store(word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);

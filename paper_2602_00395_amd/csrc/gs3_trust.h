@@ -44,14 +44,17 @@ __device__ __forceinline__ float sh_rest_abs_max(int deg) {
   return deg == 1 ? 0.8462843753216346f : (deg == 2 ? 2.145449272073426f : 3.926815898482296f);
 }
 
-__device__ __forceinline__ Radius trust_radius(const float* __restrict__ x, int64_t n, int64_t g, float eps,
-                                               uint32_t variant, int deg) {
+// Opacity of the radius: the same expression wherever a radius is formed.
+__device__ __forceinline__ float radius_alpha(const float* __restrict__ x, int64_t n, int64_t g) {
+  return 1.f / (1.f + expf(-x[10 * n + g]));
+}
+
+// Mean, log-scale, quaternion and opacity-logit radii of Gaussian g.
+__device__ __forceinline__ void radius_geo(const float* __restrict__ x, int64_t n, int64_t g, float eps,
+                                           uint32_t variant, float alpha, Radius& o) {
 #pragma clang fp contract(off)  // the same rounding in every translation unit that uses it
   const bool second = variant & GS3_TR_SECOND_ORDER;
-  const float k_s = second ? 8.f / 3.f : 2.f, k_q = second ? 16.f : 8.f, k_a = second ? 8.f : 4.f,
-              k_c = second ? 8.f : 4.f;
-  Radius o;
-  const float alpha = 1.f / (1.f + expf(-x[10 * n + g]));
+  const float k_s = second ? 8.f / 3.f : 2.f, k_q = second ? 16.f : 8.f, k_a = second ? 8.f : 4.f;
   const float s0 = expf(x[3 * n + g]), s1 = expf(x[4 * n + g]), s2 = expf(x[5 * n + g]);
   const float qx = x[6 * n + g], qy = x[7 * n + g], qz = x[8 * n + g], qw = x[9 * n + g];
   const float r2 = qx * qx + qy * qy + qz * qz + qw * qw;
@@ -64,9 +67,6 @@ __device__ __forceinline__ Radius trust_radius(const float* __restrict__ x, int6
   const float R20 = 2.f * (qx * qz - qw * qy) * ir2, R21 = 2.f * (qy * qz + qw * qx) * ir2,
               R22 = 1.f - 2.f * (qx * qx + qy * qy) * ir2;
   const float v0 = s0 * s0, v1 = s1 * s1, v2 = s2 * s2;
-  const float Sxx = R00 * R00 * v0 + R01 * R01 * v1 + R02 * R02 * v2;
-  const float Syy = R10 * R10 * v0 + R11 * R11 * v1 + R12 * R12 * v2;
-  const float Szz = R20 * R20 * v0 + R21 * R21 * v1 + R22 * R22 * v2;
   const float L = eps < alpha ? -log1pf(-eps / alpha) : INFINITY;
   if (variant & GS3_TR_MEAN_EXACT) {
     // (Sigma^-1)_cc = sum_k R_ck^2 / s_k^2
@@ -75,6 +75,9 @@ __device__ __forceinline__ Radius trust_radius(const float* __restrict__ x, int6
     o.mu[1] = sqrtf(8.f * L / (R10 * R10 * w0 + R11 * R11 * w1 + R12 * R12 * w2));
     o.mu[2] = sqrtf(8.f * L / (R20 * R20 * w0 + R21 * R21 * w1 + R22 * R22 * w2));
   } else {
+    const float Sxx = R00 * R00 * v0 + R01 * R01 * v1 + R02 * R02 * v2;
+    const float Syy = R10 * R10 * v0 + R11 * R11 * v1 + R12 * R12 * v2;
+    const float Szz = R20 * R20 * v0 + R21 * R21 * v1 + R22 * R22 * v2;
     o.mu[0] = sqrtf(8.f * Sxx * L);
     o.mu[1] = sqrtf(8.f * Syy * L);
     o.mu[2] = sqrtf(8.f * Szz * L);
@@ -91,6 +94,14 @@ __device__ __forceinline__ Radius trust_radius(const float* __restrict__ x, int6
     o.q[c] = beta > 0.f ? sqrtf(k_q * L / beta) : INFINITY;
   }
   o.logit = sqrtf(k_a * alpha * eps) / (alpha * (1.f - alpha));
+}
+
+// Colour radii of Gaussian g: the DC coefficient's (col) and the
+// view-dependent coefficients' (rest) per channel.
+__device__ __forceinline__ void radius_colour(const float* __restrict__ x, int64_t n, int64_t g, float eps,
+                                              uint32_t variant, int deg, float alpha, Radius& o) {
+#pragma clang fp contract(off)
+  const float k_c = (variant & GS3_TR_SECOND_ORDER) ? 8.f : 4.f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float base = 0.5f + SH_C0 * x[(int64_t)(11 + c) * n + g];
@@ -98,6 +109,14 @@ __device__ __forceinline__ Radius trust_radius(const float* __restrict__ x, int6
     o.col[c] = eta_c / SH_C0;
     o.rest[c] = (variant & GS3_TR_SH_JOINT) && deg > 0 ? eta_c / sh_rest_abs_max(deg) : o.col[c];
   }
+}
+
+__device__ __forceinline__ Radius trust_radius(const float* __restrict__ x, int64_t n, int64_t g, float eps,
+                                               uint32_t variant, int deg) {
+  Radius o;
+  const float alpha = radius_alpha(x, n, g);
+  radius_geo(x, n, g, eps, variant, alpha, o);
+  radius_colour(x, n, g, eps, variant, deg, alpha, o);
   return o;
 }
 
@@ -112,23 +131,31 @@ __device__ __forceinline__ float row_radius(const Radius& r, int row) {
 
 __device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
 
-// One row of the update of Algorithm 1 for entry k: the EMAs (D only on a
-// Hutchinson step), dx = -ghat / Dhat where Dhat > 0 (else -sign(ghat) eta,
-// or 0 if eta is infinite), clipped to [-eta, eta].  Returns the step.
-__device__ __forceinline__ float tr_update(float* __restrict__ ghat, float* __restrict__ dhat,
-                                           const float* __restrict__ D, int64_t k, float g, float eta,
-                                           const TrArgs& a) {
+// One row of the update of Algorithm 1 from its loaded state: the EMAs (D
+// only on a Hutchinson step), dx = -ghat / Dhat where Dhat > 0 (else
+// -sign(ghat) eta, or 0 if eta is infinite), clipped to [-eta, eta].
+// gh_io / dh_io hold the old EMAs on entry and the new ones on return.
+__device__ __forceinline__ float tr_row(float g, float& gh_io, float& dh_io, float D, float eta, const TrArgs& a) {
 #pragma clang fp contract(off)
-  const float gh = a.theta1 * ghat[k] + (1.f - a.theta1) * g;
-  float dh = dhat[k];
-  if (a.hutch) {
-    dh = a.theta2 * dh + (1.f - a.theta2) * D[k];
-    dhat[k] = dh;
-  }
-  ghat[k] = gh;
+  const float gh = a.theta1 * gh_io + (1.f - a.theta1) * g;
+  float dh = dh_io;
+  if (a.hutch) dh = a.theta2 * dh + (1.f - a.theta2) * D;
+  gh_io = gh;
+  dh_io = dh;
   const float newton = -gh / dh;
   const float dx = (dh > 0.f && isfinite(dh) && isfinite(newton)) ? newton : (isfinite(eta) ? -sgnf(gh) * eta : 0.f);
   return fminf(fmaxf(dx, -eta), eta);
+}
+
+// The same for entry k of the state arrays, loading and storing in place.
+__device__ __forceinline__ float tr_update(float* __restrict__ ghat, float* __restrict__ dhat,
+                                           const float* __restrict__ D, int64_t k, float g, float eta,
+                                           const TrArgs& a) {
+  float gh = ghat[k], dh = dhat[k];
+  const float step = tr_row(g, gh, dh, a.hutch ? D[k] : 0.f, eta, a);
+  ghat[k] = gh;
+  if (a.hutch) dhat[k] = dh;
+  return step;
 }
 
 __host__ __device__ constexpr int degree_of_rows(int P) { return P == 14 ? 0 : (P == 23 ? 1 : (P == 38 ? 2 : 3)); }

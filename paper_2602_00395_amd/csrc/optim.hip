@@ -22,7 +22,8 @@ template <int P>
 __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const float* __restrict__ grad,
                                                   float* __restrict__ ghat, float* __restrict__ dhat,
                                                   const float* __restrict__ D, int64_t n, TrArgs a,
-                                                  float* __restrict__ eta_out, float* __restrict__ dx_out) {
+                                                  float* __restrict__ eta_out, float* __restrict__ dx_out,
+                                                  uint32_t* nonfinite) {
   constexpr int R = (P + 3) / 4;
   const int64_t g = (int64_t)blockIdx.x * kGaussPerBlock + (threadIdx.x & 63);
   const int r0 = (threadIdx.x >> 6) * R;
@@ -41,8 +42,11 @@ __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const fl
       if (r >= P) break;
       const int64_t k = (int64_t)r * n + g;
       const float eta = row_radius(rad, r);
-      const float step = tr_update(ghat, dhat, D, k, grad[k], eta, a);
-      x[k] += step;
+      const float gk = grad[k];
+      const float step = tr_update(ghat, dhat, D, k, gk, eta, a);
+      const float xn = x[k] + step;
+      x[k] = xn;
+      note_nonfinite(nonfinite, gk, xn);
       if (eta_out) eta_out[k] = eta;
       if (dx_out) dx_out[k] = step;
     }
@@ -58,7 +62,7 @@ __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const fl
 template <int P>
 __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const float* __restrict__ grad,
                                                     float* __restrict__ m, float* __restrict__ v, int64_t n,
-                                                    AdamArgs a) {
+                                                    AdamArgs a, uint32_t* nonfinite) {
   constexpr int R = (P + 3) / 4;
   const int64_t g = (int64_t)blockIdx.x * kGaussPerBlock + (threadIdx.x & 63);
   const int r0 = (threadIdx.x >> 6) * R;
@@ -88,7 +92,9 @@ __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const 
         const float eta = row_radius(rad, r);
         step = fminf(fmaxf(step, -eta), eta);
       }
-      x[k] += step;
+      const float xn = x[k] + step;
+      x[k] = xn;
+      note_nonfinite(nonfinite, gr, xn);
     }
   };
   switch (r0 / R) {
@@ -110,13 +116,13 @@ __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const 
   }
 
 void launch_tr_step(float* x, const float* grad, float* ghat, float* dhat, const float* D, int64_t n, int deg,
-                    TrArgs a, float* eta_out, float* dx_out, hipStream_t st) {
+                    TrArgs a, float* eta_out, float* dx_out, uint32_t* nonfinite, hipStream_t st) {
   const dim3 grid((unsigned)((n + kGaussPerBlock - 1) / kGaussPerBlock));
-  GS3_P_DISPATCH(deg, k_tr_step, grid, dim3(256), 0, st, x, grad, ghat, dhat, D, n, a, eta_out, dx_out);
+  GS3_P_DISPATCH(deg, k_tr_step, grid, dim3(256), 0, st, x, grad, ghat, dhat, D, n, a, eta_out, dx_out, nonfinite);
 }
 
 void launch_adam_step(float* x, const float* grad, float* m, float* v, int64_t n, int deg, const AdamArgs& a,
-                      hipStream_t st) {
+                      uint32_t* nonfinite, hipStream_t st) {
   const dim3 grid((unsigned)((n + kGaussPerBlock - 1) / kGaussPerBlock));
-  GS3_P_DISPATCH(deg, k_adam_step, grid, dim3(256), 0, st, x, grad, m, v, n, a);
+  GS3_P_DISPATCH(deg, k_adam_step, grid, dim3(256), 0, st, x, grad, m, v, n, a, nonfinite);
 }

@@ -19,6 +19,8 @@
 // The backward pass is the same chain written out in reverse (adjoint) mode,
 // one pass per Gaussian for the mean, log-scale, quaternion and opacity rows
 // (the view direction of the SH colour included); SH rows have closed forms.
+#include <type_traits>
+
 #include "gs3_trust.h"
 
 namespace {
@@ -382,39 +384,6 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
   }
 }
 
-// Trust-region radius of every Gaussian from the parameters before the
-// update, for the fused update: rad[c][g] for the 15 components of
-// gs3trust::Radius (mu 0-2, log-scale 3, quaternion 4-7, logit 8, colour
-// 9-11, view-dependent SH 12-14).
-template <int DEG>
-__global__ __launch_bounds__(256) void k_trust_radius(const float* __restrict__ x, int64_t n, float eps,
-                                                       uint32_t variant, float* __restrict__ rad) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const gs3trust::Radius r = gs3trust::trust_radius(x, n, g, eps, variant, DEG);
-  const float v[15] = {r.mu[0], r.mu[1], r.mu[2], r.ls, r.q[0], r.q[1], r.q[2], r.q[3],
-                       r.logit, r.col[0], r.col[1], r.col[2], r.rest[0], r.rest[1], r.rest[2]};
-#pragma unroll
-  for (int c = 0; c < 15; ++c) rad[(int64_t)c * n + g] = v[c];
-}
-
-__device__ __forceinline__ int radius_component(int row) {
-  if (row < 3) return row;
-  if (row < 6) return 3;
-  if (row < 10) return row - 2;
-  if (row == 10) return 8;
-  if (row < 14) return row - 2;
-  return 12 + (row - 11) % 3;
-}
-
-// SH coefficients per role of the projection backward (role 0 takes the
-// eleven geometric and opacity rows)
-constexpr int kShPerRole = 4;
-template <int DEG>
-constexpr int bwd_roles() {
-  return 1 + ((DEG + 1) * (DEG + 1) + kShPerRole - 1) / kShPerRole;
-}
-
 // Reverse-mode derivative of project_geo: from the summed screen-space
 // partials G[0..4] (d/du, d/dv, d/dconic a, b, c) to the mean (3),
 // log-scale (3) and quaternion (4) rows, out[0..9].  Every intermediate is
@@ -584,94 +553,192 @@ __device__ __forceinline__ void sh_grad(int k, float x, float y, float z, float 
   gr[2] = c;
 }
 
-// Output of row r of Gaussian g (see launch_project_bwd for the modes).
-__device__ __forceinline__ void emit_row(const float* __restrict__ x, int64_t n, int64_t g, int r, float v, int mode,
-                                         int accumulate, uint64_t inner, float scale, float* __restrict__ out,
-                                         const FusedTr& ft) {
-  const int64_t k = (int64_t)r * n + g;
-  if (mode == 0) {
-    out[k] = accumulate ? out[k] + v : v;
-  } else if (mode == 1) {
-    out[k] += scale * probe_sign(inner, (uint64_t)k) * v;
-  } else {
-    // the update of Algorithm 1; x is only read, the update goes to x_out
-    const float gk = ft.gacc ? ft.gacc[k] + v : v;
-    const float eta = ft.rad[(int64_t)radius_component(r) * n + g];
-    ft.x_out[k] = x[k] + gs3trust::tr_update(ft.ghat, ft.dhat, ft.D, k, gk, eta, ft.a);
+// Rows of the projection backward per wave: a workgroup takes 64 consecutive
+// Gaussians (lane = Gaussian, so every row access of a wave is one coalesced
+// 256-byte transaction) and its four waves split the rows of those
+// Gaussians: wave 0 the mean, log-scale, quaternion and opacity rows (0..10),
+// waves 1..3 the SH coefficients [sh_lo(w), sh_lo(w + 1)) in three near-equal
+// runs (K = 16 at degree 3: 6, 5, 5 coefficients, 18, 15, 15 rows).
+constexpr int kBwdGauss = 64;
+template <int DEG>
+__host__ __device__ constexpr int sh_lo(int w) {
+  return w >= 4 ? (DEG + 1) * (DEG + 1) : ((w - 1) * (DEG + 1) * (DEG + 1) + 2) / 3;
+}
+
+// What a wave does with the gradient v of its rows (see launch_project_bwd):
+// mode 0 writes (or adds to) out, mode 1 adds scale z v to out for the probe
+// z, mode 2 applies the update of Algorithm 1.  Rows go in chunks of kChunk:
+// every load of a chunk is issued before any of its stores (the state arrays
+// may alias as far as the compiler knows, so loads would otherwise wait for
+// the previous row's stores), which keeps up to 5 x kChunk loads in flight
+// per wave without the registers of all rows at once.
+constexpr int kChunk = 6;
+
+template <int R, class RowOf, class ValOf, class EtaOf>
+__device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n, int64_t g, int mode, int accumulate,
+                                          uint64_t inner, float scale, float* __restrict__ out, const FusedTr& ft,
+                                          const RowOf& row_of, const ValOf& val_of, const EtaOf& eta_of) {
+#pragma unroll
+  for (int c0 = 0; c0 < R; c0 += kChunk) {
+    constexpr int C = kChunk;
+    if (mode == 0) {
+      float o[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if (c0 + j < R) o[j] = accumulate ? out[(int64_t)row_of(c0 + j) * n + g] : 0.f;
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if (c0 + j < R) out[(int64_t)row_of(c0 + j) * n + g] = accumulate ? o[j] + val_of(c0 + j) : val_of(c0 + j);
+    } else if (mode == 1) {
+      float o[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if (c0 + j < R) o[j] = out[(int64_t)row_of(c0 + j) * n + g];
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if (c0 + j < R) {
+          const int64_t k = (int64_t)row_of(c0 + j) * n + g;
+          out[k] = o[j] + scale * probe_sign(inner, (uint64_t)k) * val_of(c0 + j);
+        }
+    } else {
+      const TrArgs& a = ft.a;
+      float xv[C], gh[C], dh[C], dv[C], ga[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if (c0 + j < R) {
+          const int64_t k = (int64_t)row_of(c0 + j) * n + g;
+          xv[j] = x[k];
+          gh[j] = ft.ghat[k];
+          dh[j] = ft.dhat[k];
+          dv[j] = a.hutch ? ft.D[k] : 0.f;
+          ga[j] = ft.gacc ? ft.gacc[k] : 0.f;
+        }
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if (c0 + j < R) {
+          const int64_t k = (int64_t)row_of(c0 + j) * n + g;
+          // the view's part added to the other views' sum, as the separate
+          // gradient accumulates it
+          const float gk = ft.gacc ? ga[j] + val_of(c0 + j) : val_of(c0 + j);
+          const float xn = xv[j] + gs3trust::tr_row(gk, gh[j], dh[j], dv[j], eta_of(c0 + j), a);
+          ft.x_out[k] = xn;
+          ft.ghat[k] = gh[j];
+          if (a.hutch) ft.dhat[k] = dh[j];
+          note_nonfinite(ft.nonfinite, gk, xn);
+        }
+    }
   }
 }
 
 // Chain rule from the summed screen-space partials G (d/du, d/dv, d/dconic
-// a, b, c, d/dalpha, d/drgb) to the raw parameters.  blockIdx.y picks the
-// work of a thread: 0 the mean, log-scale, quaternion and opacity rows --
-// the reverse-mode pass (geo_vjp), the colour's dependence on the mean
-// through the view direction dir = (mu - campos) / |mu - campos| (sum_k
-// (sum_c g_c f_kc) grad Y_k(dir), projected on the plane normal to dir and
-// divided by |mu - campos|) and d alpha / d logit = s (1 - s); 1.. four SH
-// coefficients each, d rgb_c / d f_kc = Y_k(dir) where the colour clamp is
-// inactive.  One thread per (Gaussian, role) keeps more waves in flight
-// than one thread per Gaussian walking every row.
+// a, b, c, d/dalpha, d/drgb) to the raw parameters.  Wave 0: the reverse-mode
+// pass through the projection (geo_vjp), d alpha / d logit = s (1 - s), and
+// the colour's dependence on the mean through the view direction dir =
+// (mu - campos) / |mu - campos|: sum_k (sum_c g_c f_kc) grad Y_k(dir),
+// projected on the plane normal to dir and divided by |mu - campos|.  Waves
+// 1..3: d rgb_c / d f_kc = Y_k(dir) where the colour clamp is inactive, and
+// their coefficients' share of that direction term, passed to wave 0 through
+// LDS and summed in wave order.  In mode 2 each wave forms the trust-region
+// radii of its rows from the parameters before the update (the same
+// expressions as the separate update kernel), so the update needs no radius
+// pass of its own.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
                                                       const float* __restrict__ G, int mode, int accumulate,
                                                       uint64_t inner, float scale, float* __restrict__ out,
                                                       FusedTr ft) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int role = blockIdx.y;
-  // this role's rows: [r0, r1)
-  const int r0 = role == 0 ? 0 : 11 + 3 * kShPerRole * (role - 1);
-  const int r1 = role == 0 ? 11 : min(11 + 3 * K, r0 + 3 * kShPerRole);
-  if (tiles[g] == 0u) {  // no gradient from this view
-    if (mode == 2 || (mode == 0 && !accumulate))
-      for (int r = r0; r < r1; ++r) emit_row(x, n, g, r, 0.f, mode, accumulate, inner, scale, out, ft);
-    return;
+  __shared__ float gdir_part[3][3][kBwdGauss];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t g = (int64_t)blockIdx.x * kBwdGauss + lane;
+  const bool live = g < n;
+  const bool vis = live && tiles[g] != 0u;
+  auto xr = [&](int r) { return x[(int64_t)r * n + g]; };
+  // view direction and the unclamped colour cotangents
+  float gc[3] = {0.f, 0.f, 0.f}, e[3] = {0.f, 0.f, 0.f}, inv = 0.f;
+  if (vis) {
+    const uint32_t posm = __float_as_uint(rec[g].c.w);
+    const float* Gg = G + g * 9;
+    gc[0] = (posm & 1u) ? Gg[6] : 0.f;
+    gc[1] = (posm & 2u) ? Gg[7] : 0.f;
+    gc[2] = (posm & 4u) ? Gg[8] : 0.f;
+    const float dx = xr(0) - cam.campos[0], dy = xr(1) - cam.campos[1], dz = xr(2) - cam.campos[2];
+    inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
+    e[0] = dx * inv;
+    e[1] = dy * inv;
+    e[2] = dz * inv;
   }
-  auto Gk = [&](int k) { return G[(int64_t)g * 9 + k]; };
-  const uint32_t posm = __float_as_uint(rec[g].c.w);
-  const float gc[3] = {(posm & 1u) ? Gk(6) : 0.f, (posm & 2u) ? Gk(7) : 0.f, (posm & 4u) ? Gk(8) : 0.f};
-  const float dx = x[g] - cam.campos[0], dy = x[n + g] - cam.campos[1], dz = x[2 * n + g] - cam.campos[2];
-  const float inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
-  const float e[3] = {dx * inv, dy * inv, dz * inv};
-  if (role == 0) {
-    const float Gs[5] = {Gk(0), Gk(1), Gk(2), Gk(3), Gk(4)};
-    float d[10];
-    geo_vjp(x, n, g, cam, Gs, d);
-    if (DEG > 0) {
-      float gdir[3] = {0.f, 0.f, 0.f};
+  const float eps = ft.a.epsilon;
+  const uint32_t variant = ft.a.variant;
+  if (w > 0) {
+    // the wave's coefficient run as compile-time indices, so the basis
+    // values and radii stay in registers
+    auto run = [&](auto wave) {
+      constexpr int W = decltype(wave)::value;
+      constexpr int k0 = sh_lo<DEG>(W), k1 = sh_lo<DEG>(W + 1);
+      float Y[K];
+      float part[3] = {0.f, 0.f, 0.f};
+      if (vis) {
+        sh_basis<float, DEG>(e[0], e[1], e[2], Y);
+        // this wave's share of the direction term, coefficients in order
 #pragma unroll
-      for (int k = 1; k < K; ++k) {
-        const float gy = (gc[0] * x[(int64_t)(11 + 3 * k) * n + g] + gc[1] * x[(int64_t)(12 + 3 * k) * n + g]) +
-                         gc[2] * x[(int64_t)(13 + 3 * k) * n + g];
-        float gr[3];
-        sh_grad(k, e[0], e[1], e[2], gr);
+        for (int k = k0; k < k1; ++k) {
+          if (k == 0) continue;
+          const float gy = (gc[0] * xr(11 + 3 * k) + gc[1] * xr(12 + 3 * k)) + gc[2] * xr(13 + 3 * k);
+          float gr[3];
+          sh_grad(k, e[0], e[1], e[2], gr);
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) gdir[ax] += gy * gr[ax];
+          for (int ax = 0; ax < 3; ++ax) part[ax] += gy * gr[ax];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) Y[k] = 0.f;
       }
-      const float ed = (e[0] * gdir[0] + e[1] * gdir[1]) + e[2] * gdir[2];
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) d[ax] += (gdir[ax] - e[ax] * ed) * inv;
-    }
-#pragma unroll
-    for (int r = 0; r < 10; ++r) emit_row(x, n, g, r, d[r], mode, accumulate, inner, scale, out, ft);
-    const float s = sigmoid_(x[10 * n + g]);
-    emit_row(x, n, g, 10, Gk(5) * s * (1.f - s), mode, accumulate, inner, scale, out, ft);
+      for (int ax = 0; ax < 3; ++ax) gdir_part[W - 1][ax][lane] = part[ax];
+      __syncthreads();
+      // an invisible Gaussian adds nothing to an accumulated output
+      if (!live || (!vis && (mode == 1 || (mode == 0 && accumulate)))) return;
+      if constexpr (k1 > k0) {
+        gs3trust::Radius rad;
+        if (mode == 2) gs3trust::radius_colour(x, n, g, eps, variant, DEG, gs3trust::radius_alpha(x, n, g), rad);
+        emit_rows<3 * (k1 - k0)>(
+            x, n, g, mode, accumulate, inner, scale, out, ft, [&](int i) { return 11 + 3 * k0 + i; },
+            [&](int i) { return gc[i % 3] * Y[k0 + i / 3]; },
+            [&](int i) { return k0 + i / 3 == 0 ? rad.col[i % 3] : rad.rest[i % 3]; });
+      }
+    };
+    if (w == 1) run(std::integral_constant<int, 1>{});
+    else if (w == 2) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 3>{});
     return;
   }
-  // the SH basis at the view direction (same expressions as the forward's
-  // colour) and the forward's clamp mask: no SH coefficient is read
-  float Y[K];
-  sh_basis<float, DEG>(e[0], e[1], e[2], Y);
-  const int k0 = kShPerRole * (role - 1);
+  // wave 0: geometry and opacity
+  float d[11];
 #pragma unroll
-  for (int kk = 0; kk < kShPerRole; ++kk) {
-    const int k = k0 + kk;
-    if (k >= K) break;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) emit_row(x, n, g, 11 + 3 * k + c, gc[c] * Y[k], mode, accumulate, inner, scale, out, ft);
+  for (int r = 0; r < 11; ++r) d[r] = 0.f;
+  if (vis) {
+    const float* Gg = G + g * 9;
+    const float Gs[5] = {Gg[0], Gg[1], Gg[2], Gg[3], Gg[4]};
+    geo_vjp(x, n, g, cam, Gs, d);
+    const float s = sigmoid_(xr(10));
+    d[10] = Gg[5] * s * (1.f - s);
   }
+  __syncthreads();
+  if (vis && DEG > 0) {
+    float gdir[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) gdir[ax] = (gdir_part[0][ax][lane] + gdir_part[1][ax][lane]) + gdir_part[2][ax][lane];
+    const float ed = (e[0] * gdir[0] + e[1] * gdir[1]) + e[2] * gdir[2];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) d[ax] += (gdir[ax] - e[ax] * ed) * inv;
+  }
+  if (!live || (!vis && (mode == 1 || (mode == 0 && accumulate)))) return;
+  gs3trust::Radius rad;
+  if (mode == 2) gs3trust::radius_geo(x, n, g, eps, variant, gs3trust::radius_alpha(x, n, g), rad);
+  emit_rows<11>(x, n, g, mode, accumulate, inner, scale, out, ft, [](int i) { return i; },
+                [&](int i) { return d[i]; }, [&](int i) { return gs3trust::row_radius(rad, i); });
 }
 
 uint64_t probe_inner(uint64_t seed, uint32_t i) {
@@ -707,17 +774,15 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
                    probe_inner(seed, probe_index), tangent, trec);
 }
 
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* order,
-                        const uint32_t* offsets, const uint32_t* counts, const uint32_t* tiles,
-                        const float* partials, float* gsum, int mode, int accumulate, uint64_t seed,
-                        uint32_t probe_index, float scale, float* out, const FusedTr& ft, hipStream_t st) {
+void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint32_t* counts, const float* partials,
+                      int64_t n, float* gsum, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_pair_partials, dim3(blocks_for(n, kSumRanks)), dim3(256), 0, st, order, offsets, counts,
                      partials, n, gsum);
-  if (mode == 2)
-    GS3_DEG_DISPATCH(deg, k_trust_radius, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, ft.a.epsilon,
-                     ft.a.variant, ft.rad);
-  const unsigned roles = deg == 0 ? bwd_roles<0>() : (deg == 1 ? bwd_roles<1>() : (deg == 2 ? bwd_roles<2>()
-                                                                                            : bwd_roles<3>()));
-  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, 256), roles), dim3(256), 0, st, x, n, cam, rec, tiles,
+}
+
+void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* tiles,
+                        const float* gsum, int mode, int accumulate, uint64_t seed, uint32_t probe_index, float scale,
+                        float* out, const FusedTr& ft, hipStream_t st) {
+  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, cam, rec, tiles,
                    gsum, mode, accumulate, probe_inner(seed, probe_index), scale, out, ft);
 }

@@ -77,10 +77,15 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __rest
 // total_host (nullable): pinned host word that also receives the total, with
 // a system-scope store (written through to memory; nothing else needs to be
 // visible with it), so the host can read it while the rest of
-// the scan still runs
+// the scan still runs.  The total is summed in 64 bits (each block sum fits
+// 32 bits: a view has fewer than 2^20 tiles); a total of 0xfffffffe or more
+// is reported as 0xfffffffe in both words, and the host refuses the view.
 __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ block_sums, int nb,
                                                         uint32_t* __restrict__ total, uint32_t* total_host) {
+  __shared__ unsigned long long sum64;
+  if (threadIdx.x == 0) sum64 = 0ull;
   uint32_t running = 0;
+  uint64_t mine = 0;
   for (int base = 0; base < nb; base += kThreads) {
     const int i = base + threadIdx.x;
     const uint32_t v = i < nb ? block_sums[i] : 0u;
@@ -88,10 +93,14 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bl
     const uint32_t ex = block_excl_scan(v, &tot);
     if (i < nb) block_sums[i] = running + ex;
     running += tot;
+    mine += v;
   }
+  atomicAdd(&sum64, (unsigned long long)mine);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    *total = running;
-    if (total_host) __hip_atomic_store(total_host, running, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint32_t t = sum64 >= 0xfffffffeull ? 0xfffffffeu : (uint32_t)sum64;
+    *total = t;
+    if (total_host) __hip_atomic_store(total_host, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 

@@ -52,6 +52,7 @@ class FitResult:
     reached: bool
     n: int
     final_params: object = None
+    error: str | None = None  # set when the fit raised; such a request counts as failed
 
     @property
     def latency_s(self) -> float:
@@ -65,9 +66,19 @@ class ServerStats:
     budget: int = 0
     wall_s: float = 0.0
 
+    @property
+    def failed(self) -> list:
+        return [r for r in self.results if r.error is not None]
+
     def percentile(self, q: float) -> float:
-        lat = np.array([r.latency_s for r in self.results])
-        return float(np.percentile(lat, q)) if len(lat) else float("nan")
+        """Latency percentile over every request; a failed request counts as
+        never finishing (+inf), so failures can only raise the figure (with
+        failures present the percentile takes the next sample up instead of
+        interpolating, which would mix inf into finite values)."""
+        lat = np.array([r.latency_s if r.error is None else np.inf for r in self.results])
+        if not len(lat):
+            return float("nan")
+        return float(np.percentile(lat, q, method="higher" if np.isinf(lat).any() else "linear"))
 
     def gaussian_updates_per_s(self) -> float:
         tot = sum(r.iters * r.n for r in self.results)
@@ -125,11 +136,14 @@ class Server:
         queue = list(reqs)
 
         def worker(req: FitRequest, start_s: float):
-            stream = self.stream_factory()
             try:
+                stream = self.stream_factory()
                 it, psnr, reached, params = fit_fn(req, stream, self.keep_params, self.trainer_factory)
                 end = self.clock() - t0
                 res = FitResult(req.rid, req.arrival_s, start_s, end, it, psnr, reached, req.n, params)
+            except Exception as e:  # recorded, not dropped: the stats count it as a failure
+                res = FitResult(req.rid, req.arrival_s, start_s, self.clock() - t0, 0, float("nan"), False, req.n,
+                                None, error=f"{type(e).__name__}: {e}")
             finally:
                 with self._cv:
                     self._in_use -= req.bytes_needed

@@ -115,13 +115,17 @@ def mean_psnr(scene: Scene, ids) -> float:
 
 
 def fit(trainer, scene: Scene, test_ids, iters: int, eval_every: int = 500, target_psnr: float | None = None,
-        log=None):
-    """Run `iters` iterations; evaluate every `eval_every`.  The clock counts
-    training only (evaluation excluded).  Returns (history, seconds to target)."""
+        log=None, interpolate: bool = False):
+    """Run `iters` iterations; evaluate the held-out PSNR every `eval_every`.
+    The clock counts training only (evaluation excluded).  Returns (history,
+    seconds to target): the training time of the first evaluation at or above
+    the target, or with `interpolate` the time at which the PSNR line between
+    that evaluation and the one before it crosses the target."""
     hist = []
     train_s = 0.0
     reached = None
     done = 0
+    prev = (0, 0.0, mean_psnr(scene, test_ids)) if interpolate else None
     while done < iters:
         n = min(eval_every, iters - done)
         torch.cuda.synchronize()
@@ -137,4 +141,8 @@ def fit(trainer, scene: Scene, test_ids, iters: int, eval_every: int = 500, targ
             log(f"iter {done} train_s {train_s:.2f} psnr {p:.3f}")
         if target_psnr is not None and reached is None and p >= target_psnr:
             reached = train_s
+            if interpolate and prev is not None and prev[2] < target_psnr:
+                f = (target_psnr - prev[2]) / (p - prev[2])
+                reached = prev[1] + f * (train_s - prev[1])
+        prev = (done, train_s, p)
     return hist, reached

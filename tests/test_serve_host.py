@@ -61,3 +61,20 @@ def test_slot_limit_and_oversized_request():
     assert active["max"] <= 3 and len(st.results) == 9
     with pytest.raises(ValueError):
         Server(hbm_budget=10, stream_factory=lambda: None).run([_req(0, 0.0, 11, 0.0)], fit_fn=fake_fit)
+
+
+def test_failed_fit_is_recorded_and_counts_against_latency():
+    def fake_fit(req, stream, keep, tf):
+        time.sleep(0.01)
+        if req.rid == 2:
+            raise RuntimeError("device lost")
+        return 5, 25.0, True, None
+
+    reqs = [_req(i, 0.0, 10, 0.01) for i in range(4)]
+    st = Server(hbm_budget=100, max_active=2, stream_factory=lambda: None).run(reqs, fit_fn=fake_fit)
+    assert len(st.results) == 4
+    assert [r.rid for r in st.failed] == [2] and "device lost" in st.failed[0].error
+    assert not st.failed[0].reached
+    # a failure is an unfinished request: the p99 over 4 requests then is not finite
+    assert st.percentile(99) == float("inf")
+    assert st.percentile(25) < 1.0
