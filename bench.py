@@ -390,7 +390,16 @@ def main():
     import torch
 
     from paper_2602_00395_amd import Scene, profile_count, profile_enable, profile_read, profile_reset
+    from paper_2602_00395_amd.api import trim_cache
     from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer, mean_psnr
+
+    def free_after_trim():
+        # blocks of destroyed scenes wait in the library's cache: release them
+        # so the drop in free memory counts only what the next scene takes
+        torch.cuda.synchronize()
+        trim_cache()
+        torch.cuda.empty_cache()
+        return torch.cuda.mem_get_info()[0]
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
@@ -436,8 +445,7 @@ def main():
 
     # ---- timed TR iterations: the dominant stage's launches are bracketed by
     # events only, so they run the same kernels as every other launch
-    torch.cuda.synchronize()
-    free0 = torch.cuda.mem_get_info()[0]
+    free0 = free_after_trim()
     s = make()
     tr = TRTrainer(s, train_ids, cfg)
     for _ in range(args.warmup):
@@ -487,15 +495,14 @@ def main():
                     args.workload)
 
     # ---- Adam on the same views, same clock
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()
-    free0 = torch.cuda.mem_get_info()[0]
+    free0 = free_after_trim()
     s = make()
     ad = AdamTrainer(s, train_ids, extent_of(cams))
     for _ in range(args.warmup):
         ad.step()
     torch.cuda.synchronize()
     adam_bytes = free0 - torch.cuda.mem_get_info()[0]
+    adam_scene_bytes = s.device_bytes()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ad.step()
@@ -513,9 +520,12 @@ def main():
                     resolution=f"{cams[0].width}x{cams[0].height}", tr_variant=cfg.variant),
         roofline=roof,
         adam_iters_per_s=round(args.steps / dt_adam, 3),
-        device_bytes=dict(tr=int(tr_bytes), adam=int(adam_bytes), tr_scene_reported=int(tr_scene_bytes),
-                          note="drop in free device memory from before scene creation to after warm-up: "
-                               "parameters, targets, the method's optimizer state and per-view scratch"),
+        device_bytes=dict(tr=int(tr_bytes), adam=int(adam_bytes), tr_scene=int(tr_scene_bytes),
+                          adam_scene=int(adam_scene_bytes),
+                          note="tr / adam: drop in free device memory from before scene creation to after "
+                               "warm-up (library cache emptied first): parameters, targets, the method's optimizer "
+                               "state and per-view scratch; *_scene: the scene's own count "
+                               "(gs3_scene_device_bytes)"),
         stage_ms_per_iter={k: round(v, 4) for k, v in stage_ms.items()},
         psnr_after=round(psnr_tr, 3),
     )

@@ -146,7 +146,7 @@ gs3_status gs3_scene_set_params(gs3_scene* scene, const float* params_dev, hipSt
 /* Resident bytes (targets, parameters and the trust-region method's state:
  * six float[P][N] buffers and the radius scratch, where Adam needs three
  * buffers) and the scratch a scene described by desc allocates at creation:
- * per-Gaussian and per-pixel buffers and pair buffers reserved for 20
+ * per-Gaussian and per-pixel buffers and pair buffers reserved for 12
  * (Gaussian, tile) pairs per Gaussian with 25% slack.  A view with more pairs
  * grows the pair buffers (stream-ordered, without waiting for the device);
  * gs3_scene_device_bytes reports what a scene holds.  Used to admit scenes

@@ -441,11 +441,12 @@ gs3_status need_fused_state(gs3_scene* s, hipStream_t st) {
 }
 
 // Pair scratch reserved at scene creation: kPairsPerGaussian pairs per
-// Gaussian (the same estimate gs3_scene_bytes reports).  A view with more
+// Gaussian (the same estimate gs3_scene_bytes reports; object-scale views
+// of 800x800 hold about 11).  A view with more
 // pairs grows it; the outgrown blocks go back to the cache stream-ordered
 // (on `st`, behind the work that still reads them), so growing never waits
 // for the device.
-constexpr int64_t kPairsPerGaussian = 20;
+constexpr int64_t kPairsPerGaussian = 12;
 
 int64_t reserved_pairs(int64_t n) { return kPairsPerGaussian * n; }
 

@@ -310,7 +310,9 @@ __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x
 // for hundreds of serial steps) is summed by the whole workgroup: thread t
 // takes slots t, t + 256, ... and the 256 partial sums are combined in a
 // fixed tree.  Every order is fixed, so the result is deterministic.
-// Invisible Gaussians (count 0) get zeros.
+// Invisible Gaussians (count 0) sort last and get nothing: their rows of G
+// are never read (the chain rule skips them), so a workgroup whose first
+// rank is invisible returns at once.
 constexpr int kSumRanks = 28;  // 28 x 9 = 252 of the 256 threads
 constexpr uint32_t kSumLong = 48;
 
@@ -330,13 +332,16 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kSumRanks;
   const int nr = (int)(i0 + kSumRanks < n ? kSumRanks : n - i0);
+  if (counts[i0] == 0u) return;  // this rank and every later one is invisible
   const int j = tid / 9, k = tid % 9;
   if (tid == 0) long_ranks = 0u;
   __syncthreads();
   if (tid < 9 * kSumRanks && j < nr) {
     const int64_t i = i0 + j;
     const uint32_t c = counts[i];
-    if (c <= kSumLong) {
+    if (c == 0u) {
+      // invisible: nothing to sum
+    } else if (c <= kSumLong) {
       const float* p = partials + (int64_t)offsets[i] * 9 + k;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
       // rounds of 16 slots, all loads of a round issued before any is added
@@ -643,11 +648,11 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
 // expressions as the separate update kernel), so the update needs no radius
 // pass of its own.
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
-                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
-                                                      const float* __restrict__ G, int mode, int accumulate,
-                                                      uint64_t inner, float scale, float* __restrict__ out,
-                                                      FusedTr ft) {
+__device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, int64_t n, const CamDev& cam,
+                                                 const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
+                                                 const float* __restrict__ G, int mode, int accumulate,
+                                                 uint64_t inner, float scale, float* __restrict__ out,
+                                                 const FusedTr& ft) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ float gdir_part[3][3][kBwdGauss];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -741,6 +746,24 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
                 [&](int i) { return d[i]; }, [&](int i) { return gs3trust::row_radius(rad, i); });
 }
 
+// The chain rule into a gradient (mode 0) or a Hutchinson diagonal (mode 1).
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
+                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
+                                                      const float* __restrict__ G, int mode, int accumulate,
+                                                      uint64_t inner, float scale, float* __restrict__ out) {
+  project_bwd_body<DEG>(x, n, cam, rec, tiles, G, mode, accumulate, inner, scale, out, FusedTr{});
+}
+
+// The chain rule fused with the update of Algorithm 1 (mode 2): a kernel of
+// its own name, so profiles tell it from the gradient launches.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_tr_update(const float* __restrict__ x, int64_t n, CamDev cam,
+                                                    const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
+                                                    const float* __restrict__ G, FusedTr ft) {
+  project_bwd_body<DEG>(x, n, cam, rec, tiles, G, 2, 0, 0ull, 0.f, nullptr, ft);
+}
+
 uint64_t probe_inner(uint64_t seed, uint32_t i) {
   uint64_t z = (seed ^ (uint64_t)i) + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -783,6 +806,11 @@ void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint
 void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* tiles,
                         const float* gsum, int mode, int accumulate, uint64_t seed, uint32_t probe_index, float scale,
                         float* out, const FusedTr& ft, hipStream_t st) {
-  GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, cam, rec, tiles,
-                   gsum, mode, accumulate, probe_inner(seed, probe_index), scale, out, ft);
+  if (mode == 2) {
+    GS3_DEG_DISPATCH(deg, k_tr_update, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, cam, rec, tiles, gsum,
+                     ft);
+  } else {
+    GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, cam, rec, tiles,
+                     gsum, mode, accumulate, probe_inner(seed, probe_index), scale, out);
+  }
 }

@@ -47,7 +47,11 @@ class TRConfig:
     budget: int = 30000
     seed: int = 4002
     probe_seed: int = 5002
-    variant: int = 0  # trust-region radius variant bits (0 = as printed)
+    # trust-region radius variant bits; default TR_SH_JOINT: the view-dependent
+    # SH coefficients share the radius that bounds the colour change of moving
+    # all of them at once (the printed radius gives each of them the base
+    # colour's, which lets the colour move by many times eta_C)
+    variant: int = 4
     fused: bool = True  # one gs3_tr_iteration call per step (else grad / hvp_diag / tr_step)
 
 
