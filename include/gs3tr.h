@@ -174,6 +174,27 @@ gs3_status gs3_scene_sync(gs3_scene* scene);
  * C = sum_i c_i abar_i T_i + T_final * background. */
 gs3_status gs3_render(gs3_scene* scene, int32_t cam, float* rgb_dev, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gs3_render
+ * without a scene.  Renders params_dev (float[P][N], device, read only; N =
+ * n_gaussians, P from sh_degree) from *camera (host) into rgb_dev
+ * (float[H][W][3], device) with background[3] (host; NULL = black), with the
+ * same kernels as gs3_render, so the image is bit-identical to a scene's.
+ * Every scratch buffer is carved from one library-owned static device array
+ * of 128 MiB per GPU (held by each GPU the library runs on until the process
+ * ends); the call performs no device or pinned-host allocation and no free.
+ * Limits: the per-Gaussian and per-pixel buffers (88 B per Gaussian, 8 B
+ * per pixel, 12 B per tile) must fit, and the view's (Gaussian, tile) pairs
+ * must fit the rest (about 33 B per pair: some 3.5M pairs for 100k Gaussians
+ * at 800x800); EINVAL otherwise, before any work for the size check and
+ * after the binning for the pair count.  Synchronises the stream once (to read
+ * the pair count).  Calls that overlap on one GPU share the array and race:
+ * serialise them (every call rewrites the parts it reads; nothing needs to
+ * start at zero). */
+gs3_status gs3_render_noalloc(int64_t n_gaussians, int32_t sh_degree, const float* params_dev,
+                              const gs3_camera* camera, const float background[3], float* rgb_dev,
+                              hipStream_t stream);
+
 /* Bin camera `cam`: writes the sorted 64-bit keys ((tile << 32) | float bits
  * of depth) and the Gaussian index of every (Gaussian, tile) pair into
  * keys_dev / gids_dev (capacity entries each, device; either may be NULL),

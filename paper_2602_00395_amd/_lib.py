@@ -51,6 +51,8 @@ _SIGS = {
     "gs3_trim_cache": (c_int32, []),
     "gs3_scene_sync": (c_int32, [c_void_p]),
     "gs3_render": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "gs3_render_noalloc": (c_int32, [c_int64, c_int32, c_void_p, POINTER(Camera), POINTER(c_float), c_void_p,
+                                     c_void_p]),
     "gs3_bin": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int64, POINTER(c_int64), c_void_p]),
     "gs3_grad": (c_int32, [c_void_p, POINTER(c_int32), c_int32, c_void_p, POINTER(c_double), c_void_p]),
     "gs3_hvp_diag": (c_int32, [c_void_p, POINTER(c_int32), c_int32, c_int32, c_uint64, c_void_p, c_void_p]),

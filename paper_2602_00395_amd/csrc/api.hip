@@ -695,6 +695,107 @@ gs3_status validate_desc(const gs3_scene_desc* d) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- static scratch
+// Device scratch of gs3_render_noalloc, the render for callers that cannot
+// allocate: one array per GPU, created with the code object and held until
+// the process ends.  Host code never takes the array's name as an address:
+// each device's address comes from hipGetSymbolAddress on the first call on
+// that device (with that device current) and is kept per device.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+namespace statics {
+std::mutex mu;
+constexpr int kMaxDevices = 64;
+void* addr[kMaxDevices] = {};
+}  // namespace statics
+
+gs3_status static_scratch(void** out) {
+  int dev = 0;
+  GS3_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= statics::kMaxDevices) return fail(GS3_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(statics::mu);
+  if (!statics::addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(GS3_EDEVICE, std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e));
+    }
+    statics::addr[dev] = p;
+  }
+  *out = statics::addr[dev];
+  return GS3_OK;
+}
+
+// Consecutive 256-byte aligned pieces of one buffer.
+struct Carver {
+  char* base;
+  size_t size, used = 0;
+  template <class T>
+  T* take(size_t count) {
+    const size_t at = (used + 255) & ~(size_t)255;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (at + bytes > size) return nullptr;
+    used = at + bytes;
+    return reinterpret_cast<T*>(base + at);
+  }
+  // bytes the same takes would need, for the size check before any work
+  template <class T>
+  void need(size_t count) {
+    used = ((used + 255) & ~(size_t)255) + std::max<size_t>(count, 1) * sizeof(T);
+  }
+};
+
+// The render's buffers for n Gaussians and one camera, laid out by `c`;
+// `pairs` is the pair capacity.  With take == false only sizes are summed.
+template <bool Take>
+void carve_render(Carver& c, gs3_scene& t, int64_t n, int64_t px, int64_t tiles, int64_t pairs) {
+  auto get = [&](auto** p, size_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+    if constexpr (Take) {
+      *p = c.template take<std::remove_pointer_t<T>>(count);
+    } else {
+      c.template need<std::remove_pointer_t<T>>(count);
+    }
+  };
+  get(&t.rec, n);
+  get(&t.rect, n);
+  get(&t.depth_key, n);
+  get(&t.tiles, n);
+  get(&t.ka, n);
+  get(&t.va, n);
+  get(&t.kb, n);
+  get(&t.vb, n);
+  get(&t.counts, n);
+  get(&t.offsets, n);
+  get(&t.total_dev, 4);
+  get((char**)&t.stmp, scan_temp_bytes(n));
+  get(&t.ranges, tiles);
+  get(&t.tile_order, tiles);
+  get(&t.pix_last, px);
+  get(&t.pix_T, px);
+  get(&t.pt, pairs);
+  get(&t.pg, pairs);
+  get(&t.pt2, pairs);
+  get(&t.pg2, pairs);
+  get(&t.units, seg_slots(tiles, pairs));
+  get(&t.seg, seg_slots(tiles, pairs) * GS3_BLOCK);
+  get((char**)&t.rtmp, radix_temp_bytes(std::max<int64_t>(pairs, n)));
+  get(&t.block_owner, pairs / 256 + 1);
+}
+
+size_t render_bytes(int64_t n, int64_t px, int64_t tiles, int64_t pairs) {
+  gs3_scene t;
+  Carver c{nullptr, 0};
+  carve_render<false>(c, t, n, px, tiles, pairs);
+  return c.used;
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t gs3_n_params(int32_t sh_degree) { return params_for(sh_degree); }
@@ -882,6 +983,53 @@ gs3_status gs3_render(gs3_scene* s, int32_t cam, float* rgb, hipStream_t st) {
   const CamDev cd = make_cam(s->cams[cam]);
   blend_fwd(s, cd, rgb, st);
   return finish(s, st);
+}
+
+gs3_status gs3_render_noalloc(int64_t n_gaussians, int32_t sh_degree, const float* params_dev,
+                              const gs3_camera* camera, const float background[3], float* rgb_dev, hipStream_t st) {
+  if (n_gaussians < 1 || n_gaussians > 0x7fffffffLL) return fail(GS3_EINVAL, "n_gaussians must be in [1, 2^31)");
+  if (params_for(sh_degree) < 0) return fail(GS3_EINVAL, "sh_degree must be 0..3");
+  if (!params_dev || !camera || !rgb_dev) return fail(GS3_EINVAL, "params_dev, camera and rgb_dev must not be NULL");
+  const gs3_camera& c = *camera;
+  if (c.width < 1 || c.height < 1 || c.width > kMaxSide || c.height > kMaxSide)
+    return fail(GS3_EINVAL, "camera has an invalid size");
+  if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(GS3_EINVAL, "camera has fx/fy <= 0");
+  const CamDev cd = make_cam(c);
+  const int64_t px = (int64_t)c.width * c.height, tiles = (int64_t)cd.tiles_x * cd.tiles_y;
+  // the largest pair capacity whose buffers fit beside the per-Gaussian and
+  // per-pixel ones (none when even those do not fit)
+  if (render_bytes(n_gaussians, px, tiles, 0) > kStaticScratchBytes)
+    return fail(GS3_EINVAL, std::to_string(n_gaussians) + " Gaussians at " + std::to_string(c.width) + "x" +
+                                std::to_string(c.height) + " do not fit the " + std::to_string(kStaticScratchBytes >> 20) +
+                                " MiB static scratch");
+  int64_t lo = 0, hi = (int64_t)(kStaticScratchBytes / 16);
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (render_bytes(n_gaussians, px, tiles, mid) <= kStaticScratchBytes) lo = mid;
+    else hi = mid - 1;
+  }
+  void* base = nullptr;
+  GS3_TRY(static_scratch(&base));
+  gs3_scene t;
+  t.N = n_gaussians;
+  t.deg = sh_degree;
+  t.K = (sh_degree + 1) * (sh_degree + 1);
+  t.P = params_for(sh_degree);
+  t.n_cams = 1;
+  t.max_px = px;
+  t.max_tiles = (int)tiles;
+  t.x = const_cast<float*>(params_dev);  // only read by the projection
+  for (int k = 0; k < 3; ++k) t.bg[k] = background ? background[k] : 0.f;
+  Carver carver{(char*)base, kStaticScratchBytes};
+  carve_render<true>(carver, t, n_gaussians, px, tiles, lo);
+  t.pair_cap = lo;
+  t.rtmp_bytes = radix_temp_bytes(std::max<int64_t>(lo, n_gaussians));
+  t.owner_blocks = lo / 256 + 1;
+  t.fixed_scratch = true;
+  GS3_TRY(bin_camera(&t, c, 0, st));
+  blend_fwd(&t, cd, rgb_dev, st);
+  GS3_LAUNCHED();
+  return GS3_OK;
 }
 
 gs3_status gs3_bin(gs3_scene* s, int32_t cam, uint64_t* keys, uint32_t* gids, uint32_t* ranges, int64_t capacity,
