@@ -218,58 +218,83 @@ __device__ __forceinline__ float probe_sign(uint64_t inner, uint64_t k) {
 __device__ __forceinline__ float opacity_of(float logit) { return (float)(1.0 / (1.0 + exp(-(double)logit))); }
 __device__ __forceinline__ float skip_threshold(float op) { return (float)(-log(255.0 * (double)op)); }
 
-// blockIdx.y = 0: geometry -- screen centre, conic, opacity, skip
-// threshold, tile rectangle, depth key, tile count; 1: the view-dependent
-// colour and its clamp bits.  The two roles write disjoint words of the
-// record, so the 48 SH rows are read by threads of their own.
+// A workgroup takes 64 consecutive Gaussians.  Wave 0: geometry -- screen
+// centre, conic, opacity, skip threshold, tile rectangle, depth key, tile
+// count -- and whether the splat is visible; waves 1..3: colour channel
+// w - 1 of the visible splats only (an invisible Gaussian's SH rows are never
+// read: at city scale most Gaussians are outside the view) and its clamp bit.
+// The four waves write disjoint words of the record.
+constexpr int kFwdGauss = 64;
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       Rec* __restrict__ rec, uint2* __restrict__ rect,
                                                       uint32_t* __restrict__ depth_key,
                                                       uint32_t* __restrict__ tiles) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
+  __shared__ uint32_t vis_bits[2];  // bit l of word l / 32: lane l's splat is visible
+  __shared__ uint32_t clamp_bits[kFwdGauss];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t g = (int64_t)blockIdx.x * kFwdGauss + lane;
+  const bool live = g < n;
   auto src = [&](int r) { return x[(int64_t)r * n + g]; };
   float* rw = reinterpret_cast<float*>(rec + g);  // words of the record
-  if (blockIdx.y == 1) {
-    float rgb[3];
-    bool pos[3];
-    colour<float, DEG>(src, cam, rgb, pos);
-    // spare word: which colour channels are unclamped (bit c), for the backward
-    const uint32_t posm = (pos[0] ? 1u : 0u) | (pos[1] ? 2u : 0u) | (pos[2] ? 4u : 0u);
-    rw[6] = rgb[0];
-    rw[7] = rgb[1];
-    rw[8] = rgb[2];
-    rw[11] = __uint_as_float(posm);
-    return;
+  if (w == 0) {
+    bool vis = false;
+    if (live) {
+      const float sv[3] = {exp_ls(src(3)), exp_ls(src(4)), exp_ls(src(5))};
+      Proj<float> p;
+      project_geo<float>(src, sv, cam, p);
+      const float inv = 0.0625f;
+      const float txf = (float)cam.tiles_x, tyf = (float)cam.tiles_y;
+      const float x0 = fminf(fmaxf(floorf((p.u - p.radius) * inv), 0.f), txf);
+      const float x1 = fminf(fmaxf(floorf((p.u + p.radius) * inv) + 1.f, 0.f), txf);
+      const float y0 = fminf(fmaxf(floorf((p.v - p.radius) * inv), 0.f), tyf);
+      const float y1 = fminf(fmaxf(floorf((p.v + p.radius) * inv) + 1.f, 0.f), tyf);
+      vis = p.ok && isfinite(p.u) && isfinite(p.v) && isfinite(p.radius);
+      const int ix0 = vis ? (int)x0 : 0, ix1 = vis ? (int)x1 : 0, iy0 = vis ? (int)y0 : 0, iy1 = vis ? (int)y1 : 0;
+      const int touched = max(ix1 - ix0, 0) * max(iy1 - iy0, 0);
+      vis = vis && touched > 0;
+      if (!vis) {
+        depth_key[g] = 0xffffffffu;
+        tiles[g] = 0u;
+      } else {
+        const float op = opacity_of(src(10));
+        *reinterpret_cast<float4*>(rw) = make_float4(p.u, p.v, -0.5f * p.ca, -p.cb);
+        rw[4] = -0.5f * p.cc;
+        rw[5] = op;
+        rw[9] = skip_threshold(op);
+        rw[10] = 0.f;
+        rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
+        depth_key[g] = __float_as_uint(p.depth);
+        tiles[g] = (uint32_t)touched;
+      }
+    }
+    const uint64_t b = __ballot(vis);
+    clamp_bits[lane] = 0u;
+    if (lane == 0) {
+      vis_bits[0] = (uint32_t)b;
+      vis_bits[1] = (uint32_t)(b >> 32);
+    }
   }
-  const float sv[3] = {exp_ls(src(3)), exp_ls(src(4)), exp_ls(src(5))};
-  Proj<float> p;
-  project_geo<float>(src, sv, cam, p);
-  const float inv = 0.0625f;
-  const float txf = (float)cam.tiles_x, tyf = (float)cam.tiles_y;
-  const float x0 = fminf(fmaxf(floorf((p.u - p.radius) * inv), 0.f), txf);
-  const float x1 = fminf(fmaxf(floorf((p.u + p.radius) * inv) + 1.f, 0.f), txf);
-  const float y0 = fminf(fmaxf(floorf((p.v - p.radius) * inv), 0.f), tyf);
-  const float y1 = fminf(fmaxf(floorf((p.v + p.radius) * inv) + 1.f, 0.f), tyf);
-  bool vis = p.ok && isfinite(p.u) && isfinite(p.v) && isfinite(p.radius);
-  const int ix0 = vis ? (int)x0 : 0, ix1 = vis ? (int)x1 : 0, iy0 = vis ? (int)y0 : 0, iy1 = vis ? (int)y1 : 0;
-  const int touched = max(ix1 - ix0, 0) * max(iy1 - iy0, 0);
-  vis = vis && touched > 0;
-  if (!vis) {
-    depth_key[g] = 0xffffffffu;
-    tiles[g] = 0u;
-    return;
+  __syncthreads();
+  const bool vis = (vis_bits[lane >> 5] >> (lane & 31)) & 1u;
+  if (w > 0 && vis) {
+    // RGB_c = sum_k Y_k(dir) f_kc + 0.5, clamped at 0 (as colour<>, one channel)
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int c = w - 1;
+    const float dx = src(0) - cam.campos[0], dy = src(1) - cam.campos[1], dz = src(2) - cam.campos[2];
+    const float inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
+    float Y[K];
+    sh_basis<float, DEG>(dx * inv, dy * inv, dz * inv, Y);
+    float acc = 0.5f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = acc + Y[k] * src(11 + 3 * k + c);
+    rw[6 + c] = fmaxf(acc, 0.f);
+    if (acc >= 0.f) atomicOr(&clamp_bits[lane], 1u << c);
   }
-  const float op = opacity_of(src(10));
-  *reinterpret_cast<float4*>(rw) = make_float4(p.u, p.v, -0.5f * p.ca, -p.cb);
-  rw[4] = -0.5f * p.cc;
-  rw[5] = op;
-  rw[9] = skip_threshold(op);
-  rw[10] = 0.f;
-  rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
-  depth_key[g] = __float_as_uint(p.depth);
-  tiles[g] = (uint32_t)touched;
+  __syncthreads();
+  // spare word: which colour channels are unclamped (bit c), for the backward
+  if (w == 1 && vis) rw[11] = __uint_as_float(clamp_bits[lane]);
 }
 
 template <int DEG>
@@ -785,7 +810,7 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, Rec* rec, uint2* rect,
                         uint32_t* depth_key, uint32_t* tiles, hipStream_t st) {
-  GS3_DEG_DISPATCH(deg, k_project_fwd, dim3(blocks_for(n, 256), 2), dim3(256), 0, st, x, n, cam, rec, rect,
+  GS3_DEG_DISPATCH(deg, k_project_fwd, dim3(blocks_for(n, kFwdGauss)), dim3(256), 0, st, x, n, cam, rec, rect,
                    depth_key, tiles);
 }
 
