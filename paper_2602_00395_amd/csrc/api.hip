@@ -651,6 +651,9 @@ void blend_jvp(gs3_scene* s, const CamDev& cd, float* out, float* tan, hipStream
 
 void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st) {
   auto p = prof::begin("blend_bwd", st, true);
+  // the backward writes the partials of the pairs it walks; the others
+  // (behind each tile's last contribution) stay at these zeros
+  launch_fill_f32(s->partials, 9 * s->n_pairs, 0.f, st);
   if (s->have_order)
     launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, s->units, seg_slots(cd.tiles_x * cd.tiles_y, s->n_pairs),
                      cd, s->pix_last, s->pix_T, s->seg, s->bg, cot, s->partials, st, p.c);

@@ -626,14 +626,11 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   __syncthreads();
   if (last > 0u) atomicMax(&tile_end, last);
   __syncthreads();
-  // pairs at or after the tile's last contribution: zero slots
+  // pairs at or after the tile's last contribution keep the zeros the
+  // launcher filled the partials with (a streaming fill instead of two
+  // random record reads per such pair; at city scale most pairs of a tile
+  // lie behind its last contribution)
   const uint32_t end = min(max(tile_end, lo), hi);
-  for (uint32_t i = end + tid; i < hi; i += GS3_BLOCK) {
-    const uint32_t g = pair_gid[i];
-    float* dst = partials + (int64_t)pair_slot(__float_as_uint(rec[g].c.z), rect[g], tx, ty) * 9;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) dst[k] = 0.f;
-  }
   // where this lane's wave sums land in the reduction rows (lanes 7 and 15
   // of each 16-lane row; see the reduction in the walk)
   const bool hi8 = (lane & 8) != 0;
