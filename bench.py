@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--tr-variant", type=int, default=None,
                     help="trust-region radius variant bits (1 mean exact, 2 second order, 4 joint SH); "
                          "default: the trainer's")
+    ap.add_argument("--ablation", type=int, default=0,
+                    help="object-scale ablation at this many iterations: Adam, ADAM-TR and TR with each radius "
+                         "variant, final held-out PSNR and training seconds")
     ap.add_argument("--serve", type=int, default=0,
                     help="also serve this many scene-fit requests of the Poisson trace (p50/p99 time-to-fit)")
     ap.add_argument("--serve-iters", type=int, default=400,
@@ -311,6 +314,37 @@ def time_to_adam_psnr(tr_iters: int, variant, dev: str) -> dict:
                 tr_history=[(i, round(t, 2), round(p, 3)) for i, t, p in hist_t[::10]])
 
 
+def ablation(iters: int, dev: str) -> dict:
+    """Adam, ADAM-TR (Adam's step clipped by the Hellinger radius) and TR with
+    the radius variants on the object-scale workload, all with the same
+    budget, init, views and clock: final and best held-out PSNR (evaluated
+    every 500 iterations) and training seconds."""
+    import torch
+
+    from paper_2602_00395_amd import Scene
+    from paper_2602_00395_amd.trainer import AdamTrainer, TRConfig, TRTrainer, fit
+
+    sc, flat, mask = build_workload("object", dev)
+    x0 = torch.tensor(sc.init, device=dev)
+    train_ids, test_ids = sc.train_ids(), sc.test_ids()
+    extent = extent_of(sc.cameras)
+    runs = [("adam", None), ("adam_tr", None), ("tr_joint_sh", 4), ("tr_joint_sh_mean_exact", 5),
+            ("tr_joint_sh_second_order", 6), ("tr_all_variants", 7), ("tr_as_printed", 0)]
+    out = {}
+    for name, variant in runs:
+        s = Scene(x0, flat, sc.cameras, sc.sh_degree, lam=0.2, train_mask=mask)
+        if variant is None:
+            tr = AdamTrainer(s, train_ids, extent, budget=iters, trust_region=name == "adam_tr")
+        else:
+            tr = TRTrainer(s, train_ids, TRConfig(budget=iters, variant=variant))
+        hist, _ = fit(tr, s, test_ids, iters, eval_every=500)
+        s.close()
+        out[name] = dict(variant=variant, final_psnr=round(hist[-1][2], 3), best_psnr=round(max(h[2] for h in hist), 3),
+                         train_s=round(hist[-1][1], 3))
+        print("ablation", name, out[name], file=sys.stderr, flush=True)
+    return dict(workload=WORKLOADS["object"], iters=iters, runs=out)
+
+
 def serving(n_req: int, k_iters: int, dev: str) -> dict:
     """Continuous-batching scene fitting on the Poisson request trace.
 
@@ -494,6 +528,21 @@ def main():
     roof = roofline(dominant, dict(timed, work0=counted["work0"], work1=counted["work1"]), N, P, hutch,
                     args.workload)
 
+    # ---- mini-batches of four views (|S1| = |S2| = 4, the paper's trade-off
+    # knob): every batch of views shares one blend and one backward launch
+    s = make()
+    tr4 = TRTrainer(s, train_ids, TRConfig(s1=4, s2=4, variant=cfg.variant))
+    for _ in range(max(2, args.warmup // 2)):
+        tr4.step()
+    torch.cuda.synchronize()
+    steps4 = max(5, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(steps4):
+        tr4.step()
+    torch.cuda.synchronize()
+    dt4 = time.perf_counter() - t0
+    s.close()
+
     # ---- Adam on the same views, same clock
     free0 = free_after_trim()
     s = make()
@@ -520,6 +569,9 @@ def main():
                     resolution=f"{cams[0].width}x{cams[0].height}", tr_variant=cfg.variant),
         roofline=roof,
         adam_iters_per_s=round(args.steps / dt_adam, 3),
+        batch4_iters_per_s=dict(value=round(steps4 / dt4, 3), views_per_s=round(4 * steps4 / dt4, 3),
+                                note="TR iterations with |S1| = |S2| = 4 views (nu = 1, l = 10): four views "
+                                     "per blend and backward launch"),
         device_bytes=dict(tr=int(tr_bytes), adam=int(adam_bytes), tr_scene=int(tr_scene_bytes),
                           adam_scene=int(adam_scene_bytes),
                           note="tr / adam: drop in free device memory from before scene creation to after "
@@ -532,6 +584,8 @@ def main():
     print("throughput", out["value"], "it/s", file=sys.stderr, flush=True)
     if args.fit > 0:
         out["time_to_adam_psnr"] = time_to_adam_psnr(args.fit, args.tr_variant, dev)
+    if args.ablation > 0:
+        out["ablation"] = ablation(args.ablation, dev)
     if args.serve > 0:
         out["serving"] = serving(args.serve, args.serve_iters, dev)
     if not args.no_cpu_baseline:

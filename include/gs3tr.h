@@ -209,7 +209,9 @@ gs3_status gs3_bin(gs3_scene* scene, int32_t cam, uint64_t* keys_dev, uint32_t* 
 /* Stochastic gradient of Methodology / Algorithm 1:
  *   g_t = (1/m) (M/|S1|) sum_{j in S1} J_j^T f_j
  * with f_j the square roots of image j's loss components (Eq. pixel_loss,
- * Eq. objective) and S1 = cams[0..n_cams).  Writes grad_dev (float[P][N],
+ * Eq. objective) and S1 = cams[0..n_cams); the views go in batches of up to
+ * 8, each batch one blend-forward, one blend-backward and one projection-
+ * backward launch over all its views.  Writes grad_dev (float[P][N],
  * device).  If loss_out is not NULL it receives
  * 1/(2m) sum_{j in S1} sum_k l_jk (host double; synchronises). */
 gs3_status gs3_grad(gs3_scene* scene, const int32_t* cams, int32_t n_cams, float* grad_dev, double* loss_out,
@@ -220,7 +222,10 @@ gs3_status gs3_grad(gs3_scene* scene, const int32_t* cams, int32_t n_cams, float
  * with Rademacher probes z_i: entry k = row * N + gaussian is +1 when the
  * top bit of SplitMix64(SplitMix64(seed ^ i) ^ k) is clear, else -1.
  * J_j^T J_j z is formed as an image JVP, the loss Jacobian with Gauss-Newton
- * weights 1/(4 max(l, 1e-6)) and an image VJP.  Writes D_dev (float[P][N]). */
+ * weights 1/(4 max(l, 1e-6)) and an image VJP.  Writes D_dev (float[P][N]).
+ * The (view, probe) entries go in batches of up to 8: each view is binned
+ * once per batch, and one JVP blend launch, one backward launch and one
+ * projection backward cover every entry of the batch. */
 gs3_status gs3_hvp_diag(gs3_scene* scene, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed,
                         float* D_dev, hipStream_t stream);
 

@@ -110,6 +110,55 @@ void clear_locked() {
 
 }  // namespace
 
+// Buffers of one slot of a batch: the binning of a view (the slot of the
+// view's first entry) and one entry's blend state, backward partials and
+// image scratch (an entry is a view of a gradient batch, or one probe of a
+// view of a Hutchinson batch).  Slot 0 is created with the scene, the others
+// on the first batch that needs them.
+struct ViewBufs {
+  bool ready = false;
+  // per-Gaussian binning scratch
+  Rec* rec = nullptr;
+  uint2* rect = nullptr;
+  uint32_t *depth_key = nullptr, *tiles = nullptr, *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
+  uint32_t *counts = nullptr, *offsets = nullptr, *total_dev = nullptr;
+  void* stmp = nullptr;
+  void* rtmp = nullptr;
+  size_t rtmp_bytes = 0;
+  // per-pair binning scratch
+  int64_t pair_cap = 0;
+  uint32_t *pt = nullptr, *pg = nullptr, *pt2 = nullptr, *pg2 = nullptr;
+  // depth rank owning pair 256 b, written by the offsets scan for the
+  // emission; sized from the pair capacity of earlier views
+  uint32_t* block_owner = nullptr;
+  int64_t owner_blocks = 0;
+  // the backward's (tile, depth segment) units, seg_slots(max_tiles,
+  // pair_cap) entries
+  uint2* units = nullptr;
+  uint2* ranges = nullptr;
+  uint32_t* tile_order = nullptr;
+  bool have_order = false;
+  // state of the binned view
+  const uint32_t* sorted_gid = nullptr;
+  const uint32_t* order = nullptr;  // Gaussians in depth order
+  const uint32_t* sorted_tile = nullptr;
+  int64_t n_pairs = 0;
+  int cam = -1;  // camera index of the binned view (-1: a camera given directly)
+  CamDev cd{};   // its device camera
+  // the entry's blend state: the long tiles' segment states
+  // (seg_slots(max_tiles, blend_cap) rows) and the backward partials
+  int64_t blend_cap = 0;
+  float4* seg = nullptr;
+  float* partials = nullptr;
+  float* gsum = nullptr;  // float[N][9]: each Gaussian's summed partials
+  TRec* trec = nullptr;
+  // per-pixel image scratch
+  float *img = nullptr, *cot = nullptr, *tan_img = nullptr, *ssim_tmp = nullptr;
+  uint32_t* pix_last = nullptr;  // per pixel: 1 + pair index of the last contributing splat
+  float* pix_T = nullptr;        // per pixel: final transmittance
+  double* dpart = nullptr;
+};
+
 struct gs3_scene {
   int64_t N = 0;
   int deg = 0, K = 1, P = 14, n_cams = 0, n_train = 0;
@@ -125,46 +174,13 @@ struct gs3_scene {
   // resident state
   float *x = nullptr, *targets = nullptr, *ghat = nullptr, *dhat = nullptr, *am = nullptr, *av = nullptr;
   // gs3_tr_iteration: the fused update writes x_alt (then the two swap); its
-  // Hutchinson diagonal and the gradient of all but the last view
+  // Hutchinson diagonal and the gradient of the views of earlier batches
   float *x_alt = nullptr, *dbuf = nullptr, *gacc = nullptr;
-  // per-Gaussian scratch
-  Rec* rec = nullptr;
-  uint2* rect = nullptr;
-  TRec* trec = nullptr;
-  uint32_t *depth_key = nullptr, *tiles = nullptr, *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
-  uint32_t *counts = nullptr, *offsets = nullptr, *total_dev = nullptr;
-  void* stmp = nullptr;
-  void* rtmp = nullptr;
-  size_t rtmp_bytes = 0;
-  // per-pair scratch
-  int64_t pair_cap = 0;
-  uint32_t *pt = nullptr, *pg = nullptr, *pt2 = nullptr, *pg2 = nullptr;
-  // depth rank owning pair 256 b, written by the offsets scan for the
-  // emission; sized from the pair capacity of earlier views
-  uint32_t* block_owner = nullptr;
-  int64_t owner_blocks = 0;
-  // the backward's (tile, depth segment) units and the long tiles' segment
-  // states, seg_slots(max_tiles, pair_cap) rows each
-  uint2* units = nullptr;
-  float4* seg = nullptr;
-  float* partials = nullptr;
-  float* gsum = nullptr;  // float[N][9]: each Gaussian's summed partials
-  // per-view image scratch
-  uint2* ranges = nullptr;
-  uint32_t* tile_order = nullptr;
-  bool have_order = false;
-  float *img = nullptr, *cot = nullptr, *tan_img = nullptr, *ssim_tmp = nullptr;
-  uint32_t* pix_last = nullptr;  // per pixel: 1 + pair index of the last contributing splat
-  float* pix_T = nullptr;        // per pixel: final transmittance
-  double *dpart = nullptr, *dsum = nullptr;
+  ViewBufs vb[GS3_MAX_VIEWS];
+  double* dsum = nullptr;
   uint32_t* host_u32 = nullptr;
   double* host_f64 = nullptr;
   hipEvent_t done_ev = nullptr;
-  // state of the last binned view
-  const uint32_t* sorted_gid = nullptr;
-  const uint32_t* order = nullptr;  // Gaussians in depth order
-  const uint32_t* sorted_tile = nullptr;
-  int64_t n_pairs = 0;
   // every buffer carved from the static scratch: nothing may be allocated
   bool fixed_scratch = false;
 };
@@ -359,6 +375,42 @@ void dfree(T*& p, const hipStream_t* st = nullptr) {
   p = nullptr;
 }
 
+void free_slot(ViewBufs& v) {
+  dfree(v.rec);
+  dfree(v.rect);
+  dfree(v.trec);
+  dfree(v.depth_key);
+  dfree(v.tiles);
+  dfree(v.ka);
+  dfree(v.va);
+  dfree(v.kb);
+  dfree(v.vb);
+  dfree(v.counts);
+  dfree(v.offsets);
+  dfree(v.total_dev);
+  dfree(v.stmp);
+  dfree(v.rtmp);
+  dfree(v.pt);
+  dfree(v.pg);
+  dfree(v.pt2);
+  dfree(v.pg2);
+  dfree(v.partials);
+  dfree(v.block_owner);
+  dfree(v.units);
+  dfree(v.seg);
+  dfree(v.gsum);
+  dfree(v.ranges);
+  dfree(v.tile_order);
+  dfree(v.img);
+  dfree(v.cot);
+  dfree(v.tan_img);
+  dfree(v.pix_last);
+  dfree(v.pix_T);
+  dfree(v.ssim_tmp);
+  dfree(v.dpart);
+  v = ViewBufs{};
+}
+
 void free_all(gs3_scene* s) {
   dfree(s->x);
   dfree(s->x_alt);
@@ -369,38 +421,8 @@ void free_all(gs3_scene* s) {
   dfree(s->dhat);
   dfree(s->am);
   dfree(s->av);
-  dfree(s->rec);
-  dfree(s->rect);
-  dfree(s->trec);
-  dfree(s->depth_key);
-  dfree(s->tiles);
-  dfree(s->ka);
-  dfree(s->va);
-  dfree(s->kb);
-  dfree(s->vb);
-  dfree(s->counts);
-  dfree(s->offsets);
-  dfree(s->total_dev);
-  dfree(s->stmp);
-  dfree(s->rtmp);
-  dfree(s->pt);
-  dfree(s->pg);
-  dfree(s->pt2);
-  dfree(s->pg2);
-  dfree(s->partials);
-  dfree(s->block_owner);
-  dfree(s->units);
-  dfree(s->seg);
-  dfree(s->gsum);
-  dfree(s->ranges);
-  dfree(s->tile_order);
-  dfree(s->img);
-  dfree(s->cot);
-  dfree(s->tan_img);
-  dfree(s->pix_last);
-  dfree(s->pix_T);
-  dfree(s->ssim_tmp);
-  dfree(s->dpart);
+  for (auto& v : s->vb)
+    if (v.ready) free_slot(v);
   dfree(s->dsum);
   mem::host_release(s->host_u32, kHostWords * sizeof(uint32_t));
   mem::host_release(s->host_f64, sizeof(double) * kMaxLossViews);
@@ -462,49 +484,116 @@ int64_t pair_bytes(int64_t cap, int64_t max_tiles, int64_t n) {
 // capacity allocated for a view of n pairs: 25% slack
 int64_t pair_capacity(int64_t n_pairs) { return n_pairs + n_pairs / 4 + 4096; }
 
-// per-Gaussian and per-pixel scratch allocated at scene creation
+// per-Gaussian and per-pixel scratch of one slot (slot 0 is allocated at
+// scene creation)
 int64_t view_scratch_bytes(int64_t n, int64_t max_px, int64_t max_tiles) {
   return 172 * n + (int64_t)scan_temp_bytes(n) + 16 + 12 * max_tiles + 44 * max_px +
-         4 * (int64_t)ssim_tmp_floats(1, (int)max_px) + 8 * (max_px * 3 / 256 + max_tiles + 1024) + 8 * kMaxLossViews;
+         4 * (int64_t)ssim_tmp_floats(1, (int)max_px) + 8 * (max_px * 3 / 256 + max_tiles + 1024);
 }
 
-gs3_status ensure_pairs(gs3_scene* s, int64_t n_pairs, const hipStream_t* st) {
-  if (n_pairs <= s->pair_cap && s->rtmp) return GS3_OK;
+// Binning buffers of a slot for a view of n_pairs pairs.
+gs3_status ensure_pairs(gs3_scene* s, ViewBufs& v, int64_t n_pairs, const hipStream_t* st) {
+  if (n_pairs <= v.pair_cap && v.rtmp) return GS3_OK;
   if (s->fixed_scratch)
     return fail(GS3_EINVAL, "the view has " + std::to_string(n_pairs) + " (Gaussian, tile) pairs; the static scratch holds " +
-                                std::to_string(s->pair_cap));
-  const int64_t cap = std::max<int64_t>(pair_capacity(n_pairs), s->pair_cap);
-  dfree(s->pt, st);
-  dfree(s->pg, st);
-  dfree(s->pt2, st);
-  dfree(s->pg2, st);
-  dfree(s->partials, st);
-  dfree(s->rtmp, st);
-  dfree(s->units, st);
-  dfree(s->seg, st);
-  s->pair_cap = 0;
-  GS3_TRY(dalloc(&s->pt, cap));
-  GS3_TRY(dalloc(&s->pg, cap));
-  GS3_TRY(dalloc(&s->pt2, cap));
-  GS3_TRY(dalloc(&s->pg2, cap));
-  GS3_TRY(dalloc(&s->partials, (size_t)cap * 9));
-  GS3_TRY(dalloc(&s->units, (size_t)seg_slots(s->max_tiles, cap)));
-  GS3_TRY(dalloc(&s->seg, (size_t)seg_slots(s->max_tiles, cap) * GS3_BLOCK));
-  s->rtmp_bytes = radix_temp_bytes(std::max<int64_t>(cap, s->N));
-  GS3_TRY(dalloc((char**)&s->rtmp, s->rtmp_bytes));
-  s->pair_cap = cap;
+                                std::to_string(v.pair_cap));
+  const int64_t cap = std::max<int64_t>(pair_capacity(n_pairs), v.pair_cap);
+  dfree(v.pt, st);
+  dfree(v.pg, st);
+  dfree(v.pt2, st);
+  dfree(v.pg2, st);
+  dfree(v.rtmp, st);
+  dfree(v.units, st);
+  v.pair_cap = 0;
+  GS3_TRY(dalloc(&v.pt, cap));
+  GS3_TRY(dalloc(&v.pg, cap));
+  GS3_TRY(dalloc(&v.pt2, cap));
+  GS3_TRY(dalloc(&v.pg2, cap));
+  GS3_TRY(dalloc(&v.units, (size_t)seg_slots(s->max_tiles, cap)));
+  v.rtmp_bytes = radix_temp_bytes(std::max<int64_t>(cap, s->N));
+  GS3_TRY(dalloc((char**)&v.rtmp, v.rtmp_bytes));
+  v.pair_cap = cap;
+  return GS3_OK;
+}
+
+// Blend state of a slot for an entry of a view of n_pairs pairs: the
+// backward partials and the long tiles' segment states.
+// (the allocation-free render has segment states only: no backward)
+gs3_status ensure_blend(gs3_scene* s, ViewBufs& v, int64_t n_pairs, const hipStream_t* st) {
+  if (n_pairs <= v.blend_cap && v.seg && (v.partials || s->fixed_scratch)) return GS3_OK;
+  if (s->fixed_scratch)
+    return fail(GS3_EINVAL, "the view has " + std::to_string(n_pairs) + " (Gaussian, tile) pairs; the static scratch holds " +
+                                std::to_string(v.blend_cap));
+  const int64_t cap = std::max<int64_t>(pair_capacity(n_pairs), v.blend_cap);
+  dfree(v.partials, st);
+  dfree(v.seg, st);
+  v.blend_cap = 0;
+  GS3_TRY(dalloc(&v.partials, (size_t)cap * 9));
+  GS3_TRY(dalloc(&v.seg, (size_t)seg_slots(s->max_tiles, cap) * GS3_BLOCK));
+  v.blend_cap = cap;
   return GS3_OK;
 }
 
 // The offsets scan records the owner of every 256-pair block of the pair
 // capacity known before the view (the emission searches for the owners of
 // blocks beyond it), so this array follows the capacity one view later.
-gs3_status ensure_owner_blocks(gs3_scene* s, const hipStream_t* st) {
-  if (s->owner_blocks >= s->pair_cap / 256 + 1 || s->fixed_scratch) return GS3_OK;
-  dfree(s->block_owner, st);
-  s->owner_blocks = 0;
-  GS3_TRY(dalloc(&s->block_owner, (size_t)(s->pair_cap / 256 + 1)));
-  s->owner_blocks = s->pair_cap / 256 + 1;
+gs3_status ensure_owner_blocks(gs3_scene* s, ViewBufs& v, const hipStream_t* st) {
+  if (v.owner_blocks >= v.pair_cap / 256 + 1 || s->fixed_scratch) return GS3_OK;
+  dfree(v.block_owner, st);
+  v.owner_blocks = 0;
+  GS3_TRY(dalloc(&v.block_owner, (size_t)(v.pair_cap / 256 + 1)));
+  v.owner_blocks = v.pair_cap / 256 + 1;
+  return GS3_OK;
+}
+
+// Per-Gaussian and per-pixel buffers of a slot, and its pair buffers for
+// `pairs` pairs.
+gs3_status alloc_slot(gs3_scene* s, ViewBufs& v, int64_t pairs) {
+  if (v.ready) return GS3_OK;
+  const int64_t N = s->N;
+  gs3_status rc = GS3_OK;
+  auto step = [&](gs3_status r) {
+    if (rc == GS3_OK) rc = r;
+  };
+  step(dalloc(&v.rec, N));
+  step(dalloc(&v.rect, N));
+  step(dalloc(&v.trec, N));
+  step(dalloc(&v.depth_key, N));
+  step(dalloc(&v.tiles, N));
+  step(dalloc(&v.ka, N));
+  step(dalloc(&v.va, N));
+  step(dalloc(&v.kb, N));
+  step(dalloc(&v.vb, N));
+  step(dalloc(&v.counts, N));
+  step(dalloc(&v.gsum, 9 * N));
+  step(dalloc(&v.offsets, N));
+  step(dalloc(&v.total_dev, 4));
+  step(dalloc((char**)&v.stmp, scan_temp_bytes(N)));
+  step(dalloc(&v.ranges, s->max_tiles));
+  step(dalloc(&v.tile_order, s->max_tiles));
+  step(dalloc(&v.img, s->max_px * 3));
+  step(dalloc(&v.cot, s->max_px * 3));
+  step(dalloc(&v.tan_img, s->max_px * 3));
+  step(dalloc(&v.pix_last, s->max_px));
+  step(dalloc(&v.pix_T, s->max_px));
+  step(dalloc(&v.ssim_tmp, ssim_tmp_floats(1, (int)s->max_px)));
+  step(dalloc(&v.dpart, s->max_px * 3 / 256 + s->max_tiles + 1024));
+  if (rc == GS3_OK) rc = ensure_pairs(s, v, pairs, nullptr);
+  if (rc == GS3_OK) rc = ensure_blend(s, v, pairs, nullptr);
+  if (rc == GS3_OK) rc = ensure_owner_blocks(s, v, nullptr);
+  if (rc != GS3_OK) {
+    free_slot(v);
+    return rc;
+  }
+  v.ready = true;
+  return GS3_OK;
+}
+
+// Slots 0..n-1 ready (new ones sized like slot 0's current pair capacity).
+gs3_status need_slots(gs3_scene* s, int n) {
+  if (n > GS3_MAX_VIEWS) return fail(GS3_EINVAL, "batch of more than GS3_MAX_VIEWS entries");
+  for (int k = 1; k < n; ++k)
+    GS3_TRY(alloc_slot(s, s->vb[k], std::max<int64_t>(s->vb[0].n_pairs, 4096)));
   return GS3_OK;
 }
 
@@ -556,20 +645,21 @@ int bits_for(int n_tiles) {
 
 // Project, sort by depth, emit pairs, sort pairs by tile, per-tile ranges.
 // Waits once for the pair count (see wait_count), not for the whole stream.
-gs3_status bin_camera(gs3_scene* s, const gs3_camera& camera, int cam, hipStream_t st) {
+gs3_status bin_camera(gs3_scene* s, ViewBufs& v, const gs3_camera& camera, int cam, hipStream_t st) {
   const CamDev cd = make_cam(camera);
+  v.cd = cd;
   const int64_t N = s->N;
-  GS3_TRY(ensure_owner_blocks(s, &st));
+  GS3_TRY(ensure_owner_blocks(s, v, &st));
   auto p0 = prof::begin("project_fwd", st);
-  launch_project_fwd(s->x, N, s->deg, cd, s->rec, s->rect, s->depth_key, s->tiles, st);
+  launch_project_fwd(s->x, N, s->deg, cd, v.rec, v.rect, v.depth_key, v.tiles, st);
   prof::end(p0, st);
   GS3_LAUNCHED();
   auto p1 = prof::begin("depth_sort", st);
   uint32_t *k_sorted, *order;
-  radix_sort_u32(s->depth_key, nullptr, s->ka, s->va, s->kb, s->vb, N, 32, s->rtmp, st, &k_sorted, &order);
+  radix_sort_u32(v.depth_key, nullptr, v.ka, v.va, v.kb, v.vb, N, 32, v.rtmp, st, &k_sorted, &order);
   prof::end(p1, st);
   auto p2 = prof::begin("scan", st);
-  launch_gather_counts(order, s->tiles, N, s->counts, st);
+  launch_gather_counts(order, v.tiles, N, v.counts, st);
   // the scan stores the pair count into a pinned host word as soon as it is
   // known; the host waits for that word (not for the stream), so the
   // launches below are queued while the scan's last kernel still runs
@@ -579,40 +669,44 @@ gs3_status bin_camera(gs3_scene* s, const gs3_camera& camera, int cam, hipStream
   volatile uint32_t* count_word = s->host_u32 ? s->host_u32 : &copied;
   *count_word = kCountPending;
   std::atomic_thread_fence(std::memory_order_seq_cst);
-  scan_exclusive_u32(s->counts, s->offsets, N, s->total_dev, s->stmp, st, s->block_owner, s->owner_blocks,
+  scan_exclusive_u32(v.counts, v.offsets, N, v.total_dev, v.stmp, st, v.block_owner, v.owner_blocks,
                      s->host_u32);
   prof::end(p2, st);
   GS3_LAUNCHED();
   if (s->host_u32) {
     GS3_TRY(wait_count(count_word, st));
   } else {
-    GS3_HIP(hipMemcpyAsync(&copied, s->total_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GS3_HIP(hipMemcpyAsync(&copied, v.total_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     GS3_HIP(hipStreamSynchronize(st));
   }
   if (*count_word == kCountOverflow)
     return fail(GS3_EINVAL, "camera " + std::to_string(cam) + ": the view has 2^32 - 2 or more (Gaussian, tile) pairs");
   const int64_t n_pairs = *count_word;
-  GS3_TRY(ensure_pairs(s, n_pairs, &st));
+  GS3_TRY(ensure_pairs(s, v, n_pairs, &st));
+  GS3_TRY(ensure_blend(s, v, n_pairs, &st));
   auto p3 = prof::begin("emit_pairs", st);
-  launch_emit_pairs(order, s->offsets, s->block_owner, s->owner_blocks, s->rec, s->rect, N, n_pairs, cd.tiles_x,
-                    s->pt, s->pg, st);
+  launch_emit_pairs(order, v.offsets, v.block_owner, v.owner_blocks, v.rec, v.rect, N, n_pairs, cd.tiles_x,
+                    v.pt, v.pg, st);
   prof::end(p3, st, N, n_pairs);
   const int n_tiles = cd.tiles_x * cd.tiles_y;
   uint32_t *tk, *tv;
   auto p4 = prof::begin("pair_sort", st);
-  radix_sort_u32(s->pt, s->pg, s->pt2, s->pg2, s->pt, s->pg, n_pairs, bits_for(n_tiles), s->rtmp, st, &tk, &tv);
-  launch_tile_ranges(tk, n_pairs, s->ranges, n_tiles, st);
-  s->have_order = launch_tile_order(s->ranges, n_tiles, s->tile_order, s->units, seg_slots(n_tiles, n_pairs), st);
+  radix_sort_u32(v.pt, v.pg, v.pt2, v.pg2, v.pt, v.pg, n_pairs, bits_for(n_tiles), v.rtmp, st, &tk, &tv);
+  launch_tile_ranges(tk, n_pairs, v.ranges, n_tiles, st);
+  v.have_order = launch_tile_order(v.ranges, n_tiles, v.tile_order, v.units, seg_slots(n_tiles, n_pairs), st);
   prof::end(p4, st, n_pairs, bits_for(n_tiles));
   GS3_LAUNCHED();
-  s->sorted_gid = tv;
-  s->sorted_tile = tk;
-  s->order = order;
-  s->n_pairs = n_pairs;
+  v.sorted_gid = tv;
+  v.sorted_tile = tk;
+  v.order = order;
+  v.n_pairs = n_pairs;
   return GS3_OK;
 }
 
-gs3_status bin_view(gs3_scene* s, int cam, hipStream_t st) { return bin_camera(s, s->cams[cam], cam, st); }
+gs3_status bin_view(gs3_scene* s, ViewBufs& v, int cam, hipStream_t st) {
+  v.cam = cam;
+  return bin_camera(s, v, s->cams[cam], cam, st);
+}
 
 gs3_status finish(gs3_scene* s, hipStream_t st) {
   (void)s;
@@ -635,46 +729,111 @@ struct CallEnd {
 
 const float* target_of(gs3_scene* s, int cam) { return s->targets + s->tgt_off[cam]; }
 
-void blend_fwd(gs3_scene* s, const CamDev& cd, float* out, hipStream_t st) {
+// Entry k of a batch: its view's binning is in slot b[k], its blend state
+// in slot e[k] (equal for the views of a gradient batch; the probes of one
+// view in a Hutchinson batch share the binning of the view's first slot).
+struct Entries {
+  int n = 0;
+  int b[GS3_MAX_VIEWS] = {}, e[GS3_MAX_VIEWS] = {};
+  uint32_t probe[GS3_MAX_VIEWS] = {};
+};
+
+BlendView blend_view(const ViewBufs& b, ViewBufs& e) {
+  BlendView V;
+  V.rec = b.rec;
+  V.trec = e.trec;
+  V.pair_gid = b.sorted_gid;
+  V.ranges = b.ranges;
+  V.order = b.have_order ? b.tile_order : nullptr;
+  V.rect = b.rect;
+  V.units = b.units;
+  V.cam = b.cd;
+  V.n_tiles = b.cd.tiles_x * b.cd.tiles_y;
+  V.n_units = b.have_order ? seg_slots(V.n_tiles, b.n_pairs) : 0;
+  V.cot = e.cot;
+  V.partials = e.partials;
+  V.img = e.img;
+  V.tan_img = e.tan_img;
+  V.pix_last = e.pix_last;
+  V.pix_T = e.pix_T;
+  V.seg = e.seg;
+  return V;
+}
+
+BlendBatch blend_batch(gs3_scene* s, const Entries& E) {
+  BlendBatch B;
+  B.n = E.n;
+  for (int k = 0; k < E.n; ++k) B.v[k] = blend_view(s->vb[E.b[k]], s->vb[E.e[k]]);
+  return B;
+}
+
+// out (nullable): the image of a single-entry batch goes there instead of
+// the slot's image buffer
+void blend_fwd(gs3_scene* s, const Entries& E, hipStream_t st, float* out = nullptr) {
+  BlendBatch B = blend_batch(s, E);
+  if (out) B.v[0].img = out;
   auto p = prof::begin("blend_fwd", st, true);
-  launch_blend_fwd(s->rec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg, out,
-                   s->pix_last, s->pix_T, s->seg, st, p.c);
+  launch_blend_fwd(B, s->bg, st, p.c);
   prof::end(p, st);
 }
 
-void blend_jvp(gs3_scene* s, const CamDev& cd, float* out, float* tan, hipStream_t st) {
+void blend_jvp(gs3_scene* s, const Entries& E, hipStream_t st, float* out = nullptr, float* tan = nullptr) {
+  BlendBatch B = blend_batch(s, E);
+  if (out) B.v[0].img = out;
+  if (tan) B.v[0].tan_img = tan;
   auto p = prof::begin("blend_jvp", st, true);
-  launch_blend_jvp(s->rec, s->trec, s->sorted_gid, s->ranges, s->have_order ? s->tile_order : nullptr, cd, s->bg,
-                   out, tan, s->pix_last, s->pix_T, s->seg, st, p.c);
+  launch_blend_jvp(B, s->bg, st, p.c);
   prof::end(p, st);
 }
 
-void blend_bwd(gs3_scene* s, const CamDev& cd, const float* cot, hipStream_t st) {
+// cot (nullable): the cotangent of a single-entry batch, in place of the slot's
+void blend_bwd(gs3_scene* s, const Entries& E, hipStream_t st, const float* cot = nullptr) {
+  BlendBatch B = blend_batch(s, E);
+  if (cot) B.v[0].cot = cot;
   auto p = prof::begin("blend_bwd", st, true);
   // the backward writes the partials of the pairs it walks; the others
   // (behind each tile's last contribution) stay at these zeros
-  launch_fill_f32(s->partials, 9 * s->n_pairs, 0.f, st);
-  if (s->have_order)
-    launch_blend_bwd(s->rec, s->rect, s->sorted_gid, s->ranges, s->units, seg_slots(cd.tiles_x * cd.tiles_y, s->n_pairs),
-                     cd, s->pix_last, s->pix_T, s->seg, s->bg, cot, s->partials, st, p.c);
+  for (int k = 0; k < E.n; ++k) launch_fill_f32(s->vb[E.e[k]].partials, 9 * s->vb[E.b[k]].n_pairs, 0.f, st);
+  launch_blend_bwd(B, s->bg, st, p.c);
   prof::end(p, st);
 }
 
-void project_bwd(gs3_scene* s, const CamDev& cd, int mode, int acc, uint64_t seed, uint32_t i, float scale,
-                 float* out, hipStream_t st, const FusedTr& ft = FusedTr{}) {
+// Pair sums of every entry, then the chain rule over the batch (modes as
+// launch_project_bwd; mode 1 takes each entry's probe of `seed`).
+void project_bwd(gs3_scene* s, const Entries& E, int mode, int acc, uint64_t seed, float scale, float* out,
+                 hipStream_t st, const FusedTr& ft = FusedTr{}) {
+  BwdBatch B;
+  B.n = E.n;
   auto ps = prof::begin("pair_sums", st);
-  launch_pair_sums(s->order, s->offsets, s->counts, s->partials, s->N, s->gsum, st);
-  prof::end(ps, st, s->N, s->n_pairs);
+  int64_t pairs = 0;
+  for (int k = 0; k < E.n; ++k) {
+    const ViewBufs& b = s->vb[E.b[k]];
+    ViewBufs& e = s->vb[E.e[k]];
+    launch_pair_sums(b.order, b.offsets, b.counts, e.partials, s->N, e.gsum, st);
+    B.v[k].rec = b.rec;
+    B.v[k].tiles = b.tiles;
+    B.v[k].G = e.gsum;
+    B.v[k].cam = b.cd;
+    B.v[k].inner = mode == 1 ? probe_key(seed, E.probe[k]) : 0ull;
+    pairs += b.n_pairs;
+  }
+  prof::end(ps, st, s->N, pairs);
   auto p = prof::begin(mode == 2 ? "tr_update" : "project_bwd", st);
-  launch_project_bwd(s->x, s->N, s->deg, cd, s->rec, s->tiles, s->gsum, mode, acc, seed, i, scale, out, ft, st);
+  launch_project_bwd(s->x, s->N, s->deg, B, mode, acc, scale, out, ft, st);
   prof::end(p, st, s->N, 0);
 }
 
-void project_jvp(gs3_scene* s, const CamDev& cd, int kind, uint64_t seed, uint32_t i, const float* tangent,
-                 hipStream_t st) {
+void project_jvp(gs3_scene* s, const ViewBufs& b, ViewBufs& e, int kind, uint64_t seed, uint32_t i,
+                 const float* tangent, hipStream_t st) {
   auto p = prof::begin("project_jvp", st);
-  launch_project_jvp(s->x, s->N, s->deg, cd, s->rec, s->tiles, kind, seed, i, tangent, s->trec, st);
+  launch_project_jvp(s->x, s->N, s->deg, b.cd, b.rec, b.tiles, kind, seed, i, tangent, e.trec, st);
   prof::end(p, st, s->N, 0);
+}
+
+Entries single() {
+  Entries E;
+  E.n = 1;
+  return E;
 }
 
 gs3_status validate_desc(const gs3_scene_desc* d) {
@@ -755,7 +914,7 @@ struct Carver {
 // The render's buffers for n Gaussians and one camera, laid out by `c`;
 // `pairs` is the pair capacity.  With take == false only sizes are summed.
 template <bool Take>
-void carve_render(Carver& c, gs3_scene& t, int64_t n, int64_t px, int64_t tiles, int64_t pairs) {
+void carve_render(Carver& c, ViewBufs& t, int64_t n, int64_t px, int64_t tiles, int64_t pairs) {
   auto get = [&](auto** p, size_t count) {
     using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
     if constexpr (Take) {
@@ -791,7 +950,7 @@ void carve_render(Carver& c, gs3_scene& t, int64_t n, int64_t px, int64_t tiles,
 }
 
 size_t render_bytes(int64_t n, int64_t px, int64_t tiles, int64_t pairs) {
-  gs3_scene t;
+  ViewBufs t;
   Carver c{nullptr, 0};
   carve_render<false>(c, t, n, px, tiles, pairs);
   return c.used;
@@ -866,37 +1025,13 @@ gs3_status gs3_scene_create(const gs3_scene_desc* d, const float* params_dev, co
   };
   step(dalloc(&s->x, PN));
   step(dalloc(&s->targets, off));
-  step(dalloc(&s->rec, s->N));
-  step(dalloc(&s->rect, s->N));
-  step(dalloc(&s->trec, s->N));
-  step(dalloc(&s->depth_key, s->N));
-  step(dalloc(&s->tiles, s->N));
-  step(dalloc(&s->ka, s->N));
-  step(dalloc(&s->va, s->N));
-  step(dalloc(&s->kb, s->N));
-  step(dalloc(&s->vb, s->N));
-  step(dalloc(&s->counts, s->N));
-  step(dalloc(&s->gsum, 9 * s->N));
-  step(dalloc(&s->offsets, s->N));
-  step(dalloc(&s->total_dev, 4));
-  step(dalloc((char**)&s->stmp, scan_temp_bytes(s->N)));
-  step(dalloc(&s->ranges, s->max_tiles));
-  step(dalloc(&s->tile_order, s->max_tiles));
-  step(dalloc(&s->img, s->max_px * 3));
-  step(dalloc(&s->cot, s->max_px * 3));
-  step(dalloc(&s->tan_img, s->max_px * 3));
-  step(dalloc(&s->pix_last, s->max_px));
-  step(dalloc(&s->pix_T, s->max_px));
-  step(dalloc(&s->ssim_tmp, ssim_tmp_floats(1, (int)s->max_px)));
-  step(dalloc(&s->dpart, s->max_px * 3 / 256 + s->max_tiles + 1024));
   step(dalloc(&s->dsum, kMaxLossViews));
   if (rc == GS3_OK) rc = mem::host_alloc((void**)&s->host_u32, kHostWords * sizeof(uint32_t));
   if (rc == GS3_OK) rc = mem::host_alloc((void**)&s->host_f64, sizeof(double) * kMaxLossViews);
   if (rc == GS3_OK) s->host_u32[1] = 0u;
   if (rc == GS3_OK && hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming) != hipSuccess)
     rc = fail(GS3_EDEVICE, "hipEventCreate failed");
-  if (rc == GS3_OK) rc = ensure_pairs(s, reserved_pairs(s->N), nullptr);
-  if (rc == GS3_OK) rc = ensure_owner_blocks(s, nullptr);
+  if (rc == GS3_OK) rc = alloc_slot(s, s->vb[0], reserved_pairs(s->N));
   if (rc != GS3_OK) {
     free_all(s);
     delete s;
@@ -937,9 +1072,12 @@ gs3_status gs3_scene_device_bytes(gs3_scene* s, int64_t* bytes) {
   int64_t px_total = 0;
   for (const auto& c : s->cams) px_total += (int64_t)c.width * c.height;
   const float* state[7] = {s->ghat, s->dhat, s->am, s->av, s->x_alt, s->dbuf, s->gacc};
-  int64_t b = 12 * px_total + 4 * PN;
+  int64_t b = 12 * px_total + 4 * PN + 8 * kMaxLossViews;
   for (const float* v : state) b += v ? 4 * PN : 0;
-  b += view_scratch_bytes(s->N, s->max_px, s->max_tiles) + pair_bytes(s->pair_cap, s->max_tiles, s->N);
+  for (const auto& v : s->vb)
+    if (v.ready)
+      b += view_scratch_bytes(s->N, s->max_px, s->max_tiles) + pair_bytes(v.pair_cap, s->max_tiles, s->N) +
+           (v.blend_cap - v.pair_cap) * (36 + 16);
   *bytes = b;
   return GS3_OK;
 }
@@ -982,9 +1120,8 @@ gs3_status gs3_render(gs3_scene* s, int32_t cam, float* rgb, hipStream_t st) {
   CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!rgb) return fail(GS3_EINVAL, "rgb_dev is NULL");
-  GS3_TRY(bin_view(s, cam, st));
-  const CamDev cd = make_cam(s->cams[cam]);
-  blend_fwd(s, cd, rgb, st);
+  GS3_TRY(bin_view(s, s->vb[0], cam, st));
+  blend_fwd(s, single(), st, rgb);
   return finish(s, st);
 }
 
@@ -1023,14 +1160,17 @@ gs3_status gs3_render_noalloc(int64_t n_gaussians, int32_t sh_degree, const floa
   t.max_tiles = (int)tiles;
   t.x = const_cast<float*>(params_dev);  // only read by the projection
   for (int k = 0; k < 3; ++k) t.bg[k] = background ? background[k] : 0.f;
-  Carver carver{(char*)base, kStaticScratchBytes};
-  carve_render<true>(carver, t, n_gaussians, px, tiles, lo);
-  t.pair_cap = lo;
-  t.rtmp_bytes = radix_temp_bytes(std::max<int64_t>(lo, n_gaussians));
-  t.owner_blocks = lo / 256 + 1;
   t.fixed_scratch = true;
-  GS3_TRY(bin_camera(&t, c, 0, st));
-  blend_fwd(&t, cd, rgb_dev, st);
+  ViewBufs& v = t.vb[0];
+  Carver carver{(char*)base, kStaticScratchBytes};
+  carve_render<true>(carver, v, n_gaussians, px, tiles, lo);
+  v.pair_cap = lo;
+  v.blend_cap = lo;
+  v.rtmp_bytes = radix_temp_bytes(std::max<int64_t>(lo, n_gaussians));
+  v.owner_blocks = lo / 256 + 1;
+  v.ready = true;
+  GS3_TRY(bin_camera(&t, v, c, -1, st));
+  blend_fwd(&t, single(), st, rgb_dev);
   GS3_LAUNCHED();
   return GS3_OK;
 }
@@ -1041,16 +1181,17 @@ gs3_status gs3_bin(gs3_scene* s, int32_t cam, uint64_t* keys, uint32_t* gids, ui
   CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!n_pairs) return fail(GS3_EINVAL, "n_pairs is NULL");
-  GS3_TRY(bin_view(s, cam, st));
-  *n_pairs = s->n_pairs;
-  if ((keys || gids) && s->n_pairs > capacity)
-    return fail(GS3_EINVAL, "pair count " + std::to_string(s->n_pairs) + " exceeds capacity");
-  if (keys) launch_make_keys(s->sorted_tile, s->sorted_gid, s->depth_key, s->n_pairs, keys, st);
-  if (gids && s->n_pairs > 0)
-    GS3_HIP(hipMemcpyAsync(gids, s->sorted_gid, s->n_pairs * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  ViewBufs& v = s->vb[0];
+  GS3_TRY(bin_view(s, v, cam, st));
+  *n_pairs = v.n_pairs;
+  if ((keys || gids) && v.n_pairs > capacity)
+    return fail(GS3_EINVAL, "pair count " + std::to_string(v.n_pairs) + " exceeds capacity");
+  if (keys) launch_make_keys(v.sorted_tile, v.sorted_gid, v.depth_key, v.n_pairs, keys, st);
+  if (gids && v.n_pairs > 0)
+    GS3_HIP(hipMemcpyAsync(gids, v.sorted_gid, v.n_pairs * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
   if (ranges) {
     const CamDev cd = make_cam(s->cams[cam]);
-    GS3_HIP(hipMemcpyAsync(ranges, s->ranges, (size_t)cd.tiles_x * cd.tiles_y * sizeof(uint2),
+    GS3_HIP(hipMemcpyAsync(ranges, v.ranges, (size_t)cd.tiles_x * cd.tiles_y * sizeof(uint2),
                            hipMemcpyDeviceToDevice, st));
   }
   GS3_TRY(finish(s, st));
@@ -1061,30 +1202,40 @@ gs3_status gs3_bin(gs3_scene* s, int32_t cam, uint64_t* keys, uint32_t* gids, ui
 namespace {
 
 // The gradient of Eq. objective over views cams[0..n) into grad (mode 0);
-// with `fuse` set, the last view's projection backward applies the update of
-// Algorithm 1 instead of writing its gradient (the other views' sum is in
-// grad, passed to the update as the accumulated part).
+// with `fuse` set, the last batch's projection backward applies the update
+// of Algorithm 1 instead of writing its gradient (the earlier batches' sum
+// is in grad, passed to the update as the accumulated part).  Views go in
+// batches of up to GS3_MAX_VIEWS: each view is binned into a slot of its
+// own, then one blend launch, one backward launch and one projection
+// backward cover the whole batch.
 gs3_status grad_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* grad, double* loss_out,
                       const FusedTr* fuse, hipStream_t st) {
   const float scale = (float)((double)s->n_train / (2.0 * (double)s->m_comp * n_cams));
-  for (int k = 0; k < n_cams; ++k) {
-    const int j = cams[k];
-    GS3_TRY(bin_view(s, j, st));
-    const CamDev cd = make_cam(s->cams[j]);
-    blend_fwd(s, cd, s->img, st);
-    int np = 0;
-    auto pl = prof::begin("loss", st);
-    launch_loss_grad(s->img, target_of(s, j), cd.width, cd.height, s->lam, scale, s->cot, s->ssim_tmp, s->dpart, &np,
-                     st);
-    prof::end(pl, st);
-    if (loss_out) launch_sum_partials(s->dpart, np, s->dsum + k, st);
-    blend_bwd(s, cd, s->cot, st);
-    if (fuse && k == n_cams - 1) {
+  GS3_TRY(need_slots(s, std::min<int>(n_cams, GS3_MAX_VIEWS)));
+  for (int c0 = 0; c0 < n_cams; c0 += GS3_MAX_VIEWS) {
+    Entries E;
+    E.n = std::min<int>(GS3_MAX_VIEWS, n_cams - c0);
+    for (int k = 0; k < E.n; ++k) {
+      E.b[k] = E.e[k] = k;
+      GS3_TRY(bin_view(s, s->vb[k], cams[c0 + k], st));
+    }
+    blend_fwd(s, E, st);
+    for (int k = 0; k < E.n; ++k) {
+      ViewBufs& v = s->vb[k];
+      int np = 0;
+      auto pl = prof::begin("loss", st);
+      launch_loss_grad(v.img, target_of(s, v.cam), v.cd.width, v.cd.height, s->lam, scale, v.cot, v.ssim_tmp, v.dpart,
+                       &np, st);
+      prof::end(pl, st);
+      if (loss_out) launch_sum_partials(v.dpart, np, s->dsum + c0 + k, st);
+    }
+    blend_bwd(s, E, st);
+    if (fuse && c0 + E.n == n_cams) {
       FusedTr ft = *fuse;
-      ft.gacc = k > 0 ? grad : nullptr;
-      project_bwd(s, cd, 2, 0, 0, 0, 0.f, nullptr, st, ft);
+      ft.gacc = c0 > 0 ? grad : nullptr;
+      project_bwd(s, E, 2, 0, 0, 0.f, nullptr, st, ft);
     } else {
-      project_bwd(s, cd, 0, k > 0, 0, 0, 0.f, grad, st);
+      project_bwd(s, E, 0, c0 > 0, 0, 0.f, grad, st);
     }
     GS3_LAUNCHED();
   }
@@ -1098,24 +1249,48 @@ gs3_status grad_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* 
   return GS3_OK;
 }
 
+// D_t of Hutchinson over views cams[0..n) and nu probes.  The (view, probe)
+// entries go in batches of up to GS3_MAX_VIEWS: a view is binned once per
+// batch (into the slot of its first probe), every entry gets its own tangent
+// records, images and partials, and one JVP blend launch, one backward launch
+// and one projection backward cover the batch.
 gs3_status hvp_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed, float* D,
                      hipStream_t st) {
   launch_fill_f32(D, (int64_t)s->P * s->N, 0.f, st);
   const float scale = (float)((double)s->n_train / ((double)s->m_comp * n_cams * nu));
-  for (int k = 0; k < n_cams; ++k) {
-    const int j = cams[k];
-    GS3_TRY(bin_view(s, j, st));
-    const CamDev cd = make_cam(s->cams[j]);
-    for (int i = 0; i < nu; ++i) {
-      project_jvp(s, cd, PROBE_HASH, seed, (uint32_t)i, nullptr, st);
-      blend_jvp(s, cd, s->img, s->tan_img, st);
-      auto pl = prof::begin("loss", st);
-      launch_loss_gn(s->img, target_of(s, j), s->tan_img, cd.width, cd.height, s->lam, 1.f, s->cot, s->ssim_tmp, st);
-      prof::end(pl, st);
-      blend_bwd(s, cd, s->cot, st);
-      project_bwd(s, cd, 1, 0, seed, (uint32_t)i, scale, D, st);
-      GS3_LAUNCHED();
+  const int64_t total = (int64_t)n_cams * nu;
+  GS3_TRY(need_slots(s, (int)std::min<int64_t>(total, GS3_MAX_VIEWS)));
+  for (int64_t q0 = 0; q0 < total; q0 += GS3_MAX_VIEWS) {
+    Entries E;
+    E.n = (int)std::min<int64_t>(GS3_MAX_VIEWS, total - q0);
+    for (int k = 0; k < E.n; ++k) {
+      const int64_t q = q0 + k;
+      const int j = (int)(q / nu);
+      E.e[k] = k;
+      E.probe[k] = (uint32_t)(q % nu);
+      // the view's binning: in this batch's slot of its first entry
+      const int first = (int)std::max<int64_t>(q0, (int64_t)j * nu) - (int)q0;
+      E.b[k] = first;
+      if (first == k) {
+        GS3_TRY(bin_view(s, s->vb[k], cams[j], st));
+      } else {
+        GS3_TRY(ensure_blend(s, s->vb[k], s->vb[first].n_pairs, &st));
+      }
     }
+    for (int k = 0; k < E.n; ++k)
+      project_jvp(s, s->vb[E.b[k]], s->vb[k], PROBE_HASH, seed, E.probe[k], nullptr, st);
+    blend_jvp(s, E, st);
+    for (int k = 0; k < E.n; ++k) {
+      ViewBufs& v = s->vb[k];
+      const ViewBufs& b = s->vb[E.b[k]];
+      auto pl = prof::begin("loss", st);
+      launch_loss_gn(v.img, target_of(s, b.cam), v.tan_img, b.cd.width, b.cd.height, s->lam, 1.f, v.cot, v.ssim_tmp,
+                     st);
+      prof::end(pl, st);
+    }
+    blend_bwd(s, E, st);
+    project_bwd(s, E, 1, 0, seed, scale, D, st);
+    GS3_LAUNCHED();
   }
   return GS3_OK;
 }
@@ -1241,13 +1416,13 @@ gs3_status gs3_psnr(gs3_scene* s, int32_t cam, double* out, hipStream_t st) {
   CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!out) return fail(GS3_EINVAL, "psnr_out is NULL");
-  GS3_TRY(bin_view(s, cam, st));
-  const CamDev cd = make_cam(s->cams[cam]);
-  blend_fwd(s, cd, s->img, st);
+  ViewBufs& v = s->vb[0];
+  GS3_TRY(bin_view(s, v, cam, st));
+  blend_fwd(s, single(), st);
   int np = 0;
-  const int64_t n = (int64_t)cd.width * cd.height * 3;
-  launch_sq_err(s->img, target_of(s, cam), n, s->dpart, &np, st);
-  launch_sum_partials(s->dpart, np, s->dsum, st);
+  const int64_t n = (int64_t)v.cd.width * v.cd.height * 3;
+  launch_sq_err(v.img, target_of(s, cam), n, v.dpart, &np, st);
+  launch_sum_partials(v.dpart, np, s->dsum, st);
   GS3_HIP(hipMemcpyAsync(s->host_f64, s->dsum, sizeof(double), hipMemcpyDeviceToHost, st));
   GS3_HIP(hipStreamSynchronize(st));
   const double mse = s->host_f64[0] / (double)n;
@@ -1260,11 +1435,10 @@ gs3_status gs3_render_vjp(gs3_scene* s, int32_t cam, const float* cot, float* gr
   CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!cot || !grad) return fail(GS3_EINVAL, "cot_dev and grad_dev must not be NULL");
-  GS3_TRY(bin_view(s, cam, st));
-  const CamDev cd = make_cam(s->cams[cam]);
-  blend_fwd(s, cd, s->img, st);
-  blend_bwd(s, cd, cot, st);
-  project_bwd(s, cd, 0, 0, 0, 0, 0.f, grad, st);
+  GS3_TRY(bin_view(s, s->vb[0], cam, st));
+  blend_fwd(s, single(), st);
+  blend_bwd(s, single(), st, cot);
+  project_bwd(s, single(), 0, 0, 0, 0.f, grad, st);
   return finish(s, st);
 }
 
@@ -1273,10 +1447,10 @@ gs3_status gs3_render_jvp(gs3_scene* s, int32_t cam, const float* tangent, float
   CallEnd end_{s, st};
   GS3_TRY(check_cam(s, cam));
   if (!tangent || !rgb || !tan) return fail(GS3_EINVAL, "tangent_dev, rgb_dev and tan_dev must not be NULL");
-  GS3_TRY(bin_view(s, cam, st));
-  const CamDev cd = make_cam(s->cams[cam]);
-  project_jvp(s, cd, PROBE_ARRAY, 0, 0, tangent, st);
-  blend_jvp(s, cd, rgb, tan, st);
+  ViewBufs& v = s->vb[0];
+  GS3_TRY(bin_view(s, v, cam, st));
+  project_jvp(s, v, v, PROBE_ARRAY, 0, 0, tangent, st);
+  blend_jvp(s, single(), st, rgb, tan);
   return finish(s, st);
 }
 

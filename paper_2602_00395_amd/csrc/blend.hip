@@ -53,6 +53,8 @@
 // wave64 reduction with permlane swaps and DPP row scans, then the four waves
 // in LDS in a fixed order) and written to the pair's own slot: no float
 // atomics, so the backward is deterministic.
+#include <algorithm>
+
 #include "gs3_internal.h"
 
 namespace {
@@ -208,15 +210,13 @@ struct StageW {
 };
 
 template <bool COUNT>
-__global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(const Rec* __restrict__ rec,
-                                                          const uint32_t* __restrict__ pair_gid,
-                                                          const uint2* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ order, CamDev cam, float bg0,
-                                                          float bg1, float bg2, float* __restrict__ img,
-                                                          uint32_t* __restrict__ pix_last, float* __restrict__ pix_T,
-                                                          float4* __restrict__ seg, int n_tiles, int chunk,
-                                                          unsigned long long* __restrict__ ctr) {
-  const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
+__device__ __forceinline__ void blend_fwd_body(const Rec* __restrict__ rec, const uint32_t* __restrict__ pair_gid,
+                                               const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
+                                               const CamDev& cam, float bg0, float bg1, float bg2,
+                                               float* __restrict__ img, uint32_t* __restrict__ pix_last,
+                                               float* __restrict__ pix_T, float4* __restrict__ seg, int n_tiles,
+                                               int chunk, int bid, unsigned long long* __restrict__ ctr) {
+  const int t = tile_of_block(bid, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ StageW stage[4];
   uint32_t nev = 0, ncon = 0;
@@ -356,15 +356,15 @@ struct StageJW {
 };
 
 template <bool COUNT>
-__global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(const Rec* __restrict__ rec, const TRec* __restrict__ trec,
-                                                          const uint32_t* __restrict__ pair_gid,
-                                                          const uint2* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ order, CamDev cam, float bg0,
-                                                          float bg1, float bg2, float* __restrict__ img,
-                                                          float* __restrict__ tan_img, uint32_t* __restrict__ pix_last,
-                                                          float* __restrict__ pix_T, float4* __restrict__ seg,
-                                                          int n_tiles, int chunk, unsigned long long* __restrict__ ctr) {
-  const int t = tile_of_block(blockIdx.x, order, n_tiles, chunk);
+__device__ __forceinline__ void blend_jvp_body(const Rec* __restrict__ rec, const TRec* __restrict__ trec,
+                                               const uint32_t* __restrict__ pair_gid,
+                                               const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
+                                               const CamDev& cam, float bg0, float bg1, float bg2,
+                                               float* __restrict__ img, float* __restrict__ tan_img,
+                                               uint32_t* __restrict__ pix_last, float* __restrict__ pix_T,
+                                               float4* __restrict__ seg, int n_tiles, int chunk, int bid,
+                                               unsigned long long* __restrict__ ctr) {
+  const int t = tile_of_block(bid, order, n_tiles, chunk);
   if (t >= n_tiles) return;
   __shared__ StageJW stage[4];
   uint32_t nev = 0, ncon = 0;
@@ -571,18 +571,15 @@ __device__ __forceinline__ uint32_t pair_slot(uint32_t pair_off, uint2 rc, int t
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__ rec,
-                                                          const uint2* __restrict__ rect,
-                                                          const uint32_t* __restrict__ pair_gid,
-                                                          const uint2* __restrict__ ranges,
-                                                          const uint2* __restrict__ units, CamDev cam,
-                                                          const uint32_t* __restrict__ pix_last,
-                                                          const float* __restrict__ pix_T,
-                                                          const float4* __restrict__ seg, float bg0, float bg1,
-                                                          float bg2, const float* __restrict__ cot,
-                                                          float* __restrict__ partials, int n_tiles,
-                                                          unsigned long long* __restrict__ ctr) {
-  const uint2 unit = units[blockIdx.x];
+__device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, const uint2* __restrict__ rect,
+                                               const uint32_t* __restrict__ pair_gid,
+                                               const uint2* __restrict__ ranges, const uint2* __restrict__ units,
+                                               const CamDev& cam, const uint32_t* __restrict__ pix_last,
+                                               const float* __restrict__ pix_T, const float4* __restrict__ seg,
+                                               float bg0, float bg1, float bg2, const float* __restrict__ cot,
+                                               float* __restrict__ partials, int n_tiles, int bid,
+                                               unsigned long long* __restrict__ ctr) {
+  const uint2 unit = units[bid];
   const int t = (int)__builtin_amdgcn_readfirstlane(unit.x);
   if (t >= n_tiles) return;
   const uint32_t m = __builtin_amdgcn_readfirstlane(unit.y);  // depth segment of the tile's list
@@ -781,35 +778,78 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(const Rec* __restrict__
   count_evals<COUNT>(ctr, nev, ncon);
 }
 
+// Views of one launch: workgroup b works for view b mod n on that view's
+// block b / n (views interleaved, so every view's longest tiles start early),
+// and returns at once past the view's own block count.
+__device__ __forceinline__ bool view_of_block(const BlendBatch& B, int& v, int& local) {
+  v = (int)(blockIdx.x % (unsigned)B.n);
+  local = (int)(blockIdx.x / (unsigned)B.n);
+  return local < B.v[v].blocks;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(GS3_BLOCK) void k_blend_fwd(BlendBatch B, float bg0, float bg1, float bg2,
+                                                          unsigned long long* __restrict__ ctr) {
+  int v, b;
+  if (!view_of_block(B, v, b)) return;
+  const BlendView& V = B.v[v];
+  blend_fwd_body<COUNT>(V.rec, V.pair_gid, V.ranges, V.order, V.cam, bg0, bg1, bg2, V.img, V.pix_last, V.pix_T,
+                        V.seg, V.n_tiles, V.chunk, b, ctr);
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(GS3_BLOCK) void k_blend_jvp(BlendBatch B, float bg0, float bg1, float bg2,
+                                                          unsigned long long* __restrict__ ctr) {
+  int v, b;
+  if (!view_of_block(B, v, b)) return;
+  const BlendView& V = B.v[v];
+  blend_jvp_body<COUNT>(V.rec, V.trec, V.pair_gid, V.ranges, V.order, V.cam, bg0, bg1, bg2, V.img, V.tan_img,
+                        V.pix_last, V.pix_T, V.seg, V.n_tiles, V.chunk, b, ctr);
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(BlendBatch B, float bg0, float bg1, float bg2,
+                                                          unsigned long long* __restrict__ ctr) {
+  int v, b;
+  if (!view_of_block(B, v, b)) return;
+  const BlendView& V = B.v[v];
+  blend_bwd_body<COUNT>(V.rec, V.rect, V.pair_gid, V.ranges, V.units, V.cam, V.pix_last, V.pix_T, V.seg, bg0, bg1,
+                        bg2, V.cot, V.partials, V.n_tiles, b, ctr);
+}
+
 inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }
+
+// Fills the per-launch fields of each view (block counts) and the grid.
+unsigned batch_grid(BlendBatch& B, int kind) {
+  int span = 0;
+  for (int v = 0; v < B.n; ++v) {
+    BlendView& V = B.v[v];
+    V.chunk = chunk_for(V.n_tiles);
+    V.blocks = kind == 2 ? (int)V.n_units : (V.order ? V.n_tiles : 8 * V.chunk);
+    span = std::max(span, V.blocks);
+  }
+  return (unsigned)span * (unsigned)B.n;
+}
 
 }  // namespace
 
-void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
-                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T, float4* seg,
-                      hipStream_t st, unsigned long long* ctr) {
-  const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
+void launch_blend_fwd(BlendBatch B, const float* bg, hipStream_t st, unsigned long long* ctr) {
+  const unsigned grid = batch_grid(B, 0);
+  if (grid == 0) return;
   auto kernel = ctr ? k_blend_fwd<true> : k_blend_fwd<false>;
-  hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, pair_gid, ranges, order,
-                     cam, bg[0], bg[1], bg[2], img, pix_last, pix_T, seg, nt, ch, ctr);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(GS3_BLOCK), 0, st, B, bg[0], bg[1], bg[2], ctr);
 }
 
-void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
-                      uint32_t* pix_last, float* pix_T, float4* seg, hipStream_t st, unsigned long long* ctr) {
-  const int nt = cam.tiles_x * cam.tiles_y, ch = chunk_for(nt);
+void launch_blend_jvp(BlendBatch B, const float* bg, hipStream_t st, unsigned long long* ctr) {
+  const unsigned grid = batch_grid(B, 1);
+  if (grid == 0) return;
   auto kernel = ctr ? k_blend_jvp<true> : k_blend_jvp<false>;
-  hipLaunchKernelGGL(kernel, dim3(order ? nt : 8 * ch), dim3(GS3_BLOCK), 0, st, rec, trec, pair_gid, ranges,
-                     order, cam, bg[0], bg[1], bg[2], img, tan_img, pix_last, pix_T, seg, nt, ch, ctr);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(GS3_BLOCK), 0, st, B, bg[0], bg[1], bg[2], ctr);
 }
 
-void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint2* units, int64_t n_units, const CamDev& cam, const uint32_t* pix_last,
-                      const float* pix_T, const float4* seg, const float* bg, const float* cot, float* partials,
-                      hipStream_t st, unsigned long long* ctr) {
-  const int nt = cam.tiles_x * cam.tiles_y;
-  if (n_units < 1) return;
+void launch_blend_bwd(BlendBatch B, const float* bg, hipStream_t st, unsigned long long* ctr) {
+  const unsigned grid = batch_grid(B, 2);
+  if (grid == 0) return;
   auto kernel = ctr ? k_blend_bwd<true> : k_blend_bwd<false>;
-  hipLaunchKernelGGL(kernel, dim3((unsigned)n_units), dim3(GS3_BLOCK), 0, st, rec, rect, pair_gid, ranges, units,
-                     cam, pix_last, pix_T, seg, bg[0], bg[1], bg[2], cot, partials, nt, ctr);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(GS3_BLOCK), 0, st, B, bg[0], bg[1], bg[2], ctr);
 }

@@ -13,6 +13,8 @@
 // depth segment of a tile's pair list processed by one backward workgroup
 // (a multiple of the backward's 128-splat batch)
 #define GS3_SEG 256
+// views (or probes) one blend or projection-backward launch covers
+#define GS3_MAX_VIEWS 8
 
 // Rasteriser constants of the original 3DGS design (the paper states only the
 // blend equation): near plane, screen-space dilation, frustum clamp of the
@@ -94,11 +96,27 @@ struct FusedTr {
 // depth rank; gsum: float[n][9] (a Gaussian's nine values contiguous).
 void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint32_t* counts, const float* partials,
                       int64_t n, float* gsum, hipStream_t st);
-// Chain rule from gsum to the raw parameters.  mode 0: out = (accumulate ?
-// out : 0) + dL/dx; mode 1: out += scale z dL/dx for probe i of `seed`
-// (invisible Gaussians untouched); mode 2: the fused update described by ft.
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* tiles,
-                        const float* gsum, int mode, int accumulate, uint64_t seed, uint32_t probe_index, float scale,
+// One view (or one probe of a view) of a projection-backward batch: its
+// records, tile counts (0: the view does not see the Gaussian), summed
+// partials and camera; `inner` is the probe's key (probe_key) in mode 1.
+struct BwdView {
+  const Rec* rec = nullptr;
+  const uint32_t* tiles = nullptr;
+  const float* G = nullptr;
+  CamDev cam{};
+  uint64_t inner = 0;
+};
+struct BwdBatch {
+  BwdView v[GS3_MAX_VIEWS];
+  int n = 0;
+};
+// Key of probe i of `seed` (the inner SplitMix64 of the probe definition).
+uint64_t probe_key(uint64_t seed, uint32_t probe_index);
+// Chain rule from each view's gsum to the raw parameters, summed over the
+// views of B.  mode 0: out = (accumulate ? out : 0) + dL/dx; mode 1: out +=
+// scale sum_i z_i dL_i/dx for the probes of B's entries (Gaussians no entry
+// sees untouched); mode 2: the fused update described by ft.
+void launch_project_bwd(const float* x, int64_t n, int deg, const BwdBatch& B, int mode, int accumulate, float scale,
                         float* out, const FusedTr& ft, hipStream_t st);
 
 // sorting and binning
@@ -137,10 +155,11 @@ void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const
                       int64_t n_pairs, uint64_t* keys, hipStream_t st);
 
 // blending
-// order (nullable): tile processed by workgroup b is order[b] (longest list
-// first); NULL = XCD-banded order.  ctr (nullable): two u64 counters
-// receiving the number of (pixel, splat) evaluations and of contributing
-// evaluations (measurement only).
+// A blend launch covers up to GS3_MAX_VIEWS views (several views of a
+// mini-batch, or several Hutchinson probes of one view, in one launch).  Per
+// view:
+// order (nullable): tile processed by the view's workgroup b is order[b]
+// (longest list first); NULL = XCD-banded order.
 // pix_last / pix_T (float[H][W] each): 1 + pair index of each pixel's last
 // contributing splat (0: none) and its final transmittance, written by the
 // forward (or the JVP) and read by the backward.
@@ -149,19 +168,38 @@ void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const
 // after the segment and the colour the segment added, at row
 // t + ranges[t].x / GS3_SEG + m; written by the forward (or the JVP) for the
 // segments its pixels reach, read by the backward's segment units.
+// units / n_units: the backward's (tile, segment) units from
+// launch_tile_order (one workgroup per unit).
+// ctr (nullable): two u64 counters receiving the number of (pixel, splat)
+// evaluations and of contributing evaluations (measurement only).
 inline int64_t seg_slots(int64_t n_tiles, int64_t n_pairs) { return n_tiles + n_pairs / GS3_SEG + 1; }
-void launch_blend_fwd(const Rec* rec, const uint32_t* pair_gid, const uint2* ranges, const uint32_t* order,
-                      const CamDev& cam, const float* bg, float* img, uint32_t* pix_last, float* pix_T, float4* seg,
-                      hipStream_t st, unsigned long long* ctr = nullptr);
-void launch_blend_jvp(const Rec* rec, const TRec* trec, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint32_t* order, const CamDev& cam, const float* bg, float* img, float* tan_img,
-                      uint32_t* pix_last, float* pix_T, float4* seg, hipStream_t st,
-                      unsigned long long* ctr = nullptr);
-// units / n_units: from launch_tile_order (one workgroup per unit)
-void launch_blend_bwd(const Rec* rec, const uint2* rect, const uint32_t* pair_gid, const uint2* ranges,
-                      const uint2* units, int64_t n_units, const CamDev& cam, const uint32_t* pix_last,
-                      const float* pix_T, const float4* seg, const float* bg, const float* cot, float* partials,
-                      hipStream_t st, unsigned long long* ctr = nullptr);
+struct BlendView {
+  const Rec* rec = nullptr;
+  const TRec* trec = nullptr;  // JVP
+  const uint32_t* pair_gid = nullptr;
+  const uint2* ranges = nullptr;
+  const uint32_t* order = nullptr;
+  const uint2* rect = nullptr;    // backward
+  const uint2* units = nullptr;   // backward
+  int64_t n_units = 0;            // backward
+  const float* cot = nullptr;     // backward
+  float* partials = nullptr;      // backward
+  float* img = nullptr;           // forward, JVP
+  float* tan_img = nullptr;       // JVP
+  uint32_t* pix_last = nullptr;
+  float* pix_T = nullptr;
+  float4* seg = nullptr;
+  CamDev cam{};
+  int n_tiles = 0;
+  int chunk = 0, blocks = 0;  // set by the launcher
+};
+struct BlendBatch {
+  BlendView v[GS3_MAX_VIEWS];
+  int n = 0;
+};
+void launch_blend_fwd(BlendBatch views, const float* bg, hipStream_t st, unsigned long long* ctr = nullptr);
+void launch_blend_jvp(BlendBatch views, const float* bg, hipStream_t st, unsigned long long* ctr = nullptr);
+void launch_blend_bwd(BlendBatch views, const float* bg, hipStream_t st, unsigned long long* ctr = nullptr);
 
 // loss
 // cot = scale * d(sum_k l_k)/dC; optional per-block loss partial sums (double).

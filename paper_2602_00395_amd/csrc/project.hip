@@ -595,19 +595,21 @@ __host__ __device__ constexpr int sh_lo(int w) {
   return w >= 4 ? (DEG + 1) * (DEG + 1) : ((w - 1) * (DEG + 1) * (DEG + 1) + 2) / 3;
 }
 
-// What a wave does with the gradient v of its rows (see launch_project_bwd):
-// mode 0 writes (or adds to) out, mode 1 adds scale z v to out for the probe
-// z, mode 2 applies the update of Algorithm 1.  Rows go in chunks of kChunk:
-// every load of a chunk is issued before any of its stores (the state arrays
-// may alias as far as the compiler knows, so loads would otherwise wait for
-// the previous row's stores), which keeps up to 5 x kChunk loads in flight
-// per wave without the registers of all rows at once.
+// What a wave does with the summed value v of each of its rows (see
+// launch_project_bwd; `have` false: no view of the batch sees the Gaussian):
+// mode 0 writes (or adds to) out, mode 1 adds v to out (v already holds the
+// probes' signs and the scale), mode 2 applies the update of Algorithm 1.
+// Rows go in chunks of kChunk: every load of a chunk is issued before any of
+// its stores (the state arrays may alias as far as the compiler knows, so
+// loads would otherwise wait for the previous row's stores), which keeps up
+// to 5 x kChunk loads in flight per wave without the registers of all rows
+// at once.
 constexpr int kChunk = 6;
 
 template <int R, class RowOf, class ValOf, class EtaOf>
 __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n, int64_t g, int mode, int accumulate,
-                                          uint64_t inner, float scale, float* __restrict__ out, const FusedTr& ft,
-                                          const RowOf& row_of, const ValOf& val_of, const EtaOf& eta_of) {
+                                          bool have, float* __restrict__ out, const FusedTr& ft, const RowOf& row_of,
+                                          const ValOf& val_of, const EtaOf& eta_of) {
 #pragma unroll
   for (int c0 = 0; c0 < R; c0 += kChunk) {
     constexpr int C = kChunk;
@@ -626,10 +628,7 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
         if (c0 + j < R) o[j] = out[(int64_t)row_of(c0 + j) * n + g];
 #pragma unroll
       for (int j = 0; j < C; ++j)
-        if (c0 + j < R) {
-          const int64_t k = (int64_t)row_of(c0 + j) * n + g;
-          out[k] = o[j] + scale * probe_sign(inner, (uint64_t)k) * val_of(c0 + j);
-        }
+        if (c0 + j < R) out[(int64_t)row_of(c0 + j) * n + g] = o[j] + val_of(c0 + j);
     } else {
       const TrArgs& a = ft.a;
       float xv[C], gh[C], dh[C], dv[C], ga[C];
@@ -647,9 +646,10 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
       for (int j = 0; j < C; ++j)
         if (c0 + j < R) {
           const int64_t k = (int64_t)row_of(c0 + j) * n + g;
-          // the view's part added to the other views' sum, as the separate
-          // gradient accumulates it
-          const float gk = ft.gacc ? ga[j] + val_of(c0 + j) : val_of(c0 + j);
+          // this batch's part added to the earlier batches' sum, as the
+          // separate gradient accumulates it
+          const float v = have ? val_of(c0 + j) : 0.f;
+          const float gk = ft.gacc ? (have ? ga[j] + v : ga[j]) : v;
           const float xn = xv[j] + gs3trust::tr_row(gk, gh[j], dh[j], dv[j], eta_of(c0 + j), a);
           ft.x_out[k] = xn;
           ft.ghat[k] = gh[j];
@@ -661,81 +661,104 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
 }
 
 // Chain rule from the summed screen-space partials G (d/du, d/dv, d/dconic
-// a, b, c, d/dalpha, d/drgb) to the raw parameters.  Wave 0: the reverse-mode
-// pass through the projection (geo_vjp), d alpha / d logit = s (1 - s), and
-// the colour's dependence on the mean through the view direction dir =
-// (mu - campos) / |mu - campos|: sum_k (sum_c g_c f_kc) grad Y_k(dir),
-// projected on the plane normal to dir and divided by |mu - campos|.  Waves
-// 1..3: d rgb_c / d f_kc = Y_k(dir) where the colour clamp is inactive, and
-// their coefficients' share of that direction term, passed to wave 0 through
-// LDS and summed in wave order.  In mode 2 each wave forms the trust-region
-// radii of its rows from the parameters before the update (the same
-// expressions as the separate update kernel), so the update needs no radius
-// pass of its own.
-template <int DEG>
-__device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, int64_t n, const CamDev& cam,
-                                                 const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
-                                                 const float* __restrict__ G, int mode, int accumulate,
-                                                 uint64_t inner, float scale, float* __restrict__ out,
+// a, b, c, d/dalpha, d/drgb) of every view of a batch to the raw
+// parameters, summed over the views in batch order.  Wave 0: per view the
+// reverse-mode pass through the projection (geo_vjp), d alpha / d logit =
+// s (1 - s), and the colour's dependence on the mean through the view
+// direction dir = (mu - campos) / |mu - campos|: sum_k (sum_c g_c f_kc)
+// grad Y_k(dir), projected on the plane normal to dir and divided by
+// |mu - campos|.  Waves 1..3: d rgb_c / d f_kc = Y_k(dir) where the colour
+// clamp is inactive, and their coefficients' share of the direction term,
+// passed to wave 0 through LDS and summed in wave order.  A view adds
+// nothing for a Gaussian it does not see.  In mode 1 each batch entry is a
+// probe of a view, and its part is multiplied by the scale and the probe's
+// sign before the sum.  In mode 2 each wave forms the trust-region radii of
+// its rows from the parameters before the update (the same expressions as
+// the separate update kernel).
+template <int DEG, int mode>
+__device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, int64_t n, const BwdBatch& B,
+                                                 int accumulate, float scale, float* __restrict__ out,
                                                  const FusedTr& ft) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  __shared__ float gdir_part[3][3][kBwdGauss];
+  __shared__ float gdir_part[GS3_MAX_VIEWS][3][3][kBwdGauss];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t g = (int64_t)blockIdx.x * kBwdGauss + lane;
   const bool live = g < n;
-  const bool vis = live && tiles[g] != 0u;
   auto xr = [&](int r) { return x[(int64_t)r * n + g]; };
-  // view direction and the unclamped colour cotangents
-  float gc[3] = {0.f, 0.f, 0.f}, e[3] = {0.f, 0.f, 0.f}, inv = 0.f;
-  if (vis) {
-    const uint32_t posm = __float_as_uint(rec[g].c.w);
-    const float* Gg = G + g * 9;
-    gc[0] = (posm & 1u) ? Gg[6] : 0.f;
-    gc[1] = (posm & 2u) ? Gg[7] : 0.f;
-    gc[2] = (posm & 4u) ? Gg[8] : 0.f;
-    const float dx = xr(0) - cam.campos[0], dy = xr(1) - cam.campos[1], dz = xr(2) - cam.campos[2];
+  const float mu[3] = {live ? xr(0) : 0.f, live ? xr(1) : 0.f, live ? xr(2) : 0.f};
+  // view direction of the Gaussian in view v
+  auto direction = [&](const CamDev& cam, float e[3], float& inv) {
+    const float dx = mu[0] - cam.campos[0], dy = mu[1] - cam.campos[1], dz = mu[2] - cam.campos[2];
     inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
     e[0] = dx * inv;
     e[1] = dy * inv;
     e[2] = dz * inv;
-  }
+  };
+  // the unclamped colour cotangents of view v
+  auto colour_cot = [&](const BwdView& V, float gc[3]) {
+    const uint32_t posm = __float_as_uint(V.rec[g].c.w);
+    const float* Gg = V.G + g * 9;
+    gc[0] = (posm & 1u) ? Gg[6] : 0.f;
+    gc[1] = (posm & 2u) ? Gg[7] : 0.f;
+    gc[2] = (posm & 4u) ? Gg[8] : 0.f;
+  };
+  // the weight of view v's part of row r: the scaled probe sign in mode 1
+  auto weight = [&](const BwdView& V, int r) {
+    return mode == 1 ? scale * probe_sign(V.inner, (uint64_t)((int64_t)r * n + g)) : 1.f;
+  };
   const float eps = ft.a.epsilon;
   const uint32_t variant = ft.a.variant;
+  bool have = false;  // some view of the batch sees the Gaussian
   if (w > 0) {
     // the wave's coefficient run as compile-time indices, so the basis
-    // values and radii stay in registers
+    // values, row sums and radii stay in registers
     auto run = [&](auto wave) {
       constexpr int W = decltype(wave)::value;
       constexpr int k0 = sh_lo<DEG>(W), k1 = sh_lo<DEG>(W + 1);
-      float Y[K];
-      float part[3] = {0.f, 0.f, 0.f};
-      if (vis) {
-        sh_basis<float, DEG>(e[0], e[1], e[2], Y);
-        // this wave's share of the direction term, coefficients in order
+      constexpr int NR = 3 * (k1 - k0) > 0 ? 3 * (k1 - k0) : 1;
+      float val[NR];
 #pragma unroll
-        for (int k = k0; k < k1; ++k) {
-          if (k == 0) continue;
-          const float gy = (gc[0] * xr(11 + 3 * k) + gc[1] * xr(12 + 3 * k)) + gc[2] * xr(13 + 3 * k);
-          float gr[3];
-          sh_grad(k, e[0], e[1], e[2], gr);
+      for (int i = 0; i < NR; ++i) val[i] = 0.f;
+      for (int v = 0; v < B.n; ++v) {
+        const BwdView& V = B.v[v];
+        const bool vis = live && V.tiles[g] != 0u;
+        float part[3] = {0.f, 0.f, 0.f};
+        if (vis) {
+          float gc[3], e[3], inv;
+          colour_cot(V, gc);
+          direction(V.cam, e, inv);
+          float Y[K];
+          sh_basis<float, DEG>(e[0], e[1], e[2], Y);
 #pragma unroll
-          for (int ax = 0; ax < 3; ++ax) part[ax] += gy * gr[ax];
+          for (int k = k0; k < k1; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const int i = 3 * (k - k0) + c;
+              const float pv = weight(V, 11 + 3 * k + c) * (gc[c] * Y[k]);
+              val[i] = have ? val[i] + pv : pv;
+            }
+            if (k == 0) continue;
+            // this wave's share of the direction term, coefficients in order
+            const float gy = (gc[0] * xr(11 + 3 * k) + gc[1] * xr(12 + 3 * k)) + gc[2] * xr(13 + 3 * k);
+            float gr[3];
+            sh_grad(k, e[0], e[1], e[2], gr);
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) part[ax] += gy * gr[ax];
+          }
+          have = true;
         }
-      } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) Y[k] = 0.f;
+        for (int ax = 0; ax < 3; ++ax) gdir_part[v][W - 1][ax][lane] = part[ax];
       }
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) gdir_part[W - 1][ax][lane] = part[ax];
       __syncthreads();
       // an invisible Gaussian adds nothing to an accumulated output
-      if (!live || (!vis && (mode == 1 || (mode == 0 && accumulate)))) return;
+      if (!live || (!have && (mode == 1 || (mode == 0 && accumulate)))) return;
       if constexpr (k1 > k0) {
         gs3trust::Radius rad;
         if (mode == 2) gs3trust::radius_colour(x, n, g, eps, variant, DEG, gs3trust::radius_alpha(x, n, g), rad);
         emit_rows<3 * (k1 - k0)>(
-            x, n, g, mode, accumulate, inner, scale, out, ft, [&](int i) { return 11 + 3 * k0 + i; },
-            [&](int i) { return gc[i % 3] * Y[k0 + i / 3]; },
+            x, n, g, mode, accumulate, have, out, ft, [&](int i) { return 11 + 3 * k0 + i; },
+            [&](int i) { return val[i]; },
             [&](int i) { return k0 + i / 3 == 0 ? rad.col[i % 3] : rad.rest[i % 3]; });
       }
     };
@@ -748,45 +771,56 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
   float d[11];
 #pragma unroll
   for (int r = 0; r < 11; ++r) d[r] = 0.f;
-  if (vis) {
-    const float* Gg = G + g * 9;
+  for (int v = 0; v < B.n; ++v) {
+    const BwdView& V = B.v[v];
+    if (!(live && V.tiles[g] != 0u)) continue;
+    const float* Gg = V.G + g * 9;
     const float Gs[5] = {Gg[0], Gg[1], Gg[2], Gg[3], Gg[4]};
-    geo_vjp(x, n, g, cam, Gs, d);
+    float dv[11];
+    geo_vjp(x, n, g, V.cam, Gs, dv);
     const float s = sigmoid_(xr(10));
-    d[10] = Gg[5] * s * (1.f - s);
+    dv[10] = Gg[5] * s * (1.f - s);
+#pragma unroll
+    for (int r = 0; r < 11; ++r) {
+      const float pv = weight(V, r) * dv[r];
+      d[r] = have ? d[r] + pv : pv;
+    }
+    have = true;
   }
   __syncthreads();
-  if (vis && DEG > 0) {
-    float gdir[3];
+  if (DEG > 0) {
+    for (int v = 0; v < B.n; ++v) {
+      const BwdView& V = B.v[v];
+      if (!(live && V.tiles[g] != 0u)) continue;
+      float e[3], inv, gdir[3];
+      direction(V.cam, e, inv);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) gdir[ax] = (gdir_part[0][ax][lane] + gdir_part[1][ax][lane]) + gdir_part[2][ax][lane];
-    const float ed = (e[0] * gdir[0] + e[1] * gdir[1]) + e[2] * gdir[2];
+      for (int ax = 0; ax < 3; ++ax)
+        gdir[ax] = (gdir_part[v][0][ax][lane] + gdir_part[v][1][ax][lane]) + gdir_part[v][2][ax][lane];
+      const float ed = (e[0] * gdir[0] + e[1] * gdir[1]) + e[2] * gdir[2];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) d[ax] += (gdir[ax] - e[ax] * ed) * inv;
+      for (int ax = 0; ax < 3; ++ax) d[ax] += weight(V, ax) * ((gdir[ax] - e[ax] * ed) * inv);
+    }
   }
-  if (!live || (!vis && (mode == 1 || (mode == 0 && accumulate)))) return;
+  if (!live || (!have && (mode == 1 || (mode == 0 && accumulate)))) return;
   gs3trust::Radius rad;
   if (mode == 2) gs3trust::radius_geo(x, n, g, eps, variant, gs3trust::radius_alpha(x, n, g), rad);
-  emit_rows<11>(x, n, g, mode, accumulate, inner, scale, out, ft, [](int i) { return i; },
-                [&](int i) { return d[i]; }, [&](int i) { return gs3trust::row_radius(rad, i); });
+  emit_rows<11>(x, n, g, mode, accumulate, have, out, ft, [](int i) { return i; }, [&](int i) { return d[i]; },
+                [&](int i) { return gs3trust::row_radius(rad, i); });
 }
 
-// The chain rule into a gradient (mode 0) or a Hutchinson diagonal (mode 1).
-template <int DEG>
-__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, CamDev cam,
-                                                      const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
-                                                      const float* __restrict__ G, int mode, int accumulate,
-                                                      uint64_t inner, float scale, float* __restrict__ out) {
-  project_bwd_body<DEG>(x, n, cam, rec, tiles, G, mode, accumulate, inner, scale, out, FusedTr{});
+// The chain rule into a gradient (MODE 0) or a Hutchinson diagonal (MODE 1).
+template <int DEG, int MODE>
+__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x, int64_t n, BwdBatch B,
+                                                      int accumulate, float scale, float* __restrict__ out) {
+  project_bwd_body<DEG, MODE>(x, n, B, accumulate, scale, out, FusedTr{});
 }
 
 // The chain rule fused with the update of Algorithm 1 (mode 2): a kernel of
 // its own name, so profiles tell it from the gradient launches.
 template <int DEG>
-__global__ __launch_bounds__(256) void k_tr_update(const float* __restrict__ x, int64_t n, CamDev cam,
-                                                    const Rec* __restrict__ rec, const uint32_t* __restrict__ tiles,
-                                                    const float* __restrict__ G, FusedTr ft) {
-  project_bwd_body<DEG>(x, n, cam, rec, tiles, G, 2, 0, 0ull, 0.f, nullptr, ft);
+__global__ __launch_bounds__(256) void k_tr_update(const float* __restrict__ x, int64_t n, BwdBatch B, FusedTr ft) {
+  project_bwd_body<DEG, 2>(x, n, B, 0, 0.f, nullptr, ft);
 }
 
 uint64_t probe_inner(uint64_t seed, uint32_t i) {
@@ -828,14 +862,27 @@ void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint
                      partials, n, gsum);
 }
 
-void launch_project_bwd(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec, const uint32_t* tiles,
-                        const float* gsum, int mode, int accumulate, uint64_t seed, uint32_t probe_index, float scale,
+void launch_project_bwd(const float* x, int64_t n, int deg, const BwdBatch& B, int mode, int accumulate, float scale,
                         float* out, const FusedTr& ft, hipStream_t st) {
+  if (B.n < 1) return;
   if (mode == 2) {
-    GS3_DEG_DISPATCH(deg, k_tr_update, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, cam, rec, tiles, gsum,
-                     ft);
+    GS3_DEG_DISPATCH(deg, k_tr_update, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, B, ft);
   } else {
-    GS3_DEG_DISPATCH(deg, k_project_bwd, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, cam, rec, tiles,
-                     gsum, mode, accumulate, probe_inner(seed, probe_index), scale, out);
+    auto kernel = [&](auto d, auto m) {
+      hipLaunchKernelGGL((k_project_bwd<decltype(d)::value, decltype(m)::value>), dim3(blocks_for(n, kBwdGauss)),
+                         dim3(256), 0, st, x, n, B, accumulate, scale, out);
+    };
+    auto by_mode = [&](auto d) {
+      if (mode == 1) kernel(d, std::integral_constant<int, 1>{});
+      else kernel(d, std::integral_constant<int, 0>{});
+    };
+    switch (deg) {
+      case 0: by_mode(std::integral_constant<int, 0>{}); break;
+      case 1: by_mode(std::integral_constant<int, 1>{}); break;
+      case 2: by_mode(std::integral_constant<int, 2>{}); break;
+      default: by_mode(std::integral_constant<int, 3>{}); break;
+    }
   }
 }
+
+uint64_t probe_key(uint64_t seed, uint32_t probe_index) { return probe_inner(seed, probe_index); }
