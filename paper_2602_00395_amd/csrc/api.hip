@@ -150,6 +150,7 @@ struct ViewBufs {
   int64_t blend_cap = 0;
   float4* seg = nullptr;
   float* partials = nullptr;
+  uint32_t* valid = nullptr;  // bit per partials slot: written by the last backward
   float* gsum = nullptr;  // float[N][9]: each Gaussian's summed partials
   TRec* trec = nullptr;
   // per-pixel image scratch
@@ -395,6 +396,7 @@ void free_slot(ViewBufs& v) {
   dfree(v.pt2);
   dfree(v.pg2);
   dfree(v.partials);
+  dfree(v.valid);
   dfree(v.block_owner);
   dfree(v.units);
   dfree(v.seg);
@@ -476,7 +478,7 @@ int64_t reserved_pairs(int64_t n) { return kPairsPerGaussian * n; }
 // max_tiles tiles: tile ids and Gaussian ids double-buffered, nine partials
 // per pair, the backward's units and segment states, the radix histograms
 int64_t pair_bytes(int64_t cap, int64_t max_tiles, int64_t n) {
-  return cap * (16 + 36) + seg_slots(max_tiles, cap) * (8 + 16 * GS3_BLOCK) +
+  return cap * (16 + 36) + cap / 8 + seg_slots(max_tiles, cap) * (8 + 16 * GS3_BLOCK) +
          (int64_t)radix_temp_bytes(std::max<int64_t>(cap, n)) + 4 * (cap / 256 + 1);
 }
 
@@ -526,9 +528,11 @@ gs3_status ensure_blend(gs3_scene* s, ViewBufs& v, int64_t n_pairs, const hipStr
                                 std::to_string(v.blend_cap));
   const int64_t cap = std::max<int64_t>(pair_capacity(n_pairs), v.blend_cap);
   dfree(v.partials, st);
+  dfree(v.valid, st);
   dfree(v.seg, st);
   v.blend_cap = 0;
   GS3_TRY(dalloc(&v.partials, (size_t)cap * 9));
+  GS3_TRY(dalloc(&v.valid, (size_t)(cap / 32 + 1)));
   GS3_TRY(dalloc(&v.seg, (size_t)seg_slots(s->max_tiles, cap) * GS3_BLOCK));
   v.blend_cap = cap;
   return GS3_OK;
@@ -752,6 +756,7 @@ BlendView blend_view(const ViewBufs& b, ViewBufs& e) {
   V.n_units = b.have_order ? seg_slots(V.n_tiles, b.n_pairs) : 0;
   V.cot = e.cot;
   V.partials = e.partials;
+  V.valid = e.valid;
   V.img = e.img;
   V.tan_img = e.tan_img;
   V.pix_last = e.pix_last;
@@ -791,9 +796,10 @@ void blend_bwd(gs3_scene* s, const Entries& E, hipStream_t st, const float* cot 
   BlendBatch B = blend_batch(s, E);
   if (cot) B.v[0].cot = cot;
   auto p = prof::begin("blend_bwd", st, true);
-  // the backward writes the partials of the pairs it walks; the others
-  // (behind each tile's last contribution) stay at these zeros
-  for (int k = 0; k < E.n; ++k) launch_fill_f32(s->vb[E.e[k]].partials, 9 * s->vb[E.b[k]].n_pairs, 0.f, st);
+  // the backward writes the partials of the pairs some wave used and sets
+  // their bits; every other slot (behind each tile's last contribution, or
+  // culled for every wave) counts as zero without being written
+  for (int k = 0; k < E.n; ++k) launch_fill_u32(s->vb[E.e[k]].valid, s->vb[E.b[k]].n_pairs / 32 + 1, 0u, st);
   launch_blend_bwd(B, s->bg, st, p.c);
   prof::end(p, st);
 }
@@ -809,7 +815,7 @@ void project_bwd(gs3_scene* s, const Entries& E, int mode, int acc, uint64_t see
   for (int k = 0; k < E.n; ++k) {
     const ViewBufs& b = s->vb[E.b[k]];
     ViewBufs& e = s->vb[E.e[k]];
-    launch_pair_sums(b.order, b.offsets, b.counts, e.partials, s->N, e.gsum, st);
+    launch_pair_sums(b.order, b.offsets, b.counts, e.partials, e.valid, s->N, e.gsum, st);
     B.v[k].rec = b.rec;
     B.v[k].tiles = b.tiles;
     B.v[k].G = e.gsum;

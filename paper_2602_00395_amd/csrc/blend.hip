@@ -577,8 +577,8 @@ __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, cons
                                                const CamDev& cam, const uint32_t* __restrict__ pix_last,
                                                const float* __restrict__ pix_T, const float4* __restrict__ seg,
                                                float bg0, float bg1, float bg2, const float* __restrict__ cot,
-                                               float* __restrict__ partials, int n_tiles, int bid,
-                                               unsigned long long* __restrict__ ctr) {
+                                               float* __restrict__ partials, uint32_t* __restrict__ valid,
+                                               int n_tiles, int bid, unsigned long long* __restrict__ ctr) {
   const uint2 unit = units[bid];
   const int t = (int)__builtin_amdgcn_readfirstlane(unit.x);
   if (t >= n_tiles) return;
@@ -749,12 +749,16 @@ __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, cons
         if (reduced != word && lane == 0) s.bits[w][q] = reduced;
       }
       __syncthreads();
-      if (tid < cnt) {
+      const uint64_t bit = 1ull << (tid & 63);
+      const bool h0 = tid < cnt && (s.bits[0][tid >> 6] & bit), h1 = tid < cnt && (s.bits[1][tid >> 6] & bit);
+      const bool h2 = tid < cnt && (s.bits[2][tid >> 6] & bit), h3 = tid < cnt && (s.bits[3][tid >> 6] & bit);
+      // a pair no wave used keeps no partials: its valid bit stays clear and
+      // the pair sums skip it (every other pair's bit is set with its store)
+      if (h0 || h1 || h2 || h3) {
         // a wave that skipped the splat contributes exactly zero
-        float* dst = partials + (int64_t)s.slot[tid] * 9;
-        const uint64_t bit = 1ull << (tid & 63);
-        const bool h0 = s.bits[0][tid >> 6] & bit, h1 = s.bits[1][tid >> 6] & bit;
-        const bool h2 = s.bits[2][tid >> 6] & bit, h3 = s.bits[3][tid >> 6] & bit;
+        const uint32_t slot = s.slot[tid];
+        float* dst = partials + (int64_t)slot * 9;
+        atomicOr(valid + (slot >> 5), 1u << (slot & 31));
         float R[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k)
@@ -814,7 +818,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(BlendBatch B, float bg0
   if (!view_of_block(B, v, b)) return;
   const BlendView& V = B.v[v];
   blend_bwd_body<COUNT>(V.rec, V.rect, V.pair_gid, V.ranges, V.units, V.cam, V.pix_last, V.pix_T, V.seg, bg0, bg1,
-                        bg2, V.cot, V.partials, V.n_tiles, b, ctr);
+                        bg2, V.cot, V.partials, V.valid, V.n_tiles, b, ctr);
 }
 
 inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }

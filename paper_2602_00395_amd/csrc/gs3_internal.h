@@ -94,8 +94,10 @@ struct FusedTr {
 // Sum of each Gaussian's per-(Gaussian, tile) backward partials: order /
 // offsets / counts are the view's depth order, first pair and tile count per
 // depth rank; gsum: float[n][9] (a Gaussian's nine values contiguous).
+// valid: bit per slot, set where the backward wrote the slot's partials
+// (the others count as zeros and are never read).
 void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint32_t* counts, const float* partials,
-                      int64_t n, float* gsum, hipStream_t st);
+                      const uint32_t* valid, int64_t n, float* gsum, hipStream_t st);
 // One view (or one probe of a view) of a projection-backward batch: its
 // records, tile counts (0: the view does not see the Gaussian), summed
 // partials and camera; `inner` is the probe's key (probe_key) in mode 1.
@@ -184,6 +186,7 @@ struct BlendView {
   int64_t n_units = 0;            // backward
   const float* cot = nullptr;     // backward
   float* partials = nullptr;      // backward
+  uint32_t* valid = nullptr;      // backward: bit per partials slot, set where the slot was written
   float* img = nullptr;           // forward, JVP
   float* tan_img = nullptr;       // JVP
   uint32_t* pix_last = nullptr;

@@ -350,8 +350,11 @@ __device__ __forceinline__ float wave_sum_xor(float v) {
 __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __restrict__ order,
                                                             const uint32_t* __restrict__ offsets,
                                                             const uint32_t* __restrict__ counts,
-                                                            const float* __restrict__ partials, int64_t n,
+                                                            const float* __restrict__ partials,
+                                                            const uint32_t* __restrict__ valid, int64_t n,
                                                             float* __restrict__ G) {
+  // slot j holds partials where its valid bit is set, else it counts as zero
+  auto set = [&](uint64_t j) { return (valid[j >> 5] >> (j & 31)) & 1u; };
   __shared__ float wsum[4][9];
   __shared__ uint32_t long_ranks;  // bit j: rank i0 + j is summed by the workgroup
   const int tid = threadIdx.x;
@@ -367,15 +370,16 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
     if (c == 0u) {
       // invisible: nothing to sum
     } else if (c <= kSumLong) {
-      const float* p = partials + (int64_t)offsets[i] * 9 + k;
+      const uint64_t o = offsets[i];
+      const float* p = partials + (int64_t)o * 9 + k;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
       // rounds of 16 slots, all loads of a round issued before any is added
-      // (one round for nine Gaussians in ten); slots past c read nothing
-      // and add an exact zero
+      // (one round for nine Gaussians in ten); slots past c or without
+      // partials read nothing and add an exact zero
       for (uint32_t t = 0; t < c; t += 16) {
         float v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = t + q < c ? p[9 * (t + q)] : 0.f;
+        for (int q = 0; q < 16; ++q) v[q] = t + q < c && set(o + t + q) ? p[9 * (t + q)] : 0.f;
 #pragma unroll
         for (int q = 0; q < 16; q += 4) {
           s0 += v[q];
@@ -394,11 +398,13 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
   for (uint32_t m = long_ranks; m != 0u; m &= m - 1u) {
     const int64_t i = i0 + __builtin_ctz(m);
     const uint32_t c = counts[i];
-    const float* p = partials + (int64_t)offsets[i] * 9;
+    const uint64_t o = offsets[i];
+    const float* p = partials + (int64_t)o * 9;
     float acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = 0.f;
     for (uint32_t t = tid; t < c; t += 256) {
+      if (!set(o + t)) continue;
 #pragma unroll
       for (int q = 0; q < 9; ++q) acc[q] += p[(int64_t)t * 9 + q];
     }
@@ -857,9 +863,9 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
 }
 
 void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint32_t* counts, const float* partials,
-                      int64_t n, float* gsum, hipStream_t st) {
+                      const uint32_t* valid, int64_t n, float* gsum, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_pair_partials, dim3(blocks_for(n, kSumRanks)), dim3(256), 0, st, order, offsets, counts,
-                     partials, n, gsum);
+                     partials, valid, n, gsum);
 }
 
 void launch_project_bwd(const float* x, int64_t n, int deg, const BwdBatch& B, int mode, int accumulate, float scale,
