@@ -28,7 +28,13 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 16;  // scan: items per thread per block
 constexpr int kTileItems = kThreads * kItems;
-constexpr int kRsItems = 4;  // radix passes: keys per thread (per lane and round) per block
+// radix passes: keys per thread (per lane and round) per block -- 4 (1,024
+// keys per workgroup) up to kRsBigFrom keys, 16 (4,096) above: large inputs
+// then write four times fewer per-block digit counts, and each digit's run
+// of a block's output spans about 64 contiguous bytes instead of 16
+constexpr int kRsItems = 4;
+constexpr int kRsItemsBig = 16;
+constexpr int64_t kRsBigFrom = (int64_t)1 << 21;
 constexpr int kRsTile = kThreads * kRsItems;
 constexpr int kRadix = 256;
 
@@ -134,14 +140,15 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restri
 
 // ---------------------------------------------------------------- radix sort
 
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_rs_upsweep(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                           uint32_t* __restrict__ hist, int nb) {
   __shared__ uint32_t h[kRadix];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  const int64_t base = (int64_t)blockIdx.x * (kThreads * ITEMS);
 #pragma unroll
-  for (int r = 0; r < kRsItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = base + r * kThreads + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xffu], 1u);
   }
@@ -178,8 +185,8 @@ __global__ __launch_bounds__(kThreads) void k_rs_scan(uint32_t* __restrict__ his
 
 // Keys [blk + w * kWaveItems, + kWaveItems) belong to wave w of block blk,
 // 64 per round; `vals` null means value = index.
-constexpr int kWaveItems = kRsItems * 64;
 
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vals,
                                                           uint32_t* __restrict__ keys_out,
@@ -188,12 +195,13 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
                                                           const uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t cnt[4][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t wbase = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kWaveItems;
+  constexpr int kWaveItems = ITEMS * 64;
+  const int64_t wbase = (int64_t)blockIdx.x * (kThreads * ITEMS) + (int64_t)w * kWaveItems;
   // the keys and values are read first, so their latency overlaps that of
   // the digit offsets below
-  uint32_t k[kRsItems], v[kRsItems], rk[kRsItems];
+  uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
 #pragma unroll
-  for (int r = 0; r < kRsItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = wbase + r * 64 + lane;
     const bool valid = i < n;
     k[r] = valid ? keys[i] : 0u;
@@ -209,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int r = 0; r < kRsItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = wbase + r * 64 + lane;
     const bool valid = i < n;
     const uint32_t d = (k[r] >> shift) & 0xffu;
@@ -238,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kRsItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = wbase + r * 64 + lane;
     if (i < n) {
       const uint32_t pos = cnt[w][(k[r] >> shift) & 0xffu] + rk[r];
@@ -462,7 +470,8 @@ void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* 
   *keys_out = ka;
   *vals_out = va;
   if (n <= 0) return;
-  const int nb = (int)nblk(n, kRsTile);
+  const bool big = n >= kRsBigFrom;
+  const int nb = (int)nblk(n, big ? kThreads * kRsItemsBig : kRsTile);
   uint32_t* hist = (uint32_t*)temp;
   uint32_t* dtot = hist + (size_t)kRadix * nb;
   const uint32_t *kin = keys_in, *vin = vals_in;
@@ -470,9 +479,17 @@ void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* 
   for (int p = 0; p < passes; ++p) {
     uint32_t* ko = (p & 1) ? kb : ka;
     uint32_t* vo = (p & 1) ? vb : va;
-    hipLaunchKernelGGL(k_rs_upsweep, dim3(nb), dim3(kThreads), 0, st, kin, n, 8 * p, hist, nb);
+    if (big)
+      hipLaunchKernelGGL(k_rs_upsweep<kRsItemsBig>, dim3(nb), dim3(kThreads), 0, st, kin, n, 8 * p, hist, nb);
+    else
+      hipLaunchKernelGGL(k_rs_upsweep<kRsItems>, dim3(nb), dim3(kThreads), 0, st, kin, n, 8 * p, hist, nb);
     hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb, dtot);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, st, kin, vin, ko, vo, n, 8 * p, hist, nb, dtot);
+    if (big)
+      hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(nb), dim3(kThreads), 0, st, kin, vin, ko, vo, n, 8 * p, hist,
+                         nb, dtot);
+    else
+      hipLaunchKernelGGL(k_rs_scatter<kRsItems>, dim3(nb), dim3(kThreads), 0, st, kin, vin, ko, vo, n, 8 * p, hist, nb,
+                         dtot);
     kin = ko;
     vin = vo;
     *keys_out = ko;
