@@ -535,7 +535,8 @@ def main():
     for _ in range(max(2, args.warmup // 2)):
         tr4.step()
     torch.cuda.synchronize()
-    steps4 = max(5, args.steps // 4)
+    # whole Hutchinson cycles: any l consecutive iterations hold exactly one
+    steps4 = cfg.l * max(1, args.steps // (4 * cfg.l))
     t0 = time.perf_counter()
     for _ in range(steps4):
         tr4.step()

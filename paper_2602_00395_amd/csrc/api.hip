@@ -655,12 +655,15 @@ gs3_status bin_camera(gs3_scene* s, ViewBufs& v, const gs3_camera& camera, int c
   const int64_t N = s->N;
   GS3_TRY(ensure_owner_blocks(s, v, &st));
   auto p0 = prof::begin("project_fwd", st);
-  launch_project_fwd(s->x, N, s->deg, cd, v.rec, v.rect, v.depth_key, v.tiles, st);
+  // the per-64 visible counts go to v.counts and their offsets to
+  // v.offsets, both free until the pair-count scan below
+  launch_project_fwd(s->x, N, s->deg, cd, v.rec, v.rect, v.depth_key, v.tiles, v.counts, st);
   prof::end(p0, st);
   GS3_LAUNCHED();
   auto p1 = prof::begin("depth_sort", st);
-  uint32_t *k_sorted, *order;
-  radix_sort_u32(v.depth_key, nullptr, v.ka, v.va, v.kb, v.vb, N, 32, v.rtmp, st, &k_sorted, &order);
+  uint32_t* order;
+  depth_order(v.depth_key, N, v.counts, v.offsets, v.total_dev + 1, v.stmp, v.ka, v.va, v.kb, v.vb, v.rtmp, st,
+              &order);
   prof::end(p1, st);
   auto p2 = prof::begin("scan", st);
   launch_gather_counts(order, v.tiles, N, v.counts, st);

@@ -65,9 +65,10 @@ enum ProbeKind { PROBE_NONE = 0, PROBE_HASH = 1, PROBE_ARRAY = 2 };
 // launchers (all asynchronous on `st`)
 
 // projection: records + depth keys + tiles touched; culled Gaussians get
-// key 0xffffffff and zero tiles.
+// key 0xffffffff and zero tiles; vis_count[b] = the number of visible
+// Gaussians among 64 b .. 64 b + 63.
 void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, Rec* rec, uint2* rect,
-                        uint32_t* depth_key, uint32_t* tiles, hipStream_t st);
+                        uint32_t* depth_key, uint32_t* tiles, uint32_t* vis_count, hipStream_t st);
 // tangent records for a probe (hash) or a caller tangent array.
 void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,
                         const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
@@ -130,6 +131,17 @@ size_t radix_temp_bytes(int64_t n);
 void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* ka, uint32_t* va, uint32_t* kb,
                     uint32_t* vb, int64_t n, int bits, void* temp, hipStream_t st, uint32_t** keys_out,
                     uint32_t** vals_out);
+// Depth order of a view's n Gaussians: the visible ones (key not
+// 0xffffffff) stably sorted by depth key, then the culled ones in index order
+// -- the order a stable sort of all n keys gives -- with only the visible
+// ones sorted.  vis_count: the projection's per-64 visible counts; vis_off
+// (ceil(n / 64) entries) and *visible (their total) are written; scan_temp
+// as for scan_exclusive_u32 over ceil(n / 64) items; (ka, va), (kb, vb):
+// n-element scratch; radix_temp: radix_temp_bytes(n).  *order names the
+// buffer holding the order (vb).
+void depth_order(const uint32_t* depth_key, int64_t n, const uint32_t* vis_count, uint32_t* vis_off,
+                 uint32_t* visible, void* scan_temp, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                 void* radix_temp, hipStream_t st, uint32_t** order);
 size_t scan_temp_bytes(int64_t n);
 // owner (nullable): owner[b] = the item whose output range holds element
 // 256 b of the expanded sequence, for b < owner_blocks.  total_host

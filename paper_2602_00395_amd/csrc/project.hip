@@ -230,7 +230,8 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       Rec* __restrict__ rec, uint2* __restrict__ rect,
                                                       uint32_t* __restrict__ depth_key,
-                                                      uint32_t* __restrict__ tiles) {
+                                                      uint32_t* __restrict__ tiles,
+                                                      uint32_t* __restrict__ vis_count) {
   __shared__ uint32_t vis_bits[2];  // bit l of word l / 32: lane l's splat is visible
   __shared__ uint32_t clamp_bits[kFwdGauss];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -274,6 +275,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
     if (lane == 0) {
       vis_bits[0] = (uint32_t)b;
       vis_bits[1] = (uint32_t)(b >> 32);
+      vis_count[blockIdx.x] = (uint32_t)__popcll(b);
     }
   }
   __syncthreads();
@@ -374,12 +376,21 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
       const float* p = partials + (int64_t)o * 9 + k;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
       // rounds of 16 slots, all loads of a round issued before any is added
-      // (one round for nine Gaussians in ten); slots past c or without
-      // partials read nothing and add an exact zero
+      // (one round for nine Gaussians in ten).  A round's slot loads and
+      // its one or two valid-bit words are issued together: a slot without
+      // partials is read (its contents are stale) and replaced by an exact
+      // zero, so no load waits on a valid bit; slots past c read nothing.
       for (uint32_t t = 0; t < c; t += 16) {
+        const uint64_t s = o + t;
+        const uint32_t last = (uint32_t)((s + (c - t < 16u ? c - t : 16u) - 1u) >> 5);
+        const uint64_t w0 = valid[s >> 5];
+        const uint64_t w1 = last != (uint32_t)(s >> 5) ? valid[last] : 0u;
+        const uint64_t bits = (w0 | (w1 << 32)) >> (s & 31);
         float v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = t + q < c && set(o + t + q) ? p[9 * (t + q)] : 0.f;
+        for (int q = 0; q < 16; ++q) v[q] = t + q < c ? p[9 * (t + q)] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = (bits >> q) & 1u ? v[q] : 0.f;
 #pragma unroll
         for (int q = 0; q < 16; q += 4) {
           s0 += v[q];
@@ -849,9 +860,9 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
   }
 
 void launch_project_fwd(const float* x, int64_t n, int deg, const CamDev& cam, Rec* rec, uint2* rect,
-                        uint32_t* depth_key, uint32_t* tiles, hipStream_t st) {
+                        uint32_t* depth_key, uint32_t* tiles, uint32_t* vis_count, hipStream_t st) {
   GS3_DEG_DISPATCH(deg, k_project_fwd, dim3(blocks_for(n, kFwdGauss)), dim3(256), 0, st, x, n, cam, rec, rect,
-                   depth_key, tiles);
+                   depth_key, tiles, vis_count);
 }
 
 void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, const Rec* rec,

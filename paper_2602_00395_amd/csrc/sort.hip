@@ -36,6 +36,8 @@ constexpr int kRsItems = 4;
 constexpr int kRsItemsBig = 16;
 constexpr int64_t kRsBigFrom = (int64_t)1 << 21;
 constexpr int kRsTile = kThreads * kRsItems;
+// workgroups per radix launch when the element count is on the device
+constexpr int kRsDevGrid = 2048;
 constexpr int kRadix = 256;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -140,28 +142,44 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restri
 
 // ---------------------------------------------------------------- radix sort
 
+// The radix kernels take the element count from n, or from the device word
+// *n_dev when it is not null (a count produced on the device, e.g. the
+// visible Gaussians of a view); then the grid may be smaller than the number
+// of blocks and each workgroup takes blocks blockIdx.x, + gridDim.x, ...
+__device__ __forceinline__ int64_t rs_count(int64_t n, const uint32_t* n_dev) { return n_dev ? (int64_t)*n_dev : n; }
+
 template <int ITEMS>
-__global__ __launch_bounds__(kThreads) void k_rs_upsweep(const uint32_t* __restrict__ keys, int64_t n, int shift,
+__global__ __launch_bounds__(kThreads) void k_rs_upsweep(const uint32_t* __restrict__ keys, int64_t n,
+                                                          const uint32_t* __restrict__ n_dev, int shift,
                                                           uint32_t* __restrict__ hist, int nb) {
   __shared__ uint32_t h[kRadix];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * (kThreads * ITEMS);
+  n = rs_count(n, n_dev);
+  const int live = (int)((n + kThreads * ITEMS - 1) / (kThreads * ITEMS));
+  for (int blk = blockIdx.x; blk < live; blk += gridDim.x) {
+    // a thread clears its bin only after reading it out for the previous
+    // block, and no thread counts into the bins before all have cleared
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blk * (kThreads * ITEMS);
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int64_t i = base + r * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xffu], 1u);
+    for (int r = 0; r < ITEMS; ++r) {
+      const int64_t i = base + r * kThreads + threadIdx.x;
+      if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blk] = h[threadIdx.x];
   }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 // One workgroup per digit: exclusive scan of hist[d][0..nb) in place, 2048
 // entries per round (8 consecutive per thread, all loaded before the scan).
 constexpr int kRsScanPer = 8;
+// With n_dev, only the live blocks' entries of each row (stride nb) count.
 __global__ __launch_bounds__(kThreads) void k_rs_scan(uint32_t* __restrict__ hist, int nb,
+                                                       const uint32_t* __restrict__ n_dev, int tile,
                                                        uint32_t* __restrict__ digit_total) {
   uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  if (n_dev) nb = (int)(((int64_t)*n_dev + tile - 1) / tile);
   uint32_t running = 0;
   for (int base = 0; base < nb; base += kThreads * kRsScanPer) {
     const int i0 = base + (int)threadIdx.x * kRsScanPer;
@@ -190,69 +208,112 @@ template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vals,
                                                           uint32_t* __restrict__ keys_out,
-                                                          uint32_t* __restrict__ vals_out, int64_t n, int shift,
+                                                          uint32_t* __restrict__ vals_out, int64_t n,
+                                                          const uint32_t* __restrict__ n_dev, int shift,
                                                           const uint32_t* __restrict__ hist, int nb,
                                                           const uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t cnt[4][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int kWaveItems = ITEMS * 64;
-  const int64_t wbase = (int64_t)blockIdx.x * (kThreads * ITEMS) + (int64_t)w * kWaveItems;
-  // the keys and values are read first, so their latency overlaps that of
-  // the digit offsets below
-  uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
-#pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int64_t i = wbase + r * 64 + lane;
-    const bool valid = i < n;
-    k[r] = valid ? keys[i] : 0u;
-    v[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) cnt[q][tid] = 0u;
-  uint32_t base;
-  {
-    uint32_t tot;
-    base = block_excl_scan(digit_total[tid], &tot) + hist[(int64_t)tid * nb + blockIdx.x];
-  }
-  __syncthreads();
+  n = rs_count(n, n_dev);
+  const int live = (int)((n + kThreads * ITEMS - 1) / (kThreads * ITEMS));
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int blk = blockIdx.x; blk < live; blk += gridDim.x) {
+    const int64_t wbase = (int64_t)blk * (kThreads * ITEMS) + (int64_t)w * kWaveItems;
+    // the keys and values are read first, so their latency overlaps that of
+    // the digit offsets below
+    uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int64_t i = wbase + r * 64 + lane;
-    const bool valid = i < n;
-    const uint32_t d = (k[r] >> shift) & 0xffu;
-    uint64_t same = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      same &= bit ? m : ~m;
+    for (int r = 0; r < ITEMS; ++r) {
+      const int64_t i = wbase + r * 64 + lane;
+      const bool valid = i < n;
+      k[r] = valid ? keys[i] : 0u;
+      v[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;
     }
-    const uint32_t below = (uint32_t)__popcll(same & lt_mask);
-    uint32_t prior = 0u;
-    if (valid) prior = cnt[w][d];
-    // the lowest lane of each digit group advances the wave's running count;
-    // LDS accesses of one wave complete in order, so the next round reads it
-    if (valid && below == 0u) cnt[w][d] = prior + (uint32_t)__popcll(same);
-    rk[r] = prior + below;
-  }
-  __syncthreads();
-  {
-    const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid];
-    cnt[0][tid] = base;
-    cnt[1][tid] = base + c0;
-    cnt[2][tid] = base + c0 + c1;
-    cnt[3][tid] = base + c0 + c1 + c2;
-  }
-  __syncthreads();
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int64_t i = wbase + r * 64 + lane;
-    if (i < n) {
-      const uint32_t pos = cnt[w][(k[r] >> shift) & 0xffu] + rk[r];
-      keys_out[pos] = k[r];
-      vals_out[pos] = v[r];
+    for (int q = 0; q < 4; ++q) cnt[q][tid] = 0u;
+    uint32_t base;
+    {
+      uint32_t tot;
+      base = block_excl_scan(digit_total[tid], &tot) + hist[(int64_t)tid * nb + blk];
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const int64_t i = wbase + r * 64 + lane;
+      const bool valid = i < n;
+      const uint32_t d = (k[r] >> shift) & 0xffu;
+      uint64_t same = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        same &= bit ? m : ~m;
+      }
+      const uint32_t below = (uint32_t)__popcll(same & lt_mask);
+      uint32_t prior = 0u;
+      if (valid) prior = cnt[w][d];
+      // the lowest lane of each digit group advances the wave's running
+      // count; LDS accesses of one wave complete in order, so the next round
+      // reads it
+      if (valid && below == 0u) cnt[w][d] = prior + (uint32_t)__popcll(same);
+      rk[r] = prior + below;
+    }
+    __syncthreads();
+    {
+      const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid];
+      cnt[0][tid] = base;
+      cnt[1][tid] = base + c0;
+      cnt[2][tid] = base + c0 + c1;
+      cnt[3][tid] = base + c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const int64_t i = wbase + r * 64 + lane;
+      if (i < n) {
+        const uint32_t pos = cnt[w][(k[r] >> shift) & 0xffu] + rk[r];
+        keys_out[pos] = k[r];
+        vals_out[pos] = v[r];
+      }
+    }
+    // the next block clears the counts only after every wave has read them
+    __syncthreads();
+  }
+}
+
+// Visible Gaussians first: one wave per 64 consecutive Gaussians (the
+// projection's workgroup b, whose visible count the scan turned into
+// vis_off[b]).  A visible Gaussian's (key, index) goes to position
+// vis_off[b] + (visible lanes below it); a culled one's index goes to
+// tail[V + (culled Gaussians before it)], V = *visible.  Both keep index
+// order, so a stable sort of the first V entries by key gives the same
+// order as a stable sort of all n keys with the culled ones' key 0xffffffff.
+__global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* __restrict__ depth_key, int64_t n,
+                                                          const uint32_t* __restrict__ vis_off,
+                                                          const uint32_t* __restrict__ visible,
+                                                          uint32_t* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out,
+                                                          uint32_t* __restrict__ tail) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t g = b * 64 + lane;
+  if (b * 64 >= n) return;
+  const bool live = g < n;
+  const uint32_t key = live ? depth_key[g] : 0xffffffffu;
+  const bool vis = key != 0xffffffffu;
+  const uint64_t m = __ballot(vis);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t before = vis_off[b];
+  if (vis) {
+    const uint32_t pos = before + (uint32_t)__popcll(m & below);
+    keys_out[pos] = key;
+    vals_out[pos] = (uint32_t)g;
+  } else if (live) {
+    // every lane below a live lane is live: the culled ones below are the
+    // unset bits below
+    const uint64_t culled_before = (uint64_t)(b * 64) - before;
+    tail[*visible + culled_before + (uint64_t)__popcll(~m & below)] = (uint32_t)g;
   }
 }
 
@@ -464,14 +525,20 @@ size_t radix_temp_bytes(int64_t n) {
   return (size_t)(kRadix * nb + kRadix) * sizeof(uint32_t);
 }
 
-void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* ka, uint32_t* va, uint32_t* kb,
-                    uint32_t* vb, int64_t n, int bits, void* temp, hipStream_t st, uint32_t** keys_out,
-                    uint32_t** vals_out) {
+namespace {
+// passes of `bits` key bits; with n_dev the element count is *n_dev <= n
+void radix_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* ka, uint32_t* va, uint32_t* kb,
+                  uint32_t* vb, int64_t n, const uint32_t* n_dev, int bits, void* temp, hipStream_t st,
+                  uint32_t** keys_out, uint32_t** vals_out) {
   *keys_out = ka;
   *vals_out = va;
   if (n <= 0) return;
-  const bool big = n >= kRsBigFrom;
-  const int nb = (int)nblk(n, big ? kThreads * kRsItemsBig : kRsTile);
+  // a count known only on the device takes the small blocks (it is usually
+  // far below its bound n) and at most kRsDevGrid workgroups per launch
+  const bool big = !n_dev && n >= kRsBigFrom;
+  const int tile = big ? kThreads * kRsItemsBig : kRsTile;
+  const int nb = (int)nblk(n, tile);
+  const dim3 grid(n_dev ? std::min(nb, kRsDevGrid) : nb);
   uint32_t* hist = (uint32_t*)temp;
   uint32_t* dtot = hist + (size_t)kRadix * nb;
   const uint32_t *kin = keys_in, *vin = vals_in;
@@ -480,21 +547,43 @@ void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* 
     uint32_t* ko = (p & 1) ? kb : ka;
     uint32_t* vo = (p & 1) ? vb : va;
     if (big)
-      hipLaunchKernelGGL(k_rs_upsweep<kRsItemsBig>, dim3(nb), dim3(kThreads), 0, st, kin, n, 8 * p, hist, nb);
+      hipLaunchKernelGGL(k_rs_upsweep<kRsItemsBig>, grid, dim3(kThreads), 0, st, kin, n, n_dev, 8 * p, hist, nb);
     else
-      hipLaunchKernelGGL(k_rs_upsweep<kRsItems>, dim3(nb), dim3(kThreads), 0, st, kin, n, 8 * p, hist, nb);
-    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb, dtot);
+      hipLaunchKernelGGL(k_rs_upsweep<kRsItems>, grid, dim3(kThreads), 0, st, kin, n, n_dev, 8 * p, hist, nb);
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb, n_dev, tile, dtot);
     if (big)
-      hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(nb), dim3(kThreads), 0, st, kin, vin, ko, vo, n, 8 * p, hist,
-                         nb, dtot);
+      hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, grid, dim3(kThreads), 0, st, kin, vin, ko, vo, n, n_dev, 8 * p,
+                         hist, nb, dtot);
     else
-      hipLaunchKernelGGL(k_rs_scatter<kRsItems>, dim3(nb), dim3(kThreads), 0, st, kin, vin, ko, vo, n, 8 * p, hist, nb,
-                         dtot);
+      hipLaunchKernelGGL(k_rs_scatter<kRsItems>, grid, dim3(kThreads), 0, st, kin, vin, ko, vo, n, n_dev, 8 * p,
+                         hist, nb, dtot);
     kin = ko;
     vin = vo;
     *keys_out = ko;
     *vals_out = vo;
   }
+}
+}  // namespace
+
+void radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* ka, uint32_t* va, uint32_t* kb,
+                    uint32_t* vb, int64_t n, int bits, void* temp, hipStream_t st, uint32_t** keys_out,
+                    uint32_t** vals_out) {
+  radix_passes(keys_in, vals_in, ka, va, kb, vb, n, nullptr, bits, temp, st, keys_out, vals_out);
+}
+
+void depth_order(const uint32_t* depth_key, int64_t n, const uint32_t* vis_count, uint32_t* vis_off,
+                 uint32_t* visible, void* scan_temp, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                 void* radix_temp, hipStream_t st, uint32_t** order) {
+  *order = vb;
+  if (n <= 0) return;
+  const int64_t groups = (n + 63) / 64;
+  scan_exclusive_u32(vis_count, vis_off, groups, visible, scan_temp, st);
+  // visible (key, index) into (kb, vb)[0, V), culled indices into vb[V, n);
+  // four passes then go kb -> ka -> kb -> ka -> kb over [0, V) only
+  hipLaunchKernelGGL(k_compact_visible, dim3(nblk(groups, 4)), dim3(256), 0, st, depth_key, n, vis_off, visible, kb,
+                     vb, vb);
+  uint32_t* keys_out;
+  radix_passes(kb, vb, ka, va, kb, vb, n, visible, 32, radix_temp, st, &keys_out, order);
 }
 
 void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
