@@ -666,7 +666,9 @@ gs3_status bin_camera(gs3_scene* s, ViewBufs& v, const gs3_camera& camera, int c
               &order);
   prof::end(p1, st);
   auto p2 = prof::begin("scan", st);
-  launch_gather_counts(order, v.tiles, N, v.counts, st);
+  // ranks past the visible count V = v.total_dev[1] hold culled Gaussians:
+  // the counts, their scan, the emission and the pair sums stop at V
+  launch_gather_counts(order, v.tiles, N, v.total_dev + 1, v.counts, st);
   // the scan stores the pair count into a pinned host word as soon as it is
   // known; the host waits for that word (not for the stream), so the
   // launches below are queued while the scan's last kernel still runs
@@ -677,7 +679,7 @@ gs3_status bin_camera(gs3_scene* s, ViewBufs& v, const gs3_camera& camera, int c
   *count_word = kCountPending;
   std::atomic_thread_fence(std::memory_order_seq_cst);
   scan_exclusive_u32(v.counts, v.offsets, N, v.total_dev, v.stmp, st, v.block_owner, v.owner_blocks,
-                     s->host_u32);
+                     s->host_u32, v.total_dev + 1);
   prof::end(p2, st);
   GS3_LAUNCHED();
   if (s->host_u32) {
@@ -692,8 +694,8 @@ gs3_status bin_camera(gs3_scene* s, ViewBufs& v, const gs3_camera& camera, int c
   GS3_TRY(ensure_pairs(s, v, n_pairs, &st));
   GS3_TRY(ensure_blend(s, v, n_pairs, &st));
   auto p3 = prof::begin("emit_pairs", st);
-  launch_emit_pairs(order, v.offsets, v.block_owner, v.owner_blocks, v.rec, v.rect, N, n_pairs, cd.tiles_x,
-                    v.pt, v.pg, st);
+  launch_emit_pairs(order, v.offsets, v.block_owner, v.owner_blocks, v.rec, v.rect, N, v.total_dev + 1, n_pairs,
+                    cd.tiles_x, v.pt, v.pg, st);
   prof::end(p3, st, N, n_pairs);
   const int n_tiles = cd.tiles_x * cd.tiles_y;
   uint32_t *tk, *tv;
@@ -818,7 +820,7 @@ void project_bwd(gs3_scene* s, const Entries& E, int mode, int acc, uint64_t see
   for (int k = 0; k < E.n; ++k) {
     const ViewBufs& b = s->vb[E.b[k]];
     ViewBufs& e = s->vb[E.e[k]];
-    launch_pair_sums(b.order, b.offsets, b.counts, e.partials, e.valid, s->N, e.gsum, st);
+    launch_pair_sums(b.order, b.offsets, b.counts, e.partials, e.valid, s->N, b.total_dev + 1, e.gsum, st);
     B.v[k].rec = b.rec;
     B.v[k].tiles = b.tiles;
     B.v[k].G = e.gsum;

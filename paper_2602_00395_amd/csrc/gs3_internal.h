@@ -98,7 +98,7 @@ struct FusedTr {
 // valid: bit per slot, set where the backward wrote the slot's partials
 // (the others count as zeros and are never read).
 void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint32_t* counts, const float* partials,
-                      const uint32_t* valid, int64_t n, float* gsum, hipStream_t st);
+                      const uint32_t* valid, int64_t n, const uint32_t* n_dev, float* gsum, hipStream_t st);
 // One view (or one probe of a view) of a projection-backward batch: its
 // records, tile counts (0: the view does not see the Gaussian), summed
 // partials and camera; `inner` is the probe's key (probe_key) in mode 1.
@@ -147,16 +147,19 @@ size_t scan_temp_bytes(int64_t n);
 // 256 b of the expanded sequence, for b < owner_blocks.  total_host
 // (nullable): pinned host word that receives the total as soon as it is
 // known (before the last kernel of the scan ends)
+// n_dev (nullable): the item count is *n_dev <= n, known on the device only.
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st,
-                        uint32_t* owner = nullptr, int64_t owner_blocks = 0, uint32_t* total_host = nullptr);
-void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
-                          hipStream_t st);
+                        uint32_t* owner = nullptr, int64_t owner_blocks = 0, uint32_t* total_host = nullptr,
+                        const uint32_t* n_dev = nullptr);
+// counts_sorted[i] = tiles[order[i]] for i < n (or *n_dev)
+void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, const uint32_t* n_dev,
+                          uint32_t* counts_sorted, hipStream_t st);
 // writes each visible Gaussian's pair offset into its record (rec.c.z);
 // owner (nullable, from scan_exclusive_u32) names the first pair's item of
 // each 256-pair block b < owner_blocks, the others search the offsets
 void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, const uint32_t* owner,
-                       int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, int64_t n_pairs, int tiles_x,
-                       uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st);
+                       int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, const uint32_t* n_dev,
+                       int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st);
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st);
 // Tile ids in (approximately) descending order of their pair count, and the
 // backward's work units: each non-empty tile's list cut into depth segments

@@ -354,6 +354,7 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
                                                             const uint32_t* __restrict__ counts,
                                                             const float* __restrict__ partials,
                                                             const uint32_t* __restrict__ valid, int64_t n,
+                                                            const uint32_t* __restrict__ n_dev,
                                                             float* __restrict__ G) {
   // slot j holds partials where its valid bit is set, else it counts as zero
   auto set = [&](uint64_t j) { return (valid[j >> 5] >> (j & 31)) & 1u; };
@@ -362,7 +363,8 @@ __global__ __launch_bounds__(256) void k_sum_pair_partials(const uint32_t* __res
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kSumRanks;
   const int nr = (int)(i0 + kSumRanks < n ? kSumRanks : n - i0);
-  if (counts[i0] == 0u) return;  // this rank and every later one is invisible
+  if (n_dev) n = *n_dev;  // the visible ranks, when the count is on the device
+  if (i0 >= n || counts[i0] == 0u) return;  // this rank and every later one is invisible
   const int j = tid / 9, k = tid % 9;
   if (tid == 0) long_ranks = 0u;
   __syncthreads();
@@ -874,9 +876,9 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
 }
 
 void launch_pair_sums(const uint32_t* order, const uint32_t* offsets, const uint32_t* counts, const float* partials,
-                      const uint32_t* valid, int64_t n, float* gsum, hipStream_t st) {
+                      const uint32_t* valid, int64_t n, const uint32_t* n_dev, float* gsum, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_pair_partials, dim3(blocks_for(n, kSumRanks)), dim3(256), 0, st, order, offsets, counts,
-                     partials, valid, n, gsum);
+                     partials, valid, n, n_dev, gsum);
 }
 
 void launch_project_bwd(const float* x, int64_t n, int deg, const BwdBatch& B, int mode, int accumulate, float scale,

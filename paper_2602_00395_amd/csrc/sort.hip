@@ -70,8 +70,13 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
 
 // ---------------------------------------------------------------- scan
 
+// The scan kernels take the item count from n, or from *n_dev when it is not
+// null (then blocks past the count return at once).
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                           const uint32_t* __restrict__ n_dev,
                                                            uint32_t* __restrict__ block_sums) {
+  if (n_dev) n = *n_dev;
+  if ((int64_t)blockIdx.x * kTileItems >= n) return;
   const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
   uint32_t s = 0;
 #pragma unroll
@@ -89,7 +94,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __rest
 // 32 bits: a view has fewer than 2^20 tiles); a total of 0xfffffffe or more
 // is reported as 0xfffffffe in both words, and the host refuses the view.
 __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ block_sums, int nb,
+                                                        const uint32_t* __restrict__ n_dev,
                                                         uint32_t* __restrict__ total, uint32_t* total_host) {
+  if (n_dev) nb = (int)(((int64_t)*n_dev + kTileItems - 1) / kTileItems);
   __shared__ unsigned long long sum64;
   if (threadIdx.x == 0) sum64 = 0ull;
   uint32_t running = 0;
@@ -116,8 +123,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* __restrict__ bl
 // output range [out[i], out[i] + in[i]), owner[b] = i -- the item that owns
 // element 256 b of the expanded sequence
 __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                         int64_t n, const uint32_t* __restrict__ block_sums,
+                                                         int64_t n, const uint32_t* __restrict__ n_dev,
+                                                         const uint32_t* __restrict__ block_sums,
                                                          uint32_t* __restrict__ owner, int64_t owner_blocks) {
+  if (n_dev) n = *n_dev;
+  if ((int64_t)blockIdx.x * kTileItems >= n) return;
   const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
   uint32_t v[kItems];
   uint32_t s = 0;
@@ -321,7 +331,9 @@ __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* __restr
 
 __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ tiles, int64_t n,
+                                                        const uint32_t* __restrict__ n_dev,
                                                         uint32_t* __restrict__ counts) {
+  if (n_dev) n = *n_dev;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) counts[i] = tiles[order[i]];
 }
@@ -349,8 +361,9 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
                                                      const uint32_t* __restrict__ offsets,
                                                      const uint32_t* __restrict__ owner, int64_t owner_blocks,
                                                      Rec* __restrict__ rec, const uint2* __restrict__ rect, int64_t n,
-                                                     int64_t n_pairs, int tiles_x, uint32_t* __restrict__ pair_tile,
-                                                     uint32_t* __restrict__ pair_gid) {
+                                                     const uint32_t* __restrict__ n_dev, int64_t n_pairs, int tiles_x,
+                                                     uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_gid) {
+  if (n_dev) n = *n_dev;
   __shared__ uint32_t soff[256];
   __shared__ int64_t bounds[2];
   const int tid = threadIdx.x;
@@ -507,7 +520,7 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 size_t scan_temp_bytes(int64_t n) { return (size_t)(nblk(n, kTileItems) + 1) * sizeof(uint32_t); }
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* temp, hipStream_t st,
-                        uint32_t* owner, int64_t owner_blocks, uint32_t* total_host) {
+                        uint32_t* owner, int64_t owner_blocks, uint32_t* total_host, const uint32_t* n_dev) {
   const int nb = (int)nblk(n, kTileItems);
   uint32_t* sums = (uint32_t*)temp;
   if (n <= 0) {
@@ -515,9 +528,9 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
     if (total_host) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, total_host, (int64_t)1, 0u);
     return;
   }
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, st, in, n, sums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, sums, nb, total, total_host);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, st, in, out, n, sums, owner, owner_blocks);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, st, in, n, n_dev, sums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, sums, nb, n_dev, total, total_host);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, st, in, out, n, n_dev, sums, owner, owner_blocks);
 }
 
 size_t radix_temp_bytes(int64_t n) {
@@ -586,17 +599,18 @@ void depth_order(const uint32_t* depth_key, int64_t n, const uint32_t* vis_count
   radix_passes(kb, vb, ka, va, kb, vb, n, visible, 32, radix_temp, st, &keys_out, order);
 }
 
-void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, uint32_t* counts_sorted,
-                          hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_gather_counts, dim3(nblk(n, 256)), dim3(256), 0, st, order, tiles, n, counts_sorted);
+void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t n, const uint32_t* n_dev,
+                          uint32_t* counts_sorted, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_gather_counts, dim3(nblk(n, 256)), dim3(256), 0, st, order, tiles, n, n_dev, counts_sorted);
 }
 
 void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, const uint32_t* owner,
-                       int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, int64_t n_pairs, int tiles_x,
-                       uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st) {
+                       int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, const uint32_t* n_dev,
+                       int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st) {
   if (n > 0 && n_pairs > 0)
     hipLaunchKernelGGL(k_emit_pairs, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, order, offsets_sorted, owner,
-                       owner ? owner_blocks : (int64_t)0, rec, rect, n, n_pairs, tiles_x, pair_tile, pair_gid);
+                       owner ? owner_blocks : (int64_t)0, rec, rect, n, n_dev, n_pairs, tiles_x, pair_tile, pair_gid);
 }
 
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st) {

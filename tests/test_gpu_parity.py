@@ -695,3 +695,29 @@ def test_single_gaussian_render_and_grad():
     say("single Gaussian grad")
     check(s.grad([0]).cpu().numpy(), want, 14)
     s.close()
+
+
+def test_grad_and_hvp_splats_over_many_tiles():
+    """Pair sums of splats covering more than 48 tiles (summed by the whole
+    workgroup) next to splats covering fewer (nine threads per Gaussian), up
+    to more than 2,048 tiles (several slots per thread of the workgroup): a
+    few large Gaussians at 200x184 and 800x720."""
+    sc = syn.tiny_scene(91, n=12, sh_degree=1, width=200, height=184, n_cams=2, log_scale_mean=np.log(0.3),
+                        log_scale_std=0.6)
+    x = sc.gt.astype(np.float32)
+    cams = [sc.cameras[0], syn.make_camera(tuple(syn.fibonacci_sphere(2, 3.0)[1]), 800, 720)]
+    counts = [B.bin_view(x, c).tiles_touched for c in cams]
+    say("tiles touched", [sorted(c.tolist()) for c in counts])
+    assert counts[0].min() <= 64 < counts[0].max()
+    assert counts[1].max() > 2048
+    targets = offset_targets(x, cams, 1, seed=4400)
+    s = make_scene(x, targets, cams, 1)
+    prob = Mth.Problem(cams, targets, 1, lam=0.2)
+    for j in range(2):
+        say("many-tile grad view", j)
+        want, _ = Mth.gradient(x, prob, [j])
+        check(s.grad([j]).cpu().numpy(), want, 23, flips=view_flips(x, cams, [j], 1))
+    say("many-tile hvp")
+    want = Mth.hutchinson(x, prob, [0, 1], 1, 4401)
+    check(s.hvp_diag([0, 1], 1, 4401).cpu().numpy(), want, 23, flips=view_flips(x, cams, [0, 1], 1))
+    s.close()
