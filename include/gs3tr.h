@@ -195,8 +195,13 @@ gs3_status gs3_render_noalloc(int64_t n_gaussians, int32_t sh_degree, const floa
                               const gs3_camera* camera, const float background[3], float* rgb_dev,
                               hipStream_t stream);
 
-/* Bin camera `cam`: writes the sorted 64-bit keys ((tile << 32) | float bits
- * of depth) and the Gaussian index of every (Gaussian, tile) pair into
+/* Bin camera `cam` (Background, "Review of Gaussian Splatting": splats are
+ * bucketed per 16x16 tile and sorted by depth).  A splat is paired with the
+ * tiles of its 3-sigma screen rectangle whose block of pixel centres its skip
+ * ellipse (alpha exp(power) >= 1/255, widened for float32 rounding) can
+ * reach, in row-major order; a splat that reaches no tile is culled.  Writes
+ * the sorted 64-bit keys ((tile << 32) | float bits of depth) and the
+ * Gaussian index of every (Gaussian, tile) pair into
  * keys_dev / gids_dev (capacity entries each, device; either may be NULL),
  * each tile's [start, end) into ranges_dev (uint32[tiles][2], device, may be
  * NULL) and the pair count into *n_pairs (host).  Fails with EINVAL when the

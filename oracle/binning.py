@@ -15,6 +15,9 @@ original 3DGS design:
 * radius r = ceil(3 sqrt(lambda_max)), lambda_max = mid + sqrt(max(mid^2 - det, 0));
 * tile rectangle x in [clamp(floor((u - r)/16)), clamp(floor((u + r)/16) + 1)),
   same in y, clamped to the tile grid; an empty rectangle culls;
+* tile list (see tile_spans): the tiles of the rectangle whose block of pixel
+  centres the splat's skip ellipse, widened for float32 rounding, can reach;
+  a splat that reaches none culls;
 * key = (tile_id << 32) | float32 bits of depth p_z; pairs are emitted by
   Gaussian index, then tile row, then tile column, and sorted stably.
 
@@ -119,13 +122,88 @@ def project_f32(x32: np.ndarray, cam) -> dict:
     x1 = np.where(visible, x1, 0).astype(np.int64)
     y0 = np.where(visible, y0, 0).astype(np.int64)
     y1 = np.where(visible, y1, 0).astype(np.int64)
-    touched = np.maximum(x1 - x0, 0) * np.maximum(y1 - y0, 0)
+    visible &= (x1 > x0) & (y1 > y0)
+    rect = np.stack([x0, y0, x1, y1], 1)
+    spans = tile_spans(u, v, conic, tau, rect, visible)
+    touched = np.maximum(spans[:, :, 1] - spans[:, :, 0], 0).sum(axis=1) if spans.size else np.zeros(len(u), np.int64)
     visible &= touched > 0
     touched = np.where(visible, touched, 0)
     return dict(visible=visible, depth=p[2].astype(F), u=u, v=v, radius=radius, det=det, cov2=(a, b, c),
                 conic=conic, alpha=alpha, tau=tau,
-                rect=np.stack([x0, y0, x1, y1], 1).astype(np.int32), tiles_touched=touched,
+                rect=rect.astype(np.int32), tiles_touched=touched, spans=spans,
                 tiles_x=tx, tiles_y=ty)
+
+
+def tile_spans(u, v, conic, tau, rect, visible) -> np.ndarray:
+    """Which tiles of each splat's rectangle the splat can reach: int64
+    [N, max rows, 2], the half-open column range [lo, hi) of rectangle row j
+    (tile row y0 + j), empty where hi <= lo.
+
+    The skip test passes only where the float32 power p of -1/2 d^T Q d is at
+    least tau, Q = (a, b; b, c) the conic of the record: (a, b, c) = (-2 qa,
+    -qb, -2 qc) for the stored qa = -a/2, qb = -b, qc = -c/2.  The float32
+    power errs by at most a relative 4u (1 + rho) / (1 - rho) (u = 2^-24,
+    rho^2 = b^2 / (a c)), below 1e-3 for rho^2 <= 0.999, so every passing
+    pixel centre lies in E = {d : d^T Q d <= k}, k = 2.02 (-tau) + 1e-3, with
+    room to spare (the extra 0.9% of k, and a 0.01-pixel margin on every edge
+    below, cover the float32 rounding of the extent computed here, a few
+    1e-4 relative at most).  A tile is listed when E meets the 16 x 16 block
+    of pixel centres of the tile, widened by the margin: the band of rows
+    [16 ty + 0.49, 16 ty + 15.51] cuts E in a convex set whose x-extent runs
+    from the left end of E at the band row nearest E's leftmost point to the
+    right end at the row nearest its rightmost point.  The rightmost point
+    of E is (xm, yr), xm = sqrt(k c / det), yr = -b xm / c, det = a c - b^2;
+    the leftmost is (-xm, -yr); E spans |y| <= sqrt(k a / det); at height y
+    it covers x in ((-b y) -+ sqrt(k a - det y^2)) / a.  Columns of the
+    x-extent [xl, xr] (relative to u): ceil((u + xl - 15.51) / 16) to
+    floor((u + xr - 0.49) / 16), clipped to the rectangle.  Splats with
+    rho^2 > 0.999 or a conic that is not positive definite or finite keep
+    the whole rectangle; tau > 0 reaches nothing.  Each step is written out
+    in float32 in a fixed order (numpy float32 is IEEE round-to-nearest with
+    no fused multiply-add), since the listed tiles are integers decided from
+    floating point.
+    """
+    n = len(u)
+    h = np.where(visible, rect[:, 3] - rect[:, 1], 0)
+    rows = int(h.max()) if n else 0
+    spans = np.zeros((n, rows, 2), np.int64)
+    if rows == 0:
+        return spans
+    ca, cb, cc = (np.asarray(t, F) for t in conic)
+    qa, qb, qc = F(-0.5) * ca, -cb, F(-0.5) * cc
+    a, b, c = F(-2.0) * qa, -qb, F(-2.0) * qc
+    tau32 = np.asarray(tau, F)
+    uu, vv = np.asarray(u, F), np.asarray(v, F)
+    x0, y0, x1 = rect[:, 0].astype(F), rect[:, 1], rect[:, 2].astype(F)
+    with np.errstate(all="ignore"):
+        det = a * c - b * b
+        ellipse = (a > F(0)) & (c > F(0)) & (det * F(1000.0) >= a * c) & (det < F(np.inf))
+        whole = ~ellipse
+        none = tau32 > F(0.0)
+        k = F(-2.02) * tau32 + F(1e-3)
+        ka = k * a
+        inv_a = F(1.0) / a
+        ymax = np.sqrt(ka / det)
+        yr = (-b * np.sqrt((k * c) / det)) / c
+        for j in range(rows):
+            row = F(16.0) * (y0 + j).astype(F)
+            ya = np.fmax((row + F(0.49)) - vv, -ymax)
+            yb = np.fmin((row + F(15.51)) - vv, ymax)
+            y_r = np.fmin(np.fmax(yr, ya), yb)
+            y_l = np.fmin(np.fmax(-yr, ya), yb)
+            xr = (-b * y_r + np.sqrt(np.fmax(ka - (det * y_r) * y_r, F(0.0)))) * inv_a
+            xl = (-b * y_l - np.sqrt(np.fmax(ka - (det * y_l) * y_l, F(0.0)))) * inv_a
+            clo = np.ceil(((uu + xl) - F(15.51)) * F(0.0625))
+            chi = np.floor(((uu + xr) - F(0.49)) * F(0.0625)) + F(1.0)
+            lo = np.fmin(np.fmax(clo, x0), x1)
+            hi = np.fmax(np.fmin(chi, x1), x0)
+            empty = ~(ya <= yb)
+            lo = np.where(whole, x0, np.where(empty, x0, lo))
+            hi = np.where(whole, x1, np.where(empty, x0, hi))
+            live = visible & (j < h) & ~none
+            spans[:, j, 0] = np.where(live, lo, 0).astype(np.int64)
+            spans[:, j, 1] = np.where(live, hi, 0).astype(np.int64)
+    return spans
 
 
 def bin_view(x32: np.ndarray, cam) -> Bins:
@@ -136,13 +214,23 @@ def bin_view(x32: np.ndarray, cam) -> Bins:
     depth_bits = np.where(vis, pr["depth"].view(np.uint32), 0).astype(np.uint32)
     rect = pr["rect"].astype(np.int64)
     touched = pr["tiles_touched"].astype(np.int64)
-    total = int(touched.sum())
-    gid = np.repeat(np.arange(len(touched)), touched)
-    offs = np.cumsum(touched) - touched
-    local = np.arange(total) - np.repeat(offs, touched)
-    w = np.repeat(rect[:, 2] - rect[:, 0], touched)
-    ty_ = np.repeat(rect[:, 1], touched) + local // np.maximum(w, 1)
-    tx_ = np.repeat(rect[:, 0], touched) + local % np.maximum(w, 1)
+    spans = pr["spans"]
+    # one segment per (Gaussian, rectangle row) with listed tiles, in
+    # Gaussian then row order, expanded into its columns
+    seg_n = np.maximum(spans[:, :, 1] - spans[:, :, 0], 0) if spans.size else np.zeros((len(touched), 0), np.int64)
+    seg_n = np.where(vis[:, None], seg_n, 0).reshape(-1)
+    rows = spans.shape[1]
+    seg_g = np.repeat(np.arange(len(touched)), rows)
+    seg_ty = rect[seg_g, 1] + np.tile(np.arange(rows), len(touched))
+    seg_lo = spans[:, :, 0].reshape(-1) if spans.size else np.zeros(0, np.int64)
+    keep = seg_n > 0
+    seg_g, seg_ty, seg_lo, seg_n = seg_g[keep], seg_ty[keep], seg_lo[keep], seg_n[keep]
+    total = int(seg_n.sum())
+    assert total == int(touched.sum())
+    gid = np.repeat(seg_g, seg_n)
+    first = np.cumsum(seg_n) - seg_n
+    tx_ = np.repeat(seg_lo, seg_n) + (np.arange(total) - np.repeat(first, seg_n))
+    ty_ = np.repeat(seg_ty, seg_n)
     tile = ty_ * tx + tx_
     keys = (tile.astype(np.uint64) << np.uint64(32)) | depth_bits[gid].astype(np.uint64)
     order = np.argsort(keys, kind="stable")

@@ -557,18 +557,12 @@ struct StageB {
   float4 a[kBwdBatch];
   float4 b[kBwdBatch];
   float2 c[kBwdBatch];  // b, tau
-  uint32_t slot[kBwdBatch];
+  uint32_t first[kBwdBatch];  // the Gaussian's first pair
+  uint2 rc[kBwdBatch];        // its tile rectangle
   float red[4][9][kBwdBatch];
   uint64_t bits[4][kBwdBatch / 64];
 };
 
-// Slot of the (Gaussian, tile) pair in the Gaussian-contiguous partials
-// buffer: the Gaussian's first pair plus the tile's row-major index in its
-// rectangle.
-__device__ __forceinline__ uint32_t pair_slot(uint32_t pair_off, uint2 rc, int tx, int ty) {
-  const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
-  return pair_off + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
-}
 
 template <bool COUNT>
 __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, const uint2* __restrict__ rect,
@@ -623,10 +617,9 @@ __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, cons
   __syncthreads();
   if (last > 0u) atomicMax(&tile_end, last);
   __syncthreads();
-  // pairs at or after the tile's last contribution keep the zeros the
-  // launcher filled the partials with (a streaming fill instead of two
-  // random record reads per such pair; at city scale most pairs of a tile
-  // lie behind its last contribution)
+  // pairs at or after the tile's last contribution get no partials (their
+  // valid bits stay clear) and are not staged at all; at city scale most
+  // pairs of a tile lie behind its last contribution
   const uint32_t end = min(max(tile_end, lo), hi);
   // where this lane's wave sums land in the reduction rows (lanes 7 and 15
   // of each 16-lane row; see the reduction in the walk)
@@ -651,7 +644,8 @@ __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, cons
           s.a[tid] = r.a;
           s.b[tid] = r.b;
           s.c[tid] = make_float2(r.c.x, r.c.y);
-          s.slot[tid] = pair_slot(__float_as_uint(r.c.z), rect[g], tx, ty);
+          s.first[tid] = __float_as_uint(r.c.z);
+          s.rc[tid] = rect[g];
           m = block_mask(r.a, r.b, r.c.y, tx, ty);
         }
         publish_masks(s.bits, m, tid);
@@ -755,8 +749,11 @@ __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, cons
       // a pair no wave used keeps no partials: its valid bit stays clear and
       // the pair sums skip it (every other pair's bit is set with its store)
       if (h0 || h1 || h2 || h3) {
+        // the pair's slot in the Gaussian-contiguous partials: the
+        // Gaussian's first pair plus the tile's index in its tile list
+        const Rec rr{s.a[tid], s.b[tid], make_float4(s.c[tid].x, s.c[tid].y, 0.f, 0.f)};
+        const uint32_t slot = s.first[tid] + splat_tile_index(splat_rows_of(rr, s.rc[tid]), tx, ty);
         // a wave that skipped the splat contributes exactly zero
-        const uint32_t slot = s.slot[tid];
         float* dst = partials + (int64_t)slot * 9;
         atomicOr(valid + (slot >> 5), 1u << (slot & 31));
         float R[9];

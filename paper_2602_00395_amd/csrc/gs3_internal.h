@@ -53,6 +53,138 @@ struct __align__(16) Rec {
   float4 a, b, c;
 };
 
+// Tile list of a splat.  A splat is paired with the tiles of its rectangle
+// whose 16x16 block of pixel centres meets the widened skip ellipse
+//   E = {d : d^T Q d <= k},  Q = (a, b; b, c) = (-2 qa, -qb; -qb, -2 qc),
+//   k = 2.02 (-tau) + 1e-3,
+// from the float32 conic and threshold of its record.  The skip test can
+// pass only where d^T Q d <= -2 tau (1 + r), r <= 1e-3 the relative rounding
+// error of the float32 power for rho^2 = b^2 / (a c) <= 0.999; the further
+// 0.9% of k and a 0.01-pixel margin on every edge below cover the rounding
+// of the float32 evaluation of the extent (relative errors of a few 1e-4 at
+// most near the top and bottom of E).  So every pixel the splat reaches lies
+// in a listed tile, and the render and its derivatives are those of the
+// whole rectangle.  A splat with rho^2 > 0.999 or a conic that is not
+// positive definite or finite keeps its whole rectangle; tau > 0 passes
+// nowhere (no tiles).  Row ty of the rectangle holds the columns [lo, hi) of
+// tiles that meet E within the band of pixel-centre rows 16 ty + 1/2 ..
+// 16 ty + 15.5: the band cuts E in a convex set whose x-extent runs from the
+// left end of E at the band's row nearest E's leftmost point to the right
+// end at the row nearest its rightmost point.  Every evaluation is in
+// float32 without contraction, in one fixed order, so the projection (the
+// counts), the emission and the backward (the partials slot) get the same
+// spans.  Pairs of a splat go row by row, columns in order.
+struct SplatRows {
+  int mode;  // 0: no tile, 1: the whole rectangle, 2: the ellipse rows
+  int x0, y0, x1, y1;
+  float u, v, b, det, ka, inv_a, ymax, yr;
+};
+
+__device__ __forceinline__ SplatRows splat_rows(float u, float v, float qa, float qb, float qc, float tau, int x0,
+                                                int y0, int x1, int y1) {
+#pragma clang fp contract(off)
+  SplatRows s;
+  s.x0 = x0;
+  s.y0 = y0;
+  s.x1 = x1;
+  s.y1 = y1;
+  s.u = u;
+  s.v = v;
+  if (tau > 0.f) {
+    s.mode = 0;
+    return s;
+  }
+  const float a = -2.f * qa, b = -qb, c = -2.f * qc;
+  const float det = a * c - b * b;
+  s.mode = (a > 0.f && c > 0.f && det * 1000.f >= a * c && det < INFINITY) ? 2 : 1;
+  const float k = -2.02f * tau + 1e-3f;
+  s.b = b;
+  s.det = det;
+  s.ka = k * a;
+  s.inv_a = 1.f / a;
+  s.ymax = sqrtf(s.ka / det);
+  // the rightmost point of E is (xm, yr), xm = sqrt(k c / det), yr = -b xm / c;
+  // the leftmost is (-xm, -yr)
+  s.yr = -b * sqrtf((k * c) / det) / c;
+  return s;
+}
+
+// Columns [lo, hi) of row ty (lo >= hi: none).
+__device__ __forceinline__ void splat_row_span(const SplatRows& s, int ty, int& lo, int& hi) {
+#pragma clang fp contract(off)
+  if (s.mode != 2) {
+    lo = s.x0;
+    hi = s.mode == 1 ? s.x1 : s.x0;
+    return;
+  }
+  const float row = 16.f * (float)ty;
+  const float ya = fmaxf((row + 0.49f) - s.v, -s.ymax), yb = fminf((row + 15.51f) - s.v, s.ymax);
+  if (!(ya <= yb)) {
+    lo = hi = s.x0;
+    return;
+  }
+  const float y_r = fminf(fmaxf(s.yr, ya), yb), y_l = fminf(fmaxf(-s.yr, ya), yb);
+  const float xr = (-s.b * y_r + sqrtf(fmaxf(s.ka - (s.det * y_r) * y_r, 0.f))) * s.inv_a;
+  const float xl = (-s.b * y_l - sqrtf(fmaxf(s.ka - (s.det * y_l) * y_l, 0.f))) * s.inv_a;
+  const float clo = ceilf(((s.u + xl) - 15.51f) * 0.0625f), chi = floorf(((s.u + xr) - 0.49f) * 0.0625f) + 1.f;
+  lo = (int)fminf(fmaxf(clo, (float)s.x0), (float)s.x1);
+  hi = (int)fmaxf(fminf(chi, (float)s.x1), (float)s.x0);
+}
+
+// Number of tiles of the splat.
+__device__ __forceinline__ uint32_t splat_tile_count(const SplatRows& s) {
+  if (s.mode != 2) return s.mode == 1 ? (uint32_t)((s.x1 - s.x0) * (s.y1 - s.y0)) : 0u;
+  uint32_t n = 0;
+  for (int ty = s.y0; ty < s.y1; ++ty) {
+    int lo, hi;
+    splat_row_span(s, ty, lo, hi);
+    n += hi > lo ? (uint32_t)(hi - lo) : 0u;
+  }
+  return n;
+}
+
+// Index of tile (tx, ty) among the splat's tiles (the tile is listed).
+__device__ __forceinline__ uint32_t splat_tile_index(const SplatRows& s, int tx, int ty) {
+  if (s.mode != 2) return (uint32_t)((ty - s.y0) * (s.x1 - s.x0) + (tx - s.x0));
+  uint32_t n = 0;
+  for (int r = s.y0; r < ty; ++r) {
+    int lo, hi;
+    splat_row_span(s, r, lo, hi);
+    n += hi > lo ? (uint32_t)(hi - lo) : 0u;
+  }
+  int lo, hi;
+  splat_row_span(s, ty, lo, hi);
+  return n + (uint32_t)(tx - lo);
+}
+
+// The k-th tile of the splat (k < its count), as (tx, ty).
+__device__ __forceinline__ void splat_tile_at(const SplatRows& s, uint32_t k, int& tx, int& ty) {
+  if (s.mode != 2) {
+    const int w = s.x1 - s.x0;
+    ty = s.y0 + (int)(k / (uint32_t)w);
+    tx = s.x0 + (int)(k % (uint32_t)w);
+    return;
+  }
+  for (int r = s.y0; r < s.y1; ++r) {
+    int lo, hi;
+    splat_row_span(s, r, lo, hi);
+    const uint32_t m = hi > lo ? (uint32_t)(hi - lo) : 0u;
+    if (k < m) {
+      ty = r;
+      tx = lo + (int)k;
+      return;
+    }
+    k -= m;
+  }
+  tx = s.x0;  // not reached for k below the count
+  ty = s.y0;
+}
+
+__device__ __forceinline__ SplatRows splat_rows_of(const Rec& r, uint2 rc) {
+  return splat_rows(r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.c.y, (int)(rc.x & 0xffff), (int)(rc.x >> 16),
+                    (int)(rc.y & 0xffff), (int)(rc.y >> 16));
+}
+
 // Tangent of the record under a parameter-space direction, 12 words:
 //   {du, dv, dconic_a, dconic_b}, {dconic_c, dopacity, dr, dg}, {db, 0, 0, 0}
 struct __align__(16) TRec {

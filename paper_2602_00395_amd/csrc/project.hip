@@ -253,21 +253,32 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
       const float y1 = fminf(fmaxf(floorf((p.v + p.radius) * inv) + 1.f, 0.f), tyf);
       vis = p.ok && isfinite(p.u) && isfinite(p.v) && isfinite(p.radius);
       const int ix0 = vis ? (int)x0 : 0, ix1 = vis ? (int)x1 : 0, iy0 = vis ? (int)y0 : 0, iy1 = vis ? (int)y1 : 0;
-      const int touched = max(ix1 - ix0, 0) * max(iy1 - iy0, 0);
-      vis = vis && touched > 0;
+      vis = vis && ix1 > ix0 && iy1 > iy0;
+      // the rectangle's tiles the splat can reach (the tile list, see
+      // SplatRows): a splat that reaches none is culled
+      float op = 0.f, tau = 0.f, qa = 0.f, qb = 0.f, qc = 0.f;
+      uint32_t touched = 0u;
+      if (vis) {
+        op = opacity_of(src(10));
+        tau = skip_threshold(op);
+        qa = -0.5f * p.ca;
+        qb = -p.cb;
+        qc = -0.5f * p.cc;
+        touched = splat_tile_count(splat_rows(p.u, p.v, qa, qb, qc, tau, ix0, iy0, ix1, iy1));
+      }
+      vis = vis && touched > 0u;
       if (!vis) {
         depth_key[g] = 0xffffffffu;
         tiles[g] = 0u;
       } else {
-        const float op = opacity_of(src(10));
-        *reinterpret_cast<float4*>(rw) = make_float4(p.u, p.v, -0.5f * p.ca, -p.cb);
-        rw[4] = -0.5f * p.cc;
+        *reinterpret_cast<float4*>(rw) = make_float4(p.u, p.v, qa, qb);
+        rw[4] = qc;
         rw[5] = op;
-        rw[9] = skip_threshold(op);
+        rw[9] = tau;
         rw[10] = 0.f;
         rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
         depth_key[g] = __float_as_uint(p.depth);
-        tiles[g] = (uint32_t)touched;
+        tiles[g] = touched;
       }
     }
     const uint64_t b = __ballot(vis);

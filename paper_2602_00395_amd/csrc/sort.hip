@@ -344,9 +344,10 @@ __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* __restric
 // then contiguous across the wave.  Zero-count (culled) Gaussians sort last,
 // so the owners of a workgroup's 256 pairs are at most 256 consecutive
 // entries: two threads find the first and last owner in global memory, the
-// offsets in between are staged in LDS and every thread searches those.  The
-// thread of a Gaussian's first pair also records the Gaussian's first pair in
-// its splat record.
+// offsets in between are staged in LDS and every thread searches those.  A
+// pair's tile is the k-th of its Gaussian's tile list (SplatRows), k its
+// index among the Gaussian's pairs.  The thread of a Gaussian's first pair
+// also records the Gaussian's first pair in its splat record.
 __device__ __forceinline__ int64_t last_le(const uint32_t* __restrict__ offsets, int64_t n, uint32_t target) {
   int64_t lo = 0, hi = n;  // the first index with offsets[idx] > target is in (lo, hi]
   while (hi - lo > 1) {
@@ -402,10 +403,8 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
   }
   const uint32_t g = order[own];
   const uint32_t k = (uint32_t)i - offsets[own];
-  const uint2 rc = rect[g];
-  const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
-  const int w = x1 - x0;
-  const int ty = y0 + (int)k / w, tx = x0 + (int)k % w;
+  int tx, ty;
+  splat_tile_at(splat_rows_of(rec[g], rect[g]), k, tx, ty);
   pair_tile[i] = (uint32_t)(ty * tiles_x + tx);
   pair_gid[i] = g;
   if (k == 0) rec[g].c.z = __uint_as_float((uint32_t)i);

@@ -140,7 +140,8 @@ def test_batched_gradient_object_scale_sampled_gaussians():
     # Gaussians visible (1..3 tiles) in every one of the four views
     ok = np.ones(x.shape[1], bool)
     for ob in obs:
-        ok &= (ob.tiles_touched >= 1) & (ob.tiles_touched <= 3)
+        area = (ob.rect[:, 2] - ob.rect[:, 0]) * (ob.rect[:, 3] - ob.rect[:, 1])
+        ok &= (ob.tiles_touched >= 1) & (area <= 3)
     pick = np.sort(rng.choice(np.flatnonzero(ok), size=4, replace=False))
     xt = torch.tensor(x, dtype=torch.float64)
     targets, tiles_of, masks = [], [], []

@@ -294,8 +294,9 @@ def test_grad_parity_object_scale_crop():
 
 
 def _sampled_gaussians(ob, rng, k, max_tiles):
-    """k visible Gaussians touching 1..max_tiles tiles, and the set of those tiles."""
-    cand = np.flatnonzero((ob.tiles_touched >= 1) & (ob.tiles_touched <= max_tiles))
+    """k visible Gaussians whose rectangles hold 1..max_tiles tiles, and the set of those tiles."""
+    area = (ob.rect[:, 2] - ob.rect[:, 0]) * (ob.rect[:, 3] - ob.rect[:, 1])
+    cand = np.flatnonzero((ob.tiles_touched >= 1) & (area <= max_tiles))
     pick = np.sort(rng.choice(cand, size=k, replace=False))
     tiles = set()
     for g in pick:
@@ -378,7 +379,8 @@ def _long_tile_picks(ob, rng, n_tiles, per_seg, seg=256):
         lo, hi = (int(v) for v in ob.ranges[t])
         for q in range(lo, hi, seg):
             g = ob.gids[q:min(q + seg, hi)]
-            g = g[ob.tiles_touched[g] <= 4]
+            area = (ob.rect[g, 2] - ob.rect[g, 0]) * (ob.rect[g, 3] - ob.rect[g, 1])
+            g = g[area <= 4]
             pick |= set(int(v) for v in rng.choice(g, size=min(per_seg, len(g)), replace=False))
     pick = np.array(sorted(pick))
     tiles = set()
@@ -453,12 +455,15 @@ def _stacked_tile_scene(L, seed):
     parts, have = [], 0
     while have < L:
         x = S.random_scene(rng, 8 * L, 0, -0.9, 0.9, math.log(0.01), 0.2, 0.1)
+        # the final faint opacities before binning: a splat's tile list
+        # depends on its opacity
+        x[10] = np.log(0.1 / 0.9) + rng.normal(0.0, 0.3, size=x.shape[1])
         ob = B.bin_view(x, cam)
-        ok = np.flatnonzero((ob.tiles_touched == 1) & (ob.rect[:, 0] == 0) & (ob.rect[:, 1] == 0))
+        ok = np.flatnonzero((ob.tiles_touched == 1) & np.all(ob.rect == [0, 0, 1, 1], axis=1))
         parts.append(x[:, ok])
         have += len(ok)
     x = np.concatenate(parts, axis=1)[:, :L].copy()
-    x[10] = np.log(0.1 / 0.9) + rng.normal(0.0, 0.3, size=L)
+    # a few opaque ones: a larger skip ellipse, the same rectangle (tile 0)
     x[10, rng.choice(L, size=max(1, L // 64), replace=False)] = 3.0
     return x.astype(np.float32), cam
 
@@ -702,13 +707,13 @@ def test_grad_and_hvp_splats_over_many_tiles():
     workgroup) next to splats covering fewer (nine threads per Gaussian), up
     to more than 2,048 tiles (several slots per thread of the workgroup): a
     few large Gaussians at 200x184 and 800x720."""
-    sc = syn.tiny_scene(91, n=12, sh_degree=1, width=200, height=184, n_cams=2, log_scale_mean=np.log(0.3),
-                        log_scale_std=0.6)
+    sc = syn.tiny_scene(91, n=12, sh_degree=1, width=200, height=184, n_cams=2, log_scale_mean=np.log(0.35),
+                        log_scale_std=0.7)
     x = sc.gt.astype(np.float32)
     cams = [sc.cameras[0], syn.make_camera(tuple(syn.fibonacci_sphere(2, 3.0)[1]), 800, 720)]
     counts = [B.bin_view(x, c).tiles_touched for c in cams]
     say("tiles touched", [sorted(c.tolist()) for c in counts])
-    assert counts[0].min() <= 64 < counts[0].max()
+    assert counts[0].min() <= 48 < counts[0].max()
     assert counts[1].max() > 2048
     targets = offset_targets(x, cams, 1, seed=4400)
     s = make_scene(x, targets, cams, 1)
