@@ -131,14 +131,34 @@ __device__ __forceinline__ void splat_row_span(const SplatRows& s, int ty, int& 
   hi = (int)fmaxf(fminf(chi, (float)s.x1), (float)s.x0);
 }
 
-// Number of tiles of the splat.
-__device__ __forceinline__ uint32_t splat_tile_count(const SplatRows& s) {
+// Number of tiles of the splat and the bounding rectangle of its listed
+// tiles [tx0, tx1) x [ty0, ty1) (the splat's own rectangle when every tile is
+// listed; empty when none is).  Clipping the rows to that rectangle leaves
+// every row's span as it is, so the spans may be taken from either.
+__device__ __forceinline__ uint32_t splat_tile_bounds(const SplatRows& s, int& tx0, int& ty0, int& tx1, int& ty1) {
+  tx0 = s.x0;
+  ty0 = s.y0;
+  tx1 = s.x1;
+  ty1 = s.y1;
   if (s.mode != 2) return s.mode == 1 ? (uint32_t)((s.x1 - s.x0) * (s.y1 - s.y0)) : 0u;
   uint32_t n = 0;
+  int xa = s.x1, xb = s.x0, ya = s.y1, yb = s.y0;
   for (int ty = s.y0; ty < s.y1; ++ty) {
     int lo, hi;
     splat_row_span(s, ty, lo, hi);
-    n += hi > lo ? (uint32_t)(hi - lo) : 0u;
+    if (hi > lo) {
+      n += (uint32_t)(hi - lo);
+      xa = min(xa, lo);
+      xb = max(xb, hi);
+      ya = min(ya, ty);
+      yb = ty + 1;
+    }
+  }
+  if (n) {
+    tx0 = xa;
+    tx1 = xb;
+    ty0 = ya;
+    ty1 = yb;
   }
   return n;
 }

@@ -147,14 +147,15 @@ __device__ __forceinline__ float tr_row(float g, float& gh_io, float& dh_io, flo
   return fminf(fmaxf(dx, -eta), eta);
 }
 
-// The same for entry k of the state arrays, loading and storing in place.
+// The same for entry k of the state arrays, loading and storing in place
+// (nontemporal: each entry is touched once per launch).
 __device__ __forceinline__ float tr_update(float* __restrict__ ghat, float* __restrict__ dhat,
                                            const float* __restrict__ D, int64_t k, float g, float eta,
                                            const TrArgs& a) {
-  float gh = ghat[k], dh = dhat[k];
-  const float step = tr_row(g, gh, dh, a.hutch ? D[k] : 0.f, eta, a);
-  ghat[k] = gh;
-  if (a.hutch) dhat[k] = dh;
+  float gh = __builtin_nontemporal_load(&ghat[k]), dh = __builtin_nontemporal_load(&dhat[k]);
+  const float step = tr_row(g, gh, dh, a.hutch ? __builtin_nontemporal_load(&D[k]) : 0.f, eta, a);
+  __builtin_nontemporal_store(gh, &ghat[k]);
+  if (a.hutch) __builtin_nontemporal_store(dh, &dhat[k]);
   return step;
 }
 

@@ -9,6 +9,9 @@ namespace {
 
 using namespace gs3trust;
 
+// The gradient and the optimizer state are each read and written once per
+// launch: those accesses are nontemporal (they would only evict the rows the
+// radius reads).
 // Work split: a workgroup takes 64 consecutive Gaussians and its four waves
 // take a quarter of the rows each (wave w: rows [w R, (w+1) R), R = ceil(P/4)),
 // so every row access of a wave is one coalesced 256-byte transaction and four
@@ -42,7 +45,7 @@ __global__ __launch_bounds__(256) void k_tr_step(float* __restrict__ x, const fl
       if (r >= P) break;
       const int64_t k = (int64_t)r * n + g;
       const float eta = row_radius(rad, r);
-      const float gk = grad[k];
+      const float gk = __builtin_nontemporal_load(&grad[k]);
       const float step = tr_update(ghat, dhat, D, k, gk, eta, a);
       const float xn = x[k] + step;
       x[k] = xn;
@@ -82,18 +85,18 @@ __global__ __launch_bounds__(256) void k_adam_step(float* __restrict__ x, const 
       const int r = W * R + rr;
       if (r >= P) break;
       const int64_t k = (int64_t)r * n + g;
-      const float gr = grad[k];
-      const float mm = a.b1 * m[k] + (1.f - a.b1) * gr;
-      const float vv = a.b2 * v[k] + (1.f - a.b2) * gr * gr;
-      m[k] = mm;
-      v[k] = vv;
+      const float gr = __builtin_nontemporal_load(&grad[k]);
+      const float mm = a.b1 * __builtin_nontemporal_load(&m[k]) + (1.f - a.b1) * gr;
+      const float vv = a.b2 * __builtin_nontemporal_load(&v[k]) + (1.f - a.b2) * gr * gr;
+      __builtin_nontemporal_store(mm, &m[k]);
+      __builtin_nontemporal_store(vv, &v[k]);
       float step = -a.lr_row[r] * (mm / a.bc1) / (sqrtf(vv / a.bc2) + a.eps);
       if (clip) {
         const float eta = row_radius(rad, r);
         step = fminf(fmaxf(step, -eta), eta);
       }
       const float xn = x[k] + step;
-      x[k] = xn;
+      __builtin_nontemporal_store(xn, &x[k]);
       note_nonfinite(nonfinite, gr, xn);
     }
   };

@@ -258,13 +258,16 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
       // SplatRows): a splat that reaches none is culled
       float op = 0.f, tau = 0.f, qa = 0.f, qb = 0.f, qc = 0.f;
       uint32_t touched = 0u;
+      int bx0 = ix0, by0 = iy0, bx1 = ix1, by1 = iy1;
       if (vis) {
         op = opacity_of(src(10));
         tau = skip_threshold(op);
         qa = -0.5f * p.ca;
         qb = -p.cb;
         qc = -0.5f * p.cc;
-        touched = splat_tile_count(splat_rows(p.u, p.v, qa, qb, qc, tau, ix0, iy0, ix1, iy1));
+        // the stored rectangle is the bounding box of the listed tiles, so
+        // the emission and the backward walk no rows without tiles
+        touched = splat_tile_bounds(splat_rows(p.u, p.v, qa, qb, qc, tau, ix0, iy0, ix1, iy1), bx0, by0, bx1, by1);
       }
       vis = vis && touched > 0u;
       if (!vis) {
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
         rw[5] = op;
         rw[9] = tau;
         rw[10] = 0.f;
-        rect[g] = make_uint2((uint32_t)ix0 | ((uint32_t)iy0 << 16), (uint32_t)ix1 | ((uint32_t)iy1 << 16));
+        rect[g] = make_uint2((uint32_t)bx0 | ((uint32_t)by0 << 16), (uint32_t)bx1 | ((uint32_t)by1 << 16));
         depth_key[g] = __float_as_uint(p.depth);
         tiles[g] = touched;
       }
@@ -633,7 +636,10 @@ __host__ __device__ constexpr int sh_lo(int w) {
 // its stores (the state arrays may alias as far as the compiler knows, so
 // loads would otherwise wait for the previous row's stores), which keeps up
 // to 5 x kChunk loads in flight per wave without the registers of all rows
-// at once.
+// at once.  The optimizer state (ghat, Dhat, D) and the new parameters are each
+// touched once per launch: their loads and stores are nontemporal, so they
+// do not evict the parameter rows the chain rule reads twice (1.47 -> 1.38 ms
+// per city update).
 constexpr int kChunk = 6;
 
 template <int R, class RowOf, class ValOf, class EtaOf>
@@ -667,9 +673,9 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
         if (c0 + j < R) {
           const int64_t k = (int64_t)row_of(c0 + j) * n + g;
           xv[j] = x[k];
-          gh[j] = ft.ghat[k];
-          dh[j] = ft.dhat[k];
-          dv[j] = a.hutch ? ft.D[k] : 0.f;
+          gh[j] = __builtin_nontemporal_load(&ft.ghat[k]);
+          dh[j] = __builtin_nontemporal_load(&ft.dhat[k]);
+          dv[j] = a.hutch ? __builtin_nontemporal_load(&ft.D[k]) : 0.f;
           ga[j] = ft.gacc ? ft.gacc[k] : 0.f;
         }
 #pragma unroll
@@ -681,9 +687,9 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
           const float v = have ? val_of(c0 + j) : 0.f;
           const float gk = ft.gacc ? (have ? ga[j] + v : ga[j]) : v;
           const float xn = xv[j] + gs3trust::tr_row(gk, gh[j], dh[j], dv[j], eta_of(c0 + j), a);
-          ft.x_out[k] = xn;
-          ft.ghat[k] = gh[j];
-          if (a.hutch) ft.dhat[k] = dh[j];
+          __builtin_nontemporal_store(xn, &ft.x_out[k]);
+          __builtin_nontemporal_store(gh[j], &ft.ghat[k]);
+          if (a.hutch) __builtin_nontemporal_store(dh[j], &ft.dhat[k]);
           note_nonfinite(ft.nonfinite, gk, xn);
         }
     }
