@@ -117,8 +117,10 @@ def update_bytes(p: int, n: int, hutch: bool) -> int:
     """Algorithmic HBM bytes of one fused update launch: read x, ghat and Dhat
     and write x' and ghat for every parameter (20 B; the gradient is formed in
     registers from each Gaussian's nine summed screen-space partials, 36 B
-    read), plus D_t read and Dhat written on a Hutchinson iteration (8 B)."""
-    return (20 + (8 if hutch else 0)) * p * n + 36 * n
+    read per view), plus Dhat written on a Hutchinson iteration (4 B; D_t is
+    formed in the same launch from the probe entry's nine summed partials,
+    36 B more per Gaussian)."""
+    return (20 + (4 if hutch else 0)) * p * n + 36 * n * (2 if hutch else 1)
 
 
 def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int, workload: str) -> dict | None:

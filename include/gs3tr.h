@@ -145,12 +145,14 @@ gs3_status gs3_scene_set_params(gs3_scene* scene, const float* params_dev, hipSt
 
 /* Resident bytes (targets, parameters and the trust-region method's state:
  * six float[P][N] buffers and the radius scratch, where Adam needs three
- * buffers) and the scratch a scene described by desc allocates at creation:
+ * buffers) and the peak scratch of a scene described by desc: two slots of
  * per-Gaussian and per-pixel buffers and pair buffers reserved for 12
- * (Gaussian, tile) pairs per Gaussian with 25% slack.  A view with more pairs
- * grows the pair buffers (stream-ordered, without waiting for the device);
- * gs3_scene_device_bytes reports what a scene holds.  Used to admit scenes
- * under an HBM budget.  No device work. */
+ * (Gaussian, tile) pairs per Gaussian with 25% slack (slot 0, allocated at
+ * creation, and the slot of the probe entry that a gs3_tr_iteration with one
+ * Hutchinson view and probe adds).  A view with more pairs grows the pair
+ * buffers (stream-ordered, without waiting for the device), and batches of
+ * more views or probes add slots; gs3_scene_device_bytes reports what a
+ * scene holds.  Used to admit scenes under an HBM budget.  No device work. */
 gs3_status gs3_scene_bytes(const gs3_scene_desc* desc, int64_t* resident, int64_t* peak_scratch);
 
 /* Device bytes the scene holds now: everything gs3_scene_bytes counts
@@ -249,10 +251,14 @@ gs3_status gs3_tr_step(gs3_scene* scene, const float* grad_dev, const float* D_d
  * gs3_hvp_diag); the stochastic gradient over cams1[0..n1) (as gs3_grad);
  * then the update of gs3_tr_step with D_t on Hutchinson iterations.  The
  * update is fused into the projection backward of the last gradient view,
- * so the gradient of that view never goes through memory; the parameters
- * are double-buffered (the update reads one copy and writes the other), so
- * a pointer from gs3_scene_params is not valid after this call.  D_t and the
- * other views' gradient live in scene-owned buffers.  loss_out (nullable,
+ * so the gradient of that view never goes through memory; when the n2 * nu
+ * Hutchinson entries and the n1 views fit one batch (n1 + n2 * nu <= 8) the
+ * same launch also forms D_t, which then never goes through memory either
+ * (the entries take their own view slots: a Hutchinson iteration holds n1 +
+ * n2 * nu slots of per-view scratch).  The parameters are double-buffered
+ * (the update reads one copy and writes the other), so a pointer from
+ * gs3_scene_params is not valid after this call.  A D_t of a larger batch
+ * and the other views' gradient live in scene-owned buffers.  loss_out (nullable,
  * host) receives the mini-batch objective as in gs3_grad.  Same results as
  * gs3_hvp_diag + gs3_grad + gs3_tr_step on the same views. */
 gs3_status gs3_tr_iteration(gs3_scene* scene, const int32_t* cams1, int32_t n1, const int32_t* cams2, int32_t n2,

@@ -459,7 +459,6 @@ gs3_status need_fused_state(gs3_scene* s, hipStream_t st) {
   const int64_t PN = (int64_t)s->P * s->N;
   GS3_TRY(need_tr_state(s, st));
   if (!s->x_alt) GS3_TRY(dalloc(&s->x_alt, (size_t)PN));
-  if (!s->dbuf) GS3_TRY(dalloc(&s->dbuf, (size_t)PN));
   if (!s->gacc) GS3_TRY(dalloc(&s->gacc, (size_t)PN));
   return GS3_OK;
 }
@@ -810,11 +809,14 @@ void blend_bwd(gs3_scene* s, const Entries& E, hipStream_t st, const float* cot 
 }
 
 // Pair sums of every entry, then the chain rule over the batch (modes as
-// launch_project_bwd; mode 1 takes each entry's probe of `seed`).
+// launch_project_bwd; mode 1 takes each entry's probe of `seed`, and so do
+// the last n_probe entries of a mode-2 batch).
 void project_bwd(gs3_scene* s, const Entries& E, int mode, int acc, uint64_t seed, float scale, float* out,
-                 hipStream_t st, const FusedTr& ft = FusedTr{}) {
+                 hipStream_t st, const FusedTr& ft = FusedTr{}, int n_probe = 0, float probe_scale = 0.f) {
   BwdBatch B;
   B.n = E.n;
+  B.n_probe = n_probe;
+  B.probe_scale = probe_scale;
   auto ps = prof::begin("pair_sums", st);
   int64_t pairs = 0;
   for (int k = 0; k < E.n; ++k) {
@@ -825,7 +827,7 @@ void project_bwd(gs3_scene* s, const Entries& E, int mode, int acc, uint64_t see
     B.v[k].tiles = b.tiles;
     B.v[k].G = e.gsum;
     B.v[k].cam = b.cd;
-    B.v[k].inner = mode == 1 ? probe_key(seed, E.probe[k]) : 0ull;
+    B.v[k].inner = mode == 1 || k >= E.n - n_probe ? probe_key(seed, E.probe[k]) : 0ull;
     pairs += b.n_pairs;
   }
   prof::end(ps, st, s->N, pairs);
@@ -993,7 +995,10 @@ gs3_status gs3_scene_bytes(const gs3_scene_desc* d, int64_t* resident, int64_t* 
   // EMAs, D_t and the gradient accumulator of the trust-region method (Adam
   // instead holds two moments)
   *resident = 12 * px_total + 4 * P * N * 6;
-  *peak_scratch = view_scratch_bytes(N, max_px, max_tiles) + pair_bytes(pair_capacity(reserved_pairs(N)), max_tiles, N);
+  // slot 0 at creation, and the slot of the probe entry of a trust-region
+  // iteration with one Hutchinson view and probe
+  *peak_scratch =
+      2 * (view_scratch_bytes(N, max_px, max_tiles) + pair_bytes(pair_capacity(reserved_pairs(N)), max_tiles, N));
   return GS3_OK;
 }
 
@@ -1219,28 +1224,55 @@ namespace {
 // batches of up to GS3_MAX_VIEWS: each view is binned into a slot of its
 // own, then one blend launch, one backward launch and one projection
 // backward cover the whole batch.
+// Views cams[c0 .. c0 + count) as one batch in slots [base, base + count):
+// binning, render, loss cotangent (scale: the loss weight of one view) and
+// backward, leaving the partials for the chain rule; each view's loss goes to
+// s->dsum[c0 + k] when `loss` is set.
+gs3_status grad_batch(gs3_scene* s, const int32_t* cams, int c0, int count, int base, float scale, bool loss,
+                      Entries& E, hipStream_t st) {
+  E.n = count;
+  for (int k = 0; k < count; ++k) {
+    E.b[k] = E.e[k] = base + k;
+    GS3_TRY(bin_view(s, s->vb[base + k], cams[c0 + k], st));
+  }
+  blend_fwd(s, E, st);
+  for (int k = 0; k < count; ++k) {
+    ViewBufs& v = s->vb[base + k];
+    int np = 0;
+    auto pl = prof::begin("loss", st);
+    launch_loss_grad(v.img, target_of(s, v.cam), v.cd.width, v.cd.height, s->lam, scale, v.cot, v.ssim_tmp, v.dpart,
+                     &np, st);
+    prof::end(pl, st);
+    if (loss) launch_sum_partials(v.dpart, np, s->dsum + c0 + k, st);
+  }
+  blend_bwd(s, E, st);
+  return GS3_OK;
+}
+
+// The loss of n_cams views whose per-view sums grad_batch left in s->dsum.
+gs3_status read_loss(gs3_scene* s, int32_t n_cams, double* loss_out, hipStream_t st) {
+  GS3_HIP(hipMemcpyAsync(s->host_f64, s->dsum, sizeof(double) * n_cams, hipMemcpyDeviceToHost, st));
+  GS3_HIP(hipStreamSynchronize(st));
+  double tot = 0.0;
+  for (int k = 0; k < n_cams; ++k) tot += s->host_f64[k];
+  *loss_out = tot / (2.0 * (double)s->m_comp);
+  return GS3_OK;
+}
+
+float grad_scale(const gs3_scene* s, int32_t n_cams) {
+  return (float)((double)s->n_train / (2.0 * (double)s->m_comp * n_cams));
+}
+float hvp_scale(const gs3_scene* s, int32_t n_cams, int32_t nu) {
+  return (float)((double)s->n_train / ((double)s->m_comp * n_cams * nu));
+}
+
 gs3_status grad_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* grad, double* loss_out,
                       const FusedTr* fuse, hipStream_t st) {
-  const float scale = (float)((double)s->n_train / (2.0 * (double)s->m_comp * n_cams));
+  const float scale = grad_scale(s, n_cams);
   GS3_TRY(need_slots(s, std::min<int>(n_cams, GS3_MAX_VIEWS)));
   for (int c0 = 0; c0 < n_cams; c0 += GS3_MAX_VIEWS) {
     Entries E;
-    E.n = std::min<int>(GS3_MAX_VIEWS, n_cams - c0);
-    for (int k = 0; k < E.n; ++k) {
-      E.b[k] = E.e[k] = k;
-      GS3_TRY(bin_view(s, s->vb[k], cams[c0 + k], st));
-    }
-    blend_fwd(s, E, st);
-    for (int k = 0; k < E.n; ++k) {
-      ViewBufs& v = s->vb[k];
-      int np = 0;
-      auto pl = prof::begin("loss", st);
-      launch_loss_grad(v.img, target_of(s, v.cam), v.cd.width, v.cd.height, s->lam, scale, v.cot, v.ssim_tmp, v.dpart,
-                       &np, st);
-      prof::end(pl, st);
-      if (loss_out) launch_sum_partials(v.dpart, np, s->dsum + c0 + k, st);
-    }
-    blend_bwd(s, E, st);
+    GS3_TRY(grad_batch(s, cams, c0, std::min<int>(GS3_MAX_VIEWS, n_cams - c0), 0, scale, loss_out != nullptr, E, st));
     if (fuse && c0 + E.n == n_cams) {
       FusedTr ft = *fuse;
       ft.gacc = c0 > 0 ? grad : nullptr;
@@ -1250,56 +1282,58 @@ gs3_status grad_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, float* 
     }
     GS3_LAUNCHED();
   }
-  if (loss_out) {
-    GS3_HIP(hipMemcpyAsync(s->host_f64, s->dsum, sizeof(double) * n_cams, hipMemcpyDeviceToHost, st));
-    GS3_HIP(hipStreamSynchronize(st));
-    double tot = 0.0;
-    for (int k = 0; k < n_cams; ++k) tot += s->host_f64[k];
-    *loss_out = tot / (2.0 * (double)s->m_comp);
-  }
+  if (loss_out) GS3_TRY(read_loss(s, n_cams, loss_out, st));
   return GS3_OK;
 }
 
-// D_t of Hutchinson over views cams[0..n) and nu probes.  The (view, probe)
-// entries go in batches of up to GS3_MAX_VIEWS: a view is binned once per
-// batch (into the slot of its first probe), every entry gets its own tangent
-// records, images and partials, and one JVP blend launch, one backward launch
-// and one projection backward cover the batch.
+// Hutchinson entries q0 .. q0 + count (entry q: probe q mod nu of view
+// cams[q / nu]) as one batch in slots [base, base + count): a view is binned
+// once per batch (into the slot of its first probe), every entry gets its
+// own tangent records, images and partials, and one JVP blend launch and
+// one backward launch cover the batch; the pair sums and the chain rule are
+// left to the caller.
+gs3_status hvp_batch(gs3_scene* s, const int32_t* cams, int32_t nu, uint64_t seed, int64_t q0, int count, int base,
+                     Entries& E, hipStream_t st) {
+  E.n = count;
+  for (int k = 0; k < count; ++k) {
+    const int64_t q = q0 + k;
+    const int j = (int)(q / nu);
+    E.e[k] = base + k;
+    E.probe[k] = (uint32_t)(q % nu);
+    // the view's binning: in this batch's slot of its first entry
+    const int first = (int)(std::max<int64_t>(q0, (int64_t)j * nu) - q0);
+    E.b[k] = base + first;
+    if (first == k) {
+      GS3_TRY(bin_view(s, s->vb[base + k], cams[j], st));
+    } else {
+      GS3_TRY(ensure_blend(s, s->vb[base + k], s->vb[base + first].n_pairs, &st));
+    }
+  }
+  for (int k = 0; k < count; ++k)
+    project_jvp(s, s->vb[E.b[k]], s->vb[E.e[k]], PROBE_HASH, seed, E.probe[k], nullptr, st);
+  blend_jvp(s, E, st);
+  for (int k = 0; k < count; ++k) {
+    ViewBufs& v = s->vb[E.e[k]];
+    const ViewBufs& b = s->vb[E.b[k]];
+    auto pl = prof::begin("loss", st);
+    launch_loss_gn(v.img, target_of(s, b.cam), v.tan_img, b.cd.width, b.cd.height, s->lam, 1.f, v.cot, v.ssim_tmp, st);
+    prof::end(pl, st);
+  }
+  blend_bwd(s, E, st);
+  return GS3_OK;
+}
+
+// D_t of Hutchinson over views cams[0..n) and nu probes, in batches of up to
+// GS3_MAX_VIEWS entries, each closed by one projection backward (mode 1).
 gs3_status hvp_views(gs3_scene* s, const int32_t* cams, int32_t n_cams, int32_t nu, uint64_t seed, float* D,
                      hipStream_t st) {
   launch_fill_f32(D, (int64_t)s->P * s->N, 0.f, st);
-  const float scale = (float)((double)s->n_train / ((double)s->m_comp * n_cams * nu));
+  const float scale = hvp_scale(s, n_cams, nu);
   const int64_t total = (int64_t)n_cams * nu;
   GS3_TRY(need_slots(s, (int)std::min<int64_t>(total, GS3_MAX_VIEWS)));
   for (int64_t q0 = 0; q0 < total; q0 += GS3_MAX_VIEWS) {
     Entries E;
-    E.n = (int)std::min<int64_t>(GS3_MAX_VIEWS, total - q0);
-    for (int k = 0; k < E.n; ++k) {
-      const int64_t q = q0 + k;
-      const int j = (int)(q / nu);
-      E.e[k] = k;
-      E.probe[k] = (uint32_t)(q % nu);
-      // the view's binning: in this batch's slot of its first entry
-      const int first = (int)std::max<int64_t>(q0, (int64_t)j * nu) - (int)q0;
-      E.b[k] = first;
-      if (first == k) {
-        GS3_TRY(bin_view(s, s->vb[k], cams[j], st));
-      } else {
-        GS3_TRY(ensure_blend(s, s->vb[k], s->vb[first].n_pairs, &st));
-      }
-    }
-    for (int k = 0; k < E.n; ++k)
-      project_jvp(s, s->vb[E.b[k]], s->vb[k], PROBE_HASH, seed, E.probe[k], nullptr, st);
-    blend_jvp(s, E, st);
-    for (int k = 0; k < E.n; ++k) {
-      ViewBufs& v = s->vb[k];
-      const ViewBufs& b = s->vb[E.b[k]];
-      auto pl = prof::begin("loss", st);
-      launch_loss_gn(v.img, target_of(s, b.cam), v.tan_img, b.cd.width, b.cd.height, s->lam, 1.f, v.cot, v.ssim_tmp,
-                     st);
-      prof::end(pl, st);
-    }
-    blend_bwd(s, E, st);
+    GS3_TRY(hvp_batch(s, cams, nu, seed, q0, (int)std::min<int64_t>(GS3_MAX_VIEWS, total - q0), 0, E, st));
     project_bwd(s, E, 1, 0, seed, scale, D, st);
     GS3_LAUNCHED();
   }
@@ -1354,15 +1388,38 @@ gs3_status gs3_tr_iteration(gs3_scene* s, const int32_t* cams1, int32_t n1, cons
   if (n2 > 0) GS3_TRY(check_views(s, cams2, n2));
   GS3_TRY(check_hparams(hp));
   GS3_TRY(need_fused_state(s, st));
-  if (n2 > 0) GS3_TRY(hvp_views(s, cams2, n2, nu, seed, s->dbuf, st));
   FusedTr ft;
   ft.x_out = s->x_alt;
   ft.ghat = s->ghat;
   ft.dhat = s->dhat;
-  ft.D = n2 > 0 ? s->dbuf : nullptr;
   ft.nonfinite = s->host_u32 + 1;
   ft.a = TrArgs{hp->theta1, hp->theta2, hp->epsilon, n2 > 0, hp->variant};
-  GS3_TRY(grad_views(s, cams1, n1, s->gacc, loss_out, &ft, st));
+  const int64_t nh = n2 > 0 ? (int64_t)n2 * nu : 0;
+  if (n2 > 0 && nh + n1 <= GS3_MAX_VIEWS) {
+    // one batch: the Hutchinson entries in slots [0, nh), the gradient views
+    // after them, and one update launch that sums D_t in registers (D_t never
+    // goes through device memory)
+    GS3_TRY(need_slots(s, (int)(nh + n1)));
+    Entries H, C;
+    GS3_TRY(hvp_batch(s, cams2, nu, seed, 0, (int)nh, 0, H, st));
+    GS3_TRY(grad_batch(s, cams1, 0, n1, (int)nh, grad_scale(s, n1), loss_out != nullptr, C, st));
+    for (int k = 0; k < H.n; ++k) {
+      C.b[C.n + k] = H.b[k];
+      C.e[C.n + k] = H.e[k];
+      C.probe[C.n + k] = H.probe[k];
+    }
+    C.n += H.n;
+    project_bwd(s, C, 2, 0, seed, 0.f, nullptr, st, ft, H.n, hvp_scale(s, n2, nu));
+    GS3_LAUNCHED();
+    if (loss_out) GS3_TRY(read_loss(s, n1, loss_out, st));
+  } else {
+    if (n2 > 0) {
+      if (!s->dbuf) GS3_TRY(dalloc(&s->dbuf, (size_t)s->P * s->N));
+      GS3_TRY(hvp_views(s, cams2, n2, nu, seed, s->dbuf, st));
+      ft.D = s->dbuf;
+    }
+    GS3_TRY(grad_views(s, cams1, n1, s->gacc, loss_out, &ft, st));
+  }
   std::swap(s->x, s->x_alt);
   return finish(s, st);
 }

@@ -264,13 +264,19 @@ struct BwdView {
 struct BwdBatch {
   BwdView v[GS3_MAX_VIEWS];
   int n = 0;
+  // mode 2: the last n_probe entries are Hutchinson probes whose D_t (scale
+  // probe_scale) the update takes in place of FusedTr::D
+  int n_probe = 0;
+  float probe_scale = 0.f;
 };
 // Key of probe i of `seed` (the inner SplitMix64 of the probe definition).
 uint64_t probe_key(uint64_t seed, uint32_t probe_index);
 // Chain rule from each view's gsum to the raw parameters, summed over the
 // views of B.  mode 0: out = (accumulate ? out : 0) + dL/dx; mode 1: out +=
 // scale sum_i z_i dL_i/dx for the probes of B's entries (Gaussians no entry
-// sees untouched); mode 2: the fused update described by ft.
+// sees untouched); mode 2: the fused update described by ft, its gradient
+// from the first B.n - B.n_probe entries and, when B.n_probe > 0, its D_t
+// from the rest (ft.D unused).
 void launch_project_bwd(const float* x, int64_t n, int deg, const BwdBatch& B, int mode, int accumulate, float scale,
                         float* out, const FusedTr& ft, hipStream_t st);
 

@@ -631,7 +631,9 @@ __host__ __device__ constexpr int sh_lo(int w) {
 // What a wave does with the summed value v of each of its rows (see
 // launch_project_bwd; `have` false: no view of the batch sees the Gaussian):
 // mode 0 writes (or adds to) out, mode 1 adds v to out (v already holds the
-// probes' signs and the scale), mode 2 applies the update of Algorithm 1.
+// probes' signs and the scale), mode 2 applies the update of Algorithm 1,
+// with D_t read from ft.D, or (HUT) taken from dval_of: the batch's own
+// Hutchinson entries, summed in registers.
 // Rows go in chunks of kChunk: every load of a chunk is issued before any of
 // its stores (the state arrays may alias as far as the compiler knows, so
 // loads would otherwise wait for the previous row's stores), which keeps up
@@ -642,10 +644,10 @@ __host__ __device__ constexpr int sh_lo(int w) {
 // per city update).
 constexpr int kChunk = 6;
 
-template <int R, class RowOf, class ValOf, class EtaOf>
+template <int R, bool HUT, class RowOf, class ValOf, class DValOf, class EtaOf>
 __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n, int64_t g, int mode, int accumulate,
                                           bool have, float* __restrict__ out, const FusedTr& ft, const RowOf& row_of,
-                                          const ValOf& val_of, const EtaOf& eta_of) {
+                                          const ValOf& val_of, const DValOf& dval_of, const EtaOf& eta_of) {
 #pragma unroll
   for (int c0 = 0; c0 < R; c0 += kChunk) {
     constexpr int C = kChunk;
@@ -675,7 +677,8 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
           xv[j] = x[k];
           gh[j] = __builtin_nontemporal_load(&ft.ghat[k]);
           dh[j] = __builtin_nontemporal_load(&ft.dhat[k]);
-          dv[j] = a.hutch ? __builtin_nontemporal_load(&ft.D[k]) : 0.f;
+          if constexpr (HUT) dv[j] = dval_of(c0 + j);
+          else dv[j] = a.hutch ? __builtin_nontemporal_load(&ft.D[k]) : 0.f;
           ga[j] = ft.gacc ? ft.gacc[k] : 0.f;
         }
 #pragma unroll
@@ -710,8 +713,10 @@ __device__ __forceinline__ void emit_rows(const float* __restrict__ x, int64_t n
 // probe of a view, and its part is multiplied by the scale and the probe's
 // sign before the sum.  In mode 2 each wave forms the trust-region radii of
 // its rows from the parameters before the update (the same expressions as
-// the separate update kernel).
-template <int DEG, int mode>
+// the separate update kernel); with HUT the batch's last B.n_probe entries
+// are Hutchinson probes, summed as in mode 1 (scale B.probe_scale) into a
+// second set of registers that stands in for D_t.
+template <int DEG, int mode, bool HUT = false>
 __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, int64_t n, const BwdBatch& B,
                                                  int accumulate, float scale, float* __restrict__ out,
                                                  const FusedTr& ft) {
@@ -738,13 +743,18 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
     gc[1] = (posm & 2u) ? Gg[7] : 0.f;
     gc[2] = (posm & 4u) ? Gg[8] : 0.f;
   };
-  // the weight of view v's part of row r: the scaled probe sign in mode 1
-  auto weight = [&](const BwdView& V, int r) {
-    return mode == 1 ? scale * probe_sign(V.inner, (uint64_t)((int64_t)r * n + g)) : 1.f;
+  // entry v is a Hutchinson probe (mode 1, or the tail of a HUT batch)
+  const int first_probe = HUT ? B.n - B.n_probe : (mode == 1 ? 0 : B.n);
+  // the weight of entry v's part of row r: the scaled probe sign for a probe
+  auto weight = [&](const BwdView& V, int v, int r) {
+    if (mode == 1) return scale * probe_sign(V.inner, (uint64_t)((int64_t)r * n + g));
+    if (HUT && v >= first_probe) return B.probe_scale * probe_sign(V.inner, (uint64_t)((int64_t)r * n + g));
+    return 1.f;
   };
   const float eps = ft.a.epsilon;
   const uint32_t variant = ft.a.variant;
-  bool have = false;  // some view of the batch sees the Gaussian
+  bool have = false;   // some view of the batch sees the Gaussian
+  bool haveh = false;  // HUT: some probe entry sees it
   if (w > 0) {
     // the wave's coefficient run as compile-time indices, so the basis
     // values, row sums and radii stay in registers
@@ -752,12 +762,15 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
       constexpr int W = decltype(wave)::value;
       constexpr int k0 = sh_lo<DEG>(W), k1 = sh_lo<DEG>(W + 1);
       constexpr int NR = 3 * (k1 - k0) > 0 ? 3 * (k1 - k0) : 1;
-      float val[NR];
+      float val[NR], dvl[HUT ? NR : 1];
 #pragma unroll
       for (int i = 0; i < NR; ++i) val[i] = 0.f;
+#pragma unroll
+      for (int i = 0; i < (HUT ? NR : 1); ++i) dvl[i] = 0.f;
       for (int v = 0; v < B.n; ++v) {
         const BwdView& V = B.v[v];
         const bool vis = live && V.tiles[g] != 0u;
+        const bool pr = HUT && v >= first_probe;
         float part[3] = {0.f, 0.f, 0.f};
         if (vis) {
           float gc[3], e[3], inv;
@@ -770,8 +783,13 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const int i = 3 * (k - k0) + c;
-              const float pv = weight(V, 11 + 3 * k + c) * (gc[c] * Y[k]);
-              val[i] = have ? val[i] + pv : pv;
+              const float pv = weight(V, v, 11 + 3 * k + c) * (gc[c] * Y[k]);
+              if constexpr (HUT) {
+                if (pr) dvl[i] = haveh ? dvl[i] + pv : pv;
+                else val[i] = have ? val[i] + pv : pv;
+              } else {
+                val[i] = have ? val[i] + pv : pv;
+              }
             }
             if (k == 0) continue;
             // this wave's share of the direction term, coefficients in order
@@ -781,7 +799,10 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) part[ax] += gy * gr[ax];
           }
-          have = true;
+          // value updates (a branch on which flag to set becomes a store
+          // through a selected private address)
+          haveh = haveh || pr;
+          have = have || !pr;
         }
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) gdir_part[v][W - 1][ax][lane] = part[ax];
@@ -792,9 +813,13 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
       if constexpr (k1 > k0) {
         gs3trust::Radius rad;
         if (mode == 2) gs3trust::radius_colour(x, n, g, eps, variant, DEG, gs3trust::radius_alpha(x, n, g), rad);
-        emit_rows<3 * (k1 - k0)>(
+        emit_rows<3 * (k1 - k0), HUT>(
             x, n, g, mode, accumulate, have, out, ft, [&](int i) { return 11 + 3 * k0 + i; },
             [&](int i) { return val[i]; },
+            [&](int i) {
+              if constexpr (HUT) return dvl[i];
+              else return 0.f;
+            },
             [&](int i) { return k0 + i / 3 == 0 ? rad.col[i % 3] : rad.rest[i % 3]; });
       }
     };
@@ -804,9 +829,11 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
     return;
   }
   // wave 0: geometry and opacity
-  float d[11];
+  float d[11], dd[HUT ? 11 : 1];
 #pragma unroll
   for (int r = 0; r < 11; ++r) d[r] = 0.f;
+#pragma unroll
+  for (int r = 0; r < (HUT ? 11 : 1); ++r) dd[r] = 0.f;
   for (int v = 0; v < B.n; ++v) {
     const BwdView& V = B.v[v];
     if (!(live && V.tiles[g] != 0u)) continue;
@@ -816,12 +843,19 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
     geo_vjp(x, n, g, V.cam, Gs, dv);
     const float s = sigmoid_(xr(10));
     dv[10] = Gg[5] * s * (1.f - s);
+    const bool pr = HUT && v >= first_probe;
 #pragma unroll
     for (int r = 0; r < 11; ++r) {
-      const float pv = weight(V, r) * dv[r];
-      d[r] = have ? d[r] + pv : pv;
+      const float pv = weight(V, v, r) * dv[r];
+      if constexpr (HUT) {
+        if (pr) dd[r] = haveh ? dd[r] + pv : pv;
+        else d[r] = have ? d[r] + pv : pv;
+      } else {
+        d[r] = have ? d[r] + pv : pv;
+      }
     }
-    have = true;
+    haveh = haveh || pr;
+    have = have || !pr;
   }
   __syncthreads();
   if (DEG > 0) {
@@ -835,14 +869,27 @@ __device__ __forceinline__ void project_bwd_body(const float* __restrict__ x, in
         gdir[ax] = (gdir_part[v][0][ax][lane] + gdir_part[v][1][ax][lane]) + gdir_part[v][2][ax][lane];
       const float ed = (e[0] * gdir[0] + e[1] * gdir[1]) + e[2] * gdir[2];
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) d[ax] += weight(V, ax) * ((gdir[ax] - e[ax] * ed) * inv);
+      for (int ax = 0; ax < 3; ++ax) {
+        const float t = weight(V, v, ax) * ((gdir[ax] - e[ax] * ed) * inv);
+        if constexpr (HUT) {
+          if (v >= first_probe) dd[ax] += t;
+          else d[ax] += t;
+        } else {
+          d[ax] += t;
+        }
+      }
     }
   }
   if (!live || (!have && (mode == 1 || (mode == 0 && accumulate)))) return;
   gs3trust::Radius rad;
   if (mode == 2) gs3trust::radius_geo(x, n, g, eps, variant, gs3trust::radius_alpha(x, n, g), rad);
-  emit_rows<11>(x, n, g, mode, accumulate, have, out, ft, [](int i) { return i; }, [&](int i) { return d[i]; },
-                [&](int i) { return gs3trust::row_radius(rad, i); });
+  emit_rows<11, HUT>(
+      x, n, g, mode, accumulate, have, out, ft, [](int i) { return i; }, [&](int i) { return d[i]; },
+      [&](int i) {
+        if constexpr (HUT) return dd[i];
+        else return 0.f;
+      },
+      [&](int i) { return gs3trust::row_radius(rad, i); });
 }
 
 // The chain rule into a gradient (MODE 0) or a Hutchinson diagonal (MODE 1).
@@ -854,9 +901,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ x
 
 // The chain rule fused with the update of Algorithm 1 (mode 2): a kernel of
 // its own name, so profiles tell it from the gradient launches.
-template <int DEG>
+template <int DEG, bool HUT>
 __global__ __launch_bounds__(256) void k_tr_update(const float* __restrict__ x, int64_t n, BwdBatch B, FusedTr ft) {
-  project_bwd_body<DEG, 2>(x, n, B, 0, 0.f, nullptr, ft);
+  project_bwd_body<DEG, 2, HUT>(x, n, B, 0, 0.f, nullptr, ft);
 }
 
 uint64_t probe_inner(uint64_t seed, uint32_t i) {
@@ -902,7 +949,20 @@ void launch_project_bwd(const float* x, int64_t n, int deg, const BwdBatch& B, i
                         float* out, const FusedTr& ft, hipStream_t st) {
   if (B.n < 1) return;
   if (mode == 2) {
-    GS3_DEG_DISPATCH(deg, k_tr_update, dim3(blocks_for(n, kBwdGauss)), dim3(256), 0, st, x, n, B, ft);
+    auto kernel = [&](auto d, auto h) {
+      hipLaunchKernelGGL((k_tr_update<decltype(d)::value, decltype(h)::value>), dim3(blocks_for(n, kBwdGauss)),
+                         dim3(256), 0, st, x, n, B, ft);
+    };
+    auto by_probe = [&](auto d) {
+      if (B.n_probe > 0) kernel(d, std::true_type{});
+      else kernel(d, std::false_type{});
+    };
+    switch (deg) {
+      case 0: by_probe(std::integral_constant<int, 0>{}); break;
+      case 1: by_probe(std::integral_constant<int, 1>{}); break;
+      case 2: by_probe(std::integral_constant<int, 2>{}); break;
+      default: by_probe(std::integral_constant<int, 3>{}); break;
+    }
   } else {
     auto kernel = [&](auto d, auto m) {
       hipLaunchKernelGGL((k_project_bwd<decltype(d)::value, decltype(m)::value>), dim3(blocks_for(n, kBwdGauss)),

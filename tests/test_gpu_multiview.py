@@ -100,14 +100,17 @@ def test_batched_equals_mean_of_single_views(c1):
 
 
 def test_batched_fused_iteration_matches_separate_calls(c1):
-    """gs3_tr_iteration with |S1| = |S2| = 4 and nu = 2 against the separate
-    calls on the same views, bit for bit."""
+    """gs3_tr_iteration against the separate calls on the same views, bit for
+    bit: |S1| = 4 with |S2| = 2 and nu = 2 (eight entries: D_t formed inside
+    the update launch), |S1| = |S2| = 4 with nu = 2 (twelve entries: D_t
+    through memory), and a step without Hutchinson."""
     sc, x, targets = c1
     a = make_scene(x, targets, sc.cameras, 0)
     b = make_scene(x, targets, sc.cameras, 0)
     g = a._empty_like_params()
     D = a._empty_like_params()
-    for it, (S1, S2, nu) in enumerate([([0, 2, 4, 6], [1, 3, 5, 7], 2), ([1, 2, 3, 4], [], 1)]):
+    plan = [([0, 2, 4, 6], [1, 3], 2), ([0, 2, 4, 6], [1, 3, 5, 7], 2), ([1, 2, 3, 4], [], 1)]
+    for it, (S1, S2, nu) in enumerate(plan):
         seed = 7100 + it
         say("batched fused iteration", it, "S1", S1, "S2", S2, "nu", nu)
         if S2:
