@@ -218,13 +218,21 @@ __device__ __forceinline__ float probe_sign(uint64_t inner, uint64_t k) {
 __device__ __forceinline__ float opacity_of(float logit) { return (float)(1.0 / (1.0 + exp(-(double)logit))); }
 __device__ __forceinline__ float skip_threshold(float op) { return (float)(-log(255.0 * (double)op)); }
 
-// A workgroup takes 64 consecutive Gaussians.  Wave 0: geometry -- screen
-// centre, conic, opacity, skip threshold, tile rectangle, depth key, tile
-// count -- and whether the splat is visible; waves 1..3: colour channel
-// w - 1 of the visible splats only (an invisible Gaussian's SH rows are never
-// read: at city scale most Gaussians are outside the view) and its clamp bit.
-// The four waves write disjoint words of the record.
-constexpr int kFwdGauss = 64;
+// A workgroup takes 256 consecutive Gaussians.  First each thread projects
+// one of them (screen centre, conic, depth, tile rectangle) and the
+// Gaussians whose rectangle is not empty are listed in LDS with what the
+// rest needs; the others are culled at once.  Then thread j takes listed
+// Gaussian j: opacity and skip threshold and the exact tile count of its
+// tile list (a splat that reaches no tile is culled), and for a visible
+// splat its record, tile rectangle, depth key and tile count.  Last the
+// colour: one thread per (channel, listed visible splat), each loading its
+// 16 SH coefficients before the sum, and the clamp bits.  The per-splat work
+// thus runs on dense lists (with a Gaussian per thread throughout, most
+// lanes idled behind the few visible splats of a wave: at city scale most
+// Gaussians are outside the view), and an invisible Gaussian's SH rows are
+// never read.  vis_count receives the visible count of every 64 consecutive
+// Gaussians.
+constexpr int kFwdGauss = 256;
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x, int64_t n, CamDev cam,
@@ -232,18 +240,26 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
                                                       uint32_t* __restrict__ depth_key,
                                                       uint32_t* __restrict__ tiles,
                                                       uint32_t* __restrict__ vis_count) {
-  __shared__ uint32_t vis_bits[2];  // bit l of word l / 32: lane l's splat is visible
-  __shared__ uint32_t clamp_bits[kFwdGauss];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t g = (int64_t)blockIdx.x * kFwdGauss + lane;
-  const bool live = g < n;
-  auto src = [&](int r) { return x[(int64_t)r * n + g]; };
-  float* rw = reinterpret_cast<float*>(rec + g);  // words of the record
-  if (w == 0) {
-    bool vis = false;
-    if (live) {
+  // the listed Gaussians (structure of arrays)
+  __shared__ float l_u[kFwdGauss], l_v[kFwdGauss], l_qa[kFwdGauss], l_qb[kFwdGauss], l_qc[kFwdGauss];
+  __shared__ float l_depth[kFwdGauss], l_dir[3][kFwdGauss];
+  __shared__ uint32_t l_lo[kFwdGauss], l_hi[kFwdGauss], l_off[kFwdGauss];
+  __shared__ uint32_t l_clamp[kFwdGauss];  // bit c: channel c unclamped; bit 3: the splat is visible
+  __shared__ uint32_t listed;
+  __shared__ uint32_t vis_bits[kFwdGauss / 32];  // bit o: Gaussian g0 + o is visible
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t g0 = (int64_t)blockIdx.x * kFwdGauss;
+  if (tid == 0) listed = 0u;
+  if (tid < kFwdGauss / 32) vis_bits[tid] = 0u;
+  __syncthreads();
+  {
+    const int64_t g = g0 + tid;
+    auto src = [&](int r) { return x[(int64_t)r * n + g]; };
+    bool cand = false;
+    Proj<float> p;
+    int ix0 = 0, ix1 = 0, iy0 = 0, iy1 = 0;
+    if (g < n) {
       const float sv[3] = {exp_ls(src(3)), exp_ls(src(4)), exp_ls(src(5))};
-      Proj<float> p;
       project_geo<float>(src, sv, cam, p);
       const float inv = 0.0625f;
       const float txf = (float)cam.tiles_x, tyf = (float)cam.tiles_y;
@@ -251,92 +267,150 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float* __restrict__ x
       const float x1 = fminf(fmaxf(floorf((p.u + p.radius) * inv) + 1.f, 0.f), txf);
       const float y0 = fminf(fmaxf(floorf((p.v - p.radius) * inv), 0.f), tyf);
       const float y1 = fminf(fmaxf(floorf((p.v + p.radius) * inv) + 1.f, 0.f), tyf);
-      vis = p.ok && isfinite(p.u) && isfinite(p.v) && isfinite(p.radius);
-      const int ix0 = vis ? (int)x0 : 0, ix1 = vis ? (int)x1 : 0, iy0 = vis ? (int)y0 : 0, iy1 = vis ? (int)y1 : 0;
-      vis = vis && ix1 > ix0 && iy1 > iy0;
-      // the rectangle's tiles the splat can reach (the tile list, see
-      // SplatRows): a splat that reaches none is culled
-      float op = 0.f, tau = 0.f, qa = 0.f, qb = 0.f, qc = 0.f;
-      uint32_t touched = 0u;
-      int bx0 = ix0, by0 = iy0, bx1 = ix1, by1 = iy1;
-      if (vis) {
-        op = opacity_of(src(10));
-        tau = skip_threshold(op);
-        qa = -0.5f * p.ca;
-        qb = -p.cb;
-        qc = -0.5f * p.cc;
-        // the stored rectangle is the bounding box of the listed tiles, so
-        // the emission and the backward walk no rows without tiles
-        touched = splat_tile_bounds(splat_rows(p.u, p.v, qa, qb, qc, tau, ix0, iy0, ix1, iy1), bx0, by0, bx1, by1);
+      cand = p.ok && isfinite(p.u) && isfinite(p.v) && isfinite(p.radius);
+      if (cand) {
+        ix0 = (int)x0;
+        ix1 = (int)x1;
+        iy0 = (int)y0;
+        iy1 = (int)y1;
       }
-      vis = vis && touched > 0u;
-      if (!vis) {
-        depth_key[g] = 0xffffffffu;
-        tiles[g] = 0u;
-      } else {
-        *reinterpret_cast<float4*>(rw) = make_float4(p.u, p.v, qa, qb);
-        rw[4] = qc;
-        rw[5] = op;
-        rw[9] = tau;
-        rw[10] = 0.f;
-        rect[g] = make_uint2((uint32_t)bx0 | ((uint32_t)by0 << 16), (uint32_t)bx1 | ((uint32_t)by1 << 16));
-        depth_key[g] = __float_as_uint(p.depth);
-        tiles[g] = touched;
-      }
+      cand = cand && ix1 > ix0 && iy1 > iy0;
     }
-    const uint64_t b = __ballot(vis);
-    clamp_bits[lane] = 0u;
-    if (lane == 0) {
-      vis_bits[0] = (uint32_t)b;
-      vis_bits[1] = (uint32_t)(b >> 32);
-      vis_count[blockIdx.x] = (uint32_t)__popcll(b);
+    const uint64_t b = __ballot(cand);
+    uint32_t base = 0u;
+    if (lane == 0 && b) base = atomicAdd(&listed, (uint32_t)__popcll(b));
+    base = __shfl(base, 0, 64);
+    if (cand) {
+      const int j = (int)base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      l_u[j] = p.u;
+      l_v[j] = p.v;
+      l_qa[j] = -0.5f * p.ca;
+      l_qb[j] = -p.cb;
+      l_qc[j] = -0.5f * p.cc;
+      l_depth[j] = p.depth;
+      // view direction for the colour
+      const float dx = src(0) - cam.campos[0], dy = src(1) - cam.campos[1], dz = src(2) - cam.campos[2];
+      const float inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
+      l_dir[0][j] = dx * inv;
+      l_dir[1][j] = dy * inv;
+      l_dir[2][j] = dz * inv;
+      l_lo[j] = (uint32_t)ix0 | ((uint32_t)iy0 << 16);
+      l_hi[j] = (uint32_t)ix1 | ((uint32_t)iy1 << 16);
+      l_off[j] = (uint32_t)tid;
+    } else if (g < n) {
+      depth_key[g] = 0xffffffffu;
+      tiles[g] = 0u;
     }
   }
   __syncthreads();
-  const bool vis = (vis_bits[lane >> 5] >> (lane & 31)) & 1u;
-  if (w > 0 && vis) {
-    // RGB_c = sum_k Y_k(dir) f_kc + 0.5, clamped at 0 (as colour<>, one channel)
+  const int m = (int)listed;
+  if (tid < m) {
+    const int j = tid, o = (int)l_off[j];
+    const int64_t g = g0 + o;
+    const float u = l_u[j], v = l_v[j], qa = l_qa[j], qb = l_qb[j], qc = l_qc[j];
+    const uint32_t lo = l_lo[j], hi = l_hi[j];
+    const float op = opacity_of(x[10 * n + g]);
+    const float tau = skip_threshold(op);
+    // the rectangle's tiles the splat can reach (the tile list, see
+    // SplatRows); the stored rectangle is the bounding box of the listed
+    // tiles, so the emission and the backward walk no rows without tiles
+    int bx0, by0, bx1, by1;
+    const uint32_t touched = splat_tile_bounds(
+        splat_rows(u, v, qa, qb, qc, tau, (int)(lo & 0xffffu), (int)(lo >> 16), (int)(hi & 0xffffu), (int)(hi >> 16)),
+        bx0, by0, bx1, by1);
+    l_clamp[j] = touched ? 8u : 0u;
+    if (touched == 0u) {
+      depth_key[g] = 0xffffffffu;
+      tiles[g] = 0u;
+    } else {
+      float* rw = reinterpret_cast<float*>(rec + g);
+      *reinterpret_cast<float4*>(rw) = make_float4(u, v, qa, qb);
+      rw[4] = qc;
+      rw[5] = op;
+      rw[9] = tau;
+      rw[10] = 0.f;  // filled later (the splat's first pair)
+      rect[g] = make_uint2((uint32_t)bx0 | ((uint32_t)by0 << 16), (uint32_t)bx1 | ((uint32_t)by1 << 16));
+      depth_key[g] = __float_as_uint(l_depth[j]);
+      tiles[g] = touched;
+      atomicOr(&vis_bits[o >> 5], 1u << (o & 31));
+    }
+  }
+  __syncthreads();
+  // colour channel c of listed splat j, for the visible ones:
+  // RGB_c = sum_k Y_k(dir) f_kc + 0.5, clamped at 0 (as colour<>)
+  for (int i = tid; i < 3 * m; i += 256) {
+    const int c = i / m, j = i - c * m;
+    if (!(l_clamp[j] & 8u)) continue;
+    const int64_t g = g0 + l_off[j];
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int c = w - 1;
-    const float dx = src(0) - cam.campos[0], dy = src(1) - cam.campos[1], dz = src(2) - cam.campos[2];
-    const float inv = 1.f / sqrtf((dx * dx + dy * dy) + dz * dz);
+    float f[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) f[k] = x[(int64_t)(11 + 3 * k + c) * n + g];
     float Y[K];
-    sh_basis<float, DEG>(dx * inv, dy * inv, dz * inv, Y);
+    sh_basis<float, DEG>(l_dir[0][j], l_dir[1][j], l_dir[2][j], Y);
     float acc = 0.5f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = acc + Y[k] * src(11 + 3 * k + c);
-    rw[6 + c] = fmaxf(acc, 0.f);
-    if (acc >= 0.f) atomicOr(&clamp_bits[lane], 1u << c);
+    for (int k = 0; k < K; ++k) acc = acc + Y[k] * f[k];
+    reinterpret_cast<float*>(rec + g)[6 + c] = fmaxf(acc, 0.f);
+    if (acc >= 0.f) atomicOr(&l_clamp[j], 1u << c);
   }
   __syncthreads();
   // spare word: which colour channels are unclamped (bit c), for the backward
-  if (w == 1 && vis) rw[11] = __uint_as_float(clamp_bits[lane]);
+  if (tid < m && (l_clamp[tid] & 8u)) reinterpret_cast<float*>(rec + g0 + l_off[tid])[11] = __uint_as_float(l_clamp[tid] & 7u);
+  const int64_t q = (int64_t)blockIdx.x * (kFwdGauss / 64) + w;  // this wave's 64 Gaussians
+  if (lane == 0 && q * 64 < n) vis_count[q] = (uint32_t)(__popc(vis_bits[2 * w]) + __popc(vis_bits[2 * w + 1]));
 }
+
+// Tangent records of the visible Gaussians (tiles != 0).  A workgroup takes
+// kJvpChunk consecutive Gaussians, lists its visible ones in LDS (order
+// within the list is immaterial: each Gaussian's record is computed on its
+// own), and its threads walk the list, so a wave's lanes all carry visible
+// Gaussians (one thread per Gaussian left most lanes idle: 13% lane use at
+// the city scale).
+constexpr int kJvpChunk = 1024;
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_jvp(const float* __restrict__ x, int64_t n, CamDev cam,
                                                       const uint32_t* __restrict__ tiles, int kind, uint64_t inner,
                                                       const float* __restrict__ tangent, TRec* __restrict__ trec) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  if (tiles[g] == 0u) return;
-  auto src = [&](int r) {
-    const int64_t k = (int64_t)r * n + g;
-    float t = kind == PROBE_HASH ? probe_sign(inner, (uint64_t)k) : tangent[k];
-    return Dual{x[k], t};
-  };
-  const float sv[3] = {exp_ls(x[3 * n + g]), exp_ls(x[4 * n + g]), exp_ls(x[5 * n + g])};
-  Proj<Dual> p;
-  project_geo<Dual>(src, sv, cam, p);
-  Dual rgb[3];
-  bool pos[3];
-  colour<Dual, DEG>(src, cam, rgb, pos);
-  const Dual op = sigmoid_(src(10));
-  TRec t;
-  t.a = make_float4(p.u.t, p.v.t, p.ca.t, p.cb.t);
-  t.b = make_float4(p.cc.t, op.t, rgb[0].t, rgb[1].t);
-  t.c = make_float4(rgb[2].t, 0.f, 0.f, 0.f);
-  trec[g] = t;
+  __shared__ uint32_t list[kJvpChunk];
+  __shared__ uint32_t listed;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int64_t g0 = (int64_t)blockIdx.x * kJvpChunk;
+  if (tid == 0) listed = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kJvpChunk / 256; ++j) {
+    const int o = j * 256 + tid;
+    const bool vis = g0 + o < n && tiles[g0 + o] != 0u;
+    const uint64_t b = __ballot(vis);
+    uint32_t base = 0u;
+    if (lane == 0 && b) base = atomicAdd(&listed, (uint32_t)__popcll(b));
+    base = __shfl(base, 0, 64);
+    if (vis) list[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = o;
+  }
+  __syncthreads();
+  const int m = (int)listed;
+  for (int i = tid; i < m; i += 256) {
+    const int64_t g = g0 + list[i];
+    auto src = [&](int r) {
+      const int64_t k = (int64_t)r * n + g;
+      float t = kind == PROBE_HASH ? probe_sign(inner, (uint64_t)k) : tangent[k];
+      return Dual{x[k], t};
+    };
+    const float sv[3] = {exp_ls(x[3 * n + g]), exp_ls(x[4 * n + g]), exp_ls(x[5 * n + g])};
+    Proj<Dual> p;
+    project_geo<Dual>(src, sv, cam, p);
+    Dual rgb[3];
+    bool pos[3];
+    colour<Dual, DEG>(src, cam, rgb, pos);
+    const Dual op = sigmoid_(src(10));
+    TRec t;
+    t.a = make_float4(p.u.t, p.v.t, p.ca.t, p.cb.t);
+    t.b = make_float4(p.cc.t, op.t, rgb[0].t, rgb[1].t);
+    t.c = make_float4(rgb[2].t, 0.f, 0.f, 0.f);
+    trec[g] = t;
+  }
 }
 
 // Sum of each Gaussian's per-(Gaussian, tile) partials, which sit in the
@@ -935,7 +1009,7 @@ void launch_project_jvp(const float* x, int64_t n, int deg, const CamDev& cam, c
                         const uint32_t* tiles, int probe_kind, uint64_t seed, uint32_t probe_index,
                         const float* tangent, TRec* trec, hipStream_t st) {
   (void)rec;
-  GS3_DEG_DISPATCH(deg, k_project_jvp, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, n, cam, tiles, probe_kind,
+  GS3_DEG_DISPATCH(deg, k_project_jvp, dim3(blocks_for(n, kJvpChunk)), dim3(256), 0, st, x, n, cam, tiles, probe_kind,
                    probe_inner(seed, probe_index), tangent, trec);
 }
 
