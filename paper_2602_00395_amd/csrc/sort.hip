@@ -338,16 +338,9 @@ __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* __restric
   if (i < n) counts[i] = tiles[order[i]];
 }
 
-// One thread per pair: the owning Gaussian (in depth order) is the last entry
-// whose exclusive offset is <= the pair index (a zero-count entry shares its
-// offset with the next one, so the last such entry is the owner).  Writes are
-// then contiguous across the wave.  Zero-count (culled) Gaussians sort last,
-// so the owners of a workgroup's 256 pairs are at most 256 consecutive
-// entries: two threads find the first and last owner in global memory, the
-// offsets in between are staged in LDS and every thread searches those.  A
-// pair's tile is the k-th of its Gaussian's tile list (SplatRows), k its
-// index among the Gaussian's pairs.  The thread of a Gaussian's first pair
-// also records the Gaussian's first pair in its splat record.
+// The owning Gaussian of pair index `target` (in depth order): the last
+// entry whose exclusive offset is <= target (a zero-count entry shares its
+// offset with the next one, so the last such entry is the owner).
 __device__ __forceinline__ int64_t last_le(const uint32_t* __restrict__ offsets, int64_t n, uint32_t target) {
   int64_t lo = 0, hi = n;  // the first index with offsets[idx] > target is in (lo, hi]
   while (hi - lo > 1) {
@@ -358,6 +351,30 @@ __device__ __forceinline__ int64_t last_le(const uint32_t* __restrict__ offsets,
   return lo;
 }
 
+__device__ __forceinline__ int wave_incl_max(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(v, d, 64);
+    if (lane >= d) v = max(v, y);
+  }
+  return v;
+}
+
+// A workgroup writes the window of 256 consecutive pairs [p0, p1).  Every
+// Gaussian (in depth order, count >= 1 up to the visible count) with pairs
+// in the window is walked once, by one thread: its tile list row by row
+// (SplatRows) up to the window's end, marking for each row the window
+// position of the row's first pair in the window with that pair's tile and
+// the Gaussian.  Then pair q takes the last mark at or before q (a
+// workgroup max-scan): its tile is the marked tile plus the distance, since
+// the pairs of a row are its tiles left to right.  Walking each Gaussian's
+// rows once per window, instead of once per pair up to the pair's row, cuts
+// the row evaluations of a splat of R rows from about pairs x (R + 1) / 2 to
+// R.  The owners span at most 256 consecutive entries from the owner of p0
+// (each has a pair), found from the scan's owner table or by a binary
+// search.  The thread of a Gaussian whose first pair lies in the window also
+// records that pair in the splat record.  Writes are contiguous.
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets,
                                                      const uint32_t* __restrict__ owner, int64_t owner_blocks,
@@ -365,49 +382,64 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
                                                      const uint32_t* __restrict__ n_dev, int64_t n_pairs, int tiles_x,
                                                      uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_gid) {
   if (n_dev) n = *n_dev;
-  __shared__ uint32_t soff[256];
   __shared__ int64_t bounds[2];
-  const int tid = threadIdx.x;
+  __shared__ int mark[256];            // q where a row's first pair in the window sits at q, else -1
+  __shared__ uint32_t run_tile[256];   // at a mark: that pair's tile
+  __shared__ uint32_t run_g[256];      // at a mark: the Gaussian
+  __shared__ int wmax[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int64_t p1 = p0 + 256 < n_pairs ? p0 + 256 : n_pairs;
   if ((int64_t)blockIdx.x < owner_blocks) {
-    // the owner of the first pair, from the scan; every item has at least
-    // one pair up to the last visible one, so the block's 256 pairs belong
-    // to at most 256 consecutive items from there
     if (tid == 0) {
       bounds[0] = owner[blockIdx.x];
       bounds[1] = min(bounds[0] + 255, n - 1);
     }
   } else if (tid < 2) {
-    const int64_t p = tid == 0 ? p0 : (p0 + 255 < n_pairs ? p0 + 255 : n_pairs - 1);
-    bounds[tid] = last_le(offsets, n, (uint32_t)p);
+    bounds[tid] = last_le(offsets, n, (uint32_t)(tid == 0 ? p0 : p1 - 1));
   }
+  mark[tid] = -1;
   __syncthreads();
   const int64_t first = bounds[0];
-  const int64_t span = bounds[1] - first + 1;
-  const bool staged = span <= 256;
-  if (staged && tid < span) soff[tid] = offsets[first + tid];
-  __syncthreads();
-  const int64_t i = p0 + tid;
-  if (i >= n_pairs) return;
-  int64_t own;
-  if (staged) {
-    int a = 0, b = (int)span;  // the last j with soff[j] <= i is in [a, b)
-    while (b - a > 1) {
-      const int mid = (a + b) >> 1;
-      if (soff[mid] <= (uint32_t)i) a = mid;
-      else b = mid;
+  if (tid <= bounds[1] - first) {
+    const int64_t rank = first + tid;
+    const int64_t off = offsets[rank];
+    const int64_t end = rank + 1 < n ? (int64_t)offsets[rank + 1] : n_pairs;
+    // the Gaussian's pairs k in [k_lo, k_hi) lie in the window
+    const int64_t k_lo = p0 > off ? p0 - off : 0, k_hi = (p1 < end ? p1 : end) - off;
+    if (k_lo < k_hi) {
+      const uint32_t g = order[rank];
+      const SplatRows sr = splat_rows_of(rec[g], rect[g]);
+      if (k_lo == 0) rec[g].c.z = __uint_as_float((uint32_t)off);
+      int64_t c = 0;  // pairs in the rows before row ty
+      for (int ty = sr.y0; ty < sr.y1 && c < k_hi; ++ty) {
+        int lo, hi;
+        splat_row_span(sr, ty, lo, hi);
+        const int64_t m = hi > lo ? hi - lo : 0;
+        if (c + m > k_lo) {
+          const int64_t kk = c > k_lo ? c : k_lo;
+          const int q = (int)(off + kk - p0);
+          mark[q] = q;
+          run_tile[q] = (uint32_t)(ty * tiles_x + lo + (int)(kk - c));
+          run_g[q] = g;
+        }
+        c += m;
+      }
     }
-    own = first + a;
-  } else {
-    own = last_le(offsets, n, (uint32_t)i);
   }
-  const uint32_t g = order[own];
-  const uint32_t k = (uint32_t)i - offsets[own];
-  int tx, ty;
-  splat_tile_at(splat_rows_of(rec[g], rect[g]), k, tx, ty);
-  pair_tile[i] = (uint32_t)(ty * tiles_x + tx);
-  pair_gid[i] = g;
-  if (k == 0) rec[g].c.z = __uint_as_float((uint32_t)i);
+  __syncthreads();
+  // the last mark at or before this position (position 0 is always marked:
+  // the owner of p0 marks the row of its pair k_lo)
+  int s = wave_incl_max(mark[tid]);
+  if (lane == 63) wmax[w] = s;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s = i < w ? max(s, wmax[i]) : s;
+  const int64_t i = p0 + tid;
+  if (i < p1) {
+    pair_tile[i] = run_tile[s] + (uint32_t)(tid - s);
+    pair_gid[i] = run_g[s];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ tile, int64_t n,
