@@ -128,6 +128,7 @@ struct ViewBufs {
   // per-pair binning scratch
   int64_t pair_cap = 0;
   uint32_t *pt = nullptr, *pg = nullptr, *pt2 = nullptr, *pg2 = nullptr;
+  uint32_t* rowtab = nullptr;  // per-row entries of the tile lists (k_emit_pairs)
   // depth rank owning pair 256 b, written by the offsets scan for the
   // emission; sized from the pair capacity of earlier views
   uint32_t* block_owner = nullptr;
@@ -395,6 +396,7 @@ void free_slot(ViewBufs& v) {
   dfree(v.pg);
   dfree(v.pt2);
   dfree(v.pg2);
+  dfree(v.rowtab);
   dfree(v.partials);
   dfree(v.valid);
   dfree(v.block_owner);
@@ -474,10 +476,10 @@ constexpr int64_t kPairsPerGaussian = 12;
 int64_t reserved_pairs(int64_t n) { return kPairsPerGaussian * n; }
 
 // bytes of pair scratch for a capacity of `cap` pairs on views of up to
-// max_tiles tiles: tile ids and Gaussian ids double-buffered, nine partials
-// per pair, the backward's units and segment states, the radix histograms
+// max_tiles tiles: tile ids and Gaussian ids double-buffered, the tile
+// lists' row entries, nine partials per pair, the backward's units and segment states, the radix histograms
 int64_t pair_bytes(int64_t cap, int64_t max_tiles, int64_t n) {
-  return cap * (16 + 36) + cap / 8 + seg_slots(max_tiles, cap) * (8 + 16 * GS3_BLOCK) +
+  return cap * (20 + 36) + cap / 8 + seg_slots(max_tiles, cap) * (8 + 16 * GS3_BLOCK) +
          (int64_t)radix_temp_bytes(std::max<int64_t>(cap, n)) + 4 * (cap / 256 + 1);
 }
 
@@ -503,6 +505,7 @@ gs3_status ensure_pairs(gs3_scene* s, ViewBufs& v, int64_t n_pairs, const hipStr
   dfree(v.pg, st);
   dfree(v.pt2, st);
   dfree(v.pg2, st);
+  dfree(v.rowtab, st);
   dfree(v.rtmp, st);
   dfree(v.units, st);
   v.pair_cap = 0;
@@ -510,6 +513,7 @@ gs3_status ensure_pairs(gs3_scene* s, ViewBufs& v, int64_t n_pairs, const hipStr
   GS3_TRY(dalloc(&v.pg, cap));
   GS3_TRY(dalloc(&v.pt2, cap));
   GS3_TRY(dalloc(&v.pg2, cap));
+  GS3_TRY(dalloc(&v.rowtab, cap));
   GS3_TRY(dalloc(&v.units, (size_t)seg_slots(s->max_tiles, cap)));
   v.rtmp_bytes = radix_temp_bytes(std::max<int64_t>(cap, s->N));
   GS3_TRY(dalloc((char**)&v.rtmp, v.rtmp_bytes));
@@ -694,7 +698,7 @@ gs3_status bin_camera(gs3_scene* s, ViewBufs& v, const gs3_camera& camera, int c
   GS3_TRY(ensure_blend(s, v, n_pairs, &st));
   auto p3 = prof::begin("emit_pairs", st);
   launch_emit_pairs(order, v.offsets, v.block_owner, v.owner_blocks, v.rec, v.rect, N, v.total_dev + 1, n_pairs,
-                    cd.tiles_x, v.pt, v.pg, st);
+                    cd.tiles_x, v.pt, v.pg, v.rowtab, st);
   prof::end(p3, st, N, n_pairs);
   const int n_tiles = cd.tiles_x * cd.tiles_y;
   uint32_t *tk, *tv;
@@ -754,6 +758,8 @@ BlendView blend_view(const ViewBufs& b, ViewBufs& e) {
   V.ranges = b.ranges;
   V.order = b.have_order ? b.tile_order : nullptr;
   V.rect = b.rect;
+  V.tiles = b.tiles;
+  V.rowtab = b.rowtab;
   V.units = b.units;
   V.cam = b.cd;
   V.n_tiles = b.cd.tiles_x * b.cd.tiles_y;
@@ -956,6 +962,7 @@ void carve_render(Carver& c, ViewBufs& t, int64_t n, int64_t px, int64_t tiles, 
   get(&t.pg, pairs);
   get(&t.pt2, pairs);
   get(&t.pg2, pairs);
+  get(&t.rowtab, pairs);
   get(&t.units, seg_slots(tiles, pairs));
   get(&t.seg, seg_slots(tiles, pairs) * GS3_BLOCK);
   get((char**)&t.rtmp, radix_temp_bytes(std::max<int64_t>(pairs, n)));

@@ -558,6 +558,7 @@ struct StageB {
   float4 b[kBwdBatch];
   float2 c[kBwdBatch];  // b, tau
   uint32_t first[kBwdBatch];  // the Gaussian's first pair
+  uint32_t cnt[kBwdBatch];    // its tile count
   uint2 rc[kBwdBatch];        // its tile rectangle
   float red[4][9][kBwdBatch];
   uint64_t bits[4][kBwdBatch / 64];
@@ -566,6 +567,8 @@ struct StageB {
 
 template <bool COUNT>
 __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, const uint2* __restrict__ rect,
+                                               const uint32_t* __restrict__ tiles,
+                                               const uint32_t* __restrict__ rowtab,
                                                const uint32_t* __restrict__ pair_gid,
                                                const uint2* __restrict__ ranges, const uint2* __restrict__ units,
                                                const CamDev& cam, const uint32_t* __restrict__ pix_last,
@@ -645,6 +648,7 @@ __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, cons
           s.b[tid] = r.b;
           s.c[tid] = make_float2(r.c.x, r.c.y);
           s.first[tid] = __float_as_uint(r.c.z);
+          s.cnt[tid] = tiles[g];
           s.rc[tid] = rect[g];
           m = block_mask(r.a, r.b, r.c.y, tx, ty);
         }
@@ -750,9 +754,20 @@ __device__ __forceinline__ void blend_bwd_body(const Rec* __restrict__ rec, cons
       // the pair sums skip it (every other pair's bit is set with its store)
       if (h0 || h1 || h2 || h3) {
         // the pair's slot in the Gaussian-contiguous partials: the
-        // Gaussian's first pair plus the tile's index in its tile list
-        const Rec rr{s.a[tid], s.b[tid], make_float4(s.c[tid].x, s.c[tid].y, 0.f, 0.f)};
-        const uint32_t slot = s.first[tid] + splat_tile_index(splat_rows_of(rr, s.rc[tid]), tx, ty);
+        // Gaussian's first pair plus the tile's index in its tile list,
+        // from the row's entry (or, without one, a walk over the rows)
+        const uint32_t first = s.first[tid];
+        const uint2 rc = s.rc[tid];
+        const int row_off = ty - (int)(rc.x >> 16);
+        uint32_t idx;
+        if (row_entry_kept(row_off, s.cnt[tid])) {
+          const uint32_t e = rowtab[first + (uint32_t)row_off];
+          idx = (e & 0xffffu) + (uint32_t)(tx - (int)(e >> 16));
+        } else {
+          const Rec rr{s.a[tid], s.b[tid], make_float4(s.c[tid].x, s.c[tid].y, 0.f, 0.f)};
+          idx = splat_tile_index(splat_rows_of(rr, rc), tx, ty);
+        }
+        const uint32_t slot = first + idx;
         // a wave that skipped the splat contributes exactly zero
         float* dst = partials + (int64_t)slot * 9;
         atomicOr(valid + (slot >> 5), 1u << (slot & 31));
@@ -814,7 +829,7 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(BlendBatch B, float bg0
   int v, b;
   if (!view_of_block(B, v, b)) return;
   const BlendView& V = B.v[v];
-  blend_bwd_body<COUNT>(V.rec, V.rect, V.pair_gid, V.ranges, V.units, V.cam, V.pix_last, V.pix_T, V.seg, bg0, bg1,
+  blend_bwd_body<COUNT>(V.rec, V.rect, V.tiles, V.rowtab, V.pair_gid, V.ranges, V.units, V.cam, V.pix_last, V.pix_T, V.seg, bg0, bg1,
                         bg2, V.cot, V.partials, V.valid, V.n_tiles, b, ctr);
 }
 

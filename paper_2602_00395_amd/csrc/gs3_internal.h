@@ -200,6 +200,22 @@ __device__ __forceinline__ void splat_tile_at(const SplatRows& s, uint32_t k, in
   ty = s.y0;
 }
 
+// Row entries of the tile lists, written by the emission and read by the
+// backward in place of a row walk.  A Gaussian whose pairs take the slots
+// [first, first + count) and whose stored rectangle starts at row y0 has, at
+// rowtab[first + ty - y0], for each row ty of its list with pairs: the
+// number of its pairs in the rows before ty (low 16 bits) and the row's
+// first column (high 16 bits) -- kept only where ty - y0 < count and count
+// fits 16 bits, so an entry stays inside the Gaussian's own slots (the rows
+// of a list are the rows a convex ellipse reaches, contiguous in practice,
+// but a float32 row span might still come out empty).
+__device__ __forceinline__ bool row_entry_kept(int row_off, uint32_t count) {
+  return row_off >= 0 && (uint32_t)row_off < count && count <= 0xffffu;
+}
+__device__ __forceinline__ uint32_t row_entry(uint32_t before, int first_col) {
+  return before | ((uint32_t)first_col << 16);
+}
+
 __device__ __forceinline__ SplatRows splat_rows_of(const Rec& r, uint2 rc) {
   return splat_rows(r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.c.y, (int)(rc.x & 0xffff), (int)(rc.x >> 16),
                     (int)(rc.y & 0xffff), (int)(rc.y >> 16));
@@ -315,9 +331,11 @@ void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t 
 // writes each visible Gaussian's pair offset into its record (rec.c.z);
 // owner (nullable, from scan_exclusive_u32) names the first pair's item of
 // each 256-pair block b < owner_blocks, the others search the offsets
+// rowtab: the row entries of the tile lists (row_entry), n_pairs words
 void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, const uint32_t* owner,
                        int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, const uint32_t* n_dev,
-                       int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st);
+                       int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid, uint32_t* rowtab,
+                       hipStream_t st);
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st);
 // Tile ids in (approximately) descending order of their pair count, and the
 // backward's work units: each non-empty tile's list cut into depth segments
@@ -355,6 +373,8 @@ struct BlendView {
   const uint2* ranges = nullptr;
   const uint32_t* order = nullptr;
   const uint2* rect = nullptr;    // backward
+  const uint32_t* tiles = nullptr;   // backward: tile count per Gaussian
+  const uint32_t* rowtab = nullptr;  // backward: row entries of the tile lists (row_entry)
   const uint2* units = nullptr;   // backward
   int64_t n_units = 0;            // backward
   const float* cot = nullptr;     // backward

@@ -374,13 +374,16 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 // R.  The owners span at most 256 consecutive entries from the owner of p0
 // (each has a pair), found from the scan's owner table or by a binary
 // search.  The thread of a Gaussian whose first pair lies in the window also
-// records that pair in the splat record.  Writes are contiguous.
+// records that pair in the splat record, and each row's entry (row_entry)
+// is written by the window that holds the row's first pair.  Pair writes
+// are contiguous.
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets,
                                                      const uint32_t* __restrict__ owner, int64_t owner_blocks,
                                                      Rec* __restrict__ rec, const uint2* __restrict__ rect, int64_t n,
                                                      const uint32_t* __restrict__ n_dev, int64_t n_pairs, int tiles_x,
-                                                     uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_gid) {
+                                                     uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_gid,
+                                                     uint32_t* __restrict__ rowtab) {
   if (n_dev) n = *n_dev;
   __shared__ int64_t bounds[2];
   __shared__ int mark[256];            // q where a row's first pair in the window sits at q, else -1
@@ -422,6 +425,9 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
           mark[q] = q;
           run_tile[q] = (uint32_t)(ty * tiles_x + lo + (int)(kk - c));
           run_g[q] = g;
+          // the row's entry, written by the window that holds its first pair
+          if (kk == c && row_entry_kept(ty - sr.y0, (uint32_t)(end - off)))
+            rowtab[off + (ty - sr.y0)] = row_entry((uint32_t)c, lo);
         }
         c += m;
       }
@@ -638,10 +644,12 @@ void launch_gather_counts(const uint32_t* order, const uint32_t* tiles, int64_t 
 
 void launch_emit_pairs(const uint32_t* order, const uint32_t* offsets_sorted, const uint32_t* owner,
                        int64_t owner_blocks, Rec* rec, const uint2* rect, int64_t n, const uint32_t* n_dev,
-                       int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid, hipStream_t st) {
+                       int64_t n_pairs, int tiles_x, uint32_t* pair_tile, uint32_t* pair_gid, uint32_t* rowtab,
+                       hipStream_t st) {
   if (n > 0 && n_pairs > 0)
     hipLaunchKernelGGL(k_emit_pairs, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, order, offsets_sorted, owner,
-                       owner ? owner_blocks : (int64_t)0, rec, rect, n, n_dev, n_pairs, tiles_x, pair_tile, pair_gid);
+                       owner ? owner_blocks : (int64_t)0, rec, rect, n, n_dev, n_pairs, tiles_x, pair_tile, pair_gid,
+                       rowtab);
 }
 
 void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* ranges, int n_tiles, hipStream_t st) {
