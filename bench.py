@@ -85,9 +85,11 @@ def parse():
     return ap.parse_args()
 
 
-# stage -> (kernel name in the profile summaries, its source file)
+# stage -> (kernel name in the profile summaries, its source file); the fused
+# update has an instance for plain and one for Hutchinson iterations
 _KERNEL_OF = {"blend_bwd": ("k_blend_bwd<false>", "blend.hip"), "blend_fwd": ("k_blend_fwd<false>", "blend.hip"),
-              "blend_jvp": ("k_blend_jvp<false>", "blend.hip"), "tr_update": ("k_tr_update<3>", "project.hip"),
+              "blend_jvp": ("k_blend_jvp<false>", "blend.hip"), "tr_update": ("k_tr_update<3, false>", "project.hip"),
+              "tr_update_hutch": ("k_tr_update<3, true>", "project.hip"),
               "tr_step": ("k_tr_step<59>", "optim.hip"), "adam_step": ("k_adam_step<59>", "optim.hip")}
 
 
@@ -130,6 +132,12 @@ def roofline(stage: str, st: dict, n: int, p: int, hutch_launches: int, workload
     sec = st["total_ms"] / 1e3
     avg_ms = st["total_ms"] / st["launches"]
     traffic = measured_traffic(stage, workload)
+    if stage == "tr_update" and traffic is not None and hutch_launches:
+        # launch-weighted over the plain and the Hutchinson instance, as the
+        # algorithmic bytes below
+        th = measured_traffic("tr_update_hutch", workload)
+        n_l = st["launches"]
+        traffic = None if th is None else (traffic * (n_l - hutch_launches) + th * hutch_launches) // n_l
     if stage in OPS_PER_EVAL:
         flops = OPS_PER_EVAL[stage] * st["work0"]
         ach = flops / sec / 1e12
