@@ -255,7 +255,9 @@ gs3_status gs3_tr_step(gs3_scene* scene, const float* grad_dev, const float* D_d
  * Hutchinson entries and the n1 views fit one batch (n1 + n2 * nu <= 8) the
  * same launch also forms D_t, which then never goes through memory either
  * (the entries take their own view slots: a Hutchinson iteration holds n1 +
- * n2 * nu slots of per-view scratch).  The parameters are double-buffered
+ * n2 * nu slots of per-view scratch, and the probe entries run on a second
+ * stream the scene creates, forked from `stream` and joined to it before
+ * the update, so the call still completes in `stream` order).  The parameters are double-buffered
  * (the update reads one copy and writes the other), so a pointer from
  * gs3_scene_params is not valid after this call.  A D_t of a larger batch
  * and the other views' gradient live in scene-owned buffers.  loss_out (nullable,

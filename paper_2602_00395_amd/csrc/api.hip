@@ -161,6 +161,11 @@ struct ViewBufs {
   double* dpart = nullptr;
 };
 
+struct aux_stream_t {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct gs3_scene {
   int64_t N = 0;
   int deg = 0, K = 1, P = 14, n_cams = 0, n_train = 0;
@@ -183,6 +188,9 @@ struct gs3_scene {
   uint32_t* host_u32 = nullptr;
   double* host_f64 = nullptr;
   hipEvent_t done_ev = nullptr;
+  // gs3_tr_iteration: a second stream (default priority) for the probe
+  // entries of a Hutchinson batch, forked from and joined to the caller's
+  aux_stream_t aux{};
   // every buffer carved from the static scratch: nothing may be allocated
   bool fixed_scratch = false;
 };
@@ -434,6 +442,12 @@ void free_all(gs3_scene* s) {
   s->host_f64 = nullptr;
   if (s->done_ev) (void)hipEventDestroy(s->done_ev);
   s->done_ev = nullptr;
+  // every use of the second stream precedes a join the caller's stream
+  // waited for, so the completion event above covered it
+  if (s->aux.fork) (void)hipEventDestroy(s->aux.fork);
+  if (s->aux.join) (void)hipEventDestroy(s->aux.join);
+  if (s->aux.st) (void)hipStreamDestroy(s->aux.st);
+  s->aux = aux_stream_t{};
 }
 
 // Optimizer state is allocated (and zeroed) on first use, so a scene holds
@@ -457,6 +471,14 @@ gs3_status need_adam_state(gs3_scene* s, hipStream_t st) {
   GS3_TRY(zeroed(&s->am, PN, st));
   return zeroed(&s->av, PN, st);
 }
+gs3_status need_aux(gs3_scene* s) {
+  if (s->aux.st) return GS3_OK;
+  GS3_HIP(hipStreamCreateWithFlags(&s->aux.st, hipStreamNonBlocking));
+  GS3_HIP(hipEventCreateWithFlags(&s->aux.fork, hipEventDisableTiming));
+  GS3_HIP(hipEventCreateWithFlags(&s->aux.join, hipEventDisableTiming));
+  return GS3_OK;
+}
+
 gs3_status need_fused_state(gs3_scene* s, hipStream_t st) {
   const int64_t PN = (int64_t)s->P * s->N;
   GS3_TRY(need_tr_state(s, st));
@@ -1405,11 +1427,31 @@ gs3_status gs3_tr_iteration(gs3_scene* s, const int32_t* cams1, int32_t n1, cons
   if (n2 > 0 && nh + n1 <= GS3_MAX_VIEWS) {
     // one batch: the Hutchinson entries in slots [0, nh), the gradient views
     // after them, and one update launch that sums D_t in registers (D_t never
-    // goes through device memory)
+    // goes through device memory).  The two parts share no buffer until the
+    // update, so the probe entries run on the second stream beside the
+    // gradient views (much of either part is latency-bound: pair sums,
+    // emission, radix passes), forked after the caller's earlier work and
+    // joined before the update.
     GS3_TRY(need_slots(s, (int)(nh + n1)));
+    GS3_TRY(need_aux(s));
+    GS3_HIP(hipEventRecord(s->aux.fork, st));
+    GS3_HIP(hipStreamWaitEvent(s->aux.st, s->aux.fork, 0));
+    // on every exit from here the caller's stream waits for the second one,
+    // so the scene's completion event covers the probe work
+    struct Join {
+      gs3_scene* s;
+      hipStream_t st;
+      ~Join() {
+        (void)hipEventRecord(s->aux.join, s->aux.st);
+        (void)hipStreamWaitEvent(st, s->aux.join, 0);
+      }
+    };
     Entries H, C;
-    GS3_TRY(hvp_batch(s, cams2, nu, seed, 0, (int)nh, 0, H, st));
-    GS3_TRY(grad_batch(s, cams1, 0, n1, (int)nh, grad_scale(s, n1), loss_out != nullptr, C, st));
+    {
+      Join join_{s, st};
+      GS3_TRY(hvp_batch(s, cams2, nu, seed, 0, (int)nh, 0, H, s->aux.st));
+      GS3_TRY(grad_batch(s, cams1, 0, n1, (int)nh, grad_scale(s, n1), loss_out != nullptr, C, st));
+    }
     for (int k = 0; k < H.n; ++k) {
       C.b[C.n + k] = H.b[k];
       C.e[C.n + k] = H.e[k];
