@@ -177,29 +177,6 @@ __device__ __forceinline__ uint32_t splat_tile_index(const SplatRows& s, int tx,
   return n + (uint32_t)(tx - lo);
 }
 
-// The k-th tile of the splat (k < its count), as (tx, ty).
-__device__ __forceinline__ void splat_tile_at(const SplatRows& s, uint32_t k, int& tx, int& ty) {
-  if (s.mode != 2) {
-    const int w = s.x1 - s.x0;
-    ty = s.y0 + (int)(k / (uint32_t)w);
-    tx = s.x0 + (int)(k % (uint32_t)w);
-    return;
-  }
-  for (int r = s.y0; r < s.y1; ++r) {
-    int lo, hi;
-    splat_row_span(s, r, lo, hi);
-    const uint32_t m = hi > lo ? (uint32_t)(hi - lo) : 0u;
-    if (k < m) {
-      ty = r;
-      tx = lo + (int)k;
-      return;
-    }
-    k -= m;
-  }
-  tx = s.x0;  // not reached for k below the count
-  ty = s.y0;
-}
-
 // Row entries of the tile lists, written by the emission and read by the
 // backward in place of a row walk.  A Gaussian whose pairs take the slots
 // [first, first + count) and whose stored rectangle starts at row y0 has, at
