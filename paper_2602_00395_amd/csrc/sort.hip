@@ -497,13 +497,35 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
   }
 }
 
+// Four consecutive sorted pairs per thread (one 16-byte load, the
+// neighbours on either side from the adjacent words): a tile's range starts
+// where the tile id differs from the previous pair's and ends where it
+// differs from the next one's.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ tile, int64_t n,
                                                       uint2* __restrict__ ranges) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t t = tile[i];
-  if (i == 0 || tile[i - 1] != t) ranges[t].x = (uint32_t)i;
-  if (i == n - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  constexpr uint32_t kNone = 0xffffffffu;  // no tile id takes this value
+  uint32_t t[6];
+  t[0] = i0 > 0 ? tile[i0 - 1] : kNone;
+  if (i0 + 4 <= n) {
+    const uint4 q = *reinterpret_cast<const uint4*>(tile + i0);
+    t[1] = q.x;
+    t[2] = q.y;
+    t[3] = q.z;
+    t[4] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[1 + j] = i0 + j < n ? tile[i0 + j] : kNone;
+  }
+  t[5] = i0 + 4 < n ? tile[i0 + 4] : kNone;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t i = i0 + j;
+    if (i >= n) break;
+    if (t[j] != t[j + 1]) ranges[t[j + 1]].x = (uint32_t)i;
+    if (t[j + 2] != t[j + 1]) ranges[t[j + 1]].y = (uint32_t)(i + 1);
+  }
 }
 
 // Longest-list-first schedule of the tiles (approximate): one workgroup
@@ -705,7 +727,7 @@ void launch_tile_ranges(const uint32_t* pair_tile, int64_t n_pairs, uint2* range
   hipLaunchKernelGGL(k_fill_u32, dim3(nblk(2 * (int64_t)n_tiles, 256)), dim3(256), 0, st, (uint32_t*)ranges,
                      2 * (int64_t)n_tiles, 0u);
   if (n_pairs > 0)
-    hipLaunchKernelGGL(k_tile_ranges, dim3(nblk(n_pairs, 256)), dim3(256), 0, st, pair_tile, n_pairs, ranges);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(nblk(n_pairs, 1024)), dim3(256), 0, st, pair_tile, n_pairs, ranges);
 }
 
 void launch_make_keys(const uint32_t* pair_tile, const uint32_t* pair_gid, const uint32_t* depth_key,
