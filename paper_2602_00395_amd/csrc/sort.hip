@@ -405,11 +405,11 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 // pairs) or by a binary search.  The thread of a Gaussian whose first pair
 // lies in the window also records that pair in the splat record, and each
 // row's entry (row_entry) is written by the window that holds the row's
-// first pair.  A window holds two pairs per thread: the kernel is bound by
-// the latency of its dependent loads and barriers, and with a workgroup per
-// 256 pairs a city view took 0.160 ms against 0.115.  Pair writes are
-// contiguous.
-constexpr int kEmitWin = 512;
+// first pair.  A window holds four pairs per thread: the kernel is bound by
+// the latency of its dependent loads and barriers (a city view took 0.160 ms
+// with a workgroup per 256 pairs and 0.115 per 512; 1,024 take 15-24 us less
+// than 512).  Pair writes are contiguous.
+constexpr int kEmitWin = 1024;
 
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets,
