@@ -499,7 +499,8 @@ int64_t reserved_pairs(int64_t n) { return kPairsPerGaussian * n; }
 
 // bytes of pair scratch for a capacity of `cap` pairs on views of up to
 // max_tiles tiles: tile ids and Gaussian ids double-buffered, the tile
-// lists' row entries, nine partials per pair, the backward's units and segment states, the radix histograms
+// lists' row entries, nine partials per pair, the backward's units and
+// segment states, the radix histograms
 int64_t pair_bytes(int64_t cap, int64_t max_tiles, int64_t n) {
   return cap * (20 + 36) + cap / 8 + seg_slots(max_tiles, cap) * (8 + 16 * GS3_BLOCK) +
          (int64_t)radix_temp_bytes(std::max<int64_t>(cap, n)) + 4 * (cap / 256 + 1);

@@ -829,8 +829,8 @@ __global__ __launch_bounds__(GS3_BLOCK) void k_blend_bwd(BlendBatch B, float bg0
   int v, b;
   if (!view_of_block(B, v, b)) return;
   const BlendView& V = B.v[v];
-  blend_bwd_body<COUNT>(V.rec, V.rect, V.tiles, V.rowtab, V.pair_gid, V.ranges, V.units, V.cam, V.pix_last, V.pix_T, V.seg, bg0, bg1,
-                        bg2, V.cot, V.partials, V.valid, V.n_tiles, b, ctr);
+  blend_bwd_body<COUNT>(V.rec, V.rect, V.tiles, V.rowtab, V.pair_gid, V.ranges, V.units, V.cam, V.pix_last, V.pix_T,
+                        V.seg, bg0, bg1, bg2, V.cot, V.partials, V.valid, V.n_tiles, b, ctr);
 }
 
 inline int chunk_for(int n_tiles) { return (n_tiles + 7) / 8; }
